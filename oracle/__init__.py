@@ -1,0 +1,188 @@
+"""FP64 CPU oracle of the IFEM coupling step -- test infrastructure only.
+
+Thin ctypes marshalling around ``ifem_oracle.c`` (plain C, double precision,
+single threaded).  Only the tests, the smoke check and the CPU-baseline leg
+of the benchmark use it; the HIP library never imports it and shares none
+of its code.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "ifem_oracle.c")
+LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction beyond explicit fma calls)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+_D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_I = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_L = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(LIB)
+        L.orc_weight.argtypes = [C.c_double]
+        L.orc_weight.restype = C.c_double
+        L.orc_membrane_W.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_membrane_W.restype = C.c_double
+        L.orc_solid_W.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_solid_W.restype = C.c_double
+        L.orc_membrane_element.argtypes = [_D, _D, C.c_int, C.c_double, C.c_double, _D]
+        L.orc_tet_element.argtypes = [_D, _D, C.c_double, C.c_double, _D]
+        L.orc_mls.argtypes = [_D, _I, C.c_double, _D, C.c_int, _L, _D]
+        L.orc_forces.argtypes = [C.c_int, _D, _D, C.c_int, _I, _I, _I, _I, C.c_int, _I, C.c_int, _I, _D, _D, _D, _D,
+                                 C.c_int, C.c_int, _D, _L]
+        L.orc_energy.argtypes = [C.c_int, _D, _D, C.c_int, _I, _I, _I, C.c_int, _I, C.c_int, _I, _D, _D, _D]
+        L.orc_reduce.argtypes = [C.c_int, _D, C.c_int, _I, _I, _I, C.c_int, _I, C.c_int, _D]
+        L.orc_curvature.argtypes = [_D, C.c_long, C.c_int, C.c_int, _I, C.c_long, C.c_int, C.c_int, _D, _D, _D, _D]
+        L.orc_laplacian.argtypes = [_D, C.c_long, C.c_int, C.c_int, _I, C.c_long, C.c_int, C.c_int, _D, _D, _D]
+        L.orc_spread.argtypes = [C.c_int, _D, _D, _I, _I, _D, _D, _L, C.c_int64, _D]
+        L.orc_interp.argtypes = [C.c_int, _D, _I, _I, _D, _D, _L, C.c_int64, _D, _D]
+        _lib = L
+    return _lib
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ---------------------------------------------------------------- element level
+def weight(r: float) -> float:
+    return lib().orc_weight(float(r))
+
+
+def membrane_W(law, mu, mu2, I1, I2) -> float:
+    return lib().orc_membrane_W(int(law), float(mu), float(mu2), float(I1), float(I2))
+
+
+def solid_W(mu, lam, I1, I3) -> float:
+    return lib().orc_solid_W(float(mu), float(lam), float(I1), float(I3))
+
+
+def membrane_element(X, x, law, mu, mu2):
+    """(3,3) reference and current node rows -> (3,3) nodal forces, status."""
+    f = np.zeros((3, 3))
+    st = lib().orc_membrane_element(_c(X, np.float64), _c(x, np.float64), int(law), float(mu), float(mu2), f)
+    return f, st
+
+
+def tet_element(X, x, mu, lam):
+    f = np.zeros((4, 3))
+    st = lib().orc_tet_element(_c(X, np.float64), _c(x, np.float64), float(mu), float(lam), f)
+    return f, st
+
+
+# ---------------------------------------------------------------- scene level
+def _scene_args(scene):
+    return (_c(scene.node_start, np.int32), _c(scene.tri_start, np.int32), _c(scene.tet_start, np.int32),
+            _c(scene.tri, np.int32), scene.n_tris, _c(scene.tet, np.int32), scene.n_tets)
+
+
+def forces(scene, x=None, elastic=True, bending=True):
+    """Internal nodal forces [3][n_nodes] and counts (degenerate/inverted elements, non-finite outputs)."""
+    x = scene.x64 if x is None else x
+    F = np.zeros((3, scene.n_nodes))
+    counts = np.zeros(2, dtype=np.int64)
+    ns, ts, qs, tri, ntri, tet, ntet = _scene_args(scene)
+    lib().orc_forces(scene.n_nodes, _c(scene.X_ref, np.float64), _c(x, np.float64), scene.n_particles, ns, ts, qs,
+                     tri, ntri, tet, ntet, _c(scene.law, np.int32), _c(scene.mu, np.float64), _c(scene.mu2, np.float64),
+                     _c(scene.kb, np.float64), _c(scene.c0, np.float64), int(bool(elastic)), int(bool(bending)), F,
+                     counts)
+    return F, counts
+
+
+def energy(scene, x=None):
+    x = scene.x64 if x is None else x
+    E = np.zeros(scene.n_particles)
+    ns, ts, qs, tri, ntri, tet, ntet = _scene_args(scene)
+    lib().orc_energy(scene.n_nodes, _c(scene.X_ref, np.float64), _c(x, np.float64), scene.n_particles, ts, qs, tri,
+                     ntri, tet, ntet, _c(scene.law, np.int32), _c(scene.mu, np.float64), _c(scene.mu2, np.float64), E)
+    return E
+
+
+def reduce(scene, x=None):
+    """[n_particles][5] = V, A, centroid."""
+    x = scene.x64 if x is None else x
+    red = np.zeros((scene.n_particles, 5))
+    ns, ts, qs, tri, ntri, tet, ntet = _scene_args(scene)
+    lib().orc_reduce(scene.n_nodes, _c(x, np.float64), scene.n_particles, ts, qs, tri, ntri, tet, ntet, red)
+    return red
+
+
+def curvature(scene, p: int, x=None):
+    """Per-node (A, kH, kG, normals[3][n]) of membrane particle p."""
+    x = _c(scene.x64 if x is None else x, np.float64)
+    s, e = int(scene.node_start[p]), int(scene.node_start[p + 1])
+    n = e - s
+    A, kH, kG, nr = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(3 * n)
+    lib().orc_curvature(x, scene.n_nodes, s, e, _c(scene.tri, np.int32), scene.n_tris, int(scene.tri_start[p]),
+                        int(scene.tri_start[p + 1]), A, kH, kG, nr)
+    return A, kH, kG, nr.reshape(3, n)
+
+
+def laplacian(scene, p: int, g, A, x=None):
+    x = _c(scene.x64 if x is None else x, np.float64)
+    s, e = int(scene.node_start[p]), int(scene.node_start[p + 1])
+    out = np.zeros(e - s)
+    lib().orc_laplacian(x, scene.n_nodes, s, e, _c(scene.tri, np.int32), scene.n_tris, int(scene.tri_start[p]),
+                        int(scene.tri_start[p + 1]), _c(A, np.float64), _c(g, np.float64), out)
+    return out
+
+
+def mls(p, box, comp: int):
+    """(base[3] int64, phi[27]) of one point on lattice ``comp`` of ``box``."""
+    base = np.zeros(3, dtype=np.int64)
+    phi = np.zeros(27)
+    st = lib().orc_mls(_c(p, np.float64), np.asarray(box.n, dtype=np.int32), float(box.h),
+                       np.asarray(box.origin, dtype=np.float64), int(comp), base, phi)
+    if st:
+        raise RuntimeError("singular MLS moment matrix")
+    return base, phi
+
+
+def _box_args(scene):
+    n, h, o, off = scene.box_arrays()
+    return _c(n, np.int32), _c(h, np.float64), _c(o, np.float64), _c(off, np.int64)
+
+
+def _points(scene, x, box_of_point):
+    if box_of_point is None:
+        box_of_point = scene.box[scene.node_particle()]
+    return _c(x, np.float64), _c(box_of_point, np.int32)
+
+
+def spread(scene, F, x=None, box_of_point=None):
+    """[3][total_cells] spread of nodal forces F [3][n_points]."""
+    x, bop = _points(scene, scene.x64 if x is None else x, box_of_point)
+    n, h, o, off = _box_args(scene)
+    grid = np.zeros((3, scene.total_cells))
+    lib().orc_spread(x.shape[1], x, _c(F, np.float64), bop, n, h, o, off, scene.total_cells, grid)
+    return grid
+
+
+def interp(scene, grid, x=None, box_of_point=None):
+    """[3][n_points] interpolation of a [3][total_cells] grid field."""
+    x, bop = _points(scene, scene.x64 if x is None else x, box_of_point)
+    n, h, o, off = _box_args(scene)
+    v = np.zeros((3, x.shape[1]))
+    lib().orc_interp(x.shape[1], x, bop, n, h, o, off, scene.total_cells, _c(grid, np.float64), v)
+    return v

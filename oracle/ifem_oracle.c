@@ -1,0 +1,663 @@
+/*
+ * FP64 CPU oracle for the IFEM coupling step of Saadat, Guido, Iaccarino &
+ * Shaqfeh, "Immersed-finite-element method for deformable particle
+ * suspensions in viscous and viscoelastic media" (arXiv 1807.08219).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the HIP library is checked against.  It shares no code,
+ * header, table or helper with the library, and the library never calls it.
+ *
+ * Everything is plain double precision, single threaded, in the order the
+ * paper states it:
+ *   - membrane element forces in a per-element tangent frame
+ *       (Sec. II.B, eq. FEM_Membrane and the surface deformation gradient),
+ *     with the constitutive laws of Sec. II.A (tension relation, neo-Hookean
+ *     and Skalak energies);
+ *   - tetrahedral element forces (Sec. II.B, eq. FEM with the discrete
+ *     deformation gradient and the first Piola-Kirchhoff stress of the
+ *     slightly compressible neo-Hookean solid);
+ *   - Helfrich bending nodal force (Sec. II.B, bending force equation) with
+ *     the discrete curvature operators of Meyer, Desbrun, Schroeder & Barr
+ *     (2003) for the quantities the paper names (Voronoi area, mean and
+ *     Gaussian curvature, surface Laplacian);
+ *   - linear moving-least-squares weights, interpolation and spreading
+ *     (Sec. II.C, Interpolation Scheme);
+ *   - per-particle volume (Sec. II.E volume formula), area and centroid.
+ *
+ * Readings of the paper where it is silent or garbled are marked READING.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_LAW_TRI_NEOHOOKE 0
+#define ORC_LAW_TRI_SKALAK 1
+#define ORC_LAW_TET_NEOHOOKE 2
+
+/* ------------------------------------------------------------ small linear algebra */
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
+static void sub3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[0] - b[0];
+  c[1] = a[1] - b[1];
+  c[2] = a[2] - b[2];
+}
+static double det3(const double m[3][3]) {
+  return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+         m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+/* inverse by cofactors; returns the determinant */
+static double inv3(const double m[3][3], double r[3][3]) {
+  double d = det3(m);
+  r[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) / d;
+  r[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) / d;
+  r[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) / d;
+  r[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) / d;
+  r[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) / d;
+  r[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) / d;
+  r[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) / d;
+  r[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) / d;
+  r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) / d;
+  return d;
+}
+static void pos(const double* x, long stride, int k, double out[3]) {
+  out[0] = x[k];
+  out[1] = x[stride + k];
+  out[2] = x[2 * stride + k];
+}
+
+/* ------------------------------------------------------------ constitutive laws (Sec. II.A) */
+/* Membrane energy density per reference area as a function of I1 = tr C^, I2 = det C^. */
+double orc_membrane_W(int law, double mu, double mu2, double I1, double I2) {
+  if (law == ORC_LAW_TRI_NEOHOOKE) return 0.5 * mu * (I1 + 1.0 / I2 - 3.0); /* neo-Hookean membrane */
+  /* Skalak law with the shifted invariants I1 - 2 and I2 - 1 */
+  double a = I1 - 2.0, b = I2 - 1.0;
+  return 0.5 * mu * (0.5 * a * a + a - b) + mu2 / 8.0 * b * b;
+}
+/* dW/dI1 and dW/dI2 of the two membrane laws. */
+static void membrane_dW(int law, double mu, double mu2, double I1, double I2, double* W1, double* W2) {
+  if (law == ORC_LAW_TRI_NEOHOOKE) {
+    *W1 = 0.5 * mu;
+    *W2 = -0.5 * mu / (I2 * I2);
+  } else {
+    *W1 = 0.5 * mu * ((I1 - 2.0) + 1.0);
+    *W2 = -0.5 * mu + 0.25 * mu2 * (I2 - 1.0);
+  }
+}
+/* Slightly compressible neo-Hookean solid, I3 = J^2.  READING: the logarithmic
+ * term is ln(I3^(1/2)) = ln J, the only reading consistent with the discrete
+ * stress the paper gives for tetrahedra. */
+double orc_solid_W(double mu, double lam, double I1, double I3) {
+  return 0.25 * lam * (I3 - 1.0) - (0.5 * lam + mu) * log(sqrt(I3)) + 0.5 * mu * (I1 - 3.0);
+}
+
+/* ------------------------------------------------------------ membrane element (Sec. II.B) */
+/* Local orthonormal tangent frame of a triangle: e1 along edge 0->1, e2 = n x e1. */
+static int tri_frame(const double p0[3], const double p1[3], const double p2[3], double e1[3], double e2[3]) {
+  double a[3], b[3], n[3];
+  sub3(p1, p0, a);
+  sub3(p2, p0, b);
+  cross3(a, b, n);
+  double la = norm3(a), ln = norm3(n);
+  if (!(la > 0.0) || !(ln > 0.0)) return 1;
+  for (int i = 0; i < 3; ++i) {
+    e1[i] = a[i] / la;
+    n[i] /= ln;
+  }
+  cross3(n, e1, e2);
+  return 0;
+}
+
+/* Reference data of a linear triangle: gradients of the three shape functions
+ * in the reference tangent coordinates and the reference area. */
+static int tri_reference(const double X[3][3], double gradN[3][2], double* A0) {
+  double E1[3], E2[3], d1[3], d2[3];
+  if (tri_frame(X[0], X[1], X[2], E1, E2)) return 1;
+  sub3(X[1], X[0], d1);
+  sub3(X[2], X[0], d2);
+  /* columns of D0 are the two reference edges in the local frame */
+  double D0[2][2] = {{dot3(d1, E1), dot3(d2, E1)}, {dot3(d1, E2), dot3(d2, E2)}};
+  double det = D0[0][0] * D0[1][1] - D0[0][1] * D0[1][0];
+  if (!(det > 0.0)) return 1;
+  /* barycentric (s, t) = D0^-1 (xi - xi0): grad N1 and grad N2 are the rows of D0^-1 */
+  double inv[2][2] = {{D0[1][1] / det, -D0[0][1] / det}, {-D0[1][0] / det, D0[0][0] / det}};
+  gradN[1][0] = inv[0][0];
+  gradN[1][1] = inv[0][1];
+  gradN[2][0] = inv[1][0];
+  gradN[2][1] = inv[1][1];
+  gradN[0][0] = -gradN[1][0] - gradN[2][0];
+  gradN[0][1] = -gradN[1][1] - gradN[2][1];
+  *A0 = 0.5 * det;
+  return 0;
+}
+
+/* Surface deformation gradient F^_ij = sum_k (x_k . e_i) dN^_k/dxi_j in the
+ * current tangent frame.  The sum over k of the shape-function gradients is
+ * zero, so positions are taken relative to node 0 (same value, no loss of
+ * digits far from the origin). */
+static void tri_defgrad(const double x[3][3], const double gradN[3][2], const double e[2][3], double Fh[2][2]) {
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double s = 0.0;
+      for (int k = 1; k < 3; ++k) {
+        double d[3];
+        sub3(x[k], x[0], d);
+        s += dot3(d, e[i]) * gradN[k][j];
+      }
+      Fh[i][j] = s;
+    }
+}
+
+/* Membrane element: nodal forces f[k][i] = -A0 sum_{l,j} P^_lj dN^_k/dxi_j e_l,i.
+ * Returns 0, or 1 when the element is degenerate (I2 <= 0) and contributes 0. */
+int orc_membrane_element(const double X[3][3], const double x[3][3], int law, double mu, double mu2,
+                         double f[3][3]) {
+  memset(f, 0, 9 * sizeof(double));
+  double gradN[3][2], A0, e[2][3];
+  if (tri_reference(X, gradN, &A0)) return 1;
+  if (tri_frame(x[0], x[1], x[2], e[0], e[1])) return 1;
+  double Fh[2][2];
+  tri_defgrad(x, gradN, (const double(*)[3])e, Fh);
+  double C[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) C[i][j] = Fh[0][i] * Fh[0][j] + Fh[1][i] * Fh[1][j];
+  double I1 = C[0][0] + C[1][1];
+  double I2 = C[0][0] * C[1][1] - C[0][1] * C[1][0];
+  if (!(I2 > 0.0)) return 1;
+  double W1, W2;
+  membrane_dW(law, mu, mu2, I1, I2, &W1, &W2);
+  /* S^ = 2 (dW/dI1 I + J^2 C^-1 dW/dI2) with J^2 = I2 */
+  double Ci[2][2] = {{C[1][1] / I2, -C[0][1] / I2}, {-C[1][0] / I2, C[0][0] / I2}};
+  double S[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) S[i][j] = 2.0 * ((i == j ? W1 : 0.0) + I2 * Ci[i][j] * W2);
+  double P[2][2]; /* P^ = F^ S^ */
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) P[i][j] = Fh[i][0] * S[0][j] + Fh[i][1] * S[1][j];
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 2; ++l) {
+      double c = 0.0;
+      for (int j = 0; j < 2; ++j) c += P[l][j] * gradN[k][j];
+      for (int i = 0; i < 3; ++i) f[k][i] -= A0 * c * e[l][i];
+    }
+  return 0;
+}
+
+double orc_membrane_element_energy(const double X[3][3], const double x[3][3], int law, double mu, double mu2) {
+  double gradN[3][2], A0, e[2][3];
+  if (tri_reference(X, gradN, &A0)) return NAN;
+  if (tri_frame(x[0], x[1], x[2], e[0], e[1])) return NAN;
+  double Fh[2][2];
+  tri_defgrad(x, gradN, (const double(*)[3])e, Fh);
+  double C[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) C[i][j] = Fh[0][i] * Fh[0][j] + Fh[1][i] * Fh[1][j];
+  return A0 * orc_membrane_W(law, mu, mu2, C[0][0] + C[1][1], C[0][0] * C[1][1] - C[0][1] * C[1][0]);
+}
+
+/* ------------------------------------------------------------ tetrahedral element (Sec. II.B) */
+/* Shape-function gradients of a linear tetrahedron: rows of D0^-1 for nodes
+ * 1..3, minus their sum for node 0.  Returns the reference volume. */
+static double tet_reference(const double X[4][3], double gradN[4][3]) {
+  double D0[3][3], Di[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) D0[i][a] = X[a + 1][i] - X[0][i];
+  double det = inv3(D0, Di);
+  for (int a = 0; a < 3; ++a)
+    for (int j = 0; j < 3; ++j) gradN[a + 1][j] = Di[a][j];
+  for (int j = 0; j < 3; ++j) gradN[0][j] = -(gradN[1][j] + gradN[2][j] + gradN[3][j]);
+  return det / 6.0;
+}
+
+/* F_ij = sum_k x_i,k dN_k/dX_j, with positions relative to node 0 (the gradients sum to zero). */
+static void tet_defgrad(const double x[4][3], const double gradN[4][3], double F[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 1; k < 4; ++k) s += (x[k][i] - x[0][i]) * gradN[k][j];
+      F[i][j] = s;
+    }
+}
+
+/* Tet element: f[k][i] = -V0 P_ij dN_k/dX_j with
+ * P = F S,  S = lam/2 (J^2 - 1) F^-1 F^-T + mu (I - F^-1 F^-T).
+ * Returns 1 (and zero forces) for a degenerate reference or J <= 0. */
+int orc_tet_element(const double X[4][3], const double x[4][3], double mu, double lam, double f[4][3]) {
+  memset(f, 0, 12 * sizeof(double));
+  double gradN[4][3];
+  double V0 = tet_reference(X, gradN);
+  if (!(V0 > 0.0)) return 1;
+  double F[3][3], Fi[3][3];
+  tet_defgrad(x, gradN, F);
+  double J = inv3(F, Fi);
+  if (!(J > 0.0)) return 1;
+  double Cinv[3][3]; /* F^-1 F^-T */
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) Cinv[k][j] = Fi[k][0] * Fi[j][0] + Fi[k][1] * Fi[j][1] + Fi[k][2] * Fi[j][2];
+  double S[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) S[k][j] = 0.5 * lam * (J * J - 1.0) * Cinv[k][j] + mu * ((k == j) - Cinv[k][j]);
+  double P[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[i][j] = F[i][0] * S[0][j] + F[i][1] * S[1][j] + F[i][2] * S[2][j];
+  for (int k = 0; k < 4; ++k)
+    for (int i = 0; i < 3; ++i) f[k][i] = -V0 * (P[i][0] * gradN[k][0] + P[i][1] * gradN[k][1] + P[i][2] * gradN[k][2]);
+  return 0;
+}
+
+double orc_tet_element_energy(const double X[4][3], const double x[4][3], double mu, double lam) {
+  double gradN[4][3];
+  double V0 = tet_reference(X, gradN);
+  double F[3][3];
+  tet_defgrad(x, gradN, F);
+  double J = det3(F);
+  double I1 = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) I1 += F[i][j] * F[i][j];
+  return V0 * orc_solid_W(mu, lam, I1, J * J);
+}
+
+/* ------------------------------------------------------------ bending (Sec. II.B) */
+/* Discrete differential-geometry quantities per node of one closed triangulated
+ * surface (Meyer et al. 2003):
+ *   A[k]   mixed Voronoi area,
+ *   K[k]   sum_j (cot a_kj + cot b_kj)(x_k - x_j)   (not yet divided by 2 A_k),
+ *   th[k]  sum of the triangle angles at k,
+ *   N[k]   sum of the face area vectors around k.
+ * READING: the paper names Sinha & Graham's operators without stating them;
+ * these are the published operators behind that choice. */
+static void tri_angles_cot(const double p[3][3], double theta[3], double cotv[3]) {
+  for (int v = 0; v < 3; ++v) {
+    double u[3], w[3], c[3];
+    sub3(p[(v + 1) % 3], p[v], u);
+    sub3(p[(v + 2) % 3], p[v], w);
+    cross3(u, w, c);
+    double s = norm3(c), d = dot3(u, w);
+    theta[v] = atan2(s, d);
+    cotv[v] = d / s;
+  }
+}
+
+int orc_curvature(const double* x, long stride, int node_begin, int node_end, const int* tri, long tri_stride,
+                  int tri_begin, int tri_end, double* A, double* kH, double* kG, double* nrm /*[3][n_local]*/) {
+  int n = node_end - node_begin;
+  double* K = (double*)calloc((size_t)3 * n, sizeof(double));
+  double* th = (double*)calloc((size_t)n, sizeof(double));
+  for (int i = 0; i < n; ++i) A[i] = 0.0;
+  for (int i = 0; i < 3 * n; ++i) nrm[i] = 0.0;
+  for (int t = tri_begin; t < tri_end; ++t) {
+    int id[3] = {tri[t] - node_begin, tri[tri_stride + t] - node_begin, tri[2 * tri_stride + t] - node_begin};
+    double p[3][3], theta[3], cotv[3];
+    for (int v = 0; v < 3; ++v) pos(x, stride, id[v] + node_begin, p[v]);
+    tri_angles_cot(p, theta, cotv);
+    double e1[3], e2[3], fa[3];
+    sub3(p[1], p[0], e1);
+    sub3(p[2], p[0], e2);
+    cross3(e1, e2, fa);
+    double area = 0.5 * norm3(fa);
+    int obtuse = -1;
+    for (int v = 0; v < 3; ++v)
+      if (theta[v] > M_PI / 2) obtuse = v;
+    for (int v = 0; v < 3; ++v) {
+      int a = (v + 1) % 3, b = (v + 2) % 3; /* edge (v,a) is opposite b, edge (v,b) opposite a */
+      double dva[3], dvb[3];
+      sub3(p[v], p[a], dva);
+      sub3(p[v], p[b], dvb);
+      for (int i = 0; i < 3; ++i) K[3 * id[v] + i] += cotv[b] * dva[i] + cotv[a] * dvb[i];
+      th[id[v]] += theta[v];
+      for (int i = 0; i < 3; ++i) nrm[i * n + id[v]] += 0.5 * fa[i];
+      if (obtuse < 0)
+        A[id[v]] += 0.125 * (dot3(dvb, dvb) * cotv[a] + dot3(dva, dva) * cotv[b]);
+      else
+        A[id[v]] += (obtuse == v) ? 0.5 * area : 0.25 * area;
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    double nv[3] = {nrm[k], nrm[n + k], nrm[2 * n + k]};
+    double ln = norm3(nv);
+    for (int i = 0; i < 3; ++i) nrm[i * n + k] = nv[i] / ln;
+    double Kk[3] = {K[3 * k] / (2.0 * A[k]), K[3 * k + 1] / (2.0 * A[k]), K[3 * k + 2] / (2.0 * A[k])};
+    kH[k] = 0.5 * (Kk[0] * nrm[k] + Kk[1] * nrm[n + k] + Kk[2] * nrm[2 * n + k]);
+    kG[k] = (2.0 * M_PI - th[k]) / A[k];
+  }
+  free(K);
+  free(th);
+  return 0;
+}
+
+/* Cotangent surface Laplacian (1/2A_k) sum_j (cot a + cot b)(g_j - g_k) of a nodal field g. */
+int orc_laplacian(const double* x, long stride, int node_begin, int node_end, const int* tri, long tri_stride,
+                  int tri_begin, int tri_end, const double* A, const double* g, double* out) {
+  int n = node_end - node_begin;
+  for (int i = 0; i < n; ++i) out[i] = 0.0;
+  for (int t = tri_begin; t < tri_end; ++t) {
+    int id[3] = {tri[t] - node_begin, tri[tri_stride + t] - node_begin, tri[2 * tri_stride + t] - node_begin};
+    double p[3][3], theta[3], cotv[3];
+    for (int v = 0; v < 3; ++v) pos(x, stride, id[v] + node_begin, p[v]);
+    tri_angles_cot(p, theta, cotv);
+    for (int v = 0; v < 3; ++v) {
+      int a = (v + 1) % 3, b = (v + 2) % 3;
+      out[id[v]] += cotv[b] * (g[id[a]] - g[id[v]]) + cotv[a] * (g[id[b]] - g[id[v]]);
+    }
+  }
+  for (int k = 0; k < n; ++k) out[k] /= 2.0 * A[k];
+  return 0;
+}
+
+/* Helfrich bending force of one membrane particle, added to F:
+ * F_k = 2 kb [ Lap(kH - kH0) + 2 (kH - kH0)(kH^2 - kG + kH0 kH) ] n_k A_k,
+ * READING: kH0 = -c0/2 so that the energy density kb/2 (2 kH + c0)^2 equals
+ * 2 kb (kH - kH0)^2; kH = +1/R on a sphere with outward normals. */
+int orc_bending(const double* x, long stride, int node_begin, int node_end, const int* tri, long tri_stride,
+                int tri_begin, int tri_end, double kb, double c0, double* F /*[3][stride], accumulated*/) {
+  int n = node_end - node_begin;
+  double* A = (double*)malloc(sizeof(double) * n);
+  double* kH = (double*)malloc(sizeof(double) * n);
+  double* kG = (double*)malloc(sizeof(double) * n);
+  double* nr = (double*)malloc(sizeof(double) * 3 * n);
+  double* g = (double*)malloc(sizeof(double) * n);
+  double* lap = (double*)malloc(sizeof(double) * n);
+  double kH0 = -0.5 * c0;
+  orc_curvature(x, stride, node_begin, node_end, tri, tri_stride, tri_begin, tri_end, A, kH, kG, nr);
+  for (int k = 0; k < n; ++k) g[k] = kH[k] - kH0;
+  orc_laplacian(x, stride, node_begin, node_end, tri, tri_stride, tri_begin, tri_end, A, g, lap);
+  for (int k = 0; k < n; ++k) {
+    double s = 2.0 * kb * (lap[k] + 2.0 * g[k] * (kH[k] * kH[k] - kG[k] + kH0 * kH[k])) * A[k];
+    for (int i = 0; i < 3; ++i) F[i * stride + node_begin + k] += s * nr[i * n + k];
+  }
+  free(A);
+  free(kH);
+  free(kG);
+  free(nr);
+  free(g);
+  free(lap);
+  return 0;
+}
+
+/* ------------------------------------------------------------ all particle forces */
+/* Internal nodal forces of every particle (elastic always, bending when kb != 0
+ * and do_bending != 0), overwriting F [3][n_nodes].
+ * counts[0] += elements that were degenerate or inverted (contribute 0),
+ * counts[1] += non-finite nodal force components. */
+int orc_forces(int n_nodes, const double* X, const double* x, int n_particles, const int* node_start,
+               const int* tri_start, const int* tet_start, const int* tri, int n_tri, const int* tet, int n_tet,
+               const int* law, const double* mu, const double* mu2, const double* kb, const double* c0,
+               int do_elastic, int do_bending, double* F, long long* counts) {
+  memset(F, 0, sizeof(double) * 3 * (size_t)n_nodes);
+  for (int p = 0; p < n_particles; ++p) {
+    if (do_elastic) {
+      for (int t = tri_start[p]; t < tri_start[p + 1]; ++t) {
+        double Xe[3][3], xe[3][3], f[3][3];
+        int id[3] = {tri[t], tri[n_tri + t], tri[2 * n_tri + t]};
+        for (int v = 0; v < 3; ++v) {
+          pos(X, n_nodes, id[v], Xe[v]);
+          pos(x, n_nodes, id[v], xe[v]);
+        }
+        if (orc_membrane_element(Xe, xe, law[p], mu[p], mu2[p], f)) counts[0]++;
+        for (int v = 0; v < 3; ++v)
+          for (int i = 0; i < 3; ++i) F[i * (size_t)n_nodes + id[v]] += f[v][i];
+      }
+      for (int t = tet_start[p]; t < tet_start[p + 1]; ++t) {
+        double Xe[4][3], xe[4][3], f[4][3];
+        int id[4] = {tet[t], tet[n_tet + t], tet[2 * n_tet + t], tet[3 * n_tet + t]};
+        for (int v = 0; v < 4; ++v) {
+          pos(X, n_nodes, id[v], Xe[v]);
+          pos(x, n_nodes, id[v], xe[v]);
+        }
+        if (orc_tet_element(Xe, xe, mu[p], mu2[p], f)) counts[0]++;
+        for (int v = 0; v < 4; ++v)
+          for (int i = 0; i < 3; ++i) F[i * (size_t)n_nodes + id[v]] += f[v][i];
+      }
+    }
+    if (do_bending && kb[p] != 0.0 && tri_start[p + 1] > tri_start[p])
+      orc_bending(x, n_nodes, node_start[p], node_start[p + 1], tri, n_tri, tri_start[p], tri_start[p + 1], kb[p],
+                  c0[p], F);
+  }
+  for (size_t i = 0; i < 3 * (size_t)n_nodes; ++i)
+    if (!isfinite(F[i])) counts[1]++;
+  return 0;
+}
+
+/* Total elastic energy of each particle (membrane or solid), for gradient checks. */
+int orc_energy(int n_nodes, const double* X, const double* x, int n_particles, const int* tri_start,
+               const int* tet_start, const int* tri, int n_tri, const int* tet, int n_tet, const int* law,
+               const double* mu, const double* mu2, double* E) {
+  for (int p = 0; p < n_particles; ++p) {
+    double s = 0.0;
+    for (int t = tri_start[p]; t < tri_start[p + 1]; ++t) {
+      double Xe[3][3], xe[3][3];
+      int id[3] = {tri[t], tri[n_tri + t], tri[2 * n_tri + t]};
+      for (int v = 0; v < 3; ++v) {
+        pos(X, n_nodes, id[v], Xe[v]);
+        pos(x, n_nodes, id[v], xe[v]);
+      }
+      s += orc_membrane_element_energy(Xe, xe, law[p], mu[p], mu2[p]);
+    }
+    for (int t = tet_start[p]; t < tet_start[p + 1]; ++t) {
+      double Xe[4][3], xe[4][3];
+      int id[4] = {tet[t], tet[n_tet + t], tet[2 * n_tet + t], tet[3 * n_tet + t]};
+      for (int v = 0; v < 4; ++v) {
+        pos(X, n_nodes, id[v], Xe[v]);
+        pos(x, n_nodes, id[v], xe[v]);
+      }
+      s += orc_tet_element_energy(Xe, xe, mu[p], mu2[p]);
+    }
+    E[p] = s;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------ per-particle reductions */
+/* red[p] = {V, A, cx, cy, cz}.  Membranes: V by the three-term face sum
+ * (Sec. II.E volume formula), A = sum of triangle areas, c = volume centroid
+ * from the cone of every face to the coordinate origin.  Solids: V = sum of
+ * tetrahedron volumes, c = volume-weighted tetrahedron centroids, A = 0. */
+int orc_reduce(int n_nodes, const double* x, int n_particles, const int* tri_start, const int* tet_start,
+               const int* tri, int n_tri, const int* tet, int n_tet, double* red) {
+  for (int p = 0; p < n_particles; ++p) {
+    double V = 0.0, A = 0.0, m[3] = {0, 0, 0};
+    for (int t = tri_start[p]; t < tri_start[p + 1]; ++t) {
+      double a[3], b[3], c[3], bc[3], ca[3], ab[3];
+      pos(x, n_nodes, tri[t], a);
+      pos(x, n_nodes, tri[n_tri + t], b);
+      pos(x, n_nodes, tri[2 * n_tri + t], c);
+      cross3(b, c, bc);
+      cross3(c, a, ca);
+      cross3(a, b, ab);
+      double three = dot3(a, bc) + dot3(b, ca) + dot3(c, ab);
+      V += three / 18.0;
+      double cone = three / 18.0; /* volume of the tetrahedron (0, a, b, c) */
+      for (int i = 0; i < 3; ++i) m[i] += cone * (a[i] + b[i] + c[i]) / 4.0;
+      double u[3], w[3], n[3];
+      sub3(b, a, u);
+      sub3(c, a, w);
+      cross3(u, w, n);
+      A += 0.5 * norm3(n);
+    }
+    for (int t = tet_start[p]; t < tet_start[p + 1]; ++t) {
+      double q[4][3], D[3][3];
+      for (int v = 0; v < 4; ++v) pos(x, n_nodes, tet[v * n_tet + t], q[v]);
+      for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 3; ++a) D[i][a] = q[a + 1][i] - q[0][i];
+      double vol = det3(D) / 6.0;
+      V += vol;
+      for (int i = 0; i < 3; ++i) m[i] += vol * (q[0][i] + q[1][i] + q[2][i] + q[3][i]) / 4.0;
+    }
+    red[5 * p + 0] = V;
+    red[5 * p + 1] = A;
+    for (int i = 0; i < 3; ++i) red[5 * p + 2 + i] = m[i] / V;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------ MLS transfer (Sec. II.C) */
+/* Cubic-spline weight.  READING: the inner piece is printed as 2/3 - 4r + 4r^3,
+ * which is negative at r = 1/2 and discontinuous with the outer piece; the
+ * cubic B-spline 2/3 - 4r^2 + 4r^3 joins it with equal value, slope and
+ * curvature.  The outer piece 4/3 - 4r + 4r^2 - 4/3 r^3 is (4/3)(1 - r)^3. */
+double orc_weight(double r) {
+  if (r > 1.0) return 0.0;
+  if (r <= 0.5) return 2.0 / 3.0 - 4.0 * r * r + 4.0 * r * r * r;
+  double s = 1.0 - r;
+  return 4.0 / 3.0 * s * s * s;
+}
+
+/* Solve the 4x4 system A z = b by Gaussian elimination with partial pivoting. */
+static int solve4(double A[4][4], double b[4], double z[4]) {
+  for (int c = 0; c < 4; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    if (A[piv][c] == 0.0) return 1;
+    if (piv != c) {
+      for (int j = 0; j < 4; ++j) {
+        double t = A[c][j];
+        A[c][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+      double t = b[c];
+      b[c] = b[piv];
+      b[piv] = t;
+    }
+    for (int r = c + 1; r < 4; ++r) {
+      double m = A[r][c] / A[c][c];
+      for (int j = c; j < 4; ++j) A[r][j] -= m * A[c][j];
+      b[r] -= m * b[c];
+    }
+  }
+  for (int r = 3; r >= 0; --r) {
+    double s = b[r];
+    for (int j = r + 1; j < 4; ++j) s -= A[r][j] * z[j];
+    z[r] = s / A[r][r];
+  }
+  return 0;
+}
+
+static const double ORC_STAGGER[3][3] = {{0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0}};
+
+/* MLS weights of one Lagrangian point p on the lattice of velocity component
+ * `comp` of a periodic box (n cells per axis, spacing h, lattice nodes at
+ * origin + (i + s) h with s the staggering of that component).
+ *
+ * Stencil: the lattice node nearest to p and the 26 nodes sharing a cell
+ * with it.  READING (nearest-node rule, bit-specified so that every
+ * implementation selects the same stencil): q = p - origin,
+ * t = fma(q, 1/h, -s), base = floor(t + 1/2) per axis.
+ *
+ * Weights: minimise sum_J W_J (p(X_J)^T Z - q_J)^2 with linear basis
+ * p(X) = (1, X) and W_J = W(|X_J| / rho); phi = p(x_k)^T A^-1 B.
+ * READING: the support rho is the largest distance from a node to its 26
+ * neighbours, sqrt(3) h.  READING: the basis is written about x_k itself
+ * (X_J = x_J - x_k); the moving-least-squares weights do not change under a
+ * shift of the basis origin, and p(x_k) becomes (1, 0, 0, 0).
+ *
+ * Output: base[3] (unwrapped lattice index of the nearest node) and phi[27],
+ * ordered m = (mx, my, mz) in {-1,0,1}^3 with mx fastest. */
+int orc_mls(const double p[3], const int n[3], double h, const double origin[3], int comp, int64_t base[3],
+            double phi[27]) {
+  (void)n;
+  double inv_h = 1.0 / h, t[3];
+  for (int a = 0; a < 3; ++a) {
+    double q = p[a] - origin[a];
+    t[a] = fma(q, inv_h, -ORC_STAGGER[comp][a]);
+    base[a] = (int64_t)floor(t[a] + 0.5);
+  }
+  double rho = sqrt(3.0) * h;
+  double A[4][4] = {{0}}, B[27][4], Wv[27];
+  for (int mz = -1; mz <= 1; ++mz)
+    for (int my = -1; my <= 1; ++my)
+      for (int mx = -1; mx <= 1; ++mx) {
+        int idx = (mz + 1) * 9 + (my + 1) * 3 + (mx + 1);
+        int64_t m[3] = {mx, my, mz};
+        double XJ[3];
+        for (int a = 0; a < 3; ++a) {
+          double xJ = origin[a] + ((double)(base[a] + m[a]) + ORC_STAGGER[comp][a]) * h;
+          XJ[a] = xJ - p[a];
+        }
+        double W = orc_weight(norm3(XJ) / rho);
+        double pv[4] = {1.0, XJ[0], XJ[1], XJ[2]};
+        Wv[idx] = W;
+        for (int i = 0; i < 4; ++i) {
+          B[idx][i] = W * pv[i];
+          for (int j = 0; j < 4; ++j) A[i][j] += W * pv[i] * pv[j];
+        }
+      }
+  double rhs[4] = {1.0, 0.0, 0.0, 0.0}, z[4];
+  if (solve4(A, rhs, z)) return 1;
+  for (int J = 0; J < 27; ++J) phi[J] = z[0] * B[J][0] + z[1] * B[J][1] + z[2] * B[J][2] + z[3] * B[J][3];
+  (void)Wv;
+  return 0;
+}
+
+static int64_t wrap(int64_t i, int64_t n) {
+  int64_t r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+/* Spreading F_J = sum_k phi_J(x_J - x_k) F_k on every component lattice
+ * (Sec. II.C spreading operator; step 2 of the algorithm).  Overwrites grid
+ * [3][total_cells].  READING: the result is the nodal force itself (its sum
+ * over the grid equals the Lagrangian total); dividing by h^3 for a density
+ * is left to the caller. */
+int orc_spread(int n_points, const double* x, const double* F, const int* box_of_point, const int* bn,
+               const double* bh, const double* borig, const int64_t* cell_off, int64_t total_cells, double* grid) {
+  memset(grid, 0, sizeof(double) * 3 * (size_t)total_cells);
+  int bad = 0;
+  for (int k = 0; k < n_points; ++k) {
+    int b = box_of_point[k];
+    const int* n = bn + 3 * b;
+    double p[3] = {x[k], x[n_points + k], x[2 * (size_t)n_points + k]};
+    for (int d = 0; d < 3; ++d) {
+      int64_t base[3];
+      double phi[27];
+      if (orc_mls(p, n, bh[b], borig + 3 * b, d, base, phi)) {
+        bad++;
+        continue;
+      }
+      for (int mz = -1; mz <= 1; ++mz)
+        for (int my = -1; my <= 1; ++my)
+          for (int mx = -1; mx <= 1; ++mx) {
+            int64_t i = wrap(base[0] + mx, n[0]), j = wrap(base[1] + my, n[1]), kk = wrap(base[2] + mz, n[2]);
+            int64_t cell = cell_off[b] + (kk * n[1] + j) * n[0] + i;
+            grid[d * (size_t)total_cells + cell] += phi[(mz + 1) * 9 + (my + 1) * 3 + (mx + 1)] * F[d * (size_t)n_points + k];
+          }
+    }
+  }
+  return bad;
+}
+
+/* Interpolation v_k = sum_J phi_J(x_J - x_k) v_J per component (Sec. II.C;
+ * step 4 of the algorithm).  Overwrites v [3][n_points]. */
+int orc_interp(int n_points, const double* x, const int* box_of_point, const int* bn, const double* bh,
+               const double* borig, const int64_t* cell_off, int64_t total_cells, const double* grid, double* v) {
+  int bad = 0;
+  for (int k = 0; k < n_points; ++k) {
+    int b = box_of_point[k];
+    const int* n = bn + 3 * b;
+    double p[3] = {x[k], x[n_points + k], x[2 * (size_t)n_points + k]};
+    for (int d = 0; d < 3; ++d) {
+      int64_t base[3];
+      double phi[27], s = 0.0;
+      if (orc_mls(p, n, bh[b], borig + 3 * b, d, base, phi)) {
+        bad++;
+        v[d * (size_t)n_points + k] = NAN;
+        continue;
+      }
+      for (int mz = -1; mz <= 1; ++mz)
+        for (int my = -1; my <= 1; ++my)
+          for (int mx = -1; mx <= 1; ++mx) {
+            int64_t i = wrap(base[0] + mx, n[0]), j = wrap(base[1] + my, n[1]), kk = wrap(base[2] + mz, n[2]);
+            int64_t cell = cell_off[b] + (kk * n[1] + j) * n[0] + i;
+            s += phi[(mz + 1) * 9 + (my + 1) * 3 + (mx + 1)] * grid[d * (size_t)total_cells + cell];
+          }
+      v[d * (size_t)n_points + k] = s;
+    }
+  }
+  return bad;
+}
