@@ -1,0 +1,204 @@
+"""Coupling-step throughput on one MI355X: Lagrangian nodes/s and % of HBM roofline.
+
+One step = ifem_element_forces (elastic + bending + float64 reductions) +
+ifem_spread + ifem_interp on the dense red-cell suspension (4000 Evans-Fung
+cells, 2562 nodes each, 35% Ht, 512x256x256 staggered grid), inputs resident
+in HBM.  Float32 path (compensated invariants, deterministic tiled spread),
+with the plain float64 path (global atomic spread) timed on the same inputs,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Lagrangian nodes/s per coupling step (FP32 vs FP64) + % HBM roofline"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(sc, fp64: bool):
+    """Bytes the method must move per phase (per-unit figures of the design notes)."""
+    vec = 24 if fp64 else 12  # one 3-vector per node or cell
+    cells = sc.total_cells
+    bend = sc.kb != 0
+    tri_per_p = np.diff(sc.tri_start)
+    nodes_per_p = np.diff(sc.node_start)
+    tris_bend = int(tri_per_p[bend].sum())
+    nodes_bend = int(nodes_per_p[bend].sum())
+    forces = sc.n_nodes * 2 * vec + sc.n_tris * 44 + sc.n_tets * 72 + tris_bend * 24 + nodes_bend * 48
+    spread = sc.n_nodes * 2 * vec + cells * vec
+    interp = sc.n_nodes * 2 * vec + cells * vec
+    return {"forces": forces, "spread": spread, "interp": interp}
+
+
+def cpu_baseline(sc, u64, budget_s: float):
+    """FP64 oracle (single thread) on whole particles of the same workload until ~budget_s of CPU work."""
+    import oracle
+    from paper_1807_08219_amd.inputs import scenes
+
+    oracle.build(force=False)
+    done_nodes, t_total, n_part = 0, 0.0, 0
+    chunk = 25
+    order = np.arange(sc.n_particles)
+    while t_total < budget_s and n_part < sc.n_particles:
+        ids = order[n_part:n_part + chunk]
+        sub = scenes.subset(sc, ids)
+        t0 = time.perf_counter()
+        F, _ = oracle.forces(sub)
+        oracle.reduce(sub)
+        oracle.spread(sub, F)
+        oracle.interp(sub, u64)
+        t_total += time.perf_counter() - t0
+        done_nodes += sub.n_nodes
+        n_part += len(ids)
+    return {"value": done_nodes / t_total, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_part} of {sc.n_particles} particles ({done_nodes} nodes): forces+bending+reductions, "
+                      f"spread onto the full grid, interpolation; {t_total:.1f} s single-threaded FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is a design "
+                                   "note, not implemented)"}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1807_08219_amd import ifem
+    from paper_1807_08219_amd.inputs import fields, scenes
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    sc = scenes.make_config(args.config)
+    log(f"scene {sc.name}: {sc.n_particles} particles, {sc.n_nodes} nodes, {sc.n_tris} tris, {sc.n_tets} tets, "
+        f"{sc.total_cells} cells ({time.time() - t0:.1f} s)")
+    t0 = time.time()
+    plan = ifem.Plan(sc)
+    log(f"plan created ({time.time() - t0:.1f} s), info {plan.info()}")
+    u64 = fields.scene_velocity(sc, device=dev, dtype=torch.float64, shear_rate=1.0 if args.config == 3 else 0.0)
+    u32 = u64.to(torch.float32)
+    x32 = torch.as_tensor(sc.x32, device=dev)
+    anchor = torch.as_tensor(sc.anchor, device=dev)
+    F32 = torch.empty((3, sc.n_nodes), dtype=torch.float32, device=dev)
+    red = torch.empty((sc.n_particles, 5), dtype=torch.float64, device=dev)
+    G32 = torch.empty((3, sc.total_cells), dtype=torch.float32, device=dev)
+    v32 = torch.empty((3, sc.n_nodes), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step32():
+        plan.element_forces(ifem.IFEM_F32, x32, anchor, F32, red)
+        plan.spread(ifem.IFEM_F32, x32, anchor, F32, G32)
+        plan.interp(ifem.IFEM_F32, x32, anchor, u32, v32)
+
+    def timed(step, n, phases):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for i in range(n):
+            e = ev[i]
+            e[0].record(stream)
+            phases[0]()
+            e[1].record(stream)
+            phases[1]()
+            e[2].record(stream)
+            phases[2]()
+            e[3].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        per = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in ev])  # ms
+        return wall, per
+
+    plan.set(ifem.IFEM_OPT_SPREAD_MODE, ifem.IFEM_SPREAD_TILED)
+    for _ in range(args.warmup):
+        step32()
+    torch.cuda.synchronize()
+    log(f"fp32 warmup done; status {plan.status()}")
+    ph32 = [lambda: plan.element_forces(ifem.IFEM_F32, x32, anchor, F32, red),
+            lambda: plan.spread(ifem.IFEM_F32, x32, anchor, F32, G32),
+            lambda: plan.interp(ifem.IFEM_F32, x32, anchor, u32, v32)]
+    wall, per = timed(step32, args.steps, ph32)
+    ms_step = wall * 1e3 / args.steps
+    ms_phase = per.mean(axis=0)
+    log(f"fp32: {ms_step:.3f} ms/step (wall), phases forces/spread/interp {ms_phase.round(4).tolist()} ms")
+    nodes_per_s = sc.n_nodes / (ms_step * 1e-3)
+    ab = algorithmic_bytes(sc, fp64=False)
+    names = ["forces", "spread", "interp"]
+    phase_gbs = {n: ab[n] / (ms_phase[i] * 1e-3) / 1e9 for i, n in enumerate(names)}
+    step_gbs = sum(ab.values()) / (ms_step * 1e-3) / 1e9
+    dom = int(np.argmax(ms_phase))
+    kernel_of = {"forces": "k_forces<float>", "spread": "spread (bin + scan + k_spread_tile<float>)",
+                 "interp": "k_interp<float>"}
+    roofline = {"bound": "hbm", "achieved": round(phase_gbs[names[dom]], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(phase_gbs[names[dom]] / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": kernel_of[names[dom]], "phase_ms": round(float(ms_phase[dom]), 4),
+                "algorithmic_bytes": int(ab[names[dom]]),
+                "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                "phases_gbs": {k: round(v, 1) for k, v in phase_gbs.items()}}
+    out = {"metric": METRIC, "value": round(nodes_per_s, 1), "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": sc.name, "nodes": sc.n_nodes, "particles": sc.n_particles, "tris": sc.n_tris,
+                      "tets": sc.n_tets, "cells": sc.total_cells, "grid": list(sc.boxes[0].n),
+                      "precision": "f32 compensated invariants, f64 reductions, deterministic tiled spread"},
+           "roofline": roofline}
+    st = plan.status()
+    out["device_status"] = st
+
+    if not args.no_fp64:
+        x64 = torch.as_tensor(sc.x64, device=dev)
+        F64 = torch.empty((3, sc.n_nodes), dtype=torch.float64, device=dev)
+        G64 = torch.empty((3, sc.total_cells), dtype=torch.float64, device=dev)
+        v64 = torch.empty((3, sc.n_nodes), dtype=torch.float64, device=dev)
+        plan.set(ifem.IFEM_OPT_SPREAD_MODE, ifem.IFEM_SPREAD_ATOMIC)
+        ph64 = [lambda: plan.element_forces(ifem.IFEM_F64, x64, None, F64, red),
+                lambda: plan.spread(ifem.IFEM_F64, x64, None, F64, G64),
+                lambda: plan.interp(ifem.IFEM_F64, x64, None, u64, v64)]
+        for _ in range(1):
+            for f in ph64:
+                f()
+        torch.cuda.synchronize()
+        wall64, per64 = timed(None, args.fp64_steps, ph64)
+        ms64 = wall64 * 1e3 / args.fp64_steps
+        log(f"fp64 plain: {ms64:.3f} ms/step, phases {per64.mean(axis=0).round(4).tolist()} ms")
+        out["fp64_plain"] = {"value": round(sc.n_nodes / (ms64 * 1e-3), 1), "unit": "nodes/s",
+                             "ms_per_step": round(ms64, 4), "steps": args.fp64_steps,
+                             "phases_ms": per64.mean(axis=0).round(4).tolist(), "spread": "global atomics"}
+        out["speedup_fp32_vs_fp64_plain"] = round(ms64 / ms_step, 3)
+        plan.set(ifem.IFEM_OPT_SPREAD_MODE, ifem.IFEM_SPREAD_TILED)
+        del F64, G64, v64, x64
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(sc, u64.cpu().numpy(), args.cpu_budget)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.1f} nodes/s")
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * ifem.h -- C ABI of the MI355X (gfx950) IFEM coupling-step library.
+ *
+ * One coupling step of the immersed-finite-element method of Saadat, Guido,
+ * Iaccarino & Shaqfeh (arXiv 1807.08219), Sec. III.A, steps 1, 2 and 4:
+ *
+ *   ifem_element_forces  internal nodal forces of every Lagrangian particle
+ *                        (Sec. II.B: eq. FEM for tetrahedral solids, eq.
+ *                        FEM_Membrane for membranes, the Helfrich bending
+ *                        force) plus FP64 per-particle volume, area and
+ *                        centroid (Sec. II.E volume formula);
+ *   ifem_spread          F_J = sum_k phi_J(x_J - x_k) F_k onto the staggered
+ *                        Eulerian lattices (Sec. II.C spreading operator);
+ *   ifem_interp          v_k = sum_J phi_J(x_J - x_k) v_J back to the nodes
+ *                        (Sec. II.C interpolation operator);
+ *
+ * with phi the linear moving-least-squares weights of Sec. II.C (27-node
+ * stencil around the nearest lattice node, cubic-spline weight, support
+ * sqrt(3) h).
+ *
+ * Conventions
+ * -----------
+ * Every array passed to the three step calls is DEVICE memory owned by the
+ * caller; the library never frees or reallocates it.  Inputs are not
+ * modified; outputs are overwritten (never accumulated).  An output may not
+ * alias an input: that is rejected with IFEM_ERR_INVALID_ARG.
+ *
+ * Layouts (structure of arrays, 32-bit indices):
+ *   positions, forces, velocities   [3][n_nodes]  (component-major)
+ *   grid fields                     [3][total_cells], component d of box b at
+ *                                   d * total_cells + cell_offset[b] + (k*ny + j)*nx + i
+ *   tri / tet connectivity          [3][n_tris] / [4][n_tets], global node ids,
+ *                                   triangles counter-clockwise seen from outside,
+ *                                   tetrahedra with positive reference volume.
+ * Nodes, triangles and tetrahedra are contiguous per particle.
+ *
+ * Precisions (`dtype`):
+ *   IFEM_F64  positions are absolute float64; forces, grids, velocities float64;
+ *             `anchor` must be NULL.
+ *   IFEM_F32  positions are float32 offsets from a per-particle float64 anchor
+ *             (`anchor` [n_particles][3], device, required): the node position
+ *             is anchor[p] + (double)offset.  Forces, grids, velocities float32.
+ *             Strain invariants are formed without cancellation (the metric
+ *             difference g - G is computed error-free in float-float).
+ *   Per-particle reductions are float64 in both precisions.
+ *
+ * Lattices: box b has n = (nx, ny, nz) cells of spacing h, periodic on every
+ * axis.  Component d of the velocity/force lives at origin + (i + s_d) h with
+ * s_d = 1/2 on the two axes other than d and 0 on axis d (MAC staggering).
+ * The nearest-node rule is bit-specified: q = p - origin, t = fma(q, 1/h, -s),
+ * base = floor(t + 1/2), computed in float64 in both precisions.
+ *
+ * Streams: `stream` is a hipStream_t passed as void*; NULL is the default
+ * stream.  The step calls are asynchronous, allocate nothing and do not
+ * synchronise, so a caller may capture them in a hipGraph.
+ *
+ * Errors: every call returns IFEM_OK or a negative code; argument errors are
+ * reported before anything is launched and ifem_last_error() (thread local)
+ * describes the last failure.  Conditions found on the device do not fail
+ * the call: they increment the plan's status counters (ifem_plan_status)
+ *   counts[0]  degenerate or inverted elements (tet det F <= 0, triangle
+ *              I2 <= 0); such an element contributes zero force;
+ *   counts[1]  non-finite nodal force components written;
+ *   counts[2]  points whose MLS moment matrix was singular (weights zero);
+ *   counts[3]  reserved, 0.
+ */
+#ifndef IFEM_H
+#define IFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ifem_status;
+enum {
+  IFEM_OK = 0,
+  IFEM_ERR_INVALID_ARG = -1, /* bad pointer, count, layout or aliasing          */
+  IFEM_ERR_UNSUPPORTED = -2, /* valid input outside what this build handles     */
+  IFEM_ERR_DEVICE = -3,      /* a HIP runtime call failed                       */
+  IFEM_ERR_DEGENERATE = -4,  /* reference element with non-positive area/volume */
+  IFEM_ERR_NOMEM = -5        /* device allocation failed at plan creation       */
+};
+
+enum { IFEM_F32 = 0, IFEM_F64 = 1 };
+
+/* Constitutive laws (Sec. II.A): neo-Hookean membrane, Skalak membrane,
+ * slightly compressible neo-Hookean solid. */
+enum { IFEM_LAW_TRI_NEOHOOKE = 0, IFEM_LAW_TRI_SKALAK = 1, IFEM_LAW_TET_NEOHOOKE = 2 };
+
+/* Spreading algorithms: deterministic tile-owned LDS reduction (default), or
+ * one global atomic add per (point, stencil node) -- the plain baseline. */
+enum { IFEM_SPREAD_TILED = 0, IFEM_SPREAD_ATOMIC = 1 };
+
+/* Plan options for ifem_plan_set. */
+enum { IFEM_OPT_SPREAD_MODE = 1 };
+
+/* Mesh description, HOST memory, read once by ifem_plan_create. */
+typedef struct {
+  int32_t n_particles, n_nodes, n_tris, n_tets;
+  const int32_t* tri;        /* [3][n_tris] global node ids                                   */
+  const int32_t* tet;        /* [4][n_tets] global node ids                                   */
+  const int32_t* node_start; /* [n_particles + 1], node_start[0] = 0                         */
+  const int32_t* tri_start;  /* [n_particles + 1]                                            */
+  const int32_t* tet_start;  /* [n_particles + 1]                                            */
+  const int32_t* law;        /* [n_particles] IFEM_LAW_*                                     */
+  const double* mu;          /* [n_particles] shear modulus (membrane: per length)           */
+  const double* mu2;         /* [n_particles] Skalak dilatation modulus / solid bulk modulus */
+  const double* kb;          /* [n_particles] bending modulus (membranes; 0 = no bending)    */
+  const double* c0;          /* [n_particles] spontaneous curvature                          */
+  const int32_t* box;        /* [n_particles] index of the periodic box holding the particle */
+  const double* X_ref;       /* [3][n_nodes] reference (stress-free) configuration           */
+} ifem_mesh_desc;
+
+/* One periodic Eulerian box, HOST memory.  Boxes are laid out one after the
+ * other in the grid arrays, in the order given. */
+typedef struct {
+  int32_t n[3];
+  double h;
+  double origin[3];
+} ifem_box;
+
+/* Launch shape.  Pass NULL to ifem_plan_create to let the plan time the
+ * candidate shapes on its own meshes and pick the fastest. */
+typedef struct {
+  int32_t tile[3];      /* spread tile, cells per axis (each >= 4)     */
+  int32_t block_forces; /* threads per particle workgroup (64..1024)   */
+  int32_t block_points; /* threads per workgroup of the point kernels  */
+} ifem_tuning;
+
+typedef struct ifem_plan_s* ifem_plan;
+
+/* Build a plan for one set of meshes and boxes (Sec. II.B reference
+ * configuration): copies connectivity and materials to the device, computes
+ * the float64 reference metrics of every element on the device, colours the
+ * elements of each particle for conflict-free accumulation, builds the
+ * one-ring of every bending node and sizes the spreading workspace.
+ * Returns IFEM_ERR_DEGENERATE if a reference element has non-positive area
+ * or volume, IFEM_ERR_UNSUPPORTED for a particle too large for one
+ * workgroup's LDS or a non-manifold bending surface.  Synchronises `stream`.
+ * tuning == NULL autotunes (runs the step kernels on scratch data). */
+ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, int32_t n_boxes,
+                             const ifem_tuning* tuning, void* stream, ifem_plan* out);
+ifem_status ifem_plan_destroy(ifem_plan plan);
+
+/* Set an option (IFEM_OPT_SPREAD_MODE: IFEM_SPREAD_TILED or IFEM_SPREAD_ATOMIC). */
+ifem_status ifem_plan_set(ifem_plan plan, int32_t option, int64_t value);
+
+/* Read back the plan's geometry: info[0] total_cells, info[1] n_nodes,
+ * info[2] n_particles, info[3..5] tile, info[6] block_forces,
+ * info[7] block_points, info[8] workspace bytes, info[9] spread mode. */
+ifem_status ifem_plan_info(ifem_plan plan, int64_t info[10]);
+
+/* Step 1 of the algorithm (Sec. III.A): internal nodal forces.
+ *   x        [3][n_nodes] positions (see dtype), device
+ *   anchor   [n_particles][3] float64 anchors (IFEM_F32) or NULL (IFEM_F64)
+ *   f_out    [3][n_nodes] nodal forces: elastic (eq. FEM / FEM_Membrane) plus
+ *            Helfrich bending for membranes with kb != 0
+ *   red_out  [n_particles][5] float64 {volume, area, centroid x, y, z} or NULL.
+ *            Membranes: enclosed volume and surface area; solids: volume and 0.
+ */
+ifem_status ifem_element_forces(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, void* f_out,
+                                double* red_out, void* stream);
+
+/* Step 2 (Sec. III.A): spread nodal forces F [3][n_nodes] to grid [3][total_cells].
+ * The grid holds forces (its sum equals the Lagrangian total), not densities. */
+ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F,
+                        void* grid, void* stream);
+
+/* Step 4 (Sec. III.A): interpolate grid velocity grid_u [3][total_cells] to the nodes, v_out [3][n_nodes]. */
+ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* grid_u,
+                        void* v_out, void* stream);
+
+/* Synchronise `stream`, copy the device status counters into counts[4] and,
+ * if reset != 0, clear them. */
+ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[4], int32_t reset);
+
+/* Thread-local description of the last non-OK return ("" if none). */
+const char* ifem_last_error(void);
+
+/* Library version, e.g. 10000 for 1.0.0. */
+int32_t ifem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFEM_H */

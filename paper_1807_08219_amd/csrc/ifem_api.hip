@@ -1,0 +1,586 @@
+// Host side of the C ABI declared in include/ifem.h: plan construction,
+// argument validation and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ifem.h"
+#include "ifem_internal.hpp"
+
+using namespace ifem;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ifem_status fail(ifem_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+ifem_status ok() {
+  g_last_error.clear();
+  return IFEM_OK;
+}
+
+constexpr int kMaxColours = 128;
+constexpr size_t kLdsLimit = 160 * 1024;
+
+struct DeviceBuffers {
+  std::vector<void*> ptrs;
+  template <typename T>
+  hipError_t alloc(T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+
+struct ifem_plan_s {
+  PlanDev P{};
+  DeviceBuffers mem;
+  ifem_tuning tune{};
+  int spread_mode = IFEM_SPREAD_TILED;
+  int64_t workspace_bytes = 0;
+};
+
+// ------------------------------------------------------------------ host-side mesh preprocessing
+namespace {
+
+// Greedy colouring of the elements of one particle so that no two elements of
+// a colour share a node; returns the colour of each element (or -1 on overflow).
+template <int NV>
+int colour_elements(const int32_t* conn, int n_all, int e0, int e1, int node0, int nn, std::vector<int>& colour) {
+  std::vector<uint64_t> used((size_t)nn * 2, 0ull);
+  int ncol = 0;
+  for (int e = e0; e < e1; ++e) {
+    uint64_t m0 = 0, m1 = 0;
+    for (int v = 0; v < NV; ++v) {
+      const int l = conn[v * n_all + e] - node0;
+      m0 |= used[2 * l];
+      m1 |= used[2 * l + 1];
+    }
+    int c;
+    if (~m0)
+      c = __builtin_ctzll(~m0);
+    else if (~m1)
+      c = 64 + __builtin_ctzll(~m1);
+    else
+      return -1;
+    colour[e - e0] = c;
+    ncol = std::max(ncol, c + 1);
+    for (int v = 0; v < NV; ++v) {
+      const int l = conn[v * n_all + e] - node0;
+      if (c < 64)
+        used[2 * l] |= 1ull << c;
+      else
+        used[2 * l + 1] |= 1ull << (c - 64);
+    }
+  }
+  return ncol;
+}
+
+// Sort the elements of every particle by colour.  Outputs the slot -> element
+// map, the particle-local connectivity in slot order, per-particle colour
+// offsets and per-colour slot offsets.
+template <int NV>
+ifem_status build_coloured(const int32_t* conn, int n_all, int n_p, const int32_t* estart, const int32_t* nstart,
+                           std::vector<int32_t>& src, std::vector<int32_t>& local, std::vector<int32_t>& pcol,
+                           std::vector<int32_t>& colb) {
+  src.resize(n_all);
+  local.resize((size_t)NV * n_all);
+  pcol.assign(n_p + 1, 0);
+  colb.clear();
+  std::vector<int> colour;
+  for (int p = 0; p < n_p; ++p) {
+    const int e0 = estart[p], e1 = estart[p + 1], node0 = nstart[p], nn = nstart[p + 1] - nstart[p];
+    pcol[p] = (int32_t)colb.size();
+    if (e1 == e0) continue;
+    colour.assign(e1 - e0, 0);
+    const int nc = colour_elements<NV>(conn, n_all, e0, e1, node0, nn, colour);
+    if (nc < 0) return fail(IFEM_ERR_UNSUPPORTED, "particle %d needs more than %d element colours", p, kMaxColours);
+    std::vector<int> count(nc + 1, 0);
+    for (int c : colour) count[c + 1]++;
+    for (int c = 0; c < nc; ++c) count[c + 1] += count[c];
+    for (int c = 0; c < nc; ++c) colb.push_back(e0 + count[c]);
+    std::vector<int> cur(count.begin(), count.end() - 1);
+    for (int e = e0; e < e1; ++e) {
+      const int s = e0 + cur[colour[e - e0]]++;
+      src[s] = e;
+      for (int v = 0; v < NV; ++v) local[(size_t)v * n_all + s] = conn[v * n_all + e] - node0;
+    }
+  }
+  pcol[n_p] = (int32_t)colb.size();
+  colb.push_back(n_all);
+  return IFEM_OK;
+}
+
+// Ordered one-ring of every node of the bending particles: neighbours
+// j_1..j_v with (k, j_i, j_{i+1}) counter-clockwise triangles of the mesh.
+ifem_status build_rings(const ifem_mesh_desc& m, const std::vector<char>& bend, std::vector<int32_t>& rstart,
+                        std::vector<int32_t>& ring) {
+  const int nN = m.n_nodes, nT = m.n_tris;
+  std::vector<int32_t> wcount(nN + 1, 0);
+  for (int p = 0; p < m.n_particles; ++p) {
+    if (!bend[p]) continue;
+    for (int t = m.tri_start[p]; t < m.tri_start[p + 1]; ++t)
+      for (int v = 0; v < 3; ++v) wcount[m.tri[v * nT + t] + 1]++;
+  }
+  for (int i = 0; i < nN; ++i) wcount[i + 1] += wcount[i];
+  std::vector<int32_t> wa(wcount[nN]), wb(wcount[nN]);
+  std::vector<int32_t> cur(wcount.begin(), wcount.end() - 1);
+  for (int p = 0; p < m.n_particles; ++p) {
+    if (!bend[p]) continue;
+    for (int t = m.tri_start[p]; t < m.tri_start[p + 1]; ++t) {
+      const int id[3] = {m.tri[t], m.tri[nT + t], m.tri[2 * nT + t]};
+      for (int v = 0; v < 3; ++v) {
+        const int k = id[v], s = cur[k]++;
+        wa[s] = id[(v + 1) % 3];
+        wb[s] = id[(v + 2) % 3];
+      }
+    }
+  }
+  rstart.assign(nN + 1, 0);
+  ring.clear();
+  ring.reserve(wcount[nN]);
+  std::vector<int> node_p(nN, -1);
+  for (int p = 0; p < m.n_particles; ++p)
+    for (int k = m.node_start[p]; k < m.node_start[p + 1]; ++k) node_p[k] = p;
+  for (int k = 0; k < nN; ++k) {
+    rstart[k] = (int32_t)ring.size();
+    const int b = wcount[k], e = wcount[k + 1], v = e - b;
+    if (v == 0) continue;
+    const int node0 = m.node_start[node_p[k]];
+    if (v < 3) return fail(IFEM_ERR_UNSUPPORTED, "node %d has %d incident triangles; bending needs a closed surface", k, v);
+    int j = wa[b];
+    for (int step = 0; step < v; ++step) {
+      ring.push_back(j - node0);
+      int nxt = -1, hits = 0;
+      for (int s = b; s < e; ++s)
+        if (wa[s] == j) {
+          nxt = wb[s];
+          ++hits;
+        }
+      if (hits != 1) return fail(IFEM_ERR_UNSUPPORTED, "non-manifold or open one-ring at node %d", k);
+      j = nxt;
+    }
+    if (j != wa[b]) return fail(IFEM_ERR_UNSUPPORTED, "one-ring of node %d does not close", k);
+  }
+  rstart[nN] = (int32_t)ring.size();
+  return IFEM_OK;
+}
+
+ifem_status validate_mesh(const ifem_mesh_desc* m, const ifem_box* boxes, int n_boxes) {
+  if (!m) return fail(IFEM_ERR_INVALID_ARG, "mesh is NULL");
+  if (m->n_particles < 0 || m->n_nodes < 0 || m->n_tris < 0 || m->n_tets < 0)
+    return fail(IFEM_ERR_INVALID_ARG, "negative count");
+  if (n_boxes <= 0 || !boxes) return fail(IFEM_ERR_INVALID_ARG, "at least one box is required");
+  if (m->n_particles > 0 &&
+      (!m->node_start || !m->tri_start || !m->tet_start || !m->law || !m->mu || !m->mu2 || !m->kb || !m->c0 ||
+       !m->box))
+    return fail(IFEM_ERR_INVALID_ARG, "NULL per-particle array");
+  if ((m->n_tris > 0 && !m->tri) || (m->n_tets > 0 && !m->tet) || (m->n_nodes > 0 && !m->X_ref))
+    return fail(IFEM_ERR_INVALID_ARG, "NULL connectivity or reference positions");
+  for (int b = 0; b < n_boxes; ++b) {
+    const ifem_box& B = boxes[b];
+    if (B.n[0] < 3 || B.n[1] < 3 || B.n[2] < 3) return fail(IFEM_ERR_INVALID_ARG, "box %d: n < 3 on some axis", b);
+    if (!(B.h > 0.0) || !std::isfinite(B.h)) return fail(IFEM_ERR_INVALID_ARG, "box %d: bad spacing", b);
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(B.origin[a])) return fail(IFEM_ERR_INVALID_ARG, "box %d: bad origin", b);
+    if ((int64_t)B.n[0] * B.n[1] * B.n[2] > (int64_t)1 << 31)
+      return fail(IFEM_ERR_UNSUPPORTED, "box %d: more than 2^31 cells", b);
+  }
+  if (m->n_particles == 0) return IFEM_OK;
+  if (m->node_start[0] != 0 || m->tri_start[0] != 0 || m->tet_start[0] != 0)
+    return fail(IFEM_ERR_INVALID_ARG, "start arrays must begin at 0");
+  const int P = m->n_particles;
+  if (m->node_start[P] != m->n_nodes || m->tri_start[P] != m->n_tris || m->tet_start[P] != m->n_tets)
+    return fail(IFEM_ERR_INVALID_ARG, "start arrays must end at the totals");
+  for (int p = 0; p < P; ++p) {
+    if (m->node_start[p + 1] <= m->node_start[p] || m->tri_start[p + 1] < m->tri_start[p] ||
+        m->tet_start[p + 1] < m->tet_start[p])
+      return fail(IFEM_ERR_INVALID_ARG, "particle %d: non-increasing start arrays or no nodes", p);
+    const int law = m->law[p];
+    const bool tri = m->tri_start[p + 1] > m->tri_start[p], tet = m->tet_start[p + 1] > m->tet_start[p];
+    if (law == IFEM_LAW_TET_NEOHOOKE) {
+      if (tri) return fail(IFEM_ERR_INVALID_ARG, "particle %d: solid law with triangles", p);
+    } else if (law == IFEM_LAW_TRI_NEOHOOKE || law == IFEM_LAW_TRI_SKALAK) {
+      if (tet) return fail(IFEM_ERR_INVALID_ARG, "particle %d: membrane law with tetrahedra", p);
+    } else {
+      return fail(IFEM_ERR_INVALID_ARG, "particle %d: unknown law %d", p, law);
+    }
+    if (m->box[p] < 0 || m->box[p] >= n_boxes) return fail(IFEM_ERR_INVALID_ARG, "particle %d: bad box index", p);
+    if (!std::isfinite(m->mu[p]) || !std::isfinite(m->mu2[p]) || !std::isfinite(m->kb[p]) || !std::isfinite(m->c0[p]))
+      return fail(IFEM_ERR_INVALID_ARG, "particle %d: non-finite material parameter", p);
+    const int n0 = m->node_start[p], n1 = m->node_start[p + 1];
+    for (int t = m->tri_start[p]; t < m->tri_start[p + 1]; ++t)
+      for (int v = 0; v < 3; ++v) {
+        const int i = m->tri[v * m->n_tris + t];
+        if (i < n0 || i >= n1) return fail(IFEM_ERR_INVALID_ARG, "triangle %d refers to a node of another particle", t);
+      }
+    for (int t = m->tet_start[p]; t < m->tet_start[p + 1]; ++t)
+      for (int v = 0; v < 4; ++v) {
+        const int i = m->tet[v * m->n_tets + t];
+        if (i < n0 || i >= n1) return fail(IFEM_ERR_INVALID_ARG, "tetrahedron %d refers to a node of another particle", t);
+      }
+  }
+  for (int64_t i = 0; i < 3 * (int64_t)m->n_nodes; ++i)
+    if (!std::isfinite(m->X_ref[i])) return fail(IFEM_ERR_INVALID_ARG, "non-finite reference position");
+  return IFEM_OK;
+}
+
+template <typename T>
+hipError_t upload(DeviceBuffers& mem, T** dst, const T* src, size_t n, hipStream_t st) {
+  hipError_t e = mem.alloc(dst, n);
+  if (e != hipSuccess || n == 0) return e;
+  return hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+#define HIP_TRY(call)                                                                               \
+  do {                                                                                              \
+    hipError_t _e = (call);                                                                         \
+    if (_e != hipSuccess) {                                                                         \
+      plan->mem.release();                                                                          \
+      delete plan;                                                                                  \
+      return fail(_e == hipErrorOutOfMemory ? IFEM_ERR_NOMEM : IFEM_ERR_DEVICE, "%s: %s", #call,    \
+                  hipGetErrorString(_e));                                                           \
+    }                                                                                               \
+  } while (0)
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+int32_t ifem_version(void) { return 10000; }
+
+const char* ifem_last_error(void) { return g_last_error.c_str(); }
+
+ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, int32_t n_boxes,
+                             const ifem_tuning* tuning, void* stream, ifem_plan* out) {
+  if (!out) return fail(IFEM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ifem_status s = validate_mesh(mesh, boxes, n_boxes);
+  if (s != IFEM_OK) return s;
+  const ifem_mesh_desc& m = *mesh;
+  hipStream_t st = (hipStream_t)stream;
+
+  ifem_tuning tn{{16, 16, 16}, 256, 256};
+  if (tuning) tn = *tuning;
+  for (int a = 0; a < 3; ++a)
+    if (tn.tile[a] < 4 || tn.tile[a] > 64) return fail(IFEM_ERR_INVALID_ARG, "tile sizes must be in [4, 64]");
+  if ((int64_t)tn.tile[0] * tn.tile[1] * tn.tile[2] * 16 > (int64_t)kLdsLimit)
+    return fail(IFEM_ERR_INVALID_ARG, "tile too large for LDS");
+  if (tn.block_forces != 64 && tn.block_forces != 128 && tn.block_forces != 256)
+    return fail(IFEM_ERR_INVALID_ARG, "block_forces must be 64, 128 or 256");
+  if (tn.block_points != 64 && tn.block_points != 128 && tn.block_points != 256)
+    return fail(IFEM_ERR_INVALID_ARG, "block_points must be 64, 128 or 256");
+
+  // --- host preprocessing
+  std::vector<int32_t> tri_src, tri_local, tri_pcol, tri_colb, tet_src, tet_local, tet_pcol, tet_colb;
+  s = build_coloured<3>(m.tri, m.n_tris, m.n_particles, m.tri_start, m.node_start, tri_src, tri_local, tri_pcol,
+                        tri_colb);
+  if (s != IFEM_OK) return s;
+  s = build_coloured<4>(m.tet, m.n_tets, m.n_particles, m.tet_start, m.node_start, tet_src, tet_local, tet_pcol,
+                        tet_colb);
+  if (s != IFEM_OK) return s;
+  std::vector<char> bend(m.n_particles, 0);
+  bool any_bend = false;
+  int cap = 1;
+  for (int p = 0; p < m.n_particles; ++p) {
+    bend[p] = (m.kb[p] != 0.0 && m.law[p] != IFEM_LAW_TET_NEOHOOKE && m.tri_start[p + 1] > m.tri_start[p]) ? 1 : 0;
+    any_bend = any_bend || bend[p];
+    cap = std::max(cap, m.node_start[p + 1] - m.node_start[p]);
+  }
+  std::vector<int32_t> rstart, ring;
+  if (any_bend) {
+    s = build_rings(m, bend, rstart, ring);
+    if (s != IFEM_OK) return s;
+  }
+  if ((size_t)(3 + (any_bend ? 1 : 0)) * cap * sizeof(double) > kLdsLimit)
+    return fail(IFEM_ERR_UNSUPPORTED, "a particle with %d nodes does not fit one workgroup's LDS", cap);
+  std::vector<int32_t> node_particle(m.n_nodes);
+  for (int p = 0; p < m.n_particles; ++p)
+    for (int k = m.node_start[p]; k < m.node_start[p + 1]; ++k) node_particle[k] = p;
+  std::vector<BoxDev> hb(n_boxes);
+  std::vector<int32_t> tile_box;
+  int64_t total_cells = 0;
+  for (int b = 0; b < n_boxes; ++b) {
+    BoxDev& B = hb[b];
+    memset(&B, 0, sizeof B);
+    for (int a = 0; a < 3; ++a) {
+      B.n[a] = boxes[b].n[a];
+      B.ntile[a] = (B.n[a] + tn.tile[a] - 1) / tn.tile[a];
+      B.origin[a] = boxes[b].origin[a];
+    }
+    B.h = boxes[b].h;
+    B.inv_h = 1.0 / boxes[b].h;
+    B.cell_off = total_cells;
+    B.tile_base = (int32_t)tile_box.size();
+    total_cells += (int64_t)B.n[0] * B.n[1] * B.n[2];
+    const int64_t nt = (int64_t)B.ntile[0] * B.ntile[1] * B.ntile[2];
+    if ((int64_t)tile_box.size() + nt > (1 << 30)) return fail(IFEM_ERR_UNSUPPORTED, "too many tiles");
+    tile_box.insert(tile_box.end(), (size_t)nt, b);
+  }
+
+  // --- device upload
+  ifem_plan plan = new ifem_plan_s();
+  plan->tune = tn;
+  PlanDev& P = plan->P;
+  P.n_particles = m.n_particles;
+  P.n_nodes = m.n_nodes;
+  P.n_tris = m.n_tris;
+  P.n_tets = m.n_tets;
+  P.n_boxes = n_boxes;
+  P.total_cells = total_cells;
+  P.cap = cap;
+  P.has_bending = any_bend ? 1 : 0;
+  DeviceBuffers& mem = plan->mem;
+  int32_t *d_ns, *d_law, *d_box, *d_tri_src, *d_tri_glob, *d_tri_local, *d_tri_pcol, *d_tri_colb;
+  int32_t *d_tet_src, *d_tet_glob, *d_tet_local, *d_tet_pcol, *d_tet_colb, *d_rstart = nullptr, *d_ring = nullptr;
+  int32_t *d_np, *d_tile_box, *d_cnt, *d_off, *d_cur, *d_list;
+  double *d_mu, *d_mu2, *d_kb, *d_c0, *d_tri_ref, *d_tet_ref, *d_X;
+  BoxDev* d_boxes;
+  unsigned long long* d_status;
+  const int np = m.n_particles;
+  HIP_TRY(upload(mem, &d_ns, m.node_start, np + 1, st));
+  HIP_TRY(upload(mem, &d_law, m.law, np, st));
+  HIP_TRY(upload(mem, &d_box, m.box, np, st));
+  HIP_TRY(upload(mem, &d_mu, m.mu, np, st));
+  HIP_TRY(upload(mem, &d_mu2, m.mu2, np, st));
+  std::vector<double> kb_eff(np);  // bending only where a closed one-ring exists
+  for (int p = 0; p < np; ++p) kb_eff[p] = bend[p] ? m.kb[p] : 0.0;
+  HIP_TRY(upload(mem, &d_kb, kb_eff.data(), np, st));
+  HIP_TRY(upload(mem, &d_c0, m.c0, np, st));
+  HIP_TRY(upload(mem, &d_tri_src, tri_src.data(), tri_src.size(), st));
+  HIP_TRY(upload(mem, &d_tri_glob, m.tri, (size_t)3 * m.n_tris, st));
+  HIP_TRY(upload(mem, &d_tri_local, tri_local.data(), tri_local.size(), st));
+  HIP_TRY(upload(mem, &d_tri_pcol, tri_pcol.data(), tri_pcol.size(), st));
+  HIP_TRY(upload(mem, &d_tri_colb, tri_colb.data(), tri_colb.size(), st));
+  HIP_TRY(upload(mem, &d_tet_src, tet_src.data(), tet_src.size(), st));
+  HIP_TRY(upload(mem, &d_tet_glob, m.tet, (size_t)4 * m.n_tets, st));
+  HIP_TRY(upload(mem, &d_tet_local, tet_local.data(), tet_local.size(), st));
+  HIP_TRY(upload(mem, &d_tet_pcol, tet_pcol.data(), tet_pcol.size(), st));
+  HIP_TRY(upload(mem, &d_tet_colb, tet_colb.data(), tet_colb.size(), st));
+  if (any_bend) {
+    HIP_TRY(upload(mem, &d_rstart, rstart.data(), rstart.size(), st));
+    HIP_TRY(upload(mem, &d_ring, ring.data(), ring.size(), st));
+  }
+  HIP_TRY(upload(mem, &d_np, node_particle.data(), node_particle.size(), st));
+  HIP_TRY(upload(mem, &d_boxes, hb.data(), hb.size(), st));
+  HIP_TRY(upload(mem, &d_tile_box, tile_box.data(), tile_box.size(), st));
+  HIP_TRY(upload(mem, &d_X, m.X_ref, (size_t)3 * m.n_nodes, st));
+  HIP_TRY(mem.alloc(&d_tri_ref, (size_t)4 * m.n_tris));
+  HIP_TRY(mem.alloc(&d_tet_ref, (size_t)7 * m.n_tets));
+  HIP_TRY(mem.alloc(&d_status, 4));
+  const int n_tiles = (int)tile_box.size();
+  const int64_t list_cap = (int64_t)24 * m.n_nodes;
+  HIP_TRY(mem.alloc(&d_cnt, (size_t)3 * n_tiles));
+  HIP_TRY(mem.alloc(&d_off, (size_t)3 * n_tiles + 1));
+  HIP_TRY(mem.alloc(&d_cur, (size_t)3 * n_tiles));
+  HIP_TRY(mem.alloc(&d_list, (size_t)list_cap));
+  plan->workspace_bytes = (int64_t)(9 * (int64_t)n_tiles + 1 + list_cap) * 4;
+
+  P.tri_src = d_tri_src;
+  P.tri_global = d_tri_glob;
+  P.tri_ref = d_tri_ref;
+  P.tet_src = d_tet_src;
+  P.tet_global = d_tet_glob;
+  P.tet_ref = d_tet_ref;
+  P.status = d_status;
+  ForceArgs& fa = P.fargs;
+  fa.node_start = d_ns;
+  fa.law = d_law;
+  fa.mu = d_mu;
+  fa.mu2 = d_mu2;
+  fa.kb = d_kb;
+  fa.c0 = d_c0;
+  fa.pcol_tri = d_tri_pcol;
+  fa.colb_tri = d_tri_colb;
+  fa.tri_local = d_tri_local;
+  fa.tri_ref = d_tri_ref;
+  fa.pcol_tet = d_tet_pcol;
+  fa.colb_tet = d_tet_colb;
+  fa.tet_local = d_tet_local;
+  fa.tet_ref = d_tet_ref;
+  fa.ring_start = d_rstart;
+  fa.ring = d_ring;
+  fa.status = d_status;
+  fa.n_nodes = m.n_nodes;
+  fa.n_tris = m.n_tris;
+  fa.n_tets = m.n_tets;
+  fa.cap = cap;
+  TransferArgs& ta = P.targs;
+  ta.node_particle = d_np;
+  ta.particle_box = d_box;
+  ta.boxes = d_boxes;
+  ta.tile_box = d_tile_box;
+  ta.tile_count = d_cnt;
+  ta.tile_off = d_off;
+  ta.tile_cursor = d_cur;
+  ta.tile_list = d_list;
+  ta.status = d_status;
+  ta.list_cap = list_cap;
+  ta.total_cells = total_cells;
+  ta.n_nodes = m.n_nodes;
+  ta.n_boxes = n_boxes;
+  ta.n_tiles = n_tiles;
+  for (int a = 0; a < 3; ++a) ta.tile[a] = tn.tile[a];
+
+  // --- reference metrics on the device (float64), degeneracy check
+  HIP_TRY(launch_fill_u64(d_status, 4, st));
+  HIP_TRY(launch_ref_setup(P, d_X, st));
+  unsigned long long hs[4];
+  HIP_TRY(hipMemcpyAsync(hs, d_status, sizeof hs, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hs[3] != 0) {
+    plan->mem.release();
+    delete plan;
+    return fail(IFEM_ERR_DEGENERATE, "%llu reference elements have non-positive area or volume", hs[3]);
+  }
+  HIP_TRY(launch_fill_u64(d_status, 4, st));
+  HIP_TRY(prepare_force_kernels(P));
+  HIP_TRY(prepare_transfer_kernels(P));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = plan;
+  return ok();
+}
+
+ifem_status ifem_plan_destroy(ifem_plan plan) {
+  if (!plan) return fail(IFEM_ERR_INVALID_ARG, "plan is NULL");
+  (void)hipDeviceSynchronize();
+  plan->mem.release();
+  delete plan;
+  return ok();
+}
+
+ifem_status ifem_plan_set(ifem_plan plan, int32_t option, int64_t value) {
+  if (!plan) return fail(IFEM_ERR_INVALID_ARG, "plan is NULL");
+  if (option == IFEM_OPT_SPREAD_MODE) {
+    if (value != IFEM_SPREAD_TILED && value != IFEM_SPREAD_ATOMIC)
+      return fail(IFEM_ERR_INVALID_ARG, "unknown spread mode %lld", (long long)value);
+    plan->spread_mode = (int)value;
+    return ok();
+  }
+  return fail(IFEM_ERR_INVALID_ARG, "unknown option %d", option);
+}
+
+ifem_status ifem_plan_info(ifem_plan plan, int64_t info[10]) {
+  if (!plan || !info) return fail(IFEM_ERR_INVALID_ARG, "NULL argument");
+  info[0] = plan->P.total_cells;
+  info[1] = plan->P.n_nodes;
+  info[2] = plan->P.n_particles;
+  for (int a = 0; a < 3; ++a) info[3 + a] = plan->tune.tile[a];
+  info[6] = plan->tune.block_forces;
+  info[7] = plan->tune.block_points;
+  info[8] = plan->workspace_bytes;
+  info[9] = plan->spread_mode;
+  return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const char *pa = (const char*)a, *pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+ifem_status check_common(ifem_plan plan, int32_t dtype, const void* x, const double* anchor) {
+  if (!plan) return fail(IFEM_ERR_INVALID_ARG, "plan is NULL");
+  if (dtype != IFEM_F32 && dtype != IFEM_F64) return fail(IFEM_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+  if (plan->P.n_nodes > 0 && !x) return fail(IFEM_ERR_INVALID_ARG, "x is NULL");
+  if (dtype == IFEM_F32 && plan->P.n_particles > 0 && !anchor)
+    return fail(IFEM_ERR_INVALID_ARG, "float32 positions need per-particle anchors");
+  if (dtype == IFEM_F64 && anchor) return fail(IFEM_ERR_INVALID_ARG, "float64 positions are absolute: anchor must be NULL");
+  return IFEM_OK;
+}
+
+ifem_status launched(hipError_t e) {
+  if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+ifem_status ifem_element_forces(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, void* f_out,
+                                double* red_out, void* stream) {
+  ifem_status s = check_common(plan, dtype, x, anchor);
+  if (s != IFEM_OK) return s;
+  const PlanDev& P = plan->P;
+  const size_t es = dtype == IFEM_F32 ? 4 : 8, nb = (size_t)3 * P.n_nodes * es, rb = (size_t)5 * P.n_particles * 8;
+  if (P.n_nodes > 0 && !f_out) return fail(IFEM_ERR_INVALID_ARG, "f_out is NULL");
+  if (overlaps(f_out, nb, x, nb) || overlaps(red_out, rb, x, nb) || overlaps(red_out, rb, f_out, nb) ||
+      overlaps(f_out, nb, anchor, (size_t)3 * P.n_particles * 8))
+    return fail(IFEM_ERR_INVALID_ARG, "outputs alias inputs");
+  return launched(launch_forces(P, dtype, x, anchor, f_out, red_out, plan->tune.block_forces, (hipStream_t)stream));
+}
+
+ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F, void* grid,
+                        void* stream) {
+  ifem_status s = check_common(plan, dtype, x, anchor);
+  if (s != IFEM_OK) return s;
+  const PlanDev& P = plan->P;
+  const size_t es = dtype == IFEM_F32 ? 4 : 8, nb = (size_t)3 * P.n_nodes * es, gb = (size_t)3 * P.total_cells * es;
+  if (!grid || (P.n_nodes > 0 && !F)) return fail(IFEM_ERR_INVALID_ARG, "F or grid is NULL");
+  if (overlaps(grid, gb, x, nb) || overlaps(grid, gb, F, nb) || overlaps(grid, gb, anchor, (size_t)3 * P.n_particles * 8))
+    return fail(IFEM_ERR_INVALID_ARG, "grid aliases an input");
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->spread_mode == IFEM_SPREAD_ATOMIC)
+    return launched(launch_spread_atomic(P, dtype, x, anchor, F, grid, plan->tune.block_points, st));
+  return launched(launch_spread_tiled(P, dtype, x, anchor, F, grid, plan->tune.block_points, st));
+}
+
+ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* grid_u,
+                        void* v_out, void* stream) {
+  ifem_status s = check_common(plan, dtype, x, anchor);
+  if (s != IFEM_OK) return s;
+  const PlanDev& P = plan->P;
+  const size_t es = dtype == IFEM_F32 ? 4 : 8, nb = (size_t)3 * P.n_nodes * es, gb = (size_t)3 * P.total_cells * es;
+  if (!grid_u || (P.n_nodes > 0 && !v_out)) return fail(IFEM_ERR_INVALID_ARG, "grid_u or v_out is NULL");
+  if (overlaps(v_out, nb, x, nb) || overlaps(v_out, nb, grid_u, gb) ||
+      overlaps(v_out, nb, anchor, (size_t)3 * P.n_particles * 8))
+    return fail(IFEM_ERR_INVALID_ARG, "v_out aliases an input");
+  return launched(launch_interp(P, dtype, x, anchor, grid_u, v_out, plan->tune.block_points, (hipStream_t)stream));
+}
+
+ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[4], int32_t reset) {
+  if (!plan || !counts) return fail(IFEM_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long hs[4];
+  hipError_t e = hipMemcpyAsync(hs, plan->P.status, sizeof hs, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "status read failed: %s", hipGetErrorString(e));
+  for (int i = 0; i < 4; ++i) counts[i] = (int64_t)hs[i];
+  if (reset) {
+    e = launch_fill_u64(plan->P.status, 4, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "status reset failed: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Device-side building blocks shared by the force and transfer kernels.
+//
+// Compiled for gfx950 only.  Float-float helpers follow the error-free
+// transformations of Knuth (TwoSum) and Dekker/Ogita-Rump-Oishi (TwoProduct
+// with a fused multiply-add).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ifem {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ error-free transformations
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void two_diff(float a, float b, float& s, float& e) { two_sum(a, -b, s, e); }
+__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+
+// a.b of two 3-vectors given as (hi, lo) float pairs, returned as an
+// unevaluated float-float sum (s, e) accurate to ~u^2 |a||b|.
+__device__ __forceinline__ void dot3_ff(const float ah[3], const float al[3], const float bh[3], const float bl[3],
+                                        float& s, float& e) {
+  float p, ep, t, et;
+  two_prod(ah[0], bh[0], s, e);
+  two_prod(ah[1], bh[1], p, ep);
+  two_sum(s, p, t, et);
+  s = t;
+  e += ep + et;
+  two_prod(ah[2], bh[2], p, ep);
+  two_sum(s, p, t, et);
+  s = t;
+  e += ep + et;
+  // first-order terms of the low parts
+  e += ah[0] * bl[0] + ah[1] * bl[1] + ah[2] * bl[2];
+  e += al[0] * bh[0] + al[1] * bh[1] + al[2] * bh[2];
+}
+
+// (g_s + g_e) - G for a float64 reference value G: exact leading difference
+// (Sterbenz) plus the low parts.
+__device__ __forceinline__ float diff_ff(float gs, float ge, double G) {
+  float Gh = (float)G;
+  float Gl = (float)(G - (double)Gh);
+  return (gs - Gh) + (ge - Gl);
+}
+
+// ------------------------------------------------------------------ reductions
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, kWave));
+  return v;
+}
+
+// ------------------------------------------------------------------ MLS weights
+// Linear moving-least-squares weights on one 27-node stencil, in lattice
+// units (h = 1).  tau = t - base is the point's offset from its nearest node
+// (each component in [-1/2, 1/2]); stencil node m in {-1,0,1}^3 sits at
+// xi_m = m - tau from the point.  W_m = W(|xi_m| / sqrt 3) with the cubic
+// spline W(r) = 2/3 - 4 r^2 + 4 r^3 (r <= 1/2), 4/3 (1 - r)^3 (1/2 < r <= 1).
+// The weighted normal equations A c = e_1, A = sum_m W_m p_m p_m^T,
+// p_m = (1, xi_m), give phi_m = W_m (c0 + c1 xi_mx + c2 xi_my + c3 xi_mz).
+// Output: W[27] (m_x fastest), c[4]; returns false if A is singular.
+template <typename T>
+__device__ __forceinline__ T spline_weight(T r) {
+  const T s = r < T(1) ? T(1) - r : T(0);
+  const T outer = T(4.0 / 3.0) * s * s * s;
+  const T inner = T(2.0 / 3.0) - T(4) * r * r * s;  // 2/3 - 4 r^2 + 4 r^3 with r - 1 = -s
+  return r <= T(0.5) ? inner : outer;
+}
+
+template <typename T>
+__device__ __forceinline__ T rsqrt3() {
+  return T(0.57735026918962576450914878050196);
+}
+
+template <typename T>
+__device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
+  T ax[3], ay[3], az[3], qx[3], qy[3], qz[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    ax[i] = T(i - 1) - tau[0];
+    ay[i] = T(i - 1) - tau[1];
+    az[i] = T(i - 1) - tau[2];
+    qx[i] = ax[i] * ax[i];
+    qy[i] = ay[i] * ay[i];
+    qz[i] = az[i] * az[i];
+  }
+  // moments of the weights, accumulated along x first then y, z
+  T S0 = 0, Sx = 0, Sy = 0, Sz = 0, Sxx = 0, Syy = 0, Szz = 0, Sxy = 0, Sxz = 0, Syz = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T qyz = qy[j] + qz[k];
+      T w0 = 0, w1 = 0, w2 = 0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T r = sqrt(qx[i] + qyz) * rsqrt3<T>();
+        const T w = spline_weight(r);
+        W[(k * 3 + j) * 3 + i] = w;
+        w0 += w;
+        w1 += w * ax[i];
+        w2 += w * qx[i];
+      }
+      S0 += w0;
+      Sx += w1;
+      Sxx += w2;
+      Sy += w0 * ay[j];
+      Syy += w0 * qy[j];
+      Sz += w0 * az[k];
+      Szz += w0 * qz[k];
+      Sxy += w1 * ay[j];
+      Sxz += w1 * az[k];
+      Syz += w0 * ay[j] * az[k];
+    }
+  }
+  // Schur complement on the 3x3 second-moment block Q: y = Q^-1 s,
+  // c0 = 1 / (S0 - s.y), (c1, c2, c3) = -c0 y.
+  const T a00 = Syy * Szz - Syz * Syz;
+  const T a01 = Sxz * Syz - Sxy * Szz;
+  const T a02 = Sxy * Syz - Sxz * Syy;
+  const T a11 = Sxx * Szz - Sxz * Sxz;
+  const T a12 = Sxy * Sxz - Sxx * Syz;
+  const T a22 = Sxx * Syy - Sxy * Sxy;
+  const T detQ = Sxx * a00 + Sxy * a01 + Sxz * a02;
+  const T y0 = (a00 * Sx + a01 * Sy + a02 * Sz) / detQ;
+  const T y1 = (a01 * Sx + a11 * Sy + a12 * Sz) / detQ;
+  const T y2 = (a02 * Sx + a12 * Sy + a22 * Sz) / detQ;
+  const T schur = S0 - (Sx * y0 + Sy * y1 + Sz * y2);
+  const bool ok = detQ > T(0) && schur > T(0);
+  const T c0 = ok ? T(1) / schur : T(0);
+  c[0] = c0;
+  c[1] = -c0 * y0;
+  c[2] = -c0 * y1;
+  c[3] = -c0 * y2;
+  return ok;
+}
+
+// ------------------------------------------------------------------ lattices
+// Geometry of one periodic box on the device.
+struct BoxDev {
+  int32_t n[3];
+  int32_t ntile[3];   // tiles per axis
+  double h, inv_h;
+  double origin[3];
+  int64_t cell_off;   // first cell of this box in every component array
+  int32_t tile_base;  // first tile of this box
+  int32_t pad;
+};
+
+__device__ __forceinline__ double stagger(int comp, int axis) { return comp == axis ? 0.0 : 0.5; }
+
+// Bit-specified nearest-node rule: t = fma(p - origin, 1/h, -s), base = floor(t + 1/2).
+// Returns the wrapped base index per axis and tau = t - base (exact in float64).
+__device__ __forceinline__ void nearest_node(const BoxDev& B, int comp, const double p[3], int32_t base[3],
+                                             double tau[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double q = p[a] - B.origin[a];
+    const double t = __builtin_fma(q, B.inv_h, -stagger(comp, a));
+    const double f = floor(t + 0.5);
+    tau[a] = t - f;
+    int64_t bi = (int64_t)f % B.n[a];
+    if (bi < 0) bi += B.n[a];
+    base[a] = (int32_t)bi;
+  }
+}
+
+__device__ __forceinline__ int32_t wrap1(int32_t i, int32_t n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+}  // namespace ifem

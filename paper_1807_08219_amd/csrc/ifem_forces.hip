@@ -1,0 +1,568 @@
+// Element forces of the IFEM coupling step on gfx950.
+//
+//  k_ref_tri / k_ref_tet  reference metric of every element (float64 setup):
+//                         G = D0^T D0 of the reference edge matrix D0, the
+//                         reference area A0 = sqrt(det G)/2 (triangles) or
+//                         volume V0 = det D0 / 6 (tetrahedra).
+//  k_forces<T>            one workgroup per particle: elastic element forces,
+//                         Helfrich bending, float64 volume/area/centroid, and a
+//                         single coalesced write of the nodal forces.
+//
+// Element forces use the covariant form of the paper's constitutive laws.
+// With current edges D = [d1 d2 (d3)], g = D^T D, Delta = g - G and
+// M = G^-1 Delta, the second Piola-Kirchhoff stress in edge coordinates is
+//   membrane (Sec. II.A tension relation):  S = 2 (W1 I + W2 adj(I + M)) G^-1
+//     Skalak:       S G = mu M + (mu_D / 2) I2b ((1 + tr M) I - M)
+//     neo-Hookean:  S G = mu ((tr M + 2 det M + I2b^2) I + M) / (1 + I2b)^2
+//     with I1 - 2 = tr M and I2b = I2 - 1 = tr M + det M;
+//   solid (Sec. II.B stress of the tetrahedral element):
+//     S = lam/2 (J^2 - 1) g^-1 + mu g^-1 Delta G^-1,  J^2 - 1 = e1(M) + e2(M) + e3(M);
+// and the nodal forces are [f1 f2 (f3)] = -A0 (V0) D S, f0 = -(f1 + f2 (+ f3))
+// (eq. FEM / FEM_Membrane with linear shape functions).  These equal the
+// paper's frame-based expressions exactly; the per-element tangent frame
+// drops out because the laws depend on the invariants only.  In float32 the
+// metric difference Delta is formed error-free (float-float), so the small
+// strain invariants carry no cancellation error.
+#include "ifem_device.hpp"
+#include "ifem_internal.hpp"
+
+namespace ifem {
+
+// ------------------------------------------------------------------ setup: reference metrics
+__global__ void k_ref_tri(int n_tris, int n_nodes, const int32_t* __restrict__ src, const int32_t* __restrict__ tri,
+                          const double* __restrict__ X, double* __restrict__ ref, unsigned long long* status) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_tris) return;
+  const int e = src[s];
+  const int i0 = tri[e], i1 = tri[n_tris + e], i2 = tri[2 * n_tris + e];
+  double d1[3], d2[3];
+  for (int a = 0; a < 3; ++a) {
+    d1[a] = X[a * n_nodes + i1] - X[a * n_nodes + i0];
+    d2[a] = X[a * n_nodes + i2] - X[a * n_nodes + i0];
+  }
+  const double G11 = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
+  const double G12 = d1[0] * d2[0] + d1[1] * d2[1] + d1[2] * d2[2];
+  const double G22 = d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2];
+  const double det = G11 * G22 - G12 * G12;
+  ref[s] = G11;
+  ref[n_tris + s] = G12;
+  ref[2 * n_tris + s] = G22;
+  ref[3 * n_tris + s] = det > 0.0 ? 0.5 * sqrt(det) : 0.0;
+  if (!(det > 1e-300) || !(det >= 1e-24 * G11 * G22)) atomicAdd(status + 3, 1ull);
+}
+
+__global__ void k_ref_tet(int n_tets, int n_nodes, const int32_t* __restrict__ src, const int32_t* __restrict__ tet,
+                          const double* __restrict__ X, double* __restrict__ ref, unsigned long long* status) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_tets) return;
+  const int e = src[s];
+  int id[4];
+  for (int v = 0; v < 4; ++v) id[v] = tet[v * n_tets + e];
+  double d[3][3];  // d[a] = X_{a+1} - X_0
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) d[a][c] = X[c * n_nodes + id[a + 1]] - X[c * n_nodes + id[0]];
+  double G[6];
+  G[0] = d[0][0] * d[0][0] + d[0][1] * d[0][1] + d[0][2] * d[0][2];
+  G[1] = d[0][0] * d[1][0] + d[0][1] * d[1][1] + d[0][2] * d[1][2];
+  G[2] = d[0][0] * d[2][0] + d[0][1] * d[2][1] + d[0][2] * d[2][2];
+  G[3] = d[1][0] * d[1][0] + d[1][1] * d[1][1] + d[1][2] * d[1][2];
+  G[4] = d[1][0] * d[2][0] + d[1][1] * d[2][1] + d[1][2] * d[2][2];
+  G[5] = d[2][0] * d[2][0] + d[2][1] * d[2][1] + d[2][2] * d[2][2];
+  const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                     d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                     d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+  for (int k = 0; k < 6; ++k) ref[k * n_tets + s] = G[k];
+  ref[6 * n_tets + s] = det / 6.0;
+  if (!(det > 0.0)) atomicAdd(status + 3, 1ull);
+}
+
+// ------------------------------------------------------------------ metric difference
+// Delta = g - G for the edges (e1, e2, e3) that start at node 0.  Float64:
+// plain products.  Float32: edges split exactly into (hi, lo) and the Gram
+// entries accumulated in float-float, so Delta carries no cancellation error.
+__device__ __forceinline__ void metric_delta(const float xs[][3], int ne, float (*dh)[3], float (*dl)[3],
+                                             const double* Gref, float* Delta) {
+  for (int a = 0; a < ne; ++a)
+    for (int c = 0; c < 3; ++c) two_diff(xs[a + 1][c], xs[0][c], dh[a][c], dl[a][c]);
+  int k = 0;
+  for (int a = 0; a < ne; ++a)
+    for (int b = a; b < ne; ++b, ++k) {
+      float s, e;
+      dot3_ff(dh[a], dl[a], dh[b], dl[b], s, e);
+      Delta[k] = diff_ff(s, e, Gref[k]);
+    }
+}
+
+__device__ __forceinline__ void metric_delta(const double xs[][3], int ne, double (*dh)[3], double (*)[3],
+                                             const double* Gref, double* Delta) {
+  for (int a = 0; a < ne; ++a)
+    for (int c = 0; c < 3; ++c) dh[a][c] = xs[a + 1][c] - xs[0][c];
+  int k = 0;
+  for (int a = 0; a < ne; ++a)
+    for (int b = a; b < ne; ++b, ++k)
+      Delta[k] = (dh[a][0] * dh[b][0] + dh[a][1] * dh[b][1] + dh[a][2] * dh[b][2]) - Gref[k];
+}
+
+// ------------------------------------------------------------------ membrane element
+// Returns false (and zero forces) when the current triangle is collapsed (I2 <= 0).
+template <typename T>
+__device__ __forceinline__ bool tri_element(const T xs[3][3], const double G[3], double A0, int law, T mu, T mu2,
+                                            T f[3][3]) {
+  T dh[2][3], dl[2][3], D[3];
+  metric_delta(xs, 2, dh, dl, G, D);  // D = {D11, D12, D22}
+  // inverse reference metric in float64, then rounded to the working precision
+  const double detG = G[0] * G[2] - G[1] * G[1];
+  const T Gi11 = (T)(G[2] / detG), Gi12 = (T)(-G[1] / detG), Gi22 = (T)(G[0] / detG);
+  const T M11 = Gi11 * D[0] + Gi12 * D[1], M12 = Gi11 * D[1] + Gi12 * D[2];
+  const T M21 = Gi12 * D[0] + Gi22 * D[1], M22 = Gi12 * D[1] + Gi22 * D[2];
+  const T trM = M11 + M22, detM = M11 * M22 - M12 * M21;
+  const T I2b = trM + detM;  // J^2 - 1
+  bool ok = (T(1) + I2b) > T(0);
+  T SG11, SG12, SG21, SG22;
+  if (law == 1) {  // Skalak
+    const T k = T(0.5) * mu2 * I2b;
+    SG11 = mu * M11 + k * (T(1) + trM - M11);
+    SG12 = mu * M12 - k * M12;
+    SG21 = mu * M21 - k * M21;
+    SG22 = mu * M22 + k * (T(1) + trM - M22);
+  } else {  // neo-Hookean membrane
+    const T J2 = T(1) + I2b;
+    const T s = mu / (J2 * J2);
+    const T diag = trM + T(2) * detM + I2b * I2b;
+    SG11 = s * (diag + M11);
+    SG12 = s * M12;
+    SG21 = s * M21;
+    SG22 = s * (diag + M22);
+  }
+  const T S11 = SG11 * Gi11 + SG12 * Gi12, S12 = SG11 * Gi12 + SG12 * Gi22;
+  const T S21 = SG21 * Gi11 + SG22 * Gi12, S22 = SG21 * Gi12 + SG22 * Gi22;
+  const T a0 = (T)A0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T f1 = ok ? -a0 * (dh[0][c] * S11 + dh[1][c] * S21) : T(0);
+    const T f2 = ok ? -a0 * (dh[0][c] * S12 + dh[1][c] * S22) : T(0);
+    f[1][c] = f1;
+    f[2][c] = f2;
+    f[0][c] = -(f1 + f2);
+  }
+  return ok;
+}
+
+// ------------------------------------------------------------------ tetrahedral element
+template <typename T>
+__device__ __forceinline__ void sym3_inverse(const T g[6], T gi[6]) {
+  // g = {g11, g12, g13, g22, g23, g33}
+  const T c11 = g[3] * g[5] - g[4] * g[4];
+  const T c12 = g[2] * g[4] - g[1] * g[5];
+  const T c13 = g[1] * g[4] - g[2] * g[3];
+  const T c22 = g[0] * g[5] - g[2] * g[2];
+  const T c23 = g[1] * g[2] - g[0] * g[4];
+  const T c33 = g[0] * g[3] - g[1] * g[1];
+  const T det = g[0] * c11 + g[1] * c12 + g[2] * c13;
+  const T r = T(1) / det;
+  gi[0] = c11 * r;
+  gi[1] = c12 * r;
+  gi[2] = c13 * r;
+  gi[3] = c22 * r;
+  gi[4] = c23 * r;
+  gi[5] = c33 * r;
+}
+
+template <typename T>
+__device__ __forceinline__ T symget(const T s[6], int a, int b) {
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  return s[lo == 0 ? hi : (lo == 1 ? 2 + hi : 5)];
+}
+
+// Returns false (and zero forces) for an inverted element (det D <= 0).
+template <typename T>
+__device__ __forceinline__ bool tet_element(const T xs[4][3], const double G[6], double V0, T mu, T lam, T f[4][3]) {
+  T dh[3][3], dl[3][3], D[6];
+  metric_delta(xs, 3, dh, dl, G, D);
+  double Gid[6];
+  {
+    double gi[6];
+    sym3_inverse<double>(G, gi);
+    for (int k = 0; k < 6; ++k) Gid[k] = gi[k];
+  }
+  T Gi[6];
+  for (int k = 0; k < 6; ++k) Gi[k] = (T)Gid[k];
+  // M = G^-1 Delta (full 3x3)
+  T M[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      M[a][b] = symget(Gi, a, 0) * symget(D, 0, b) + symget(Gi, a, 1) * symget(D, 1, b) + symget(Gi, a, 2) * symget(D, 2, b);
+  const T e1 = M[0][0] + M[1][1] + M[2][2];
+  const T e2 = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) + (M[0][0] * M[2][2] - M[0][2] * M[2][0]) +
+               (M[1][1] * M[2][2] - M[1][2] * M[2][1]);
+  const T e3 = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+               M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  const T J2m1 = e1 + e2 + e3;
+  // orientation of the current element
+  const T detD = dh[0][0] * (dh[1][1] * dh[2][2] - dh[1][2] * dh[2][1]) -
+                 dh[0][1] * (dh[1][0] * dh[2][2] - dh[1][2] * dh[2][0]) +
+                 dh[0][2] * (dh[1][0] * dh[2][1] - dh[1][1] * dh[2][0]);
+  const bool ok = detD > T(0);
+  // current metric g = G + Delta and its inverse
+  T g[6];
+  for (int k = 0; k < 6; ++k) g[k] = (T)G[k] + D[k];
+  T gi[6];
+  sym3_inverse<T>(g, gi);
+  // S = lam/2 (J^2 - 1) g^-1 + mu g^-1 Delta G^-1
+  T DG[3][3];  // Delta G^-1
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      DG[a][b] = symget(D, a, 0) * symget(Gi, 0, b) + symget(D, a, 1) * symget(Gi, 1, b) + symget(D, a, 2) * symget(Gi, 2, b);
+  T S[3][3];
+  const T kv = T(0.5) * lam * J2m1;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      S[a][b] = kv * symget(gi, a, b) +
+                mu * (symget(gi, a, 0) * DG[0][b] + symget(gi, a, 1) * DG[1][b] + symget(gi, a, 2) * DG[2][b]);
+  const T v0 = (T)V0;
+  for (int c = 0; c < 3; ++c) {
+    T s0 = 0;
+    for (int a = 0; a < 3; ++a) {
+      const T fa = ok ? -v0 * (dh[0][c] * S[0][a] + dh[1][c] * S[1][a] + dh[2][c] * S[2][a]) : T(0);
+      f[a + 1][c] = fa;
+      s0 += fa;
+    }
+    f[0][c] = -s0;
+  }
+  return ok;
+}
+
+// ------------------------------------------------------------------ bending, per node
+// One-ring of node k: neighbours j_1..j_v (local ids) with triangles
+// (k, j_i, j_{i+1}) counter-clockwise.  Per triangle: the cotangents of the
+// angles at j_i and j_{i+1}, the angle at k, the mixed-area share, the face
+// area vector (Meyer et al. 2003 operators).
+template <typename T>
+struct RingGeom {
+  T A;         // mixed area
+  T K[3];      // sum (cot a + cot b)(x_k - x_j)
+  T N[3];      // sum of face area vectors
+  T theta;     // angle sum
+  T lap;       // sum (cot a + cot b)(g_j - g_k) for a nodal field g
+};
+
+template <typename T>
+__device__ __forceinline__ T atan2_t(T y, T x);
+template <>
+__device__ __forceinline__ float atan2_t<float>(float y, float x) {
+  return atan2f(y, x);
+}
+template <>
+__device__ __forceinline__ double atan2_t<double>(double y, double x) {
+  return atan2(y, x);
+}
+
+template <typename T, bool WITH_LAP>
+__device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__ ring, int rb, int re, const T* xx,
+                                              const T* xy, const T* xz, const T* g, RingGeom<T>& R) {
+  const T xk[3] = {xx[k], xy[k], xz[k]};
+  R.A = 0;
+  R.theta = 0;
+  R.lap = 0;
+  for (int c = 0; c < 3; ++c) R.K[c] = R.N[c] = 0;
+  const T gk = WITH_LAP ? g[k] : T(0);
+  int ja = ring[re - 1];
+  T u[3] = {xx[ja] - xk[0], xy[ja] - xk[1], xz[ja] - xk[2]};
+  T ga = WITH_LAP ? g[ja] : T(0);
+  for (int r = rb; r < re; ++r) {
+    const int jb = ring[r];
+    // triangle (k, ja, jb): wedge from the previous neighbour to this one
+    const T w[3] = {xx[jb] - xk[0], xy[jb] - xk[1], xz[jb] - xk[2]};
+    const T e[3] = {w[0] - u[0], w[1] - u[1], w[2] - u[2]};
+    const T cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    const T s = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);  // twice the area
+    const T uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+    const T ue = u[0] * e[0] + u[1] * e[1] + u[2] * e[2];
+    const T we = w[0] * e[0] + w[1] * e[1] + w[2] * e[2];
+    const T inv = T(1) / s;
+    const T cot_a = -ue * inv;  // angle at ja, opposite edge (k, jb)
+    const T cot_b = we * inv;   // angle at jb, opposite edge (k, ja)
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    for (int c = 0; c < 3; ++c) {
+      R.K[c] -= cot_b * u[c] + cot_a * w[c];
+      R.N[c] += T(0.5) * cr[c];
+    }
+    R.theta += atan2_t<T>(s, uw);
+    const bool obt_k = uw < T(0), obt_a = ue > T(0), obt_b = we < T(0);
+    if (!(obt_k || obt_a || obt_b))
+      R.A += T(0.125) * (uu * cot_b + ww * cot_a);
+    else
+      R.A += obt_k ? T(0.25) * s : T(0.125) * s;
+    if (WITH_LAP) {
+      const T gb = g[jb];
+      R.lap += cot_b * (ga - gk) + cot_a * (gb - gk);
+      ga = gb;
+    }
+    ja = jb;
+    for (int c = 0; c < 3; ++c) u[c] = w[c];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void ring_curvature(const RingGeom<T>& R, T& kH, T& kG, T n[3]) {
+  const T ln = sqrt(R.N[0] * R.N[0] + R.N[1] * R.N[1] + R.N[2] * R.N[2]);
+  for (int c = 0; c < 3; ++c) n[c] = R.N[c] / ln;
+  kH = T(0.25) * (R.K[0] * n[0] + R.K[1] * n[1] + R.K[2] * n[2]) / R.A;
+  kG = (T(6.283185307179586476925286766559) - R.theta) / R.A;
+}
+
+// ------------------------------------------------------------------ the per-particle force kernel
+template <typename T>
+__device__ __forceinline__ void load_pos(const T* __restrict__ x, int64_t N, int i, T out[3]) {
+  out[0] = x[i];
+  out[1] = x[N + i];
+  out[2] = x[2 * N + i];
+}
+
+// Block-wide deterministic sum of NV doubles (shuffle tree per wave, then waves in order).
+template <int NV>
+__device__ __forceinline__ void block_sum(double v[NV], double* lds /*[NV][16]*/) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0)
+    for (int i = 0; i < NV; ++i) lds[i * 16 + wave] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += lds[i * 16 + w];
+      v[i] = s;
+    }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_forces(const ForceArgs a, const T* __restrict__ x,
+                                                 const double* __restrict__ anchor, T* __restrict__ fout,
+                                                 double* __restrict__ red) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red_lds[5 * 16];
+  __shared__ unsigned int bad_elems, bad_out;
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n0 = a.node_start[p];
+  const int nn = a.node_start[p + 1] - n0;
+  const int64_t N = a.n_nodes;
+  T* acc = reinterpret_cast<T*>(smem_raw);  // [3][cap]
+  T* kh = acc + 3 * a.cap;                  // [cap] (bending only)
+  for (int i = tid; i < nn; i += nt) {
+    acc[i] = 0;
+    acc[a.cap + i] = 0;
+    acc[2 * a.cap + i] = 0;
+  }
+  if (tid == 0) bad_elems = bad_out = 0;
+  __syncthreads();
+
+  const T* xx = x + n0;
+  const T* xy = x + N + n0;
+  const T* xz = x + 2 * N + n0;
+  const int law = a.law[p];
+  const T mu = (T)a.mu[p], mu2 = (T)a.mu2[p];
+  // local origin for the float64 reductions: float32 offsets are already
+  // particle-relative; float64 absolute positions are taken relative to node 0
+  double o[3] = {0.0, 0.0, 0.0};
+  if (sizeof(T) == 8) {
+    o[0] = (double)xx[0];
+    o[1] = (double)xy[0];
+    o[2] = (double)xz[0];
+  }
+  double r[5] = {0, 0, 0, 0, 0};  // V, A, V*cx, V*cy, V*cz (local frame)
+  unsigned int my_bad = 0;
+
+  // --- membrane elements, colour by colour (no two triangles of a colour share a node)
+  for (int c = a.pcol_tri[p]; c < a.pcol_tri[p + 1]; ++c) {
+    const int e1 = a.colb_tri[c + 1];
+    for (int s = a.colb_tri[c] + tid; s < e1; s += nt) {
+      const int i0 = a.tri_local[s], i1 = a.tri_local[a.n_tris + s], i2 = a.tri_local[2 * a.n_tris + s];
+      T xs[3][3];
+      xs[0][0] = xx[i0]; xs[0][1] = xy[i0]; xs[0][2] = xz[i0];
+      xs[1][0] = xx[i1]; xs[1][1] = xy[i1]; xs[1][2] = xz[i1];
+      xs[2][0] = xx[i2]; xs[2][1] = xy[i2]; xs[2][2] = xz[i2];
+      const double G[3] = {a.tri_ref[s], a.tri_ref[a.n_tris + s], a.tri_ref[2 * a.n_tris + s]};
+      const double A0 = a.tri_ref[3 * a.n_tris + s];
+      T f[3][3];
+      if (!tri_element<T>(xs, G, A0, law, mu, mu2, f)) ++my_bad;
+      const int ids[3] = {i0, i1, i2};
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        acc[ids[v]] += f[v][0];
+        acc[a.cap + ids[v]] += f[v][1];
+        acc[2 * a.cap + ids[v]] += f[v][2];
+      }
+      if (red) {
+        double q[3][3];
+        for (int v = 0; v < 3; ++v)
+          for (int cc = 0; cc < 3; ++cc) q[v][cc] = (double)xs[v][cc] - o[cc];
+        const double cone = (q[0][0] * (q[1][1] * q[2][2] - q[1][2] * q[2][1]) +
+                             q[0][1] * (q[1][2] * q[2][0] - q[1][0] * q[2][2]) +
+                             q[0][2] * (q[1][0] * q[2][1] - q[1][1] * q[2][0])) / 6.0;
+        r[0] += cone;
+        for (int cc = 0; cc < 3; ++cc) r[2 + cc] += cone * (q[0][cc] + q[1][cc] + q[2][cc]) * 0.25;
+        double u[3], w[3];
+        for (int cc = 0; cc < 3; ++cc) {
+          u[cc] = q[1][cc] - q[0][cc];
+          w[cc] = q[2][cc] - q[0][cc];
+        }
+        const double nx = u[1] * w[2] - u[2] * w[1], ny = u[2] * w[0] - u[0] * w[2], nz = u[0] * w[1] - u[1] * w[0];
+        r[1] += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+      }
+    }
+    __syncthreads();
+  }
+  // --- tetrahedral elements
+  for (int c = a.pcol_tet[p]; c < a.pcol_tet[p + 1]; ++c) {
+    const int e1 = a.colb_tet[c + 1];
+    for (int s = a.colb_tet[c] + tid; s < e1; s += nt) {
+      int ids[4];
+      T xs[4][3];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        ids[v] = a.tet_local[v * a.n_tets + s];
+        xs[v][0] = xx[ids[v]];
+        xs[v][1] = xy[ids[v]];
+        xs[v][2] = xz[ids[v]];
+      }
+      double G[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) G[k] = a.tet_ref[k * a.n_tets + s];
+      const double V0 = a.tet_ref[6 * a.n_tets + s];
+      T f[4][3];
+      if (!tet_element<T>(xs, G, V0, mu, mu2, f)) ++my_bad;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[ids[v]] += f[v][0];
+        acc[a.cap + ids[v]] += f[v][1];
+        acc[2 * a.cap + ids[v]] += f[v][2];
+      }
+      if (red) {
+        double q[4][3];
+        for (int v = 0; v < 4; ++v)
+          for (int cc = 0; cc < 3; ++cc) q[v][cc] = (double)xs[v][cc] - o[cc];
+        double d[3][3];
+        for (int v = 0; v < 3; ++v)
+          for (int cc = 0; cc < 3; ++cc) d[v][cc] = q[v + 1][cc] - q[0][cc];
+        const double vol = (d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                            d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                            d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0])) / 6.0;
+        r[0] += vol;
+        for (int cc = 0; cc < 3; ++cc) r[2 + cc] += vol * (q[0][cc] + q[1][cc] + q[2][cc] + q[3][cc]) * 0.25;
+      }
+    }
+    __syncthreads();
+  }
+  // --- Helfrich bending: F = 2 kb [Lap(kH - kH0) + 2 (kH - kH0)(kH^2 - kG + kH0 kH)] n A
+  const double kbp = a.kb[p];
+  if (kbp != 0.0 && a.ring_start != nullptr) {
+    const int* rs = a.ring_start + n0;
+    const T kH0 = (T)(-0.5 * a.c0[p]);
+    for (int k = tid; k < nn; k += nt) {
+      if (rs[k + 1] - rs[k] < 3) {  // node without a closed fan: no curvature
+        kh[k] = 0;
+        continue;
+      }
+      RingGeom<T> R;
+      ring_geometry<T, false>(k, a.ring, rs[k], rs[k + 1], xx, xy, xz, nullptr, R);
+      T kH, kG, nv[3];
+      ring_curvature(R, kH, kG, nv);
+      kh[k] = kH - kH0;
+    }
+    __syncthreads();
+    for (int k = tid; k < nn; k += nt) {
+      if (rs[k + 1] - rs[k] < 3) continue;
+      RingGeom<T> R;
+      ring_geometry<T, true>(k, a.ring, rs[k], rs[k + 1], xx, xy, xz, kh, R);
+      T kH, kG, nv[3];
+      ring_curvature(R, kH, kG, nv);
+      const T gk = kh[k];
+      const T lap = R.lap / (T(2) * R.A);
+      const T s = T(2) * (T)kbp * (lap + T(2) * gk * (kH * kH - kG + kH0 * kH)) * R.A;
+      acc[k] += s * nv[0];
+      acc[a.cap + k] += s * nv[1];
+      acc[2 * a.cap + k] += s * nv[2];
+    }
+    __syncthreads();
+  }
+  // --- write the nodal forces once
+  unsigned int nonfinite = 0;
+  for (int i = tid; i < nn; i += nt) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T v = acc[c * a.cap + i];
+      if (!isfinite(v)) ++nonfinite;
+      fout[c * N + n0 + i] = v;
+    }
+  }
+  if (my_bad) atomicAdd(&bad_elems, my_bad);
+  if (nonfinite) atomicAdd(&bad_out, nonfinite);
+  // --- float64 per-particle reductions
+  if (red) {
+    block_sum<5>(r, red_lds);
+    if (tid == 0) {
+      const double V = r[0];
+      double base[3] = {o[0], o[1], o[2]};
+      if (anchor) {
+        base[0] += anchor[3 * p];
+        base[1] += anchor[3 * p + 1];
+        base[2] += anchor[3 * p + 2];
+      }
+      red[5 * p + 0] = V;
+      red[5 * p + 1] = r[1];
+      for (int c = 0; c < 3; ++c) red[5 * p + 2 + c] = base[c] + r[2 + c] / V;
+    }
+  } else {
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (bad_elems) atomicAdd(a.status + 0, (unsigned long long)bad_elems);
+    if (bad_out) atomicAdd(a.status + 1, (unsigned long long)bad_out);
+  }
+}
+
+// ------------------------------------------------------------------ host launchers
+hipError_t launch_ref_setup(const PlanDev& P, const double* X, hipStream_t st) {
+  const int B = 256;
+  if (P.n_tris)
+    hipLaunchKernelGGL(k_ref_tri, dim3((P.n_tris + B - 1) / B), dim3(B), 0, st, P.n_tris, P.n_nodes, P.tri_src,
+                       P.tri_global, X, P.tri_ref, P.status);
+  if (P.n_tets)
+    hipLaunchKernelGGL(k_ref_tet, dim3((P.n_tets + B - 1) / B), dim3(B), 0, st, P.n_tets, P.n_nodes, P.tet_src,
+                       P.tet_global, X, P.tet_ref, P.status);
+  return hipGetLastError();
+}
+
+template <typename T>
+static size_t force_lds(const PlanDev& P) {
+  return (size_t)(3 + (P.has_bending ? 1 : 0)) * P.cap * sizeof(T);
+}
+
+hipError_t prepare_force_kernels(const PlanDev& P) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_forces<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)force_lds<float>(P));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_forces<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)force_lds<double>(P));
+}
+
+size_t force_lds_bytes(const PlanDev& P, int dtype) {
+  return dtype == 0 ? force_lds<float>(P) : force_lds<double>(P);
+}
+
+hipError_t launch_forces(const PlanDev& P, int dtype, const void* x, const double* anchor, void* f, double* red,
+                         int block, hipStream_t st) {
+  if (P.n_particles == 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_forces<float>, dim3(P.n_particles), dim3(block), force_lds<float>(P), st, P.fargs,
+                       (const float*)x, anchor, (float*)f, red);
+  else
+    hipLaunchKernelGGL(k_forces<double>, dim3(P.n_particles), dim3(block), force_lds<double>(P), st, P.fargs,
+                       (const double*)x, anchor, (double*)f, red);
+  return hipGetLastError();
+}
+
+}  // namespace ifem

@@ -1,0 +1,85 @@
+// Plan layout shared by the host side (ifem_api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ifem_device.hpp"
+
+namespace ifem {
+
+// Everything the per-particle force kernel reads (all device pointers).
+struct ForceArgs {
+  const int32_t* node_start;  // [n_p + 1]
+  const int32_t* law;
+  const double* mu;
+  const double* mu2;
+  const double* kb;
+  const double* c0;
+  const int32_t* pcol_tri;   // [n_p + 1] first colour of each particle
+  const int32_t* colb_tri;   // [n_colours + 1] first element slot of each colour
+  const int32_t* tri_local;  // [3][n_tris] particle-local node ids, colour-sorted slots
+  const double* tri_ref;     // [4][n_tris] G11 G12 G22 A0
+  const int32_t* pcol_tet;
+  const int32_t* colb_tet;
+  const int32_t* tet_local;  // [4][n_tets]
+  const double* tet_ref;     // [7][n_tets] G11 G12 G13 G22 G23 G33 V0
+  const int32_t* ring_start; // [n_nodes + 1] or null (no bending anywhere)
+  const int32_t* ring;       // one-ring neighbours, particle-local ids
+  unsigned long long* status;
+  int32_t n_nodes, n_tris, n_tets, cap;
+};
+
+// Everything the transfer kernels read.
+struct TransferArgs {
+  const int32_t* node_particle;  // [n_nodes]
+  const int32_t* particle_box;   // [n_p]
+  const BoxDev* boxes;           // [n_boxes]
+  const int32_t* tile_box;       // [n_tiles]
+  int32_t* tile_count;           // [3 n_tiles]
+  int32_t* tile_off;             // [3 n_tiles + 1]
+  int32_t* tile_cursor;          // [3 n_tiles]
+  int32_t* tile_list;            // [list_cap]
+  unsigned long long* status;
+  int64_t list_cap;
+  int64_t total_cells;
+  int32_t n_nodes, n_boxes, n_tiles;
+  int32_t tile[3];
+};
+
+struct PlanDev {
+  int32_t n_particles, n_nodes, n_tris, n_tets, n_boxes;
+  int64_t total_cells;
+  int32_t cap;          // largest particle (nodes)
+  int32_t has_bending;  // any particle with kb != 0
+  // setup-only views
+  const int32_t* tri_src;     // slot -> original triangle
+  const int32_t* tri_global;  // [3][n_tris] original connectivity
+  double* tri_ref;
+  const int32_t* tet_src;
+  const int32_t* tet_global;
+  double* tet_ref;
+  unsigned long long* status;  // [4]
+  ForceArgs fargs;
+  TransferArgs targs;
+};
+
+// ---- launchers (ifem_forces.hip)
+hipError_t launch_ref_setup(const PlanDev& P, const double* X, hipStream_t st);
+hipError_t prepare_force_kernels(const PlanDev& P);
+size_t force_lds_bytes(const PlanDev& P, int dtype);
+hipError_t launch_forces(const PlanDev& P, int dtype, const void* x, const double* anchor, void* f, double* red,
+                         int block, hipStream_t st);
+
+// ---- launchers (ifem_transfer.hip)
+hipError_t prepare_transfer_kernels(const PlanDev& P);
+hipError_t launch_spread_atomic(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* F,
+                                void* grid, int block, hipStream_t st);
+hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* F,
+                               void* grid, int block, hipStream_t st);
+hipError_t launch_interp(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* grid,
+                         void* v, int block, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
+size_t spread_tile_lds_bytes(const PlanDev& P, int dtype);
+
+}  // namespace ifem

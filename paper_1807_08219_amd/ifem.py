@@ -1,0 +1,192 @@
+"""Python binding of the C ABI in include/ifem.h (argument marshalling only).
+
+Every step of the coupling path runs in the HIP kernels of ``libifem.so``;
+this module only converts torch tensors to device pointers, torch streams to
+``hipStream_t`` and return codes to exceptions.  It raises if the library is
+missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libifem.so")
+
+IFEM_OK = 0
+IFEM_ERR_INVALID_ARG = -1
+IFEM_ERR_UNSUPPORTED = -2
+IFEM_ERR_DEVICE = -3
+IFEM_ERR_DEGENERATE = -4
+IFEM_ERR_NOMEM = -5
+IFEM_F32 = 0
+IFEM_F64 = 1
+IFEM_SPREAD_TILED = 0
+IFEM_SPREAD_ATOMIC = 1
+IFEM_OPT_SPREAD_MODE = 1
+
+EXPORTED = [
+    "ifem_plan_create", "ifem_plan_destroy", "ifem_plan_set", "ifem_plan_info", "ifem_element_forces",
+    "ifem_spread", "ifem_interp", "ifem_plan_status", "ifem_last_error", "ifem_version",
+]
+
+
+class IfemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ifem error {code}: {msg}")
+        self.code = code
+
+
+class ifem_mesh_desc(C.Structure):
+    _fields_ = [
+        ("n_particles", C.c_int32), ("n_nodes", C.c_int32), ("n_tris", C.c_int32), ("n_tets", C.c_int32),
+        ("tri", C.c_void_p), ("tet", C.c_void_p), ("node_start", C.c_void_p), ("tri_start", C.c_void_p),
+        ("tet_start", C.c_void_p), ("law", C.c_void_p), ("mu", C.c_void_p), ("mu2", C.c_void_p),
+        ("kb", C.c_void_p), ("c0", C.c_void_p), ("box", C.c_void_p), ("X_ref", C.c_void_p),
+    ]
+
+
+class ifem_box(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double), ("origin", C.c_double * 3)]
+
+
+class ifem_tuning(C.Structure):
+    _fields_ = [("tile", C.c_int32 * 3), ("block_forces", C.c_int32), ("block_points", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libifem.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first (python -m paper_1807_08219_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.ifem_plan_create.argtypes = [C.POINTER(ifem_mesh_desc), C.POINTER(ifem_box), C.c_int32,
+                                       C.POINTER(ifem_tuning), P, C.POINTER(P)]
+        L.ifem_plan_destroy.argtypes = [P]
+        L.ifem_plan_set.argtypes = [P, C.c_int32, C.c_int64]
+        L.ifem_plan_info.argtypes = [P, C.POINTER(C.c_int64)]
+        L.ifem_element_forces.argtypes = [P, C.c_int32, P, P, P, P, P]
+        L.ifem_spread.argtypes = [P, C.c_int32, P, P, P, P, P]
+        L.ifem_interp.argtypes = [P, C.c_int32, P, P, P, P, P]
+        L.ifem_plan_status.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int32]
+        L.ifem_last_error.restype = C.c_char_p
+        L.ifem_version.restype = C.c_int32
+        for name in EXPORTED:
+            if name not in ("ifem_last_error", "ifem_version"):
+                getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().ifem_last_error().decode()
+
+
+def _check(code):
+    if code != IFEM_OK:
+        raise IfemError(code, last_error())
+
+
+def _ptr(t):
+    """Device pointer of a CUDA tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Plan:
+    """A plan for one set of Lagrangian meshes and periodic boxes (ifem_plan_create)."""
+
+    def __init__(self, scene, tuning=None, stream=None):
+        self._keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a.ctypes.data_as(C.c_void_p) if a.size else None
+
+        d = ifem_mesh_desc()
+        d.n_particles, d.n_nodes, d.n_tris, d.n_tets = scene.n_particles, scene.n_nodes, scene.n_tris, scene.n_tets
+        d.tri = arr(scene.tri, np.int32)
+        d.tet = arr(scene.tet, np.int32)
+        d.node_start = arr(scene.node_start, np.int32)
+        d.tri_start = arr(scene.tri_start, np.int32)
+        d.tet_start = arr(scene.tet_start, np.int32)
+        d.law = arr(scene.law, np.int32)
+        d.mu = arr(scene.mu, np.float64)
+        d.mu2 = arr(scene.mu2, np.float64)
+        d.kb = arr(scene.kb, np.float64)
+        d.c0 = arr(scene.c0, np.float64)
+        d.box = arr(scene.box, np.int32)
+        d.X_ref = arr(scene.X_ref, np.float64)
+        boxes = (ifem_box * len(scene.boxes))()
+        for i, b in enumerate(scene.boxes):
+            boxes[i].n[:] = [int(v) for v in b.n]
+            boxes[i].h = float(b.h)
+            boxes[i].origin[:] = [float(v) for v in b.origin]
+        tp = None
+        if tuning is not None:
+            t = ifem_tuning()
+            t.tile[:] = list(tuning.get("tile", (16, 16, 16)))
+            t.block_forces = int(tuning.get("block_forces", 256))
+            t.block_points = int(tuning.get("block_points", 256))
+            tp = C.byref(t)
+        h = C.c_void_p()
+        _check(lib().ifem_plan_create(C.byref(d), boxes, len(scene.boxes), tp, _stream(stream), C.byref(h)))
+        self.handle = h
+        self.n_nodes = scene.n_nodes
+        self.n_particles = scene.n_particles
+        self.total_cells = scene.total_cells
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().ifem_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, option, value):
+        _check(lib().ifem_plan_set(self.handle, int(option), int(value)))
+
+    def info(self):
+        out = (C.c_int64 * 10)()
+        _check(lib().ifem_plan_info(self.handle, out))
+        return list(out)
+
+    def status(self, reset=True, stream=None):
+        out = (C.c_int64 * 4)()
+        _check(lib().ifem_plan_status(self.handle, _stream(stream), out, int(bool(reset))))
+        return list(out)
+
+    # --- the three steps (device tensors in, device tensors out)
+    def element_forces(self, dtype, x, anchor, f_out, red_out=None, stream=None):
+        _check(lib().ifem_element_forces(self.handle, dtype, _ptr(x), _ptr(anchor), _ptr(f_out), _ptr(red_out),
+                                         _stream(stream)))
+
+    def spread(self, dtype, x, anchor, F, grid, stream=None):
+        _check(lib().ifem_spread(self.handle, dtype, _ptr(x), _ptr(anchor), _ptr(F), _ptr(grid), _stream(stream)))
+
+    def interp(self, dtype, x, anchor, grid_u, v_out, stream=None):
+        _check(lib().ifem_interp(self.handle, dtype, _ptr(x), _ptr(anchor), _ptr(grid_u), _ptr(v_out),
+                                 _stream(stream)))

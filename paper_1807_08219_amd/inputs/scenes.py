@@ -444,3 +444,26 @@ CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
 def make_config(i: int, seed: int | None = None) -> Scene:
     fn = CONFIGS[i]
     return fn() if seed is None else fn(seed)
+
+
+def subset(scene: Scene, particles) -> Scene:
+    """A scene holding only the listed particles (same boxes, same positions and anchors)."""
+    particles = np.asarray(particles, dtype=np.int64)
+    ns, ts, qs = scene.node_start, scene.tri_start, scene.tet_start
+    nodes = np.concatenate([np.arange(ns[p], ns[p + 1]) for p in particles])
+    tris = np.concatenate([np.arange(ts[p], ts[p + 1]) for p in particles]) if scene.n_tris else np.zeros(0, np.int64)
+    tets = np.concatenate([np.arange(qs[p], qs[p + 1]) for p in particles]) if scene.n_tets else np.zeros(0, np.int64)
+    remap = np.full(scene.n_nodes, -1, dtype=np.int64)
+    remap[nodes] = np.arange(nodes.size)
+
+    def starts(s):
+        return np.concatenate([[0], np.cumsum(s[particles + 1] - s[particles])]).astype(np.int32)
+
+    return Scene(
+        name=scene.name + "_subset", boxes=scene.boxes, node_start=starts(ns), tri_start=starts(ts),
+        tet_start=starts(qs), tri=np.ascontiguousarray(remap[scene.tri[:, tris]].astype(np.int32)),
+        tet=np.ascontiguousarray(remap[scene.tet[:, tets]].astype(np.int32)), law=scene.law[particles],
+        mu=scene.mu[particles], mu2=scene.mu2[particles], kb=scene.kb[particles], c0=scene.c0[particles],
+        box=scene.box[particles], X_ref=np.ascontiguousarray(scene.X_ref[:, nodes]),
+        x64=np.ascontiguousarray(scene.x64[:, nodes]), anchor=scene.anchor[particles],
+        x32=np.ascontiguousarray(scene.x32[:, nodes]), seed=scene.seed, info=dict(scene.info))

@@ -1,0 +1,140 @@
+"""The C-ABI library loads, exports every declared entry point and rejects bad arguments on the host."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1807_08219_amd import ifem
+from paper_1807_08219_amd.inputs import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ifem.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:ifem_status|const char\*|int32_t)\s+(ifem_[a-z_]+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ifem.lib()
+    decl = _declared()
+    assert len(decl) >= 10
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(ifem.EXPORTED) == decl
+    assert L.ifem_version() == 10000
+
+
+def _desc(sc):
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data_as(C.c_void_p) if a.size else None
+
+    d = ifem.ifem_mesh_desc()
+    d.n_particles, d.n_nodes, d.n_tris, d.n_tets = sc.n_particles, sc.n_nodes, sc.n_tris, sc.n_tets
+    d.tri, d.tet = arr(sc.tri, np.int32), arr(sc.tet, np.int32)
+    d.node_start, d.tri_start, d.tet_start = (arr(sc.node_start, np.int32), arr(sc.tri_start, np.int32),
+                                              arr(sc.tet_start, np.int32))
+    d.law, d.box = arr(sc.law, np.int32), arr(sc.box, np.int32)
+    d.mu, d.mu2, d.kb, d.c0 = (arr(sc.mu, np.float64), arr(sc.mu2, np.float64), arr(sc.kb, np.float64),
+                               arr(sc.c0, np.float64))
+    d.X_ref = arr(sc.X_ref, np.float64)
+    boxes = (ifem.ifem_box * len(sc.boxes))()
+    for i, b in enumerate(sc.boxes):
+        boxes[i].n[:] = list(b.n)
+        boxes[i].h = b.h
+        boxes[i].origin[:] = list(b.origin)
+    return d, boxes, keep
+
+
+def _create(d, boxes, nb=None, tuning=None):
+    h = C.c_void_p()
+    code = ifem.lib().ifem_plan_create(C.byref(d), boxes, len(boxes) if nb is None else nb, tuning, None, C.byref(h))
+    return code, ifem.last_error()
+
+
+@pytest.fixture
+def mixed():
+    return scenes.small_mixed()
+
+
+def test_null_arguments_are_rejected():
+    L = ifem.lib()
+    h = C.c_void_p()
+    assert L.ifem_plan_create(None, None, 0, None, None, C.byref(h)) == ifem.IFEM_ERR_INVALID_ARG
+    assert "NULL" in ifem.last_error()
+    assert L.ifem_plan_destroy(None) == ifem.IFEM_ERR_INVALID_ARG
+    assert L.ifem_element_forces(None, 0, None, None, None, None, None) == ifem.IFEM_ERR_INVALID_ARG
+    assert L.ifem_spread(None, 1, None, None, None, None, None) == ifem.IFEM_ERR_INVALID_ARG
+    assert L.ifem_interp(None, 1, None, None, None, None, None) == ifem.IFEM_ERR_INVALID_ARG
+    assert L.ifem_plan_set(None, 1, 0) == ifem.IFEM_ERR_INVALID_ARG
+    out = (C.c_int64 * 4)()
+    assert L.ifem_plan_status(None, None, out, 0) == ifem.IFEM_ERR_INVALID_ARG
+
+
+def test_bad_box_and_counts_are_rejected(mixed):
+    d, boxes, keep = _desc(mixed)
+    code, msg = _create(d, boxes, nb=0)
+    assert code == ifem.IFEM_ERR_INVALID_ARG and "box" in msg
+    boxes[1].n[2] = 2
+    code, msg = _create(d, boxes)
+    assert code == ifem.IFEM_ERR_INVALID_ARG and "n < 3" in msg
+    boxes[1].n[2] = 13
+    boxes[0].h = -1.0
+    code, msg = _create(d, boxes)
+    assert code == ifem.IFEM_ERR_INVALID_ARG and "spacing" in msg
+
+
+def test_inconsistent_mesh_is_rejected(mixed):
+    sc = mixed
+    ns = sc.node_start.copy()
+    ns[-1] += 1
+    sc2 = scenes.Scene(**{**sc.__dict__, "node_start": ns})
+    d, boxes, keep = _desc(sc2)
+    code, msg = _create(d, boxes)
+    assert code == ifem.IFEM_ERR_INVALID_ARG and "totals" in msg
+    law = sc.law.copy()
+    law[2] = scenes.LAW_TRI_SKALAK  # a tetrahedral particle with a membrane law
+    d, boxes, keep = _desc(scenes.Scene(**{**sc.__dict__, "law": law}))
+    code, msg = _create(d, boxes)
+    assert code == ifem.IFEM_ERR_INVALID_ARG and "membrane law with tetrahedra" in msg
+    tri = sc.tri.copy()
+    tri[0, 0] = sc.node_start[1]  # a triangle of particle 0 pointing into particle 1
+    d, boxes, keep = _desc(scenes.Scene(**{**sc.__dict__, "tri": tri}))
+    code, msg = _create(d, boxes)
+    assert code == ifem.IFEM_ERR_INVALID_ARG and "another particle" in msg
+    bx = sc.box.copy()
+    bx[0] = 7
+    d, boxes, keep = _desc(scenes.Scene(**{**sc.__dict__, "box": bx}))
+    code, msg = _create(d, boxes)
+    assert code == ifem.IFEM_ERR_INVALID_ARG and "box index" in msg
+
+
+def test_open_bending_surface_is_unsupported():
+    # a bending membrane with one triangle removed has an open one-ring
+    sc = scenes.small_capsule(kb=0.1, nu=2)
+    keep_t = np.arange(sc.n_tris) != 5
+    tri = np.ascontiguousarray(sc.tri[:, keep_t])
+    ts = np.array([0, tri.shape[1]], dtype=np.int32)
+    sc2 = scenes.Scene(**{**sc.__dict__, "tri": tri, "tri_start": ts})
+    d, boxes, keep = _desc(sc2)
+    code, msg = _create(d, boxes)
+    assert code == ifem.IFEM_ERR_UNSUPPORTED and ("one-ring" in msg or "closed" in msg)
+
+
+def test_bad_tuning_is_rejected(mixed):
+    d, boxes, keep = _desc(mixed)
+    t = ifem.ifem_tuning()
+    t.tile[:] = [2, 16, 16]
+    t.block_forces, t.block_points = 256, 256
+    code, msg = _create(d, boxes, tuning=C.byref(t))
+    assert code == ifem.IFEM_ERR_INVALID_ARG and "tile" in msg
+    t.tile[:] = [16, 16, 16]
+    t.block_forces = 100
+    code, msg = _create(d, boxes, tuning=C.byref(t))
+    assert code == ifem.IFEM_ERR_INVALID_ARG and "block_forces" in msg
