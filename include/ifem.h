@@ -62,7 +62,8 @@
  *              I2 <= 0); such an element contributes zero force;
  *   counts[1]  non-finite nodal force components written;
  *   counts[2]  points whose MLS moment matrix was singular (weights zero);
- *   counts[3]  reserved, 0.
+ *   counts[3]  spreads whose tile work lists overflowed the plan's
+ *              workspace (that grid is incomplete); 0 in normal use.
  */
 #ifndef IFEM_H
 #define IFEM_H

@@ -64,30 +64,29 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// ------------------------------------------------------------------ fast elementary functions
+// float32: the hardware square root and reciprocal (about 1 ulp); float64:
+// the correctly rounded operations.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+
 // ------------------------------------------------------------------ MLS weights
 // Linear moving-least-squares weights on one 27-node stencil, in lattice
 // units (h = 1).  tau = t - base is the point's offset from its nearest node
 // (each component in [-1/2, 1/2]); stencil node m in {-1,0,1}^3 sits at
 // xi_m = m - tau from the point.  W_m = W(|xi_m| / sqrt 3) with the cubic
-// spline W(r) = 2/3 - 4 r^2 + 4 r^3 (r <= 1/2), 4/3 (1 - r)^3 (1/2 < r <= 1).
+// spline W(r) = 2/3 - 4 r^2 + 4 r^3 (r <= 1/2), 4/3 (1 - r)^3 (1/2 < r <= 1),
+// evaluated from R^2 = |xi|^2 as 2/3 + R^2 (-4/3 + 4/(3 sqrt 3) R) when
+// R^2 <= 3/4 and 4/3 max(1 - R/sqrt 3, 0)^3 otherwise.
 // The weighted normal equations A c = e_1, A = sum_m W_m p_m p_m^T,
 // p_m = (1, xi_m), give phi_m = W_m (c0 + c1 xi_mx + c2 xi_my + c3 xi_mz).
 // Output: W[27] (m_x fastest), c[4]; returns false if A is singular.
 template <typename T>
-__device__ __forceinline__ T spline_weight(T r) {
-  const T s = r < T(1) ? T(1) - r : T(0);
-  const T outer = T(4.0 / 3.0) * s * s * s;
-  const T inner = T(2.0 / 3.0) - T(4) * r * r * s;  // 2/3 - 4 r^2 + 4 r^3 with r - 1 = -s
-  return r <= T(0.5) ? inner : outer;
-}
-
-template <typename T>
-__device__ __forceinline__ T rsqrt3() {
-  return T(0.57735026918962576450914878050196);
-}
-
-template <typename T>
 __device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
+  const T kInvSqrt3 = T(0.57735026918962576451);
+  const T kC3 = T(0.76980035891950101935);  // 4 / (3 sqrt 3)
   T ax[3], ay[3], az[3], qx[3], qy[3], qz[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -108,8 +107,12 @@ __device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
       T w0 = 0, w1 = 0, w2 = 0;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const T r = sqrt(qx[i] + qyz) * rsqrt3<T>();
-        const T w = spline_weight(r);
+        const T q = qx[i] + qyz;
+        const T R = fsqrt(q);
+        const T s = fmax(T(1) - R * kInvSqrt3, T(0));
+        const T outer = (s * s) * (s * T(4.0 / 3.0));
+        const T inner = q * (R * kC3 - T(4.0 / 3.0)) + T(2.0 / 3.0);
+        const T w = q <= T(0.75) ? inner : outer;
         W[(k * 3 + j) * 3 + i] = w;
         w0 += w;
         w1 += w * ax[i];
@@ -136,17 +139,26 @@ __device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
   const T a12 = Sxy * Sxz - Sxx * Syz;
   const T a22 = Sxx * Syy - Sxy * Sxy;
   const T detQ = Sxx * a00 + Sxy * a01 + Sxz * a02;
-  const T y0 = (a00 * Sx + a01 * Sy + a02 * Sz) / detQ;
-  const T y1 = (a01 * Sx + a11 * Sy + a12 * Sz) / detQ;
-  const T y2 = (a02 * Sx + a12 * Sy + a22 * Sz) / detQ;
+  const T inv = frcp(detQ);
+  const T y0 = (a00 * Sx + a01 * Sy + a02 * Sz) * inv;
+  const T y1 = (a01 * Sx + a11 * Sy + a12 * Sz) * inv;
+  const T y2 = (a02 * Sx + a12 * Sy + a22 * Sz) * inv;
   const T schur = S0 - (Sx * y0 + Sy * y1 + Sz * y2);
   const bool ok = detQ > T(0) && schur > T(0);
-  const T c0 = ok ? T(1) / schur : T(0);
+  const T c0 = ok ? frcp(schur) : T(0);
   c[0] = c0;
   c[1] = -c0 * y0;
   c[2] = -c0 * y1;
   c[3] = -c0 * y2;
   return ok;
+}
+
+// Round a float64 value (|v| < 2^51) to the nearest integer (ties to even)
+// and return it as int64, with one add and one integer subtract: adding
+// 1.5 * 2^52 places the integer in the low mantissa bits.
+__device__ __forceinline__ long long round_to_i64(double v) {
+  const double magic = 6755399441055744.0;  // 1.5 * 2^52
+  return __double_as_longlong(v + magic) - __double_as_longlong(magic);
 }
 
 // ------------------------------------------------------------------ lattices
@@ -156,6 +168,7 @@ struct BoxDev {
   int32_t ntile[3];   // tiles per axis
   double h, inv_h;
   double origin[3];
+  double inv_n[3];    // 1 / n per axis (wrapping)
   int64_t cell_off;   // first cell of this box in every component array
   int32_t tile_base;  // first tile of this box
   int32_t pad;
@@ -163,19 +176,33 @@ struct BoxDev {
 
 __device__ __forceinline__ double stagger(int comp, int axis) { return comp == axis ? 0.0 : 0.5; }
 
+// Lattice coordinate t = fma(p - origin, 1/h, -s) and its nearest node
+// f = floor(t + 1/2) (float64, bit-specified; the same rule everywhere).
+__device__ __forceinline__ double lattice_coord(const BoxDev& B, int comp, int a, double p, double& f) {
+  const double t = __builtin_fma(p - B.origin[a], B.inv_h, -stagger(comp, a));
+  f = floor(t + 0.5);
+  return t;
+}
+
+// Wrap an integral float64 index into [0, n) (exact for |f| < 2^52).
+__device__ __forceinline__ int32_t wrap_index(const BoxDev& B, int a, double f) {
+  const double qn = floor(f * B.inv_n[a]);
+  int32_t w = (int32_t)(f - qn * (double)B.n[a]);
+  if (w >= B.n[a]) w -= B.n[a];
+  if (w < 0) w += B.n[a];
+  return w;
+}
+
 // Bit-specified nearest-node rule: t = fma(p - origin, 1/h, -s), base = floor(t + 1/2).
 // Returns the wrapped base index per axis and tau = t - base (exact in float64).
 __device__ __forceinline__ void nearest_node(const BoxDev& B, int comp, const double p[3], int32_t base[3],
                                              double tau[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double q = p[a] - B.origin[a];
-    const double t = __builtin_fma(q, B.inv_h, -stagger(comp, a));
-    const double f = floor(t + 0.5);
+    double f;
+    const double t = lattice_coord(B, comp, a, p[a], f);
     tau[a] = t - f;
-    int64_t bi = (int64_t)f % B.n[a];
-    if (bi < 0) bi += B.n[a];
-    base[a] = (int32_t)bi;
+    base[a] = wrap_index(B, a, f);
   }
 }
 

@@ -111,8 +111,8 @@ __device__ __forceinline__ bool tri_element(const T xs[3][3], const double G[3],
   T dh[2][3], dl[2][3], D[3];
   metric_delta(xs, 2, dh, dl, G, D);  // D = {D11, D12, D22}
   // inverse reference metric in float64, then rounded to the working precision
-  const double detG = G[0] * G[2] - G[1] * G[1];
-  const T Gi11 = (T)(G[2] / detG), Gi12 = (T)(-G[1] / detG), Gi22 = (T)(G[0] / detG);
+  const double inv_detG = 1.0 / (G[0] * G[2] - G[1] * G[1]);
+  const T Gi11 = (T)(G[2] * inv_detG), Gi12 = (T)(-G[1] * inv_detG), Gi22 = (T)(G[0] * inv_detG);
   const T M11 = Gi11 * D[0] + Gi12 * D[1], M12 = Gi11 * D[1] + Gi12 * D[2];
   const T M21 = Gi12 * D[0] + Gi22 * D[1], M22 = Gi12 * D[1] + Gi22 * D[2];
   const T trM = M11 + M22, detM = M11 * M22 - M12 * M21;
@@ -275,11 +275,11 @@ __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__
     const T w[3] = {xx[jb] - xk[0], xy[jb] - xk[1], xz[jb] - xk[2]};
     const T e[3] = {w[0] - u[0], w[1] - u[1], w[2] - u[2]};
     const T cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
-    const T s = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);  // twice the area
+    const T s = fsqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);  // twice the area
     const T uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
     const T ue = u[0] * e[0] + u[1] * e[1] + u[2] * e[2];
     const T we = w[0] * e[0] + w[1] * e[1] + w[2] * e[2];
-    const T inv = T(1) / s;
+    const T inv = frcp(s);
     const T cot_a = -ue * inv;  // angle at ja, opposite edge (k, jb)
     const T cot_b = we * inv;   // angle at jb, opposite edge (k, ja)
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -306,10 +306,11 @@ __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__
 
 template <typename T>
 __device__ __forceinline__ void ring_curvature(const RingGeom<T>& R, T& kH, T& kG, T n[3]) {
-  const T ln = sqrt(R.N[0] * R.N[0] + R.N[1] * R.N[1] + R.N[2] * R.N[2]);
-  for (int c = 0; c < 3; ++c) n[c] = R.N[c] / ln;
-  kH = T(0.25) * (R.K[0] * n[0] + R.K[1] * n[1] + R.K[2] * n[2]) / R.A;
-  kG = (T(6.283185307179586476925286766559) - R.theta) / R.A;
+  const T iln = frcp(fsqrt(R.N[0] * R.N[0] + R.N[1] * R.N[1] + R.N[2] * R.N[2]));
+  for (int c = 0; c < 3; ++c) n[c] = R.N[c] * iln;
+  const T iA = frcp(R.A);
+  kH = T(0.25) * (R.K[0] * n[0] + R.K[1] * n[1] + R.K[2] * n[2]) * iA;
+  kG = (T(6.283185307179586476925286766559) - R.theta) * iA;
 }
 
 // ------------------------------------------------------------------ the per-particle force kernel

@@ -32,18 +32,22 @@ struct ForceArgs {
 
 // Everything the transfer kernels read.
 struct TransferArgs {
-  const int32_t* node_particle;  // [n_nodes]
-  const int32_t* particle_box;   // [n_p]
-  const BoxDev* boxes;           // [n_boxes]
-  const int32_t* tile_box;       // [n_tiles]
-  int32_t* tile_count;           // [3 n_tiles]
-  int32_t* tile_off;             // [3 n_tiles + 1]
-  int32_t* tile_cursor;          // [3 n_tiles]
-  int32_t* tile_list;            // [list_cap]
+  const int32_t* node_particle;   // [n_nodes]
+  const int32_t* particle_box;    // [n_p]
+  const BoxDev* boxes;            // [n_boxes]
+  const int32_t* tile_box;        // [n_tiles]
+  const int32_t* chunk_node0;     // [n_chunks] first node of each 64-node chunk
+  const int32_t* chunk_len;       // [n_chunks] nodes in the chunk (1..64)
+  const int32_t* chunk_particle;  // [n_chunks]
+  double* chunk_maxF;             // [n_chunks][3] largest |F| per component (written by the fill pass)
+  int32_t* tile_count;            // [3 n_tiles] chunks per (component, tile)
+  int32_t* tile_off;              // [3 n_tiles + 1]
+  int32_t* tile_cursor;           // [3 n_tiles]
+  int32_t* pair_list;             // [pair_cap] chunk ids, grouped by (component, tile)
   unsigned long long* status;
-  int64_t list_cap;
+  int64_t pair_cap;
   int64_t total_cells;
-  int32_t n_nodes, n_boxes, n_tiles;
+  int32_t n_nodes, n_boxes, n_tiles, n_chunks;
   int32_t tile[3];
 };
 

@@ -8,15 +8,17 @@
 //  k_spread_atomic<T>   the plain baseline: one global atomic add per
 //                       (node, component, stencil node).
 //  tiled spread         deterministic and free of global float atomics:
-//    k_bin_count        counts, per (component, lattice tile), the nodes whose
-//                       stencil touches the tile;
+//    k_chunk_bin        per (64-node chunk, component): the lattice tiles its
+//                       stencils reach (count pass, then fill pass);
 //    k_scan             exclusive scan of the counts (single workgroup);
-//    k_bin_fill         writes the node lists;
-//    k_spread_tile<T>   one workgroup per (component, tile): accumulates the
-//                       contributions of its node list in LDS as 64-bit
-//                       fixed-point integers (exact, order-independent sums;
-//                       float64 uses a two-word split), then writes every
-//                       lattice value of the tile exactly once.
+//    k_spread_tile<T>   one workgroup per (component, tile): filters the
+//                       nodes of its chunks into an LDS queue, accumulates
+//                       their contributions in LDS as 64-bit fixed-point
+//                       integers (exact, order-independent sums; float64 uses
+//                       a two-word split), then writes every lattice value of
+//                       the tile exactly once.
+#include <climits>
+
 #include "ifem_device.hpp"
 #include "ifem_internal.hpp"
 
@@ -145,52 +147,99 @@ __global__ void __launch_bounds__(256) k_spread_atomic(const TransferArgs a, con
   if (bad) atomicAdd(a.status + 2, (unsigned long long)bad);
 }
 
-// ------------------------------------------------------------------ tiled spread: binning
-// Distinct tiles (per axis) holding the cells base-1, base, base+1 (wrapped).
-__device__ __forceinline__ int axis_tiles(int32_t base, int32_t n, int32_t T, int32_t out[3]) {
-  const int32_t t0 = wrap1(base - 1, n) / T, t1 = base / T, t2 = wrap1(base + 1, n) / T;
-  int c = 0;
-  out[c++] = t0;
-  if (t1 != t0) out[c++] = t1;
-  if (t2 != t0 && t2 != t1) out[c++] = t2;
-  return c;
+// ------------------------------------------------------------------ tiled spread: chunk binning
+// Nodes are grouped in chunks of at most 64 consecutive nodes of one particle
+// (one wavefront).  For each (chunk, component) the lanes reduce the range of
+// nearest-node indices; the tiles overlapping that range grown by the
+// one-cell stencil reach receive the chunk id in their list.  Counting and
+// filling take one global atomic per (chunk, component, tile), not per node.
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+__device__ __forceinline__ double wave_max_all(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Tiles (first, count) along one axis covering the wrapped cells lo-1 .. hi+1.
+__device__ __forceinline__ void axis_tile_range(const BoxDev& B, int a, int T, int lo, int hi, int& t0, int& cnt) {
+  const int n = B.n[a], nt = B.ntile[a];
+  const int lo_c = lo - 1, hi_c = hi + 1;
+  if (hi_c - lo_c + 1 > n - T) {  // the cell range leaves no full tile outside it: every tile
+    t0 = 0;
+    cnt = nt;
+    return;
+  }
+  int w0 = lo_c % n, w1 = hi_c % n;
+  if (w0 < 0) w0 += n;
+  if (w1 < 0) w1 += n;
+  t0 = w0 / T;
+  cnt = w1 / T - t0;
+  if (cnt < 0) cnt += nt;
+  cnt += 1;
 }
 
 template <typename T, bool FILL>
-__global__ void __launch_bounds__(256) k_bin(const TransferArgs a, const T* __restrict__ x,
-                                             const double* __restrict__ anchor) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.n_nodes) return;
-  const int p = a.node_particle[k];
+__global__ void __launch_bounds__(256) k_chunk_bin(const TransferArgs a, const T* __restrict__ x,
+                                                   const double* __restrict__ anchor, const T* __restrict__ F) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (c >= a.n_chunks) return;  // whole wavefronts leave together
+  const int p = a.chunk_particle[c], k0 = a.chunk_node0[c], len = a.chunk_len[c];
   const BoxDev B = a.boxes[a.particle_box[p]];
+  const bool valid = lane < len;
+  const int k = k0 + (valid ? lane : 0);
   double pos[3];
   node_position(a, x, anchor, k, p, pos);
+  const int64_t N = a.n_nodes;
   for (int d = 0; d < 3; ++d) {
-    int32_t base[3];
-    double tau[3];
-    nearest_node(B, d, pos, base, tau);
-    int32_t tx[3], ty[3], tz[3];
-    const int nx = axis_tiles(base[0], B.n[0], a.tile[0], tx);
-    const int ny = axis_tiles(base[1], B.n[1], a.tile[1], ty);
-    const int nz = axis_tiles(base[2], B.n[2], a.tile[2], tz);
-    for (int iz = 0; iz < nz; ++iz)
-      for (int iy = 0; iy < ny; ++iy)
-        for (int ix = 0; ix < nx; ++ix) {
-          const int tile = B.tile_base + (tz[iz] * B.ntile[1] + ty[iy]) * B.ntile[0] + tx[ix];
-          const int L = d * a.n_tiles + tile;
-          if (FILL) {
-            const int slot = atomicAdd(a.tile_cursor + L, 1);
-            a.tile_list[a.tile_off[L] + slot] = k;
-          } else {
-            atomicAdd(a.tile_count + L, 1);
-          }
-        }
+    int lo[3], hi[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      double f;
+      lattice_coord(B, d, ax, pos[ax], f);
+      f = fmin(fmax(f, -1073741824.0), 1073741824.0);
+      const int nb = (int)f;
+      lo[ax] = wave_min_i(valid ? nb : INT_MAX);
+      hi[ax] = wave_max_i(valid ? nb : INT_MIN);
+    }
+    if (FILL) {
+      const double m = wave_max_all(valid ? fabs((double)F[d * N + k]) : 0.0);
+      if (lane == 0) a.chunk_maxF[3 * c + d] = m;
+    }
+    int t0[3], cn[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) axis_tile_range(B, ax, a.tile[ax], lo[ax], hi[ax], t0[ax], cn[ax]);
+    const int total = cn[0] * cn[1] * cn[2];
+    for (int i = lane; i < total; i += kWave) {
+      int tx = t0[0] + i % cn[0], ty = t0[1] + (i / cn[0]) % cn[1], tz = t0[2] + i / (cn[0] * cn[1]);
+      if (tx >= B.ntile[0]) tx -= B.ntile[0];
+      if (ty >= B.ntile[1]) ty -= B.ntile[1];
+      if (tz >= B.ntile[2]) tz -= B.ntile[2];
+      const int L = d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx;
+      if (FILL) {
+        const int64_t slot = (int64_t)a.tile_off[L] + atomicAdd(a.tile_cursor + L, 1);
+        if (slot < a.pair_cap) a.pair_list[slot] = c;
+      } else {
+        atomicAdd(a.tile_count + L, 1);
+      }
+    }
   }
 }
 
-// Exclusive scan of tile_count into tile_off (n + 1 entries) with one workgroup; zeroes the cursors.
+// Exclusive scan of tile_count into tile_off (n + 1 entries) with one
+// workgroup; zeroes the cursors; flags a list that exceeds its capacity.
 __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restrict__ cnt, int32_t* __restrict__ off,
-                                               int32_t* __restrict__ cursor) {
+                                               int32_t* __restrict__ cursor, int64_t cap,
+                                               unsigned long long* status) {
   __shared__ int32_t part[1024];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int chunk = (n + nt - 1) / nt;
@@ -199,8 +248,7 @@ __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restr
   for (int i = b; i < e; ++i) s += cnt[i];
   part[tid] = s;
   __syncthreads();
-  // Hillis-Steele inclusive scan over the per-thread sums
-  for (int o = 1; o < nt; o <<= 1) {
+  for (int o = 1; o < nt; o <<= 1) {  // Hillis-Steele inclusive scan of the per-thread sums
     const int32_t v = tid >= o ? part[tid - o] : 0;
     __syncthreads();
     part[tid] += v;
@@ -212,7 +260,10 @@ __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restr
     run += cnt[i];
     cursor[i] = 0;
   }
-  if (tid == nt - 1) off[n] = part[nt - 1];
+  if (tid == nt - 1) {
+    off[n] = part[nt - 1];
+    if ((int64_t)part[nt - 1] > cap) atomicAdd(status + 3, 1ull);
+  }
 }
 
 // ------------------------------------------------------------------ tiled spread: accumulation
@@ -227,16 +278,31 @@ struct FixedAcc<double> {
   static constexpr int kWords = 2;
 };
 
+constexpr int kChunksPerWave = 8;                        // chunks filtered per wavefront per round
+constexpr int kQueueCap = 4 * kChunksPerWave * kWave;    // 256-thread workgroups
+
+// Wrapped neighbour cells of `b` relative to the tile start, or -1 outside the tile.
+__device__ __forceinline__ void local_cells(int b, int n, int c0, int ex, int out[3]) {
+  const int cm = (b == 0 ? n - 1 : b - 1) - c0, cc = b - c0, cp = (b == n - 1 ? 0 : b + 1) - c0;
+  out[0] = (unsigned)cm < (unsigned)ex ? cm : -1;
+  out[1] = (unsigned)cc < (unsigned)ex ? cc : -1;
+  out[2] = (unsigned)cp < (unsigned)ex ? cp : -1;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const T* __restrict__ x,
                                                      const double* __restrict__ anchor, const T* __restrict__ F,
                                                      T* __restrict__ grid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double wmax[16];
+  __shared__ int queue[kQueueCap];
+  __shared__ int qn;
+  __shared__ double wm[16];
+  __shared__ int wn[16];
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);
   constexpr int NW = FixedAcc<T>::kWords;
   const int tile = blockIdx.x, d = blockIdx.y;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int nwaves = nt / kWave;
   const int L = d * a.n_tiles + tile;
   const BoxDev B = a.boxes[a.tile_box[tile]];
   const int tl = tile - B.tile_base;
@@ -245,66 +311,118 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
   int ex[3];
   for (int i = 0; i < 3; ++i) ex[i] = min(a.tile[i], B.n[i] - c0[i]);
   const int ncell = ex[0] * ex[1] * ex[2];
-  const int cnt = a.tile_count[L], off = a.tile_off[L];
+  const int64_t off = a.tile_off[L];
+  int cnt = a.tile_count[L];
+  if (off >= a.pair_cap) cnt = 0;
+  else if (off + cnt > a.pair_cap) cnt = (int)(a.pair_cap - off);
   T* g = grid + d * a.total_cells + B.cell_off;
   const int64_t NN = a.n_nodes;
 
-  // largest |F| over the list fixes the fixed-point scale (order independent)
+  // fixed-point scale from the largest |F| and the number of candidate nodes
   double m = 0.0;
-  for (int i = tid; i < cnt; i += nt) m = fmax(m, fabs((double)F[d * NN + a.tile_list[off + i]]));
+  int np = 0;
+  for (int e = tid; e < cnt; e += nt) {
+    const int c = a.pair_list[off + e];
+    m = fmax(m, a.chunk_maxF[3 * c + d]);
+    np += a.chunk_len[c];
+  }
   m = wave_max(m);
-  const int lane = tid & (kWave - 1), wave = tid / kWave, nw = (nt + kWave - 1) / kWave;
-  if (lane == 0) wmax[wave] = m;
+  np = wave_sum(np);
+  if (lane == 0) {
+    wm[wave] = m;
+    wn[wave] = np;
+  }
   for (int i = tid; i < NW * ncell; i += nt) acc[i] = 0ull;
   __syncthreads();
   m = 0.0;
-  for (int w = 0; w < nw; ++w) m = fmax(m, wmax[w]);
+  np = 0;
+  for (int w = 0; w < nwaves; ++w) {
+    m = fmax(m, wm[w]);
+    np += wn[w];
+  }
   if (cnt > 0 && m > 0.0 && isfinite(m)) {
-    // |sum| <= cnt * sum_m |phi_m| * max|F| <= 4 cnt max|F| <= 2^e  ->  scale 2^(62 - e)
-    int e;
-    frexp(4.0 * (double)cnt * m, &e);
-    const double scale = ldexp(1.0, 62 - e);
-    for (int i = tid; i < cnt; i += nt) {
-      const int k = a.tile_list[off + i];
-      const int p = a.node_particle[k];
-      double pos[3];
-      node_position(a, x, anchor, k, p, pos);
-      int32_t base[3];
-      double tau64[3];
-      nearest_node(B, d, pos, base, tau64);
-      const T tau[3] = {(T)tau64[0], (T)tau64[1], (T)tau64[2]};
-      T W[27], c[4];
-      mls_weights<T>(tau, W, c);
-      const T f = F[d * NN + k];
+    // one contribution is at most 4 max|F| (sum of |phi| <= 4), a cell sum at most np times that:
+    // keep every contribution below 2^50 and every sum below 2^62
+    int e1, e2;
+    frexp(4.0 * m, &e1);
+    frexp(4.0 * (double)np * m, &e2);
+    const int sc = min(50 - e1, 62 - e2);
+    const double scale = ldexp(1.0, sc);
+    for (int e0 = 0; e0 < cnt; e0 += nwaves * kChunksPerWave) {
+      if (tid == 0) qn = 0;
+      __syncthreads();
+      // filter: queue the candidate nodes whose stencil reaches this tile
+      for (int j = 0; j < kChunksPerWave; ++j) {
+        const int e = e0 + wave * kChunksPerWave + j;
+        if (e >= cnt) break;
+        const int c = a.pair_list[off + e];
+        const int len = a.chunk_len[c];
+        bool pass = false;
+        int k = 0;
+        if (lane < len) {
+          k = a.chunk_node0[c] + lane;
+          double pos[3], tau[3];
+          int32_t base[3];
+          node_position(a, x, anchor, k, a.chunk_particle[c], pos);
+          nearest_node(B, d, pos, base, tau);
+          int lx[3], ly[3], lz[3];
+          local_cells(base[0], B.n[0], c0[0], ex[0], lx);
+          local_cells(base[1], B.n[1], c0[1], ex[1], ly);
+          local_cells(base[2], B.n[2], c0[2], ex[2], lz);
+          pass = (lx[0] >= 0 || lx[1] >= 0 || lx[2] >= 0) && (ly[0] >= 0 || ly[1] >= 0 || ly[2] >= 0) &&
+                 (lz[0] >= 0 || lz[1] >= 0 || lz[2] >= 0);
+        }
+        const unsigned long long mask = __ballot(pass);
+        int qbase = 0;
+        if (lane == 0 && mask) qbase = atomicAdd(&qn, (int)__popcll(mask));
+        qbase = __shfl(qbase, 0, kWave);
+        if (pass) queue[qbase + (int)__popcll(mask & ((1ull << lane) - 1ull))] = k;
+      }
+      __syncthreads();
+      // accumulate the queued nodes' contributions to the tile's cells
+      const int nq = qn;
+      for (int qi = tid; qi < nq; qi += nt) {
+        const int k = queue[qi];
+        const int p = a.node_particle[k];
+        double pos[3], tau64[3];
+        int32_t base[3];
+        node_position(a, x, anchor, k, p, pos);
+        nearest_node(B, d, pos, base, tau64);
+        const T tau[3] = {(T)tau64[0], (T)tau64[1], (T)tau64[2]};
+        T W[27], cf[4];
+        mls_weights<T>(tau, W, cf);
+        const T f = F[d * NN + k];
+        int lx[3], ly[3], lz[3];
+        local_cells(base[0], B.n[0], c0[0], ex[0], lx);
+        local_cells(base[1], B.n[1], c0[1], ex[1], ly);
+        local_cells(base[2], B.n[2], c0[2], ex[2], lz);
 #pragma unroll
-      for (int mz = 0; mz < 3; ++mz) {
-        const int cz = wrap1(base[2] + mz - 1, B.n[2]) - c0[2];
-        if (cz < 0 || cz >= ex[2]) continue;
-        const T vz = c[0] + c[3] * (T(mz - 1) - tau[2]);
+        for (int mz = 0; mz < 3; ++mz) {
+          if (lz[mz] < 0) continue;
+          const T vz = cf[0] + cf[3] * (T(mz - 1) - tau[2]);
 #pragma unroll
-        for (int my = 0; my < 3; ++my) {
-          const int cy = wrap1(base[1] + my - 1, B.n[1]) - c0[1];
-          if (cy < 0 || cy >= ex[1]) continue;
-          const T vyz = vz + c[2] * (T(my - 1) - tau[1]);
+          for (int my = 0; my < 3; ++my) {
+            if (ly[my] < 0) continue;
+            const T vyz = vz + cf[2] * (T(my - 1) - tau[1]);
+            const int row = (lz[mz] * ex[1] + ly[my]) * ex[0];
 #pragma unroll
-          for (int mx = 0; mx < 3; ++mx) {
-            const int cx = wrap1(base[0] + mx - 1, B.n[0]) - c0[0];
-            if (cx < 0 || cx >= ex[0]) continue;
-            const T phi = W[(mz * 3 + my) * 3 + mx] * (vyz + c[1] * (T(mx - 1) - tau[0]));
-            const double q = (double)(phi * f) * scale;
-            const int li = (cz * ex[1] + cy) * ex[0] + cx;
-            const double qh = rint(q);
-            atomicAdd(acc + li, (unsigned long long)(long long)qh);
-            if (NW == 2) {
-              const double ql = rint((q - qh) * 0x1p40);
-              atomicAdd(acc + ncell + li, (unsigned long long)(long long)ql);
+            for (int mx = 0; mx < 3; ++mx) {
+              if (lx[mx] < 0) continue;
+              const T phi = W[(mz * 3 + my) * 3 + mx] * (vyz + cf[1] * (T(mx - 1) - tau[0]));
+              const double q = (double)(phi * f) * scale;
+              const long long qh = round_to_i64(q);
+              atomicAdd(acc + row + lx[mx], (unsigned long long)qh);
+              if (NW == 2) {
+                const long long ql = round_to_i64((q - (double)qh) * 0x1p40);
+                atomicAdd(acc + ncell + row + lx[mx], (unsigned long long)ql);
+              }
             }
           }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
-    const double inv = 1.0 / scale;
+    const double inv = ldexp(1.0, -sc);
     for (int li = tid; li < ncell; li += nt) {
       const int cx = li % ex[0], cy = (li / ex[0]) % ex[1], cz = li / (ex[0] * ex[1]);
       double v = (double)(long long)acc[li];
@@ -366,26 +484,25 @@ hipError_t launch_spread_atomic(const PlanDev& P, int dtype, const void* x, cons
 
 hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* F,
                                void* grid, int block, hipStream_t st) {
+  (void)block;
   const TransferArgs& a = P.targs;
   const int nl = 3 * a.n_tiles;
   hipError_t e = fill(a.tile_count, (int64_t)nl, 0, st);
   if (e != hipSuccess) return e;
-  if (P.n_nodes) {
+  const dim3 cg((unsigned)((a.n_chunks + 3) / 4)), cb(256);
+  if (a.n_chunks) {
     if (dtype == 0)
-      hipLaunchKernelGGL((k_bin<float, false>), node_grid(P.n_nodes, block), dim3(block), 0, st, a, (const float*)x,
-                         anchor);
+      hipLaunchKernelGGL((k_chunk_bin<float, false>), cg, cb, 0, st, a, (const float*)x, anchor, (const float*)F);
     else
-      hipLaunchKernelGGL((k_bin<double, false>), node_grid(P.n_nodes, block), dim3(block), 0, st, a,
-                         (const double*)x, anchor);
+      hipLaunchKernelGGL((k_chunk_bin<double, false>), cg, cb, 0, st, a, (const double*)x, anchor, (const double*)F);
   }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nl, a.tile_count, a.tile_off, a.tile_cursor);
-  if (P.n_nodes) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nl, a.tile_count, a.tile_off, a.tile_cursor, a.pair_cap,
+                     a.status);
+  if (a.n_chunks) {
     if (dtype == 0)
-      hipLaunchKernelGGL((k_bin<float, true>), node_grid(P.n_nodes, block), dim3(block), 0, st, a, (const float*)x,
-                         anchor);
+      hipLaunchKernelGGL((k_chunk_bin<float, true>), cg, cb, 0, st, a, (const float*)x, anchor, (const float*)F);
     else
-      hipLaunchKernelGGL((k_bin<double, true>), node_grid(P.n_nodes, block), dim3(block), 0, st, a,
-                         (const double*)x, anchor);
+      hipLaunchKernelGGL((k_chunk_bin<double, true>), cg, cb, 0, st, a, (const double*)x, anchor, (const double*)F);
   }
   const dim3 g((unsigned)a.n_tiles, 3);
   if (dtype == 0)
