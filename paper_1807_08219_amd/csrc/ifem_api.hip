@@ -358,7 +358,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   DeviceBuffers& mem = plan->mem;
   int32_t *d_ns, *d_law, *d_box, *d_tri_src, *d_tri_glob, *d_tri_local, *d_tri_pcol, *d_tri_colb;
   int32_t *d_tet_src, *d_tet_glob, *d_tet_local, *d_tet_pcol, *d_tet_colb, *d_rstart = nullptr, *d_ring = nullptr;
-  int32_t *d_np, *d_tile_box, *d_cnt, *d_off, *d_cur, *d_list, *d_ch0, *d_chlen, *d_chp;
+  int32_t *d_np, *d_tile_box, *d_cnt, *d_off, *d_cur, *d_list, *d_ch0, *d_chlen, *d_chp, *d_chrange;
   double *d_mu, *d_mu2, *d_kb, *d_c0, *d_tri_ref, *d_tet_ref, *d_X, *d_chmax;
   BoxDev* d_boxes;
   unsigned long long* d_status;
@@ -406,13 +406,14 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(upload(mem, &d_chlen, chlen.data(), chlen.size(), st));
   HIP_TRY(upload(mem, &d_chp, chp.data(), chp.size(), st));
   HIP_TRY(mem.alloc(&d_chmax, (size_t)3 * n_chunks));
+  HIP_TRY(mem.alloc(&d_chrange, (size_t)18 * n_chunks));
   const int n_tiles = (int)tile_box.size();
   const int64_t pair_cap = (int64_t)64 * 3 * std::max(n_chunks, 1);
   HIP_TRY(mem.alloc(&d_cnt, (size_t)3 * n_tiles));
   HIP_TRY(mem.alloc(&d_off, (size_t)3 * n_tiles + 1));
   HIP_TRY(mem.alloc(&d_cur, (size_t)3 * n_tiles));
   HIP_TRY(mem.alloc(&d_list, (size_t)pair_cap));
-  plan->workspace_bytes = (int64_t)(9 * (int64_t)n_tiles + 1 + pair_cap) * 4 + (int64_t)n_chunks * 24;
+  plan->workspace_bytes = (int64_t)(9 * (int64_t)n_tiles + 1 + pair_cap) * 4 + (int64_t)n_chunks * (24 + 72);
 
   P.tri_src = d_tri_src;
   P.tri_global = d_tri_glob;
@@ -456,6 +457,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ta.chunk_len = d_chlen;
   ta.chunk_particle = d_chp;
   ta.chunk_maxF = d_chmax;
+  ta.chunk_range = d_chrange;
   ta.n_chunks = n_chunks;
   ta.status = d_status;
   ta.pair_cap = pair_cap;

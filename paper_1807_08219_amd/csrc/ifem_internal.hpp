@@ -39,7 +39,8 @@ struct TransferArgs {
   const int32_t* chunk_node0;     // [n_chunks] first node of each 64-node chunk
   const int32_t* chunk_len;       // [n_chunks] nodes in the chunk (1..64)
   const int32_t* chunk_particle;  // [n_chunks]
-  double* chunk_maxF;             // [n_chunks][3] largest |F| per component (written by the fill pass)
+  double* chunk_maxF;             // [n_chunks][3] largest |F| per component (count pass)
+  int32_t* chunk_range;           // [n_chunks][3][6] first tile and tile count per axis (count pass)
   int32_t* tile_count;            // [3 n_tiles] chunks per (component, tile)
   int32_t* tile_off;              // [3 n_tiles + 1]
   int32_t* tile_cursor;           // [3 n_tiles]

@@ -8,8 +8,9 @@
 //  k_spread_atomic<T>   the plain baseline: one global atomic add per
 //                       (node, component, stencil node).
 //  tiled spread         deterministic and free of global float atomics:
-//    k_chunk_bin        per (64-node chunk, component): the lattice tiles its
-//                       stencils reach (count pass, then fill pass);
+//    k_chunk_count      per (64-node chunk, component): the lattice tiles its
+//                       stencils reach, counted once per tile;
+//    k_chunk_fill       appends the chunk to those tiles' lists;
 //    k_scan             exclusive scan of the counts (single workgroup);
 //    k_spread_tile<T>   one workgroup per (component, tile): filters the
 //                       nodes of its chunks into an LDS queue, accumulates
@@ -59,6 +60,13 @@ static hipError_t fill(T* p, int64_t n, T v, hipStream_t st) {
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) { return fill(p, n, 0ull, st); }
 
 // ------------------------------------------------------------------ interpolation
+// Three consecutive lattice values of one x-row, in one 12- or 24-byte load
+// when the row does not cross the periodic seam.
+template <typename T>
+struct alignas(sizeof(T)) Row3 {
+  T v[3];
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_interp(const TransferArgs a, const T* __restrict__ x,
                                                 const double* __restrict__ anchor, const T* __restrict__ grid,
@@ -79,25 +87,35 @@ __global__ void __launch_bounds__(256) k_interp(const TransferArgs a, const T* _
     T W[27], c[4];
     if (!mls_weights<T>(tau, W, c)) ++bad;
     const T* g = grid + d * a.total_cells + B.cell_off;
-    int32_t ix[3], iy[3], iz[3];
+    const bool seam = base[0] == 0 || base[0] == B.n[0] - 1;
+    const int32_t x0 = seam ? 0 : base[0] - 1;
+    int32_t ix[3];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      ix[m] = wrap1(base[0] + m - 1, B.n[0]);
-      iy[m] = wrap1(base[1] + m - 1, B.n[1]) * B.n[0];
-      iz[m] = wrap1(base[2] + m - 1, B.n[2]);
-    }
+    for (int m = 0; m < 3; ++m) ix[m] = wrap1(base[0] + m - 1, B.n[0]);
     T s = 0;
 #pragma unroll
     for (int mz = 0; mz < 3; ++mz) {
-      const int64_t zo = (int64_t)iz[mz] * B.n[1] * B.n[0];
+      const int64_t zo = (int64_t)wrap1(base[2] + mz - 1, B.n[2]) * B.n[1] * B.n[0];
       const T cz = c[0] + c[3] * (T(mz - 1) - tau[2]);
 #pragma unroll
       for (int my = 0; my < 3; ++my) {
+        const T* row = g + zo + (int64_t)wrap1(base[1] + my - 1, B.n[1]) * B.n[0];
+        T u[3];
+        if (!seam) {
+          const Row3<T> r3 = *reinterpret_cast<const Row3<T>*>(row + x0);
+          u[0] = r3.v[0];
+          u[1] = r3.v[1];
+          u[2] = r3.v[2];
+        } else {
+          u[0] = row[ix[0]];
+          u[1] = row[ix[1]];
+          u[2] = row[ix[2]];
+        }
         const T cyz = cz + c[2] * (T(my - 1) - tau[1]);
 #pragma unroll
         for (int mx = 0; mx < 3; ++mx) {
           const T phi = W[(mz * 3 + my) * 3 + mx] * (cyz + c[1] * (T(mx - 1) - tau[0]));
-          s += phi * g[zo + iy[my] + ix[mx]];
+          s += phi * u[mx];
         }
       }
     }
@@ -187,9 +205,12 @@ __device__ __forceinline__ void axis_tile_range(const BoxDev& B, int a, int T, i
   cnt += 1;
 }
 
-template <typename T, bool FILL>
-__global__ void __launch_bounds__(256) k_chunk_bin(const TransferArgs a, const T* __restrict__ x,
-                                                   const double* __restrict__ anchor, const T* __restrict__ F) {
+// Count pass: one wavefront per chunk.  Records, per (chunk, component), the
+// first tile and tile count along each axis and the largest |F|, and counts
+// the chunk once in every tile it reaches.
+template <typename T>
+__global__ void __launch_bounds__(256) k_chunk_count(const TransferArgs a, const T* __restrict__ x,
+                                                     const double* __restrict__ anchor, const T* __restrict__ F) {
   const int lane = threadIdx.x & (kWave - 1);
   const int c = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   if (c >= a.n_chunks) return;  // whole wavefronts leave together
@@ -211,27 +232,48 @@ __global__ void __launch_bounds__(256) k_chunk_bin(const TransferArgs a, const T
       lo[ax] = wave_min_i(valid ? nb : INT_MAX);
       hi[ax] = wave_max_i(valid ? nb : INT_MIN);
     }
-    if (FILL) {
-      const double m = wave_max_all(valid ? fabs((double)F[d * N + k]) : 0.0);
-      if (lane == 0) a.chunk_maxF[3 * c + d] = m;
-    }
+    const double m = wave_max_all(valid ? fabs((double)F[d * N + k]) : 0.0);
     int t0[3], cn[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) axis_tile_range(B, ax, a.tile[ax], lo[ax], hi[ax], t0[ax], cn[ax]);
+    if (lane == 0) {
+      a.chunk_maxF[3 * c + d] = m;
+      int32_t* r = a.chunk_range + 6 * (3 * c + d);
+      r[0] = t0[0];
+      r[1] = t0[1];
+      r[2] = t0[2];
+      r[3] = cn[0];
+      r[4] = cn[1];
+      r[5] = cn[2];
+    }
     const int total = cn[0] * cn[1] * cn[2];
     for (int i = lane; i < total; i += kWave) {
       int tx = t0[0] + i % cn[0], ty = t0[1] + (i / cn[0]) % cn[1], tz = t0[2] + i / (cn[0] * cn[1]);
       if (tx >= B.ntile[0]) tx -= B.ntile[0];
       if (ty >= B.ntile[1]) ty -= B.ntile[1];
       if (tz >= B.ntile[2]) tz -= B.ntile[2];
-      const int L = d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx;
-      if (FILL) {
-        const int64_t slot = (int64_t)a.tile_off[L] + atomicAdd(a.tile_cursor + L, 1);
-        if (slot < a.pair_cap) a.pair_list[slot] = c;
-      } else {
-        atomicAdd(a.tile_count + L, 1);
-      }
+      atomicAdd(a.tile_count + d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx, 1);
     }
+  }
+}
+
+// Fill pass: one thread per (chunk, component) appends the chunk to the
+// lists of the tiles recorded by the count pass.
+__global__ void __launch_bounds__(256) k_chunk_fill(const TransferArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * a.n_chunks) return;
+  const int c = i / 3, d = i - 3 * c;
+  const BoxDev& B = a.boxes[a.particle_box[a.chunk_particle[c]]];
+  const int32_t* r = a.chunk_range + 6 * i;
+  const int total = r[3] * r[4] * r[5];
+  for (int j = 0; j < total; ++j) {
+    int tx = r[0] + j % r[3], ty = r[1] + (j / r[3]) % r[4], tz = r[2] + j / (r[3] * r[4]);
+    if (tx >= B.ntile[0]) tx -= B.ntile[0];
+    if (ty >= B.ntile[1]) ty -= B.ntile[1];
+    if (tz >= B.ntile[2]) tz -= B.ntile[2];
+    const int L = d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx;
+    const int64_t slot = (int64_t)a.tile_off[L] + atomicAdd(a.tile_cursor + L, 1);
+    if (slot < a.pair_cap) a.pair_list[slot] = c;
   }
 }
 
@@ -278,8 +320,7 @@ struct FixedAcc<double> {
   static constexpr int kWords = 2;
 };
 
-constexpr int kChunksPerWave = 8;                        // chunks filtered per wavefront per round
-constexpr int kQueueCap = 4 * kChunksPerWave * kWave;    // 256-thread workgroups
+constexpr int kChunksPerWave = 4;  // chunks filtered per wavefront per round (256-thread workgroups)
 
 // Wrapped neighbour cells of `b` relative to the tile start, or -1 outside the tile.
 __device__ __forceinline__ void local_cells(int b, int n, int c0, int ex, int out[3]) {
@@ -289,12 +330,23 @@ __device__ __forceinline__ void local_cells(int b, int n, int c0, int ex, int ou
   out[2] = (unsigned)cp < (unsigned)ex ? cp : -1;
 }
 
+// LDS work queue of one spread tile: what the accumulation needs of a node,
+// gathered by the filter pass with chunk-coalesced global loads.
+template <typename T>
+struct TileQueue {
+  static constexpr int kCap = 4 * kChunksPerWave * kWave;
+  T tau[3][kCap];
+  T f[kCap];
+  int32_t bxy[kCap];  // base x | base y << 16
+  int32_t bz[kCap];
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const T* __restrict__ x,
                                                      const double* __restrict__ anchor, const T* __restrict__ F,
                                                      T* __restrict__ grid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int queue[kQueueCap];
+  __shared__ TileQueue<T> Q;
   __shared__ int qn;
   __shared__ double wm[16];
   __shared__ int wn[16];
@@ -351,18 +403,19 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
     for (int e0 = 0; e0 < cnt; e0 += nwaves * kChunksPerWave) {
       if (tid == 0) qn = 0;
       __syncthreads();
-      // filter: queue the candidate nodes whose stencil reaches this tile
+      // filter: queue the nodes whose stencil reaches this tile, with tau, base and F
       for (int j = 0; j < kChunksPerWave; ++j) {
         const int e = e0 + wave * kChunksPerWave + j;
         if (e >= cnt) break;
         const int c = a.pair_list[off + e];
         const int len = a.chunk_len[c];
         bool pass = false;
+        double tau[3];
+        int32_t base[3];
         int k = 0;
         if (lane < len) {
           k = a.chunk_node0[c] + lane;
-          double pos[3], tau[3];
-          int32_t base[3];
+          double pos[3];
           node_position(a, x, anchor, k, a.chunk_particle[c], pos);
           nearest_node(B, d, pos, base, tau);
           int lx[3], ly[3], lz[3];
@@ -373,29 +426,32 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
                  (lz[0] >= 0 || lz[1] >= 0 || lz[2] >= 0);
         }
         const unsigned long long mask = __ballot(pass);
-        int qbase = 0;
-        if (lane == 0 && mask) qbase = atomicAdd(&qn, (int)__popcll(mask));
-        qbase = __shfl(qbase, 0, kWave);
-        if (pass) queue[qbase + (int)__popcll(mask & ((1ull << lane) - 1ull))] = k;
+        int qb = 0;
+        if (lane == 0 && mask) qb = atomicAdd(&qn, (int)__popcll(mask));
+        qb = __shfl(qb, 0, kWave);
+        if (pass) {
+          const int q = qb + (int)__popcll(mask & ((1ull << lane) - 1ull));
+          Q.tau[0][q] = (T)tau[0];
+          Q.tau[1][q] = (T)tau[1];
+          Q.tau[2][q] = (T)tau[2];
+          Q.f[q] = F[d * NN + k];
+          Q.bxy[q] = base[0] | (base[1] << 16);
+          Q.bz[q] = base[2];
+        }
       }
       __syncthreads();
-      // accumulate the queued nodes' contributions to the tile's cells
+      // accumulate the queued nodes' contributions to the tile's cells (LDS only)
       const int nq = qn;
       for (int qi = tid; qi < nq; qi += nt) {
-        const int k = queue[qi];
-        const int p = a.node_particle[k];
-        double pos[3], tau64[3];
-        int32_t base[3];
-        node_position(a, x, anchor, k, p, pos);
-        nearest_node(B, d, pos, base, tau64);
-        const T tau[3] = {(T)tau64[0], (T)tau64[1], (T)tau64[2]};
+        const T tau[3] = {Q.tau[0][qi], Q.tau[1][qi], Q.tau[2][qi]};
+        const T f = Q.f[qi];
+        const int bxy = Q.bxy[qi];
         T W[27], cf[4];
         mls_weights<T>(tau, W, cf);
-        const T f = F[d * NN + k];
         int lx[3], ly[3], lz[3];
-        local_cells(base[0], B.n[0], c0[0], ex[0], lx);
-        local_cells(base[1], B.n[1], c0[1], ex[1], ly);
-        local_cells(base[2], B.n[2], c0[2], ex[2], lz);
+        local_cells(bxy & 0xffff, B.n[0], c0[0], ex[0], lx);
+        local_cells(bxy >> 16, B.n[1], c0[1], ex[1], ly);
+        local_cells(Q.bz[qi], B.n[2], c0[2], ex[2], lz);
 #pragma unroll
         for (int mz = 0; mz < 3; ++mz) {
           if (lz[mz] < 0) continue;
@@ -492,18 +548,14 @@ hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const
   const dim3 cg((unsigned)((a.n_chunks + 3) / 4)), cb(256);
   if (a.n_chunks) {
     if (dtype == 0)
-      hipLaunchKernelGGL((k_chunk_bin<float, false>), cg, cb, 0, st, a, (const float*)x, anchor, (const float*)F);
+      hipLaunchKernelGGL(k_chunk_count<float>, cg, cb, 0, st, a, (const float*)x, anchor, (const float*)F);
     else
-      hipLaunchKernelGGL((k_chunk_bin<double, false>), cg, cb, 0, st, a, (const double*)x, anchor, (const double*)F);
+      hipLaunchKernelGGL(k_chunk_count<double>, cg, cb, 0, st, a, (const double*)x, anchor, (const double*)F);
   }
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nl, a.tile_count, a.tile_off, a.tile_cursor, a.pair_cap,
                      a.status);
-  if (a.n_chunks) {
-    if (dtype == 0)
-      hipLaunchKernelGGL((k_chunk_bin<float, true>), cg, cb, 0, st, a, (const float*)x, anchor, (const float*)F);
-    else
-      hipLaunchKernelGGL((k_chunk_bin<double, true>), cg, cb, 0, st, a, (const double*)x, anchor, (const double*)F);
-  }
+  if (a.n_chunks)
+    hipLaunchKernelGGL(k_chunk_fill, dim3((unsigned)((3 * a.n_chunks + 255) / 256)), dim3(256), 0, st, a);
   const dim3 g((unsigned)a.n_tiles, 3);
   if (dtype == 0)
     hipLaunchKernelGGL(k_spread_tile<float>, g, dim3(256), spread_tile_lds_bytes(P, 0), st, a, (const float*)x,
