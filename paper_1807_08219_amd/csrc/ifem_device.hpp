@@ -184,8 +184,10 @@ __device__ __forceinline__ double lattice_coord(const BoxDev& B, int comp, int a
   return t;
 }
 
-// Wrap an integral float64 index into [0, n) (exact for |f| < 2^52).
+// Wrap an integral float64 index into [0, n) (exact for |f| < 2^52; a
+// non-finite or huge coordinate maps to 0, so every index stays in range).
 __device__ __forceinline__ int32_t wrap_index(const BoxDev& B, int a, double f) {
+  if (!(fabs(f) < 4503599627370496.0)) f = 0.0;
   const double qn = floor(f * B.inv_n[a]);
   int32_t w = (int32_t)(f - qn * (double)B.n[a]);
   if (w >= B.n[a]) w -= B.n[a];

@@ -242,7 +242,7 @@ struct RingGeom {
   T A;         // mixed area
   T K[3];      // sum (cot a + cot b)(x_k - x_j)
   T N[3];      // sum of face area vectors
-  T theta;     // angle sum
+  T zr, zi;    // product of (u.w + i |u x w|) over the fan: its argument is sum(theta) - 2 pi
   T lap;       // sum (cot a + cot b)(g_j - g_k) for a nodal field g
 };
 
@@ -262,7 +262,8 @@ __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__
                                               const T* xy, const T* xz, const T* g, RingGeom<T>& R) {
   const T xk[3] = {xx[k], xy[k], xz[k]};
   R.A = 0;
-  R.theta = 0;
+  R.zr = 1;
+  R.zi = 0;
   R.lap = 0;
   for (int c = 0; c < 3; ++c) R.K[c] = R.N[c] = 0;
   const T gk = WITH_LAP ? g[k] : T(0);
@@ -288,7 +289,13 @@ __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__
       R.K[c] -= cot_b * u[c] + cot_a * w[c];
       R.N[c] += T(0.5) * cr[c];
     }
-    R.theta += atan2_t<T>(s, uw);
+    if (WITH_LAP) {  // the angle at k enters through the argument of a running complex product
+      const T inv_m = frcp(fmax(fabs(uw), s));  // rescale each factor to keep the product in range
+      const T ar = uw * inv_m, ai = s * inv_m;
+      const T zr = R.zr * ar - R.zi * ai;
+      R.zi = R.zr * ai + R.zi * ar;
+      R.zr = zr;
+    }
     const bool obt_k = uw < T(0), obt_a = ue > T(0), obt_b = we < T(0);
     if (!(obt_k || obt_a || obt_b))
       R.A += T(0.125) * (uu * cot_b + ww * cot_a);
@@ -304,13 +311,16 @@ __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__
   }
 }
 
+// Mean curvature kH = K.n / (4 A), and (with_gauss) the Gaussian curvature
+// kG = (2 pi - sum theta) / A = -arg(prod z) / A; the argument is the angle
+// deficit itself when it lies in (-pi, pi), with no cancellation against 2 pi.
 template <typename T>
-__device__ __forceinline__ void ring_curvature(const RingGeom<T>& R, T& kH, T& kG, T n[3]) {
+__device__ __forceinline__ void ring_curvature(const RingGeom<T>& R, bool with_gauss, T& kH, T& kG, T n[3]) {
   const T iln = frcp(fsqrt(R.N[0] * R.N[0] + R.N[1] * R.N[1] + R.N[2] * R.N[2]));
   for (int c = 0; c < 3; ++c) n[c] = R.N[c] * iln;
   const T iA = frcp(R.A);
   kH = T(0.25) * (R.K[0] * n[0] + R.K[1] * n[1] + R.K[2] * n[2]) * iA;
-  kG = (T(6.283185307179586476925286766559) - R.theta) * iA;
+  kG = with_gauss ? -atan2_t<T>(R.zi, R.zr) * iA : T(0);
 }
 
 // ------------------------------------------------------------------ the per-particle force kernel
@@ -470,7 +480,7 @@ __global__ void __launch_bounds__(256) k_forces(const ForceArgs a, const T* __re
       RingGeom<T> R;
       ring_geometry<T, false>(k, a.ring, rs[k], rs[k + 1], xx, xy, xz, nullptr, R);
       T kH, kG, nv[3];
-      ring_curvature(R, kH, kG, nv);
+      ring_curvature(R, false, kH, kG, nv);
       kh[k] = kH - kH0;
     }
     __syncthreads();
@@ -479,7 +489,7 @@ __global__ void __launch_bounds__(256) k_forces(const ForceArgs a, const T* __re
       RingGeom<T> R;
       ring_geometry<T, true>(k, a.ring, rs[k], rs[k + 1], xx, xy, xz, kh, R);
       T kH, kG, nv[3];
-      ring_curvature(R, kH, kG, nv);
+      ring_curvature(R, true, kH, kG, nv);
       const T gk = kh[k];
       const T lap = R.lap / (T(2) * R.A);
       const T s = T(2) * (T)kbp * (lap + T(2) * gk * (kH * kH - kG + kH0 * kH)) * R.A;

@@ -196,9 +196,7 @@ __device__ __forceinline__ void axis_tile_range(const BoxDev& B, int a, int T, i
     cnt = nt;
     return;
   }
-  int w0 = lo_c % n, w1 = hi_c % n;
-  if (w0 < 0) w0 += n;
-  if (w1 < 0) w1 += n;
+  const int w0 = wrap_index(B, a, (double)lo_c), w1 = wrap_index(B, a, (double)hi_c);
   t0 = w0 / T;
   cnt = w1 / T - t0;
   if (cnt < 0) cnt += nt;
@@ -207,7 +205,25 @@ __device__ __forceinline__ void axis_tile_range(const BoxDev& B, int a, int T, i
 
 // Count pass: one wavefront per chunk.  Records, per (chunk, component), the
 // first tile and tile count along each axis and the largest |F|, and counts
-// the chunk once in every tile it reaches.
+// the chunk once in every tile it reaches.  The nearest-node rule is
+// monotonic in the coordinate (subtract, fma and floor all preserve order),
+// so the extreme nearest nodes of the chunk come from its extreme
+// coordinates: one min/max reduction per axis serves all three components.
+template <typename T>
+__device__ __forceinline__ T wave_min_t(T v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max_t(T v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int clamp_index(double f) { return (int)fmin(fmax(f, -1073741824.0), 1073741824.0); }
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_chunk_count(const TransferArgs a, const T* __restrict__ x,
                                                      const double* __restrict__ anchor, const T* __restrict__ F) {
@@ -217,27 +233,31 @@ __global__ void __launch_bounds__(256) k_chunk_count(const TransferArgs a, const
   const int p = a.chunk_particle[c], k0 = a.chunk_node0[c], len = a.chunk_len[c];
   const BoxDev B = a.boxes[a.particle_box[p]];
   const bool valid = lane < len;
-  const int k = k0 + (valid ? lane : 0);
-  double pos[3];
-  node_position(a, x, anchor, k, p, pos);
+  const int k = k0 + (valid ? lane : 0);  // invalid lanes repeat node k0: neutral for min and max
   const int64_t N = a.n_nodes;
-  for (int d = 0; d < 3; ++d) {
-    int lo[3], hi[3];
+  double lo_p[3], hi_p[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      double f;
-      lattice_coord(B, d, ax, pos[ax], f);
-      f = fmin(fmax(f, -1073741824.0), 1073741824.0);
-      const int nb = (int)f;
-      lo[ax] = wave_min_i(valid ? nb : INT_MAX);
-      hi[ax] = wave_max_i(valid ? nb : INT_MIN);
-    }
-    const double m = wave_max_all(valid ? fabs((double)F[d * N + k]) : 0.0);
+  for (int ax = 0; ax < 3; ++ax) {
+    const T v = x[ax * N + k];
+    const T vmin = wave_min_t(v), vmax = wave_max_t(v);
+    const double base = sizeof(T) == 4 ? anchor[3 * p + ax] : 0.0;
+    lo_p[ax] = sizeof(T) == 4 ? base + (double)vmin : (double)vmin;
+    hi_p[ax] = sizeof(T) == 4 ? base + (double)vmax : (double)vmax;
+  }
+  T fm[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) fm[d] = wave_max_t(valid ? fabs(F[d * N + k]) : T(0));
+  for (int d = 0; d < 3; ++d) {
     int t0[3], cn[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) axis_tile_range(B, ax, a.tile[ax], lo[ax], hi[ax], t0[ax], cn[ax]);
+    for (int ax = 0; ax < 3; ++ax) {
+      double flo, fhi;
+      lattice_coord(B, d, ax, lo_p[ax], flo);
+      lattice_coord(B, d, ax, hi_p[ax], fhi);
+      axis_tile_range(B, ax, a.tile[ax], clamp_index(flo), clamp_index(fhi), t0[ax], cn[ax]);
+    }
     if (lane == 0) {
-      a.chunk_maxF[3 * c + d] = m;
+      a.chunk_maxF[3 * c + d] = (double)fm[d];
       int32_t* r = a.chunk_range + 6 * (3 * c + d);
       r[0] = t0[0];
       r[1] = t0[1];
@@ -247,7 +267,15 @@ __global__ void __launch_bounds__(256) k_chunk_count(const TransferArgs a, const
       r[5] = cn[2];
     }
     const int total = cn[0] * cn[1] * cn[2];
-    for (int i = lane; i < total; i += kWave) {
+    if (lane < total) {
+      const int ix = lane % cn[0], iy = (lane / cn[0]) % cn[1], iz = lane / (cn[0] * cn[1]);
+      int tx = t0[0] + ix, ty = t0[1] + iy, tz = t0[2] + iz;
+      if (tx >= B.ntile[0]) tx -= B.ntile[0];
+      if (ty >= B.ntile[1]) ty -= B.ntile[1];
+      if (tz >= B.ntile[2]) tz -= B.ntile[2];
+      atomicAdd(a.tile_count + d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx, 1);
+    }
+    for (int i = lane + kWave; i < total; i += kWave) {  // more than 64 tiles: very large chunks only
       int tx = t0[0] + i % cn[0], ty = t0[1] + (i / cn[0]) % cn[1], tz = t0[2] + i / (cn[0] * cn[1]);
       if (tx >= B.ntile[0]) tx -= B.ntile[0];
       if (ty >= B.ntile[1]) ty -= B.ntile[1];
@@ -334,7 +362,8 @@ __device__ __forceinline__ void local_cells(int b, int n, int c0, int ex, int ou
 // gathered by the filter pass with chunk-coalesced global loads.
 template <typename T>
 struct TileQueue {
-  static constexpr int kCap = 4 * kChunksPerWave * kWave;
+  // one filter round adds at most 4 * kChunksPerWave * 64 entries to a carried remainder of < 256
+  static constexpr int kCap = 4 * kChunksPerWave * kWave + 256;
   T tau[3][kCap];
   T f[kCap];
   int32_t bxy[kCap];  // base x | base y << 16
@@ -400,9 +429,9 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
     frexp(4.0 * (double)np * m, &e2);
     const int sc = min(50 - e1, 62 - e2);
     const double scale = ldexp(1.0, sc);
+    if (tid == 0) qn = 0;
+    __syncthreads();
     for (int e0 = 0; e0 < cnt; e0 += nwaves * kChunksPerWave) {
-      if (tid == 0) qn = 0;
-      __syncthreads();
       // filter: queue the nodes whose stencil reaches this tile, with tau, base and F
       for (int j = 0; j < kChunksPerWave; ++j) {
         const int e = e0 + wave * kChunksPerWave + j;
@@ -440,9 +469,11 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
         }
       }
       __syncthreads();
-      // accumulate the queued nodes' contributions to the tile's cells (LDS only)
+      // accumulate whole 256-entry batches (everything in the last round); carry the rest
       const int nq = qn;
-      for (int qi = tid; qi < nq; qi += nt) {
+      const bool last = e0 + nwaves * kChunksPerWave >= cnt;
+      const int full = last ? nq : (nq / nt) * nt;
+      for (int qi = tid; qi < full; qi += nt) {
         const T tau[3] = {Q.tau[0][qi], Q.tau[1][qi], Q.tau[2][qi]};
         const T f = Q.f[qi];
         const int bxy = Q.bxy[qi];
@@ -452,6 +483,7 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
         local_cells(bxy & 0xffff, B.n[0], c0[0], ex[0], lx);
         local_cells(bxy >> 16, B.n[1], c0[1], ex[1], ly);
         local_cells(Q.bz[qi], B.n[2], c0[2], ex[2], lz);
+        const double fs = (double)f * scale;
 #pragma unroll
         for (int mz = 0; mz < 3; ++mz) {
           if (lz[mz] < 0) continue;
@@ -465,7 +497,7 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
             for (int mx = 0; mx < 3; ++mx) {
               if (lx[mx] < 0) continue;
               const T phi = W[(mz * 3 + my) * 3 + mx] * (vyz + cf[1] * (T(mx - 1) - tau[0]));
-              const double q = (double)(phi * f) * scale;
+              const double q = (double)phi * fs;
               const long long qh = round_to_i64(q);
               atomicAdd(acc + row + lx[mx], (unsigned long long)qh);
               if (NW == 2) {
@@ -476,6 +508,19 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
           }
         }
       }
+      __syncthreads();
+      const int rem = nq - full;  // < 256 and, when positive, full >= 256: no overlap
+      if (tid < rem) {
+        const int src = full + tid;
+        Q.tau[0][tid] = Q.tau[0][src];
+        Q.tau[1][tid] = Q.tau[1][src];
+        Q.tau[2][tid] = Q.tau[2][src];
+        Q.f[tid] = Q.f[src];
+        Q.bxy[tid] = Q.bxy[src];
+        Q.bz[tid] = Q.bz[src];
+      }
+      __syncthreads();
+      if (tid == 0) qn = rem;
       __syncthreads();
     }
     const double inv = ldexp(1.0, -sc);
