@@ -22,7 +22,6 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
 METRIC = "Lagrangian nodes/s per coupling step (FP32 vs FP64) + % HBM roofline"
 
 
@@ -30,19 +29,63 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(sc, fp64: bool):
-    """Bytes the method must move per phase (per-unit figures of the design notes)."""
-    vec = 24 if fp64 else 12  # one 3-vector per node or cell
+# Per-unit algorithmic figures (float32 path; float64 doubles the node and grid terms):
+#   node 12 B per 3-vector access, cell 12 B per 3-component access,
+#   triangle 44 B (12 B indices + 24 B float64 metric + 8 B area),
+#   tetrahedron 72 B, bending +24 B per triangle and +48 B per bending node;
+#   MLS weights + one transfer: 753 flops per (node, component)
+#   [27 stencil nodes x 14 (distance, spline, moments) + 9 x 20 (moment sums)
+#    + 60 (4x4 solve) + 27 x 5 (weight and multiply-add)].
+MLS_FLOPS = 27 * 14 + 9 * 20 + 60 + 27 * 5
+VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (fma) x 2.4 GHz, non-packed float32
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic(sc, fp64: bool):
+    """Algorithmic bytes and flops of each kernel of one step."""
+    vec = 24 if fp64 else 12
     cells = sc.total_cells
     bend = sc.kb != 0
-    tri_per_p = np.diff(sc.tri_start)
-    nodes_per_p = np.diff(sc.node_start)
-    tris_bend = int(tri_per_p[bend].sum())
-    nodes_bend = int(nodes_per_p[bend].sum())
-    forces = sc.n_nodes * 2 * vec + sc.n_tris * 44 + sc.n_tets * 72 + tris_bend * 24 + nodes_bend * 48
-    spread = sc.n_nodes * 2 * vec + cells * vec
-    interp = sc.n_nodes * 2 * vec + cells * vec
-    return {"forces": forces, "spread": spread, "interp": interp}
+    tris_bend = int(np.diff(sc.tri_start)[bend].sum())
+    nodes_bend = int(np.diff(sc.node_start)[bend].sum())
+    transfer_flops = 3 * sc.n_nodes * MLS_FLOPS
+    return {
+        "k_forces": (sc.n_nodes * 2 * vec + sc.n_tris * 44 + sc.n_tets * 72 + tris_bend * 24 + nodes_bend * 48, None),
+        "k_spread_tile": (sc.n_nodes * 2 * vec + cells * vec, transfer_flops),
+        "k_spread_atomic": (sc.n_nodes * 2 * vec + cells * vec, transfer_flops),
+        "k_interp": (sc.n_nodes * 2 * vec + cells * vec, transfer_flops),
+        "k_chunk_count": (sc.n_nodes * 2 * vec, None),
+    }
+
+
+def step_bytes(sc, fp64: bool):
+    a = algorithmic(sc, fp64)
+    return a["k_forces"][0] + a["k_spread_tile"][0] + a["k_interp"][0]
+
+
+def source_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1807_08219_amd", "csrc"))):
+        h.update(open(os.path.join(ROOT, "paper_1807_08219_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    try:
+        block = text.split("```json")[1].split("```")[0]
+        rec = json.loads(block)
+    except (IndexError, ValueError):
+        return None
+    if rec.get("source_digest") != source_digest():
+        return None  # the kernel changed since the counters were taken
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(sc, u64, budget_s: float):
@@ -141,24 +184,39 @@ def main():
     ph32 = [lambda: plan.element_forces(ifem.IFEM_F32, x32, anchor, F32, red),
             lambda: plan.spread(ifem.IFEM_F32, x32, anchor, F32, G32),
             lambda: plan.interp(ifem.IFEM_F32, x32, anchor, u32, v32)]
+    plan.set(ifem.IFEM_OPT_KERNEL_TIMING, 8 * args.steps + 64)
+    plan.kernel_times(reset=True)
     wall, per = timed(step32, args.steps, ph32)
+    ktimes = plan.kernel_times(reset=True)
+    plan.set(ifem.IFEM_OPT_KERNEL_TIMING, 0)
     ms_step = wall * 1e3 / args.steps
     ms_phase = per.mean(axis=0)
     log(f"fp32: {ms_step:.3f} ms/step (wall), phases forces/spread/interp {ms_phase.round(4).tolist()} ms")
+    kavg = {k: (t / n, n / args.steps) for k, (t, n) in ktimes.items() if k != "dropped"}
+    log("fp32 kernels (avg ms, launches/step): " + ", ".join(f"{k} {v[0]:.4f} x{v[1]:.0f}" for k, v in kavg.items()))
     nodes_per_s = sc.n_nodes / (ms_step * 1e-3)
-    ab = algorithmic_bytes(sc, fp64=False)
-    names = ["forces", "spread", "interp"]
-    phase_gbs = {n: ab[n] / (ms_phase[i] * 1e-3) / 1e9 for i, n in enumerate(names)}
-    step_gbs = sum(ab.values()) / (ms_step * 1e-3) / 1e9
-    dom = int(np.argmax(ms_phase))
-    kernel_of = {"forces": "k_forces<float>", "spread": "spread (bin + scan + k_spread_tile<float>)",
-                 "interp": "k_interp<float>"}
-    roofline = {"bound": "hbm", "achieved": round(phase_gbs[names[dom]], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(phase_gbs[names[dom]] / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": kernel_of[names[dom]], "phase_ms": round(float(ms_phase[dom]), 4),
-                "algorithmic_bytes": int(ab[names[dom]]),
-                "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
-                "phases_gbs": {k: round(v, 1) for k, v in phase_gbs.items()}}
+    alg = algorithmic(sc, fp64=False)
+    dom = max(kavg, key=lambda k: kavg[k][0] * kavg[k][1])
+    t_dom = kavg[dom][0] * 1e-3
+    bytes_dom, flops_dom = alg.get(dom, (None, None))
+    gbs = bytes_dom / t_dom / 1e9 if bytes_dom else None
+    tfs = flops_dom / t_dom / 1e12 if flops_dom else None
+    hbm_frac = gbs / HBM_PEAK_GBS if gbs else 0.0
+    alu_frac = tfs / VALU_PEAK_TFLOPS if tfs else 0.0
+    if alu_frac > hbm_frac:
+        roofline = {"bound": "alu", "achieved": round(tfs, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(alu_frac, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_frac, 4)}
+    roofline.update({
+        "traffic": measured_traffic(dom, sc.name), "kernel": dom, "kernel_ms": round(kavg[dom][0], 4),
+        "algorithmic_bytes": int(bytes_dom) if bytes_dom else None,
+        "algorithmic_flops": int(flops_dom) if flops_dom else None,
+        "hbm_frac": round(hbm_frac, 4), "alu_frac": round(alu_frac, 4),
+        "step_hbm_frac": round(step_bytes(sc, False) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels_ms": {k: round(v[0], 4) for k, v in kavg.items()},
+    })
     out = {"metric": METRIC, "value": round(nodes_per_s, 1), "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",

@@ -94,8 +94,27 @@ enum { IFEM_LAW_TRI_NEOHOOKE = 0, IFEM_LAW_TRI_SKALAK = 1, IFEM_LAW_TET_NEOHOOKE
  * one global atomic add per (point, stencil node) -- the plain baseline. */
 enum { IFEM_SPREAD_TILED = 0, IFEM_SPREAD_ATOMIC = 1 };
 
-/* Plan options for ifem_plan_set. */
-enum { IFEM_OPT_SPREAD_MODE = 1 };
+/* Plan options for ifem_plan_set.
+ *   IFEM_OPT_SPREAD_MODE    IFEM_SPREAD_TILED or IFEM_SPREAD_ATOMIC.
+ *   IFEM_OPT_KERNEL_TIMING  0 switches the per-kernel event timer off; n > 0
+ *                           switches it on with room for n kernel launches
+ *                           (2n HIP events created now, none per call).  While
+ *                           on, every kernel a step call launches is bracketed
+ *                           by events on the launch stream; read them with
+ *                           ifem_plan_kernel_times.  Synchronises the device. */
+enum { IFEM_OPT_SPREAD_MODE = 1, IFEM_OPT_KERNEL_TIMING = 2 };
+
+/* Kernel slots reported by ifem_plan_kernel_times. */
+enum {
+  IFEM_KERNEL_FORCES = 0,        /* per-particle element, bending and reduction kernel */
+  IFEM_KERNEL_CHUNK_COUNT = 1,   /* spread: tiles reached by each 64-node chunk         */
+  IFEM_KERNEL_SCAN = 2,          /* spread: offsets of the tile work lists              */
+  IFEM_KERNEL_CHUNK_FILL = 3,    /* spread: fill of the tile work lists                 */
+  IFEM_KERNEL_SPREAD_TILE = 4,   /* spread: per-tile LDS accumulation and grid write    */
+  IFEM_KERNEL_SPREAD_ATOMIC = 5, /* spread: plain global-atomic baseline                */
+  IFEM_KERNEL_INTERP = 6,        /* interpolation                                       */
+  IFEM_KERNEL_FILL = 7           /* zero fills                                          */
+};
 
 /* Mesh description, HOST memory, read once by ifem_plan_create. */
 typedef struct {
@@ -125,7 +144,7 @@ typedef struct {
 /* Launch shape.  Pass NULL to ifem_plan_create to let the plan time the
  * candidate shapes on its own meshes and pick the fastest. */
 typedef struct {
-  int32_t tile[3];      /* spread tile, cells per axis (each >= 4)     */
+  int32_t tile[3];      /* spread tile, cells per axis (powers of two, 4..64) */
   int32_t block_forces; /* threads per particle workgroup (64..1024)   */
   int32_t block_points; /* threads per workgroup of the point kernels  */
 } ifem_tuning;
@@ -172,6 +191,13 @@ ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const doub
 /* Step 4 (Sec. III.A): interpolate grid velocity grid_u [3][total_cells] to the nodes, v_out [3][n_nodes]. */
 ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* grid_u,
                         void* v_out, void* stream);
+
+/* Synchronise `stream` and the timer's events; total_ms[i] and launches[i]
+ * receive the summed duration and number of launches of kernel slot i
+ * (IFEM_KERNEL_*) recorded since the last reset; launches[15] counts launches
+ * not recorded because the event pool was full.  reset != 0 empties the pool. */
+ifem_status ifem_plan_kernel_times(ifem_plan plan, void* stream, double total_ms[16], int64_t launches[16],
+                                   int32_t reset);
 
 /* Synchronise `stream`, copy the device status counters into counts[4] and,
  * if reset != 0, clear them. */

@@ -57,6 +57,7 @@ struct DeviceBuffers {
 
 struct ifem_plan_s {
   PlanDev P{};
+  KernelTimer timer;
   DeviceBuffers mem;
   ifem_tuning tune{};
   int spread_mode = IFEM_SPREAD_TILED;
@@ -287,7 +288,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ifem_tuning tn{{16, 16, 16}, 256, 256};
   if (tuning) tn = *tuning;
   for (int a = 0; a < 3; ++a)
-    if (tn.tile[a] < 4 || tn.tile[a] > 64) return fail(IFEM_ERR_INVALID_ARG, "tile sizes must be in [4, 64]");
+    if (tn.tile[a] < 4 || tn.tile[a] > 64 || (tn.tile[a] & (tn.tile[a] - 1)))
+      return fail(IFEM_ERR_INVALID_ARG, "tile sizes must be powers of two in [4, 64]");
   if ((int64_t)tn.tile[0] * tn.tile[1] * tn.tile[2] * 16 > (int64_t)kLdsLimit)
     return fail(IFEM_ERR_INVALID_ARG, "tile too large for LDS");
   if (tn.block_forces != 64 && tn.block_forces != 128 && tn.block_forces != 256)
@@ -347,6 +349,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ifem_plan plan = new ifem_plan_s();
   plan->tune = tn;
   PlanDev& P = plan->P;
+  P.timer = &plan->timer;
   P.n_particles = m.n_particles;
   P.n_nodes = m.n_nodes;
   P.n_tris = m.n_tris;
@@ -465,7 +468,10 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ta.n_nodes = m.n_nodes;
   ta.n_boxes = n_boxes;
   ta.n_tiles = n_tiles;
-  for (int a = 0; a < 3; ++a) ta.tile[a] = tn.tile[a];
+  for (int a = 0; a < 3; ++a) {
+    ta.tile[a] = tn.tile[a];
+    ta.tile_shift[a] = __builtin_ctz(tn.tile[a]);
+  }
 
   // --- reference metrics on the device (float64), degeneracy check
   HIP_TRY(launch_fill_u64(d_status, 4, st));
@@ -486,9 +492,18 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   return ok();
 }
 
+static void release_timer(KernelTimer& t) {
+  for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+  t.ev.clear();
+  t.slot.clear();
+  t.used = t.dropped = 0;
+  t.enabled = false;
+}
+
 ifem_status ifem_plan_destroy(ifem_plan plan) {
   if (!plan) return fail(IFEM_ERR_INVALID_ARG, "plan is NULL");
   (void)hipDeviceSynchronize();
+  release_timer(plan->timer);
   plan->mem.release();
   delete plan;
   return ok();
@@ -500,6 +515,25 @@ ifem_status ifem_plan_set(ifem_plan plan, int32_t option, int64_t value) {
     if (value != IFEM_SPREAD_TILED && value != IFEM_SPREAD_ATOMIC)
       return fail(IFEM_ERR_INVALID_ARG, "unknown spread mode %lld", (long long)value);
     plan->spread_mode = (int)value;
+    return ok();
+  }
+  if (option == IFEM_OPT_KERNEL_TIMING) {
+    if (value < 0 || value > (1 << 20)) return fail(IFEM_ERR_INVALID_ARG, "kernel timing capacity out of range");
+    (void)hipDeviceSynchronize();
+    release_timer(plan->timer);
+    if (value > 0) {
+      KernelTimer& t = plan->timer;
+      t.ev.resize(2 * (size_t)value);
+      t.slot.assign((size_t)value, 0);
+      for (auto& e : t.ev) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+          release_timer(t);
+          return fail(IFEM_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(r));
+        }
+      }
+      t.enabled = true;
+    }
     return ok();
   }
   return fail(IFEM_ERR_INVALID_ARG, "unknown option %d", option);
@@ -586,6 +620,29 @@ ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const doub
       overlaps(v_out, nb, anchor, (size_t)3 * P.n_particles * 8))
     return fail(IFEM_ERR_INVALID_ARG, "v_out aliases an input");
   return launched(launch_interp(P, dtype, x, anchor, grid_u, v_out, plan->tune.block_points, (hipStream_t)stream));
+}
+
+ifem_status ifem_plan_kernel_times(ifem_plan plan, void* stream, double total_ms[16], int64_t launches[16],
+                                   int32_t reset) {
+  if (!plan || !total_ms || !launches) return fail(IFEM_ERR_INVALID_ARG, "NULL argument");
+  KernelTimer& t = plan->timer;
+  for (int i = 0; i < 16; ++i) {
+    total_ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e == hipSuccess && t.used) e = hipEventSynchronize(t.ev[2 * t.used - 1]);
+  if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "timer synchronisation failed: %s", hipGetErrorString(e));
+  for (size_t i = 0; i < t.used; ++i) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]);
+    if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "hipEventElapsedTime: %s", hipGetErrorString(e));
+    total_ms[t.slot[i]] += ms;
+    launches[t.slot[i]] += 1;
+  }
+  launches[15] = (int64_t)t.dropped;
+  if (reset) t.used = t.dropped = 0;
+  return ok();
 }
 
 ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[4], int32_t reset) {

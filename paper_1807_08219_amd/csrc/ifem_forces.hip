@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(256) k_forces(const ForceArgs a, const T* __re
           w[cc] = q[2][cc] - q[0][cc];
         }
         const double nx = u[1] * w[2] - u[2] * w[1], ny = u[2] * w[0] - u[0] * w[2], nz = u[0] * w[1] - u[1] * w[0];
-        r[1] += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+        r[1] += 0.5 * hw_sqrt(nx * nx + ny * ny + nz * nz);
       }
     }
     __syncthreads();
@@ -567,12 +567,14 @@ size_t force_lds_bytes(const PlanDev& P, int dtype) {
 hipError_t launch_forces(const PlanDev& P, int dtype, const void* x, const double* anchor, void* f, double* red,
                          int block, hipStream_t st) {
   if (P.n_particles == 0) return hipSuccess;
+  P.timer->begin(K_FORCES, st);
   if (dtype == 0)
     hipLaunchKernelGGL(k_forces<float>, dim3(P.n_particles), dim3(block), force_lds<float>(P), st, P.fargs,
                        (const float*)x, anchor, (float*)f, red);
   else
     hipLaunchKernelGGL(k_forces<double>, dim3(P.n_particles), dim3(block), force_lds<double>(P), st, P.fargs,
                        (const double*)x, anchor, (double*)f, red);
+  P.timer->end(st);
   return hipGetLastError();
 }
 

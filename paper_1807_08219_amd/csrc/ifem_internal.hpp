@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "ifem_device.hpp"
 
 namespace ifem {
@@ -49,7 +51,45 @@ struct TransferArgs {
   int64_t pair_cap;
   int64_t total_cells;
   int32_t n_nodes, n_boxes, n_tiles, n_chunks;
-  int32_t tile[3];
+  int32_t tile[3];        // cells per tile and axis (powers of two)
+  int32_t tile_shift[3];  // log2 of tile
+};
+
+// Kernel slots of the per-kernel event timer.
+enum KernelSlot {
+  K_FORCES = 0,
+  K_CHUNK_COUNT = 1,
+  K_SCAN = 2,
+  K_CHUNK_FILL = 3,
+  K_SPREAD_TILE = 4,
+  K_SPREAD_ATOMIC = 5,
+  K_INTERP = 6,
+  K_FILL = 7,
+  K_NSLOTS = 16
+};
+
+// Optional host-side timer: when enabled, every kernel launch of a step call
+// is bracketed by two events recorded on the launch stream.  Events come from
+// a pool created when timing is switched on; nothing is allocated per call.
+struct KernelTimer {
+  bool enabled = false;
+  std::vector<hipEvent_t> ev;  // 2 per record
+  std::vector<int> slot;       // slot of each record
+  size_t used = 0, dropped = 0;
+  void begin(int s, hipStream_t st) {
+    if (!enabled) return;
+    if (used >= slot.size()) {
+      ++dropped;
+      return;
+    }
+    slot[used] = s;
+    (void)hipEventRecord(ev[2 * used], st);
+  }
+  void end(hipStream_t st) {
+    if (!enabled || used >= slot.size()) return;
+    (void)hipEventRecord(ev[2 * used + 1], st);
+    ++used;
+  }
 };
 
 struct PlanDev {
@@ -67,6 +107,7 @@ struct PlanDev {
   unsigned long long* status;  // [4]
   ForceArgs fargs;
   TransferArgs targs;
+  KernelTimer* timer;  // host object owned by the plan
 };
 
 // ---- launchers (ifem_forces.hip)

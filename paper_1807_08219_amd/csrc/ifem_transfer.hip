@@ -86,20 +86,21 @@ __global__ void __launch_bounds__(256) k_interp(const TransferArgs a, const T* _
     const T tau[3] = {(T)tau64[0], (T)tau64[1], (T)tau64[2]};
     T W[27], c[4];
     if (!mls_weights<T>(tau, W, c)) ++bad;
-    const T* g = grid + d * a.total_cells + B.cell_off;
+    const T* g = grid + d * a.total_cells + B.cell_off;  // cells of one box fit 32-bit offsets
     const bool seam = base[0] == 0 || base[0] == B.n[0] - 1;
     const int32_t x0 = seam ? 0 : base[0] - 1;
     int32_t ix[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) ix[m] = wrap1(base[0] + m - 1, B.n[0]);
+    const int32_t nxy = B.n[0] * B.n[1];
     T s = 0;
 #pragma unroll
     for (int mz = 0; mz < 3; ++mz) {
-      const int64_t zo = (int64_t)wrap1(base[2] + mz - 1, B.n[2]) * B.n[1] * B.n[0];
+      const int32_t zo = wrap1(base[2] + mz - 1, B.n[2]) * nxy;
       const T cz = c[0] + c[3] * (T(mz - 1) - tau[2]);
 #pragma unroll
       for (int my = 0; my < 3; ++my) {
-        const T* row = g + zo + (int64_t)wrap1(base[1] + my - 1, B.n[1]) * B.n[0];
+        const T* row = g + (uint32_t)(zo + wrap1(base[1] + my - 1, B.n[1]) * B.n[0]);
         T u[3];
         if (!seam) {
           const Row3<T> r3 = *reinterpret_cast<const Row3<T>*>(row + x0);
@@ -171,16 +172,6 @@ __global__ void __launch_bounds__(256) k_spread_atomic(const TransferArgs a, con
 // nearest-node indices; the tiles overlapping that range grown by the
 // one-cell stencil reach receive the chunk id in their list.  Counting and
 // filling take one global atomic per (chunk, component, tile), not per node.
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
-  return v;
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
-  return v;
-}
 __device__ __forceinline__ double wave_max_all(double v) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
@@ -188,7 +179,8 @@ __device__ __forceinline__ double wave_max_all(double v) {
 }
 
 // Tiles (first, count) along one axis covering the wrapped cells lo-1 .. hi+1.
-__device__ __forceinline__ void axis_tile_range(const BoxDev& B, int a, int T, int lo, int hi, int& t0, int& cnt) {
+__device__ __forceinline__ void axis_tile_range(const BoxDev& B, int a, int T, int shift, int lo, int hi, int& t0,
+                                                int& cnt) {
   const int n = B.n[a], nt = B.ntile[a];
   const int lo_c = lo - 1, hi_c = hi + 1;
   if (hi_c - lo_c + 1 > n - T) {  // the cell range leaves no full tile outside it: every tile
@@ -197,8 +189,8 @@ __device__ __forceinline__ void axis_tile_range(const BoxDev& B, int a, int T, i
     return;
   }
   const int w0 = wrap_index(B, a, (double)lo_c), w1 = wrap_index(B, a, (double)hi_c);
-  t0 = w0 / T;
-  cnt = w1 / T - t0;
+  t0 = w0 >> shift;
+  cnt = (w1 >> shift) - t0;
   if (cnt < 0) cnt += nt;
   cnt += 1;
 }
@@ -254,7 +246,7 @@ __global__ void __launch_bounds__(256) k_chunk_count(const TransferArgs a, const
       double flo, fhi;
       lattice_coord(B, d, ax, lo_p[ax], flo);
       lattice_coord(B, d, ax, hi_p[ax], fhi);
-      axis_tile_range(B, ax, a.tile[ax], clamp_index(flo), clamp_index(fhi), t0[ax], cn[ax]);
+      axis_tile_range(B, ax, a.tile[ax], a.tile_shift[ax], clamp_index(flo), clamp_index(fhi), t0[ax], cn[ax]);
     }
     if (lane == 0) {
       a.chunk_maxF[3 * c + d] = (double)fm[d];
@@ -268,7 +260,12 @@ __global__ void __launch_bounds__(256) k_chunk_count(const TransferArgs a, const
     }
     const int total = cn[0] * cn[1] * cn[2];
     if (lane < total) {
-      const int ix = lane % cn[0], iy = (lane / cn[0]) % cn[1], iz = lane / (cn[0] * cn[1]);
+      // lane -> (ix, iy, iz) by float division: exact for these small integers
+      const int cxy = cn[0] * cn[1];
+      const int iz = (int)(((float)lane + 0.5f) * frcp((float)cxy));
+      const int rxy = lane - iz * cxy;
+      const int iy = (int)(((float)rxy + 0.5f) * frcp((float)cn[0]));
+      const int ix = rxy - iy * cn[0];
       int tx = t0[0] + ix, ty = t0[1] + iy, tz = t0[2] + iz;
       if (tx >= B.ntile[0]) tx -= B.ntile[0];
       if (ty >= B.ntile[1]) ty -= B.ntile[1];
@@ -348,7 +345,8 @@ struct FixedAcc<double> {
   static constexpr int kWords = 2;
 };
 
-constexpr int kChunksPerWave = 4;  // chunks filtered per wavefront per round (256-thread workgroups)
+constexpr int kTileThreads = 512;  // threads of a spread-tile workgroup (8 wavefronts)
+constexpr int kChunksPerWave = 2;  // chunks filtered per wavefront per round
 
 // Wrapped neighbour cells of `b` relative to the tile start, or -1 outside the tile.
 __device__ __forceinline__ void local_cells(int b, int n, int c0, int ex, int out[3]) {
@@ -362,8 +360,8 @@ __device__ __forceinline__ void local_cells(int b, int n, int c0, int ex, int ou
 // gathered by the filter pass with chunk-coalesced global loads.
 template <typename T>
 struct TileQueue {
-  // one filter round adds at most 4 * kChunksPerWave * 64 entries to a carried remainder of < 256
-  static constexpr int kCap = 4 * kChunksPerWave * kWave + 256;
+  // one filter round adds at most (waves x kChunksPerWave x 64) entries to a carried remainder
+  static constexpr int kCap = (kTileThreads / kWave) * kChunksPerWave * kWave + kTileThreads;
   T tau[3][kCap];
   T f[kCap];
   int32_t bxy[kCap];  // base x | base y << 16
@@ -371,7 +369,7 @@ struct TileQueue {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const T* __restrict__ x,
+__global__ void __launch_bounds__(kTileThreads) k_spread_tile(const TransferArgs a, const T* __restrict__ x,
                                                      const double* __restrict__ anchor, const T* __restrict__ F,
                                                      T* __restrict__ grid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -469,7 +467,7 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
         }
       }
       __syncthreads();
-      // accumulate whole 256-entry batches (everything in the last round); carry the rest
+      // accumulate whole workgroup-size batches (everything in the last round); carry the rest
       const int nq = qn;
       const bool last = e0 + nwaves * kChunksPerWave >= cnt;
       const int full = last ? nq : (nq / nt) * nt;
@@ -509,7 +507,7 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
         }
       }
       __syncthreads();
-      const int rem = nq - full;  // < 256 and, when positive, full >= 256: no overlap
+      const int rem = nq - full;  // < nt and, when positive, full >= nt: no overlap
       if (tid < rem) {
         const int src = full + tid;
         Q.tau[0][tid] = Q.tau[0][src];
@@ -528,12 +526,12 @@ __global__ void __launch_bounds__(256) k_spread_tile(const TransferArgs a, const
       const int cx = li % ex[0], cy = (li / ex[0]) % ex[1], cz = li / (ex[0] * ex[1]);
       double v = (double)(long long)acc[li];
       if (NW == 2) v += (double)(long long)acc[ncell + li] * 0x1p-40;
-      g[((int64_t)(c0[2] + cz) * B.n[1] + (c0[1] + cy)) * B.n[0] + c0[0] + cx] = (T)(v * inv);
+      g[(uint32_t)(((c0[2] + cz) * B.n[1] + (c0[1] + cy)) * B.n[0] + c0[0] + cx)] = (T)(v * inv);
     }
   } else {
     for (int li = tid; li < ncell; li += nt) {
       const int cx = li % ex[0], cy = (li / ex[0]) % ex[1], cz = li / (ex[0] * ex[1]);
-      g[((int64_t)(c0[2] + cz) * B.n[1] + (c0[1] + cy)) * B.n[0] + c0[0] + cx] = (T)0;
+      g[(uint32_t)(((c0[2] + cz) * B.n[1] + (c0[1] + cy)) * B.n[0] + c0[0] + cx)] = (T)0;
     }
   }
 }
@@ -557,29 +555,35 @@ static inline dim3 node_grid(int n, int block) { return dim3((unsigned)((n + blo
 hipError_t launch_interp(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* grid, void* v,
                          int block, hipStream_t st) {
   if (P.n_nodes == 0) return hipSuccess;
+  P.timer->begin(K_INTERP, st);
   if (dtype == 0)
     hipLaunchKernelGGL(k_interp<float>, node_grid(P.n_nodes, block), dim3(block), 0, st, P.targs, (const float*)x,
                        anchor, (const float*)grid, (float*)v);
   else
     hipLaunchKernelGGL(k_interp<double>, node_grid(P.n_nodes, block), dim3(block), 0, st, P.targs, (const double*)x,
                        anchor, (const double*)grid, (double*)v);
+  P.timer->end(st);
   return hipGetLastError();
 }
 
 hipError_t launch_spread_atomic(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* F,
                                 void* grid, int block, hipStream_t st) {
   hipError_t e;
+  P.timer->begin(K_FILL, st);
   if (dtype == 0)
     e = fill((float*)grid, 3 * P.total_cells, 0.0f, st);
   else
     e = fill((double*)grid, 3 * P.total_cells, 0.0, st);
+  P.timer->end(st);
   if (e != hipSuccess || P.n_nodes == 0) return e;
+  P.timer->begin(K_SPREAD_ATOMIC, st);
   if (dtype == 0)
     hipLaunchKernelGGL(k_spread_atomic<float>, node_grid(P.n_nodes, block), dim3(block), 0, st, P.targs,
                        (const float*)x, anchor, (const float*)F, (float*)grid);
   else
     hipLaunchKernelGGL(k_spread_atomic<double>, node_grid(P.n_nodes, block), dim3(block), 0, st, P.targs,
                        (const double*)x, anchor, (const double*)F, (double*)grid);
+  P.timer->end(st);
   return hipGetLastError();
 }
 
@@ -588,26 +592,37 @@ hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const
   (void)block;
   const TransferArgs& a = P.targs;
   const int nl = 3 * a.n_tiles;
+  P.timer->begin(K_FILL, st);
   hipError_t e = fill(a.tile_count, (int64_t)nl, 0, st);
+  P.timer->end(st);
   if (e != hipSuccess) return e;
   const dim3 cg((unsigned)((a.n_chunks + 3) / 4)), cb(256);
   if (a.n_chunks) {
+    P.timer->begin(K_CHUNK_COUNT, st);
     if (dtype == 0)
       hipLaunchKernelGGL(k_chunk_count<float>, cg, cb, 0, st, a, (const float*)x, anchor, (const float*)F);
     else
       hipLaunchKernelGGL(k_chunk_count<double>, cg, cb, 0, st, a, (const double*)x, anchor, (const double*)F);
+    P.timer->end(st);
   }
+  P.timer->begin(K_SCAN, st);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nl, a.tile_count, a.tile_off, a.tile_cursor, a.pair_cap,
                      a.status);
-  if (a.n_chunks)
+  P.timer->end(st);
+  if (a.n_chunks) {
+    P.timer->begin(K_CHUNK_FILL, st);
     hipLaunchKernelGGL(k_chunk_fill, dim3((unsigned)((3 * a.n_chunks + 255) / 256)), dim3(256), 0, st, a);
+    P.timer->end(st);
+  }
   const dim3 g((unsigned)a.n_tiles, 3);
+  P.timer->begin(K_SPREAD_TILE, st);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_spread_tile<float>, g, dim3(256), spread_tile_lds_bytes(P, 0), st, a, (const float*)x,
-                       anchor, (const float*)F, (float*)grid);
+    hipLaunchKernelGGL(k_spread_tile<float>, g, dim3(kTileThreads), spread_tile_lds_bytes(P, 0), st, a,
+                       (const float*)x, anchor, (const float*)F, (float*)grid);
   else
-    hipLaunchKernelGGL(k_spread_tile<double>, g, dim3(256), spread_tile_lds_bytes(P, 1), st, a, (const double*)x,
-                       anchor, (const double*)F, (double*)grid);
+    hipLaunchKernelGGL(k_spread_tile<double>, g, dim3(kTileThreads), spread_tile_lds_bytes(P, 1), st, a,
+                       (const double*)x, anchor, (const double*)F, (double*)grid);
+  P.timer->end(st);
   return hipGetLastError();
 }
 

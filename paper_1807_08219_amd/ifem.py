@@ -26,10 +26,13 @@ IFEM_F64 = 1
 IFEM_SPREAD_TILED = 0
 IFEM_SPREAD_ATOMIC = 1
 IFEM_OPT_SPREAD_MODE = 1
+IFEM_OPT_KERNEL_TIMING = 2
+KERNEL_SLOTS = {0: "k_forces", 1: "k_chunk_count", 2: "k_scan", 3: "k_chunk_fill", 4: "k_spread_tile",
+                5: "k_spread_atomic", 6: "k_interp", 7: "k_fill"}
 
 EXPORTED = [
     "ifem_plan_create", "ifem_plan_destroy", "ifem_plan_set", "ifem_plan_info", "ifem_element_forces",
-    "ifem_spread", "ifem_interp", "ifem_plan_status", "ifem_last_error", "ifem_version",
+    "ifem_spread", "ifem_interp", "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
 ]
 
 
@@ -76,6 +79,7 @@ def lib():
         L.ifem_spread.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_interp.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_plan_status.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int32]
+        L.ifem_plan_kernel_times.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.ifem_last_error.restype = C.c_char_p
         L.ifem_version.restype = C.c_int32
         for name in EXPORTED:
@@ -178,6 +182,16 @@ class Plan:
         out = (C.c_int64 * 4)()
         _check(lib().ifem_plan_status(self.handle, _stream(stream), out, int(bool(reset))))
         return list(out)
+
+    def kernel_times(self, reset=True, stream=None):
+        """{kernel name: (total ms, launches)} recorded since the last reset (needs IFEM_OPT_KERNEL_TIMING)."""
+        ms = (C.c_double * 16)()
+        n = (C.c_int64 * 16)()
+        _check(lib().ifem_plan_kernel_times(self.handle, _stream(stream), ms, n, int(bool(reset))))
+        out = {KERNEL_SLOTS[i]: (ms[i], n[i]) for i in KERNEL_SLOTS if n[i]}
+        if n[15]:
+            out["dropped"] = (0.0, n[15])
+        return out
 
     # --- the three steps (device tensors in, device tensors out)
     def element_forces(self, dtype, x, anchor, f_out, red_out=None, stream=None):
