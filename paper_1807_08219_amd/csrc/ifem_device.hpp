@@ -70,8 +70,6 @@ __device__ __forceinline__ double wave_max(double v) {
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-// float64 hardware square root (v_sqrt_f64), used where a last-bit difference is immaterial
-__device__ __forceinline__ double hw_sqrt(double x) { return __builtin_amdgcn_sqrt(x); }
 __device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
 
 // ------------------------------------------------------------------ MLS weights

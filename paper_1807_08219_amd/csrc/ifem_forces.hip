@@ -348,7 +348,10 @@ __device__ __forceinline__ void block_sum(double v[NV], double* lds /*[NV][16]*/
   __syncthreads();
 }
 
-template <typename T>
+// POS_LDS: the particle's positions are staged in LDS once (coalesced) and
+// every element and one-ring read hits LDS; otherwise they are read through
+// the caches (particles too large for the staging copy).
+template <typename T, bool POS_LDS>
 __global__ void __launch_bounds__(256) k_forces(const ForceArgs a, const T* __restrict__ x,
                                                  const double* __restrict__ anchor, T* __restrict__ fout,
                                                  double* __restrict__ red) {
@@ -373,6 +376,18 @@ __global__ void __launch_bounds__(256) k_forces(const ForceArgs a, const T* __re
   const T* xx = x + n0;
   const T* xy = x + N + n0;
   const T* xz = x + 2 * N + n0;
+  if (POS_LDS) {
+    T* px = kh + (a.ring_start ? a.cap : 0);  // [3][cap] after the curvature array
+    for (int i = tid; i < nn; i += nt) {
+      px[i] = xx[i];
+      px[a.cap + i] = xy[i];
+      px[2 * a.cap + i] = xz[i];
+    }
+    __syncthreads();
+    xx = px;
+    xy = px + a.cap;
+    xz = px + 2 * a.cap;
+  }
   const int law = a.law[p];
   const T mu = (T)a.mu[p], mu2 = (T)a.mu2[p];
   // local origin for the float64 reductions: float32 offsets are already
@@ -421,7 +436,7 @@ __global__ void __launch_bounds__(256) k_forces(const ForceArgs a, const T* __re
           w[cc] = q[2][cc] - q[0][cc];
         }
         const double nx = u[1] * w[2] - u[2] * w[1], ny = u[2] * w[0] - u[0] * w[2], nz = u[0] * w[1] - u[1] * w[0];
-        r[1] += 0.5 * hw_sqrt(nx * nx + ny * ny + nz * nz);
+        r[1] += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
       }
     }
     __syncthreads();
@@ -548,32 +563,56 @@ hipError_t launch_ref_setup(const PlanDev& P, const double* X, hipStream_t st) {
 }
 
 template <typename T>
-static size_t force_lds(const PlanDev& P) {
-  return (size_t)(3 + (P.has_bending ? 1 : 0)) * P.cap * sizeof(T);
+static size_t force_lds(const PlanDev& P, bool pos_lds) {
+  return (size_t)(3 + (P.has_bending ? 1 : 0) + (pos_lds ? 3 : 0)) * P.cap * sizeof(T);
+}
+
+// Stage positions in LDS when the particle's forces, curvature and positions fit.
+template <typename T>
+static bool use_pos_lds(const PlanDev& P) {
+  return force_lds<T>(P, true) <= 160 * 1024 - 2048;
 }
 
 hipError_t prepare_force_kernels(const PlanDev& P) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_forces<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)force_lds<float>(P));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_forces<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)force_lds<double>(P));
+  hipError_t e;
+  e = hipFuncSetAttribute((const void*)k_forces<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)force_lds<float>(P, false));
+  if (e == hipSuccess && use_pos_lds<float>(P))
+    e = hipFuncSetAttribute((const void*)k_forces<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)force_lds<float>(P, true));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_forces<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)force_lds<double>(P, false));
+  if (e == hipSuccess && use_pos_lds<double>(P))
+    e = hipFuncSetAttribute((const void*)k_forces<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)force_lds<double>(P, true));
+  return e;
 }
 
 size_t force_lds_bytes(const PlanDev& P, int dtype) {
-  return dtype == 0 ? force_lds<float>(P) : force_lds<double>(P);
+  return dtype == 0 ? force_lds<float>(P, use_pos_lds<float>(P)) : force_lds<double>(P, use_pos_lds<double>(P));
 }
 
 hipError_t launch_forces(const PlanDev& P, int dtype, const void* x, const double* anchor, void* f, double* red,
                          int block, hipStream_t st) {
   if (P.n_particles == 0) return hipSuccess;
   P.timer->begin(K_FORCES, st);
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_forces<float>, dim3(P.n_particles), dim3(block), force_lds<float>(P), st, P.fargs,
-                       (const float*)x, anchor, (float*)f, red);
-  else
-    hipLaunchKernelGGL(k_forces<double>, dim3(P.n_particles), dim3(block), force_lds<double>(P), st, P.fargs,
-                       (const double*)x, anchor, (double*)f, red);
+  const dim3 g(P.n_particles), b(block);
+  if (dtype == 0) {
+    if (use_pos_lds<float>(P))
+      hipLaunchKernelGGL((k_forces<float, true>), g, b, force_lds<float>(P, true), st, P.fargs, (const float*)x,
+                         anchor, (float*)f, red);
+    else
+      hipLaunchKernelGGL((k_forces<float, false>), g, b, force_lds<float>(P, false), st, P.fargs, (const float*)x,
+                         anchor, (float*)f, red);
+  } else {
+    if (use_pos_lds<double>(P))
+      hipLaunchKernelGGL((k_forces<double, true>), g, b, force_lds<double>(P, true), st, P.fargs, (const double*)x,
+                         anchor, (double*)f, red);
+    else
+      hipLaunchKernelGGL((k_forces<double, false>), g, b, force_lds<double>(P, false), st, P.fargs,
+                         (const double*)x, anchor, (double*)f, red);
+  }
   P.timer->end(st);
   return hipGetLastError();
 }
