@@ -111,6 +111,7 @@ enum {
   IFEM_KERNEL_SCAN = 2,          /* spread: offsets of the tile work lists              */
   IFEM_KERNEL_CHUNK_FILL = 3,    /* spread: fill of the tile work lists                 */
   IFEM_KERNEL_SPREAD_TILE = 4,   /* spread: per-tile LDS accumulation and grid write    */
+  IFEM_KERNEL_SPREAD_MERGE = 8,  /* spread: neighbour halos added to tile border cells  */
   IFEM_KERNEL_SPREAD_ATOMIC = 5, /* spread: plain global-atomic baseline                */
   IFEM_KERNEL_INTERP = 6,        /* interpolation                                       */
   IFEM_KERNEL_FILL = 7           /* zero fills                                          */

@@ -290,7 +290,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   for (int a = 0; a < 3; ++a)
     if (tn.tile[a] < 4 || tn.tile[a] > 64 || (tn.tile[a] & (tn.tile[a] - 1)))
       return fail(IFEM_ERR_INVALID_ARG, "tile sizes must be powers of two in [4, 64]");
-  if ((int64_t)tn.tile[0] * tn.tile[1] * tn.tile[2] * 16 > (int64_t)kLdsLimit)
+  if ((int64_t)(tn.tile[0] + 2) * (tn.tile[1] + 2) * (tn.tile[2] + 2) * 16 + 64 * 1024 > (int64_t)kLdsLimit)
     return fail(IFEM_ERR_INVALID_ARG, "tile too large for LDS");
   if (tn.block_forces != 64 && tn.block_forces != 128 && tn.block_forces != 256)
     return fail(IFEM_ERR_INVALID_ARG, "block_forces must be 64, 128 or 256");
@@ -361,7 +361,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   DeviceBuffers& mem = plan->mem;
   int32_t *d_ns, *d_law, *d_box, *d_tri_src, *d_tri_glob, *d_tri_local, *d_tri_pcol, *d_tri_colb;
   int32_t *d_tet_src, *d_tet_glob, *d_tet_local, *d_tet_pcol, *d_tet_colb, *d_rstart = nullptr, *d_ring = nullptr;
-  int32_t *d_np, *d_tile_box, *d_cnt, *d_off, *d_cur, *d_list, *d_ch0, *d_chlen, *d_chp, *d_chrange;
+  int32_t *d_np, *d_tile_box, *d_cnt, *d_off, *d_cur, *d_list, *d_ch0, *d_chlen, *d_chp, *d_chrange, *d_flag;
+  double* d_halo;
   double *d_mu, *d_mu2, *d_kb, *d_c0, *d_tri_ref, *d_tet_ref, *d_X, *d_chmax;
   BoxDev* d_boxes;
   unsigned long long* d_status;
@@ -416,7 +417,11 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_off, (size_t)3 * n_tiles + 1));
   HIP_TRY(mem.alloc(&d_cur, (size_t)3 * n_tiles));
   HIP_TRY(mem.alloc(&d_list, (size_t)pair_cap));
-  plan->workspace_bytes = (int64_t)(9 * (int64_t)n_tiles + 1 + pair_cap) * 4 + (int64_t)n_chunks * (24 + 72);
+  const int region_cells = (tn.tile[0] + 2) * (tn.tile[1] + 2) * (tn.tile[2] + 2);
+  HIP_TRY(mem.alloc(&d_flag, (size_t)3 * n_tiles));
+  HIP_TRY(mem.alloc(&d_halo, (size_t)3 * n_tiles * region_cells));  // sized for float64
+  plan->workspace_bytes = (int64_t)(12 * (int64_t)n_tiles + 1 + pair_cap) * 4 + (int64_t)n_chunks * (24 + 72) +
+                          (int64_t)3 * n_tiles * region_cells * 8;
 
   P.tri_src = d_tri_src;
   P.tri_global = d_tri_glob;
@@ -456,6 +461,9 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ta.tile_off = d_off;
   ta.tile_cursor = d_cur;
   ta.pair_list = d_list;
+  ta.tile_flag = d_flag;
+  ta.halo = d_halo;
+  ta.region_cells = region_cells;
   ta.chunk_node0 = d_ch0;
   ta.chunk_len = d_chlen;
   ta.chunk_particle = d_chp;

@@ -47,12 +47,15 @@ struct TransferArgs {
   int32_t* tile_off;              // [3 n_tiles + 1]
   int32_t* tile_cursor;           // [3 n_tiles]
   int32_t* pair_list;             // [pair_cap] chunk ids, grouped by (component, tile)
+  int32_t* tile_flag;             // [3 n_tiles] 1 if the tile wrote a halo shell this call
+  void* halo;                     // [3 n_tiles][region_cells] halo-shell values (float or double)
   unsigned long long* status;
   int64_t pair_cap;
   int64_t total_cells;
   int32_t n_nodes, n_boxes, n_tiles, n_chunks;
   int32_t tile[3];        // cells per tile and axis (powers of two)
   int32_t tile_shift[3];  // log2 of tile
+  int32_t region_cells;   // (tile_x + 2)(tile_y + 2)(tile_z + 2)
 };
 
 // Kernel slots of the per-kernel event timer.
@@ -62,6 +65,7 @@ enum KernelSlot {
   K_SCAN = 2,
   K_CHUNK_FILL = 3,
   K_SPREAD_TILE = 4,
+  K_SPREAD_MERGE = 8,
   K_SPREAD_ATOMIC = 5,
   K_INTERP = 6,
   K_FILL = 7,

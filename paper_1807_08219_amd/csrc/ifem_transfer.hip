@@ -8,16 +8,20 @@
 //  k_spread_atomic<T>   the plain baseline: one global atomic add per
 //                       (node, component, stencil node).
 //  tiled spread         deterministic and free of global float atomics:
-//    k_chunk_count      per (64-node chunk, component): the lattice tiles its
-//                       stencils reach, counted once per tile;
-//    k_chunk_fill       appends the chunk to those tiles' lists;
+//    k_chunk_count      per (64-node chunk, component): the lattice tiles
+//                       holding the nearest nodes of its members, counted
+//                       once per tile;
 //    k_scan             exclusive scan of the counts (single workgroup);
-//    k_spread_tile<T>   one workgroup per (component, tile): filters the
-//                       nodes of its chunks into an LDS queue, accumulates
-//                       their contributions in LDS as 64-bit fixed-point
-//                       integers (exact, order-independent sums; float64 uses
-//                       a two-word split), then writes every lattice value of
-//                       the tile exactly once.
+//    k_chunk_fill       appends the chunk to those tiles' lists;
+//    k_spread_home<T>   one workgroup per (component, tile): filters the
+//                       nodes whose nearest node is in the tile into an LDS
+//                       queue and accumulates all their contributions in an
+//                       LDS region (tile + one-cell halo) as 64-bit
+//                       fixed-point integers (exact, order-independent sums;
+//                       float64 uses a two-word split); writes the interior
+//                       to the grid and the halo shell to scratch;
+//    k_spread_merge<T>  adds the neighbours' halo values to each tile's
+//                       border cells in a fixed order.
 #include <climits>
 
 #include "ifem_device.hpp"
@@ -178,11 +182,11 @@ __device__ __forceinline__ double wave_max_all(double v) {
   return v;
 }
 
-// Tiles (first, count) along one axis covering the wrapped cells lo-1 .. hi+1.
+// Tiles (first, count) along one axis holding the wrapped nearest-node indices lo .. hi.
 __device__ __forceinline__ void axis_tile_range(const BoxDev& B, int a, int T, int shift, int lo, int hi, int& t0,
                                                 int& cnt) {
   const int n = B.n[a], nt = B.ntile[a];
-  const int lo_c = lo - 1, hi_c = hi + 1;
+  const int lo_c = lo, hi_c = hi;
   if (hi_c - lo_c + 1 > n - T) {  // the cell range leaves no full tile outside it: every tile
     t0 = 0;
     cnt = nt;
@@ -348,14 +352,6 @@ struct FixedAcc<double> {
 constexpr int kTileThreads = 512;  // threads of a spread-tile workgroup (8 wavefronts)
 constexpr int kChunksPerWave = 2;  // chunks filtered per wavefront per round
 
-// Wrapped neighbour cells of `b` relative to the tile start, or -1 outside the tile.
-__device__ __forceinline__ void local_cells(int b, int n, int c0, int ex, int out[3]) {
-  const int cm = (b == 0 ? n - 1 : b - 1) - c0, cc = b - c0, cp = (b == n - 1 ? 0 : b + 1) - c0;
-  out[0] = (unsigned)cm < (unsigned)ex ? cm : -1;
-  out[1] = (unsigned)cc < (unsigned)ex ? cc : -1;
-  out[2] = (unsigned)cp < (unsigned)ex ? cp : -1;
-}
-
 // LDS work queue of one spread tile: what the accumulation needs of a node,
 // gathered by the filter pass with chunk-coalesced global loads.
 template <typename T>
@@ -364,14 +360,18 @@ struct TileQueue {
   static constexpr int kCap = (kTileThreads / kWave) * kChunksPerWave * kWave + kTileThreads;
   T tau[3][kCap];
   T f[kCap];
-  int32_t bxy[kCap];  // base x | base y << 16
-  int32_t bz[kCap];
+  int32_t lb[kCap];  // nearest node relative to the tile start: x | y << 8 | z << 16
 };
 
+// Home-tile accumulation: workgroup (tile, component) takes every node whose
+// nearest lattice node lies in the tile and accumulates all 27 of its
+// contributions into an LDS region covering the tile plus a one-cell halo
+// (64-bit fixed point: exact, order-independent sums).  The region interior
+// is written straight to the grid, the halo shell to scratch for the merge.
 template <typename T>
-__global__ void __launch_bounds__(kTileThreads) k_spread_tile(const TransferArgs a, const T* __restrict__ x,
-                                                     const double* __restrict__ anchor, const T* __restrict__ F,
-                                                     T* __restrict__ grid) {
+__global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs a, const T* __restrict__ x,
+                                                              const double* __restrict__ anchor,
+                                                              const T* __restrict__ F, T* __restrict__ grid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ TileQueue<T> Q;
   __shared__ int qn;
@@ -389,12 +389,13 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_tile(const TransferArgs
   const int c0[3] = {tx * a.tile[0], ty * a.tile[1], tz * a.tile[2]};
   int ex[3];
   for (int i = 0; i < 3; ++i) ex[i] = min(a.tile[i], B.n[i] - c0[i]);
-  const int ncell = ex[0] * ex[1] * ex[2];
+  const int rx = ex[0] + 2, ry = ex[1] + 2, rz = ex[2] + 2, nreg = rx * ry * rz;
   const int64_t off = a.tile_off[L];
   int cnt = a.tile_count[L];
   if (off >= a.pair_cap) cnt = 0;
   else if (off + cnt > a.pair_cap) cnt = (int)(a.pair_cap - off);
   T* g = grid + d * a.total_cells + B.cell_off;
+  T* halo = reinterpret_cast<T*>(a.halo) + (int64_t)L * a.region_cells;
   const int64_t NN = a.n_nodes;
 
   // fixed-point scale from the largest |F| and the number of candidate nodes
@@ -411,7 +412,7 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_tile(const TransferArgs
     wm[wave] = m;
     wn[wave] = np;
   }
-  for (int i = tid; i < NW * ncell; i += nt) acc[i] = 0ull;
+  for (int i = tid; i < NW * nreg; i += nt) acc[i] = 0ull;
   __syncthreads();
   m = 0.0;
   np = 0;
@@ -419,18 +420,20 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_tile(const TransferArgs
     m = fmax(m, wm[w]);
     np += wn[w];
   }
-  if (cnt > 0 && m > 0.0 && isfinite(m)) {
+  const bool active = cnt > 0 && m > 0.0 && isfinite(m);
+  int sc = 0;
+  if (active) {
     // one contribution is at most 4 max|F| (sum of |phi| <= 4), a cell sum at most np times that:
     // keep every contribution below 2^50 and every sum below 2^62
     int e1, e2;
     frexp(4.0 * m, &e1);
     frexp(4.0 * (double)np * m, &e2);
-    const int sc = min(50 - e1, 62 - e2);
+    sc = min(50 - e1, 62 - e2);
     const double scale = ldexp(1.0, sc);
     if (tid == 0) qn = 0;
     __syncthreads();
     for (int e0 = 0; e0 < cnt; e0 += nwaves * kChunksPerWave) {
-      // filter: queue the nodes whose stencil reaches this tile, with tau, base and F
+      // filter: queue the nodes whose nearest lattice node lies in this tile
       for (int j = 0; j < kChunksPerWave; ++j) {
         const int e = e0 + wave * kChunksPerWave + j;
         if (e >= cnt) break;
@@ -445,12 +448,8 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_tile(const TransferArgs
           double pos[3];
           node_position(a, x, anchor, k, a.chunk_particle[c], pos);
           nearest_node(B, d, pos, base, tau);
-          int lx[3], ly[3], lz[3];
-          local_cells(base[0], B.n[0], c0[0], ex[0], lx);
-          local_cells(base[1], B.n[1], c0[1], ex[1], ly);
-          local_cells(base[2], B.n[2], c0[2], ex[2], lz);
-          pass = (lx[0] >= 0 || lx[1] >= 0 || lx[2] >= 0) && (ly[0] >= 0 || ly[1] >= 0 || ly[2] >= 0) &&
-                 (lz[0] >= 0 || lz[1] >= 0 || lz[2] >= 0);
+          pass = (unsigned)(base[0] - c0[0]) < (unsigned)ex[0] && (unsigned)(base[1] - c0[1]) < (unsigned)ex[1] &&
+                 (unsigned)(base[2] - c0[2]) < (unsigned)ex[2];
         }
         const unsigned long long mask = __ballot(pass);
         int qb = 0;
@@ -462,8 +461,7 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_tile(const TransferArgs
           Q.tau[1][q] = (T)tau[1];
           Q.tau[2][q] = (T)tau[2];
           Q.f[q] = F[d * NN + k];
-          Q.bxy[q] = base[0] | (base[1] << 16);
-          Q.bz[q] = base[2];
+          Q.lb[q] = (base[0] - c0[0]) | ((base[1] - c0[1]) << 8) | ((base[2] - c0[2]) << 16);
         }
       }
       __syncthreads();
@@ -473,34 +471,28 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_tile(const TransferArgs
       const int full = last ? nq : (nq / nt) * nt;
       for (int qi = tid; qi < full; qi += nt) {
         const T tau[3] = {Q.tau[0][qi], Q.tau[1][qi], Q.tau[2][qi]};
-        const T f = Q.f[qi];
-        const int bxy = Q.bxy[qi];
+        const int lb = Q.lb[qi];
         T W[27], cf[4];
         mls_weights<T>(tau, W, cf);
-        int lx[3], ly[3], lz[3];
-        local_cells(bxy & 0xffff, B.n[0], c0[0], ex[0], lx);
-        local_cells(bxy >> 16, B.n[1], c0[1], ex[1], ly);
-        local_cells(Q.bz[qi], B.n[2], c0[2], ex[2], lz);
-        const double fs = (double)f * scale;
+        const double fs = (double)Q.f[qi] * scale;
+        // region cell of stencil node m: local base + m (the region starts one cell before the tile)
+        const int r0 = (((lb >> 16) & 0xff) * ry + ((lb >> 8) & 0xff)) * rx + (lb & 0xff);
 #pragma unroll
         for (int mz = 0; mz < 3; ++mz) {
-          if (lz[mz] < 0) continue;
           const T vz = cf[0] + cf[3] * (T(mz - 1) - tau[2]);
 #pragma unroll
           for (int my = 0; my < 3; ++my) {
-            if (ly[my] < 0) continue;
             const T vyz = vz + cf[2] * (T(my - 1) - tau[1]);
-            const int row = (lz[mz] * ex[1] + ly[my]) * ex[0];
+            const int row = r0 + (mz * ry + my) * rx;
 #pragma unroll
             for (int mx = 0; mx < 3; ++mx) {
-              if (lx[mx] < 0) continue;
               const T phi = W[(mz * 3 + my) * 3 + mx] * (vyz + cf[1] * (T(mx - 1) - tau[0]));
               const double q = (double)phi * fs;
               const long long qh = round_to_i64(q);
-              atomicAdd(acc + row + lx[mx], (unsigned long long)qh);
+              atomicAdd(acc + row + mx, (unsigned long long)qh);
               if (NW == 2) {
                 const long long ql = round_to_i64((q - (double)qh) * 0x1p40);
-                atomicAdd(acc + ncell + row + lx[mx], (unsigned long long)ql);
+                atomicAdd(acc + nreg + row + mx, (unsigned long long)ql);
               }
             }
           }
@@ -514,39 +506,104 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_tile(const TransferArgs
         Q.tau[1][tid] = Q.tau[1][src];
         Q.tau[2][tid] = Q.tau[2][src];
         Q.f[tid] = Q.f[src];
-        Q.bxy[tid] = Q.bxy[src];
-        Q.bz[tid] = Q.bz[src];
+        Q.lb[tid] = Q.lb[src];
       }
       __syncthreads();
       if (tid == 0) qn = rem;
       __syncthreads();
     }
-    const double inv = ldexp(1.0, -sc);
-    for (int li = tid; li < ncell; li += nt) {
-      const int cx = li % ex[0], cy = (li / ex[0]) % ex[1], cz = li / (ex[0] * ex[1]);
-      double v = (double)(long long)acc[li];
-      if (NW == 2) v += (double)(long long)acc[ncell + li] * 0x1p-40;
-      g[(uint32_t)(((c0[2] + cz) * B.n[1] + (c0[1] + cy)) * B.n[0] + c0[0] + cx)] = (T)(v * inv);
+  }
+  // interior -> grid (final unless a neighbour's halo adds to it), halo shell -> scratch
+  const double inv = ldexp(1.0, -sc);
+  for (int r = tid; r < nreg; r += nt) {
+    const int ix = r % rx, iy = (r / rx) % ry, iz = r / (rx * ry);
+    const bool interior = ix >= 1 && ix <= ex[0] && iy >= 1 && iy <= ex[1] && iz >= 1 && iz <= ex[2];
+    T v = T(0);
+    if (active) {
+      double w = (double)(long long)acc[r];
+      if (NW == 2) w += (double)(long long)acc[nreg + r] * 0x1p-40;
+      v = (T)(w * inv);
     }
-  } else {
-    for (int li = tid; li < ncell; li += nt) {
-      const int cx = li % ex[0], cy = (li / ex[0]) % ex[1], cz = li / (ex[0] * ex[1]);
-      g[(uint32_t)(((c0[2] + cz) * B.n[1] + (c0[1] + cy)) * B.n[0] + c0[0] + cx)] = (T)0;
+    if (interior)
+      g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix - 1)] = v;
+    else if (active)
+      halo[r] = v;
+  }
+  if (tid == 0) a.tile_flag[L] = active ? 1 : 0;
+}
+
+// Merge: every tile adds, to its border cells, the halo values that its 26
+// neighbours (periodic; possibly itself) accumulated for them, in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_spread_merge(const TransferArgs a, T* __restrict__ grid) {
+  __shared__ int nbL[27];
+  __shared__ int nbflag[27];
+  __shared__ int nbex[27][3];
+  __shared__ int any;
+  const int tile = blockIdx.x, d = blockIdx.y, tid = threadIdx.x;
+  const BoxDev B = a.boxes[a.tile_box[tile]];
+  const int tl = tile - B.tile_base;
+  const int t[3] = {tl % B.ntile[0], (tl / B.ntile[0]) % B.ntile[1], tl / (B.ntile[0] * B.ntile[1])};
+  if (tid == 0) any = 0;
+  __syncthreads();
+  if (tid < 27) {
+    const int o[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
+    int nb[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      nb[ax] = t[ax] + o[ax];
+      if (nb[ax] < 0) nb[ax] += B.ntile[ax];
+      if (nb[ax] >= B.ntile[ax]) nb[ax] -= B.ntile[ax];
+      nbex[tid][ax] = min(a.tile[ax], B.n[ax] - nb[ax] * a.tile[ax]);
     }
+    const int Ln = d * a.n_tiles + B.tile_base + (nb[2] * B.ntile[1] + nb[1]) * B.ntile[0] + nb[0];
+    nbL[tid] = Ln;
+    const int f = tid == 13 ? 0 : a.tile_flag[Ln];  // 13 = the tile itself, already in the grid
+    nbflag[tid] = f;
+    if (f) atomicOr(&any, 1);
+  }
+  __syncthreads();
+  if (!any) return;
+  const int c0[3] = {t[0] * a.tile[0], t[1] * a.tile[1], t[2] * a.tile[2]};
+  const int ex[3] = {nbex[13][0], nbex[13][1], nbex[13][2]};
+  const int ncell = ex[0] * ex[1] * ex[2];
+  T* g = grid + d * a.total_cells + B.cell_off;
+  const T* halo = reinterpret_cast<const T*>(a.halo);
+  for (int li = tid; li < ncell; li += blockDim.x) {
+    const int i[3] = {li % ex[0], (li / ex[0]) % ex[1], li / (ex[0] * ex[1])};
+    if (i[0] > 0 && i[0] < ex[0] - 1 && i[1] > 0 && i[1] < ex[1] - 1 && i[2] > 0 && i[2] < ex[2] - 1) continue;
+    const uint32_t cell = (uint32_t)(((c0[2] + i[2]) * B.n[1] + (c0[1] + i[1])) * B.n[0] + c0[0] + i[0]);
+    T v = g[cell];
+    for (int oz = -1; oz <= 1; ++oz) {
+      if ((oz == -1 && i[2] != 0) || (oz == 1 && i[2] != ex[2] - 1)) continue;
+      for (int oy = -1; oy <= 1; ++oy) {
+        if ((oy == -1 && i[1] != 0) || (oy == 1 && i[1] != ex[1] - 1)) continue;
+        for (int ox = -1; ox <= 1; ++ox) {
+          if ((ox == -1 && i[0] != 0) || (ox == 1 && i[0] != ex[0] - 1)) continue;
+          const int nbi = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1);
+          if (!nbflag[nbi]) continue;
+          // region coordinates of this cell in the neighbour: -1 -> its last+1, +1 -> 0, 0 -> i + 1
+          const int r[3] = {ox == -1 ? nbex[nbi][0] + 1 : (ox == 1 ? 0 : i[0] + 1),
+                            oy == -1 ? nbex[nbi][1] + 1 : (oy == 1 ? 0 : i[1] + 1),
+                            oz == -1 ? nbex[nbi][2] + 1 : (oz == 1 ? 0 : i[2] + 1)};
+          const int rxn = nbex[nbi][0] + 2, ryn = nbex[nbi][1] + 2;
+          v += halo[(int64_t)nbL[nbi] * a.region_cells + (r[2] * ryn + r[1]) * rxn + r[0]];
+        }
+      }
+    }
+    g[cell] = v;
   }
 }
 
 // ------------------------------------------------------------------ host launchers
 size_t spread_tile_lds_bytes(const PlanDev& P, int dtype) {
-  const size_t cells = (size_t)P.targs.tile[0] * P.targs.tile[1] * P.targs.tile[2];
-  return cells * 8 * (dtype == 0 ? 1 : 2);
+  return (size_t)P.targs.region_cells * 8 * (dtype == 0 ? 1 : 2);
 }
 
 hipError_t prepare_transfer_kernels(const PlanDev& P) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_spread_tile<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_spread_home<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)spread_tile_lds_bytes(P, 0));
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_spread_tile<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute((const void*)k_spread_home<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)spread_tile_lds_bytes(P, 1));
 }
 
@@ -617,11 +674,17 @@ hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const
   const dim3 g((unsigned)a.n_tiles, 3);
   P.timer->begin(K_SPREAD_TILE, st);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_spread_tile<float>, g, dim3(kTileThreads), spread_tile_lds_bytes(P, 0), st, a,
+    hipLaunchKernelGGL(k_spread_home<float>, g, dim3(kTileThreads), spread_tile_lds_bytes(P, 0), st, a,
                        (const float*)x, anchor, (const float*)F, (float*)grid);
   else
-    hipLaunchKernelGGL(k_spread_tile<double>, g, dim3(kTileThreads), spread_tile_lds_bytes(P, 1), st, a,
+    hipLaunchKernelGGL(k_spread_home<double>, g, dim3(kTileThreads), spread_tile_lds_bytes(P, 1), st, a,
                        (const double*)x, anchor, (const double*)F, (double*)grid);
+  P.timer->end(st);
+  P.timer->begin(K_SPREAD_MERGE, st);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_spread_merge<float>, g, dim3(256), 0, st, a, (float*)grid);
+  else
+    hipLaunchKernelGGL(k_spread_merge<double>, g, dim3(256), 0, st, a, (double*)grid);
   P.timer->end(st);
   return hipGetLastError();
 }

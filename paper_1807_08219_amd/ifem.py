@@ -28,7 +28,7 @@ IFEM_SPREAD_ATOMIC = 1
 IFEM_OPT_SPREAD_MODE = 1
 IFEM_OPT_KERNEL_TIMING = 2
 KERNEL_SLOTS = {0: "k_forces", 1: "k_chunk_count", 2: "k_scan", 3: "k_chunk_fill", 4: "k_spread_tile",
-                5: "k_spread_atomic", 6: "k_interp", 7: "k_fill"}
+                5: "k_spread_atomic", 6: "k_interp", 7: "k_fill", 8: "k_spread_merge"}
 
 EXPORTED = [
     "ifem_plan_create", "ifem_plan_destroy", "ifem_plan_set", "ifem_plan_info", "ifem_element_forces",
