@@ -127,7 +127,7 @@ __device__ __forceinline__ bool tri_element(const T xs[3][3], const double G[3],
     SG22 = mu * M22 + k * (T(1) + trM - M22);
   } else {  // neo-Hookean membrane
     const T J2 = T(1) + I2b;
-    const T s = mu / (J2 * J2);
+    const T s = mu * frcp(J2 * J2);
     const T diag = trM + T(2) * detM + I2b * I2b;
     SG11 = s * (diag + M11);
     SG12 = s * M12;
@@ -269,22 +269,21 @@ __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__
   const T gk = WITH_LAP ? g[k] : T(0);
   int ja = ring[re - 1];
   T u[3] = {xx[ja] - xk[0], xy[ja] - xk[1], xz[ja] - xk[2]};
+  T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   T ga = WITH_LAP ? g[ja] : T(0);
   for (int r = rb; r < re; ++r) {
     const int jb = ring[r];
     // triangle (k, ja, jb): wedge from the previous neighbour to this one
     const T w[3] = {xx[jb] - xk[0], xy[jb] - xk[1], xz[jb] - xk[2]};
-    const T e[3] = {w[0] - u[0], w[1] - u[1], w[2] - u[2]};
     const T cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
     const T s = fsqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);  // twice the area
     const T uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
-    const T ue = u[0] * e[0] + u[1] * e[1] + u[2] * e[2];
-    const T we = w[0] * e[0] + w[1] * e[1] + w[2] * e[2];
+    const T ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    // with e = w - u (edge ja -> jb): u.e = uw - uu, w.e = ww - uw
+    const T ue = uw - uu, we = ww - uw;
     const T inv = frcp(s);
     const T cot_a = -ue * inv;  // angle at ja, opposite edge (k, jb)
     const T cot_b = we * inv;   // angle at jb, opposite edge (k, ja)
-    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const T ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
     for (int c = 0; c < 3; ++c) {
       R.K[c] -= cot_b * u[c] + cot_a * w[c];
       R.N[c] += T(0.5) * cr[c];
@@ -308,6 +307,7 @@ __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__
     }
     ja = jb;
     for (int c = 0; c < 3; ++c) u[c] = w[c];
+    uu = ww;
   }
 }
 
@@ -422,21 +422,21 @@ __global__ void __launch_bounds__(256) k_forces(const ForceArgs a, const T* __re
         acc[2 * a.cap + ids[v]] += f[v][2];
       }
       if (red) {
+        // cone volume q0.(q1 x q2) = q0.(u x w) with the edges u, w of the area vector
         double q[3][3];
         for (int v = 0; v < 3; ++v)
           for (int cc = 0; cc < 3; ++cc) q[v][cc] = (double)xs[v][cc] - o[cc];
-        const double cone = (q[0][0] * (q[1][1] * q[2][2] - q[1][2] * q[2][1]) +
-                             q[0][1] * (q[1][2] * q[2][0] - q[1][0] * q[2][2]) +
-                             q[0][2] * (q[1][0] * q[2][1] - q[1][1] * q[2][0])) / 6.0;
-        r[0] += cone;
-        for (int cc = 0; cc < 3; ++cc) r[2 + cc] += cone * (q[0][cc] + q[1][cc] + q[2][cc]) * 0.25;
         double u[3], w[3];
         for (int cc = 0; cc < 3; ++cc) {
           u[cc] = q[1][cc] - q[0][cc];
           w[cc] = q[2][cc] - q[0][cc];
         }
         const double nx = u[1] * w[2] - u[2] * w[1], ny = u[2] * w[0] - u[0] * w[2], nz = u[0] * w[1] - u[1] * w[0];
-        r[1] += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+        const double cone = (q[0][0] * nx + q[0][1] * ny + q[0][2] * nz) * (1.0 / 6.0);
+        r[0] += cone;
+        for (int cc = 0; cc < 3; ++cc) r[2 + cc] += cone * (q[0][cc] + q[1][cc] + q[2][cc]) * 0.25;
+        const double n2 = nx * nx + ny * ny + nz * nz;
+        r[1] += n2 > 0.0 ? 0.5 * sqrt_refined(n2) : 0.0;
       }
     }
     __syncthreads();

@@ -513,21 +513,28 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
       __syncthreads();
     }
   }
-  // interior -> grid (final unless a neighbour's halo adds to it), halo shell -> scratch
+  // interior -> grid (final unless a neighbour's halo adds to it), halo shell -> scratch; one region
+  // row (fixed iy, iz) per wavefront at a time, so no per-cell division
   const double inv = ldexp(1.0, -sc);
-  for (int r = tid; r < nreg; r += nt) {
-    const int ix = r % rx, iy = (r / rx) % ry, iz = r / (rx * ry);
-    const bool interior = ix >= 1 && ix <= ex[0] && iy >= 1 && iy <= ex[1] && iz >= 1 && iz <= ex[2];
-    T v = T(0);
-    if (active) {
-      double w = (double)(long long)acc[r];
-      if (NW == 2) w += (double)(long long)acc[nreg + r] * 0x1p-40;
-      v = (T)(w * inv);
+  for (int row = wave; row < ry * rz; row += nwaves) {
+    const int iy = row % ry, iz = row / ry;
+    const bool row_inside = iy >= 1 && iy <= ex[1] && iz >= 1 && iz <= ex[2];
+    // grid offset of the row's first interior cell (only formed for rows inside the tile)
+    const uint32_t rowbase =
+        row_inside ? (uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0]) : 0u;
+    for (int ix = lane; ix < rx; ix += kWave) {
+      const int r = row * rx + ix;
+      T v = T(0);
+      if (active) {
+        double w = (double)(long long)acc[r];
+        if (NW == 2) w += (double)(long long)acc[nreg + r] * 0x1p-40;
+        v = (T)(w * inv);
+      }
+      if (row_inside && ix >= 1 && ix <= ex[0])
+        g[rowbase + (uint32_t)(ix - 1)] = v;
+      else if (active)
+        halo[r] = v;
     }
-    if (interior)
-      g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix - 1)] = v;
-    else if (active)
-      halo[r] = v;
   }
   if (tid == 0) a.tile_flag[L] = active ? 1 : 0;
 }
@@ -565,12 +572,32 @@ __global__ void __launch_bounds__(256) k_spread_merge(const TransferArgs a, T* _
   if (!any) return;
   const int c0[3] = {t[0] * a.tile[0], t[1] * a.tile[1], t[2] * a.tile[2]};
   const int ex[3] = {nbex[13][0], nbex[13][1], nbex[13][2]};
-  const int ncell = ex[0] * ex[1] * ex[2];
   T* g = grid + d * a.total_cells + B.cell_off;
   const T* halo = reinterpret_cast<const T*>(a.halo);
-  for (int li = tid; li < ncell; li += blockDim.x) {
-    const int i[3] = {li % ex[0], (li / ex[0]) % ex[1], li / (ex[0] * ex[1])};
-    if (i[0] > 0 && i[0] < ex[0] - 1 && i[1] > 0 && i[1] < ex[1] - 1 && i[2] > 0 && i[2] < ex[2] - 1) continue;
+  // border cells only: the two z faces, then the two y faces without z-face cells, then the two x
+  // faces without y/z-face cells (each border cell exactly once, rows along x stay coalesced)
+  const int inz = max(ex[2] - 2, 0), iny = max(ex[1] - 2, 0);
+  const int zf = ex[2] > 1 ? 2 : 1, yf = ex[1] > 1 ? 2 : 1, xf = ex[0] > 1 ? 2 : 1;
+  const int nzc = zf * ex[0] * ex[1], nyc = yf * ex[0] * inz, nxc = xf * iny * inz;
+  const int total = nzc + nyc + nxc;
+  for (int bi = tid; bi < total; bi += blockDim.x) {
+    int i[3];
+    if (bi < nzc) {
+      const int f = bi / (ex[0] * ex[1]), r = bi - f * ex[0] * ex[1];
+      i[0] = r % ex[0];
+      i[1] = r / ex[0];
+      i[2] = f ? ex[2] - 1 : 0;
+    } else if (bi < nzc + nyc) {
+      const int b = bi - nzc, f = b / (ex[0] * inz), r = b - f * ex[0] * inz;
+      i[0] = r % ex[0];
+      i[1] = f ? ex[1] - 1 : 0;
+      i[2] = 1 + r / ex[0];
+    } else {
+      const int b = bi - nzc - nyc, f = b / (iny * inz), r = b - f * iny * inz;
+      i[0] = f ? ex[0] - 1 : 0;
+      i[1] = 1 + r % iny;
+      i[2] = 1 + r / iny;
+    }
     const uint32_t cell = (uint32_t)(((c0[2] + i[2]) * B.n[1] + (c0[1] + i[1])) * B.n[0] + c0[0] + i[0]);
     T v = g[cell];
     for (int oz = -1; oz <= 1; ++oz) {
