@@ -62,8 +62,9 @@
  *              I2 <= 0); such an element contributes zero force;
  *   counts[1]  non-finite nodal force components written;
  *   counts[2]  points whose MLS moment matrix was singular (weights zero);
- *   counts[3]  spreads whose tile work lists overflowed the plan's
- *              workspace (that grid is incomplete); 0 in normal use.
+ *   counts[3]  nodes a tiled spread skipped because their nearest lattice
+ *              node moved between binning and accumulation (positions
+ *              written concurrently with the call); 0 in normal use.
  */
 #ifndef IFEM_H
 #define IFEM_H
@@ -107,10 +108,10 @@ enum { IFEM_OPT_SPREAD_MODE = 1, IFEM_OPT_KERNEL_TIMING = 2 };
 /* Kernel slots reported by ifem_plan_kernel_times. */
 enum {
   IFEM_KERNEL_FORCES = 0,        /* per-particle element, bending and reduction kernel */
-  IFEM_KERNEL_CHUNK_COUNT = 1,   /* spread: tiles reached by each 64-node chunk         */
-  IFEM_KERNEL_SCAN = 2,          /* spread: offsets of the tile work lists              */
-  IFEM_KERNEL_CHUNK_FILL = 3,    /* spread: fill of the tile work lists                 */
-  IFEM_KERNEL_SPREAD_TILE = 4,   /* spread: per-tile LDS accumulation and grid write    */
+  IFEM_KERNEL_BIN_COUNT = 1,     /* spread: home-tile list lengths (per node)           */
+  IFEM_KERNEL_SCAN = 2,          /* spread: offsets of the home-tile lists              */
+  IFEM_KERNEL_BIN_FILL = 3,      /* spread: fill of the home-tile lists                 */
+  IFEM_KERNEL_SPREAD_HOME = 4,   /* spread: per-tile LDS accumulation and grid write    */
   IFEM_KERNEL_SPREAD_MERGE = 8,  /* spread: neighbour halos added to tile border cells  */
   IFEM_KERNEL_SPREAD_ATOMIC = 5, /* spread: plain global-atomic baseline                */
   IFEM_KERNEL_INTERP = 6,        /* interpolation                                       */
@@ -185,7 +186,12 @@ ifem_status ifem_element_forces(ifem_plan plan, int32_t dtype, const void* x, co
                                 double* red_out, void* stream);
 
 /* Step 2 (Sec. III.A): spread nodal forces F [3][n_nodes] to grid [3][total_cells].
- * The grid holds forces (its sum equals the Lagrangian total), not densities. */
+ * The grid holds forces (its sum equals the Lagrangian total), not densities.
+ * IFEM_SPREAD_TILED (default) sums in 64-bit fixed point per lattice tile:
+ * bitwise reproducible, no global float atomics.  A non-finite force
+ * component cannot be held in fixed point: it turns its whole home tile of
+ * that component, plus the tile's one-cell halo, into NaN (the plain
+ * IFEM_SPREAD_ATOMIC mode spreads it to the 27 stencil cells only). */
 ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F,
                         void* grid, void* stream);
 

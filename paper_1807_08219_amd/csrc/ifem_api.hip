@@ -361,9 +361,9 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   DeviceBuffers& mem = plan->mem;
   int32_t *d_ns, *d_law, *d_box, *d_tri_src, *d_tri_glob, *d_tri_local, *d_tri_pcol, *d_tri_colb;
   int32_t *d_tet_src, *d_tet_glob, *d_tet_local, *d_tet_pcol, *d_tet_colb, *d_rstart = nullptr, *d_ring = nullptr;
-  int32_t *d_np, *d_tile_box, *d_cnt, *d_off, *d_cur, *d_list, *d_ch0, *d_chlen, *d_chp, *d_chrange, *d_flag;
+  int32_t *d_np, *d_tile_box, *d_cnt, *d_off, *d_cur, *d_list, *d_flag;
   double* d_halo;
-  double *d_mu, *d_mu2, *d_kb, *d_c0, *d_tri_ref, *d_tet_ref, *d_X, *d_chmax;
+  double *d_mu, *d_mu2, *d_kb, *d_c0, *d_tri_ref, *d_tet_ref, *d_X;
   BoxDev* d_boxes;
   unsigned long long* d_status;
   const int np = m.n_particles;
@@ -397,31 +397,16 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_tri_ref, (size_t)4 * m.n_tris));
   HIP_TRY(mem.alloc(&d_tet_ref, (size_t)7 * m.n_tets));
   HIP_TRY(mem.alloc(&d_status, 4));
-  // 64-node chunks of every particle (one wavefront each) for spread binning
-  std::vector<int32_t> ch0, chlen, chp;
-  for (int p = 0; p < np; ++p)
-    for (int k = m.node_start[p]; k < m.node_start[p + 1]; k += 64) {
-      ch0.push_back(k);
-      chlen.push_back(std::min(64, m.node_start[p + 1] - k));
-      chp.push_back(p);
-    }
-  const int n_chunks = (int)ch0.size();
-  HIP_TRY(upload(mem, &d_ch0, ch0.data(), ch0.size(), st));
-  HIP_TRY(upload(mem, &d_chlen, chlen.data(), chlen.size(), st));
-  HIP_TRY(upload(mem, &d_chp, chp.data(), chp.size(), st));
-  HIP_TRY(mem.alloc(&d_chmax, (size_t)3 * n_chunks));
-  HIP_TRY(mem.alloc(&d_chrange, (size_t)18 * n_chunks));
   const int n_tiles = (int)tile_box.size();
-  const int64_t pair_cap = (int64_t)64 * 3 * std::max(n_chunks, 1);
+  const int64_t list_cap = (int64_t)3 * m.n_nodes;
   HIP_TRY(mem.alloc(&d_cnt, (size_t)3 * n_tiles));
   HIP_TRY(mem.alloc(&d_off, (size_t)3 * n_tiles + 1));
   HIP_TRY(mem.alloc(&d_cur, (size_t)3 * n_tiles));
-  HIP_TRY(mem.alloc(&d_list, (size_t)pair_cap));
+  HIP_TRY(mem.alloc(&d_list, (size_t)std::max<int64_t>(list_cap, 1)));
   const int region_cells = (tn.tile[0] + 2) * (tn.tile[1] + 2) * (tn.tile[2] + 2);
   HIP_TRY(mem.alloc(&d_flag, (size_t)3 * n_tiles));
   HIP_TRY(mem.alloc(&d_halo, (size_t)3 * n_tiles * region_cells));  // sized for float64
-  plan->workspace_bytes = (int64_t)(12 * (int64_t)n_tiles + 1 + pair_cap) * 4 + (int64_t)n_chunks * (24 + 72) +
-                          (int64_t)3 * n_tiles * region_cells * 8;
+  plan->workspace_bytes = (int64_t)(12 * (int64_t)n_tiles + 1 + list_cap) * 4 + (int64_t)3 * n_tiles * region_cells * 8;
 
   P.tri_src = d_tri_src;
   P.tri_global = d_tri_glob;
@@ -460,18 +445,12 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ta.tile_count = d_cnt;
   ta.tile_off = d_off;
   ta.tile_cursor = d_cur;
-  ta.pair_list = d_list;
+  ta.bin_list = d_list;
   ta.tile_flag = d_flag;
   ta.halo = d_halo;
   ta.region_cells = region_cells;
-  ta.chunk_node0 = d_ch0;
-  ta.chunk_len = d_chlen;
-  ta.chunk_particle = d_chp;
-  ta.chunk_maxF = d_chmax;
-  ta.chunk_range = d_chrange;
-  ta.n_chunks = n_chunks;
   ta.status = d_status;
-  ta.pair_cap = pair_cap;
+  ta.list_cap = list_cap;
   ta.total_cells = total_cells;
   ta.n_nodes = m.n_nodes;
   ta.n_boxes = n_boxes;

@@ -117,7 +117,12 @@ __device__ __forceinline__ bool tri_element(const T xs[3][3], const double G[3],
   const T M21 = Gi12 * D[0] + Gi22 * D[1], M22 = Gi12 * D[1] + Gi22 * D[2];
   const T trM = M11 + M22, detM = M11 * M22 - M12 * M21;
   const T I2b = trM + detM;  // J^2 - 1
-  bool ok = (T(1) + I2b) > T(0);
+  // J^2 = |e1 x e2|^2 / |E1 x E2|^2: a current triangle with coincident or collinear edges has J^2 = 0
+  // exactly, which 1 + (tr M + det M) only approximates; test the cross product itself as well
+  const T cx = dh[0][1] * dh[1][2] - dh[0][2] * dh[1][1];
+  const T cy = dh[0][2] * dh[1][0] - dh[0][0] * dh[1][2];
+  const T cz = dh[0][0] * dh[1][1] - dh[0][1] * dh[1][0];
+  bool ok = (T(1) + I2b) > T(0) && (cx != T(0) || cy != T(0) || cz != T(0));
   T SG11, SG12, SG21, SG22;
   if (law == 1) {  // Skalak
     const T k = T(0.5) * mu2 * I2b;

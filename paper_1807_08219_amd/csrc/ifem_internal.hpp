@@ -38,21 +38,16 @@ struct TransferArgs {
   const int32_t* particle_box;    // [n_p]
   const BoxDev* boxes;            // [n_boxes]
   const int32_t* tile_box;        // [n_tiles]
-  const int32_t* chunk_node0;     // [n_chunks] first node of each 64-node chunk
-  const int32_t* chunk_len;       // [n_chunks] nodes in the chunk (1..64)
-  const int32_t* chunk_particle;  // [n_chunks]
-  double* chunk_maxF;             // [n_chunks][3] largest |F| per component (count pass)
-  int32_t* chunk_range;           // [n_chunks][3][6] first tile and tile count per axis (count pass)
-  int32_t* tile_count;            // [3 n_tiles] chunks per (component, tile)
+  int32_t* tile_count;            // [3 n_tiles] nodes whose nearest lattice node is in the tile, per component
   int32_t* tile_off;              // [3 n_tiles + 1]
   int32_t* tile_cursor;           // [3 n_tiles]
-  int32_t* pair_list;             // [pair_cap] chunk ids, grouped by (component, tile)
+  int32_t* bin_list;              // [list_cap = 3 n_nodes] node ids, grouped by (component, tile)
   int32_t* tile_flag;             // [3 n_tiles] 1 if the tile wrote a halo shell this call
   void* halo;                     // [3 n_tiles][region_cells] halo-shell values (float or double)
   unsigned long long* status;
-  int64_t pair_cap;
+  int64_t list_cap;
   int64_t total_cells;
-  int32_t n_nodes, n_boxes, n_tiles, n_chunks;
+  int32_t n_nodes, n_boxes, n_tiles;
   int32_t tile[3];        // cells per tile and axis (powers of two)
   int32_t tile_shift[3];  // log2 of tile
   int32_t region_cells;   // (tile_x + 2)(tile_y + 2)(tile_z + 2)
@@ -61,10 +56,10 @@ struct TransferArgs {
 // Kernel slots of the per-kernel event timer.
 enum KernelSlot {
   K_FORCES = 0,
-  K_CHUNK_COUNT = 1,
+  K_BIN_COUNT = 1,
   K_SCAN = 2,
-  K_CHUNK_FILL = 3,
-  K_SPREAD_TILE = 4,
+  K_BIN_FILL = 3,
+  K_SPREAD_HOME = 4,
   K_SPREAD_MERGE = 8,
   K_SPREAD_ATOMIC = 5,
   K_INTERP = 6,

@@ -8,20 +8,19 @@
 //  k_spread_atomic<T>   the plain baseline: one global atomic add per
 //                       (node, component, stencil node).
 //  tiled spread         deterministic and free of global float atomics:
-//    k_chunk_count      per (64-node chunk, component): the lattice tiles
-//                       holding the nearest nodes of its members, counted
-//                       once per tile;
+//    k_bin_count<T>     per (node, component): counts the node in the list
+//                       of the tile holding its nearest lattice node;
 //    k_scan             exclusive scan of the counts (single workgroup);
-//    k_chunk_fill       appends the chunk to those tiles' lists;
-//    k_spread_home<T>   one workgroup per (component, tile): filters the
-//                       nodes whose nearest node is in the tile into an LDS
-//                       queue and accumulates all their contributions in an
-//                       LDS region (tile + one-cell halo) as 64-bit
-//                       fixed-point integers (exact, order-independent sums;
-//                       float64 uses a two-word split); writes the interior
-//                       to the grid and the halo shell to scratch;
+//    k_bin_fill<T>      writes every node into its lists;
+//    k_spread_home<T>   one workgroup per (component, tile): accumulates all
+//                       contributions of the tile's list in an LDS region
+//                       (tile + one-cell halo) as 64-bit fixed-point
+//                       integers (exact, order-independent sums; float64
+//                       uses a two-word split); writes the interior to the
+//                       grid and the halo shell to scratch;
 //    k_spread_merge<T>  adds the neighbours' halo values to each tile's
 //                       border cells in a fixed order.
+#include <cfloat>
 #include <climits>
 
 #include "ifem_device.hpp"
@@ -170,144 +169,87 @@ __global__ void __launch_bounds__(256) k_spread_atomic(const TransferArgs a, con
   if (bad) atomicAdd(a.status + 2, (unsigned long long)bad);
 }
 
-// ------------------------------------------------------------------ tiled spread: chunk binning
-// Nodes are grouped in chunks of at most 64 consecutive nodes of one particle
-// (one wavefront).  For each (chunk, component) the lanes reduce the range of
-// nearest-node indices; the tiles overlapping that range grown by the
-// one-cell stencil reach receive the chunk id in their list.  Counting and
-// filling take one global atomic per (chunk, component, tile), not per node.
-__device__ __forceinline__ double wave_max_all(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-  return v;
+// ------------------------------------------------------------------ tiled spread: binning
+// Every (node, component) belongs to exactly one list: the tile holding its
+// nearest lattice node.  Count, scan and fill build the lists; the atomics
+// on the list counters are aggregated per wavefront (one per distinct list
+// among 64 consecutive nodes, which lie close together on one surface).
+// Home list of a node for one component: the (component, tile) that holds
+// its nearest lattice node.  The count and fill passes both call this, on the
+// same inputs, so they agree bit for bit.
+__device__ __forceinline__ int home_list(const TransferArgs& a, const BoxDev& B, int d, const double pos[3]) {
+  int32_t base[3];
+  double tau[3];
+  nearest_node(B, d, pos, base, tau);
+  const int tx = base[0] >> a.tile_shift[0], ty = base[1] >> a.tile_shift[1], tz = base[2] >> a.tile_shift[2];
+  return d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx;
 }
 
-// Tiles (first, count) along one axis holding the wrapped nearest-node indices lo .. hi.
-__device__ __forceinline__ void axis_tile_range(const BoxDev& B, int a, int T, int shift, int lo, int hi, int& t0,
-                                                int& cnt) {
-  const int n = B.n[a], nt = B.ntile[a];
-  const int lo_c = lo, hi_c = hi;
-  if (hi_c - lo_c + 1 > n - T) {  // the cell range leaves no full tile outside it: every tile
-    t0 = 0;
-    cnt = nt;
-    return;
-  }
-  const int w0 = wrap_index(B, a, (double)lo_c), w1 = wrap_index(B, a, (double)hi_c);
-  t0 = w0 >> shift;
-  cnt = (w1 >> shift) - t0;
-  if (cnt < 0) cnt += nt;
-  cnt += 1;
-}
-
-// Count pass: one wavefront per chunk.  Records, per (chunk, component), the
-// first tile and tile count along each axis and the largest |F|, and counts
-// the chunk once in every tile it reaches.  The nearest-node rule is
-// monotonic in the coordinate (subtract, fma and floor all preserve order),
-// so the extreme nearest nodes of the chunk come from its extreme
-// coordinates: one min/max reduction per axis serves all three components.
-template <typename T>
-__device__ __forceinline__ T wave_min_t(T v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
-  return v;
-}
-template <typename T>
-__device__ __forceinline__ T wave_max_t(T v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-  return v;
-}
-
-__device__ __forceinline__ int clamp_index(double f) { return (int)fmin(fmax(f, -1073741824.0), 1073741824.0); }
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_chunk_count(const TransferArgs a, const T* __restrict__ x,
-                                                     const double* __restrict__ anchor, const T* __restrict__ F) {
+// Adds one entry per active lane (key >= 0) to counter[key] with one atomic
+// per distinct key in the wavefront; returns each lane's slot (the counter's
+// old value plus the lane's rank among the lanes with its key).  Every lane
+// of the wavefront must call it.
+__device__ __forceinline__ int wave_append(int32_t* __restrict__ counter, int key) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int c = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  if (c >= a.n_chunks) return;  // whole wavefronts leave together
-  const int p = a.chunk_particle[c], k0 = a.chunk_node0[c], len = a.chunk_len[c];
-  const BoxDev B = a.boxes[a.particle_box[p]];
-  const bool valid = lane < len;
-  const int k = k0 + (valid ? lane : 0);  // invalid lanes repeat node k0: neutral for min and max
-  const int64_t N = a.n_nodes;
-  double lo_p[3], hi_p[3];
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    const T v = x[ax * N + k];
-    const T vmin = wave_min_t(v), vmax = wave_max_t(v);
-    const double base = sizeof(T) == 4 ? anchor[3 * p + ax] : 0.0;
-    lo_p[ax] = sizeof(T) == 4 ? base + (double)vmin : (double)vmin;
-    hi_p[ax] = sizeof(T) == 4 ? base + (double)vmax : (double)vmax;
+  unsigned long long todo = __ballot(key >= 0);
+  int slot = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int kl = __builtin_amdgcn_readlane(key, leader);
+    const unsigned long long m = __ballot(key == kl) & todo;
+    int b = 0;
+    if (lane == leader) b = atomicAdd(counter + kl, (int)__popcll(m));
+    b = __builtin_amdgcn_readlane(b, leader);
+    if (key == kl) slot = b + (int)__popcll(m & ((1ull << lane) - 1ull));
+    todo &= ~m;
   }
-  T fm[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) fm[d] = wave_max_t(valid ? fabs(F[d * N + k]) : T(0));
-  for (int d = 0; d < 3; ++d) {
-    int t0[3], cn[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      double flo, fhi;
-      lattice_coord(B, d, ax, lo_p[ax], flo);
-      lattice_coord(B, d, ax, hi_p[ax], fhi);
-      axis_tile_range(B, ax, a.tile[ax], a.tile_shift[ax], clamp_index(flo), clamp_index(fhi), t0[ax], cn[ax]);
-    }
-    if (lane == 0) {
-      a.chunk_maxF[3 * c + d] = (double)fm[d];
-      int32_t* r = a.chunk_range + 6 * (3 * c + d);
-      r[0] = t0[0];
-      r[1] = t0[1];
-      r[2] = t0[2];
-      r[3] = cn[0];
-      r[4] = cn[1];
-      r[5] = cn[2];
-    }
-    const int total = cn[0] * cn[1] * cn[2];
-    if (lane < total) {
-      // lane -> (ix, iy, iz) by float division: exact for these small integers
-      const int cxy = cn[0] * cn[1];
-      const int iz = (int)(((float)lane + 0.5f) * frcp((float)cxy));
-      const int rxy = lane - iz * cxy;
-      const int iy = (int)(((float)rxy + 0.5f) * frcp((float)cn[0]));
-      const int ix = rxy - iy * cn[0];
-      int tx = t0[0] + ix, ty = t0[1] + iy, tz = t0[2] + iz;
-      if (tx >= B.ntile[0]) tx -= B.ntile[0];
-      if (ty >= B.ntile[1]) ty -= B.ntile[1];
-      if (tz >= B.ntile[2]) tz -= B.ntile[2];
-      atomicAdd(a.tile_count + d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx, 1);
-    }
-    for (int i = lane + kWave; i < total; i += kWave) {  // more than 64 tiles: very large chunks only
-      int tx = t0[0] + i % cn[0], ty = t0[1] + (i / cn[0]) % cn[1], tz = t0[2] + i / (cn[0] * cn[1]);
-      if (tx >= B.ntile[0]) tx -= B.ntile[0];
-      if (ty >= B.ntile[1]) ty -= B.ntile[1];
-      if (tz >= B.ntile[2]) tz -= B.ntile[2];
-      atomicAdd(a.tile_count + d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx, 1);
-    }
-  }
+  return slot;
 }
 
-// Fill pass: one thread per (chunk, component) appends the chunk to the
-// lists of the tiles recorded by the count pass.
-__global__ void __launch_bounds__(256) k_chunk_fill(const TransferArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * a.n_chunks) return;
-  const int c = i / 3, d = i - 3 * c;
-  const BoxDev& B = a.boxes[a.particle_box[a.chunk_particle[c]]];
-  const int32_t* r = a.chunk_range + 6 * i;
-  const int total = r[3] * r[4] * r[5];
-  for (int j = 0; j < total; ++j) {
-    int tx = r[0] + j % r[3], ty = r[1] + (j / r[3]) % r[4], tz = r[2] + j / (r[3] * r[4]);
-    if (tx >= B.ntile[0]) tx -= B.ntile[0];
-    if (ty >= B.ntile[1]) ty -= B.ntile[1];
-    if (tz >= B.ntile[2]) tz -= B.ntile[2];
-    const int L = d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx;
-    const int64_t slot = (int64_t)a.tile_off[L] + atomicAdd(a.tile_cursor + L, 1);
-    if (slot < a.pair_cap) a.pair_list[slot] = c;
+// Count pass: one thread per node; every (node, component) counts once in
+// its home list.
+template <typename T>
+__global__ void __launch_bounds__(256) k_bin_count(const TransferArgs a, const T* __restrict__ x,
+                                                   const double* __restrict__ anchor) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  int key[3] = {-1, -1, -1};
+  if (k < a.n_nodes) {
+    const int p = a.node_particle[k];
+    const BoxDev& B = a.boxes[a.particle_box[p]];
+    double pos[3];
+    node_position(a, x, anchor, k, p, pos);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) key[d] = home_list(a, B, d, pos);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) (void)wave_append(a.tile_count, key[d]);
+}
+
+// Fill pass: the same keys; each (node, component) takes a slot of its home
+// list from the cursor (initialised to the list's offset by the scan).
+template <typename T>
+__global__ void __launch_bounds__(256) k_bin_fill(const TransferArgs a, const T* __restrict__ x,
+                                                  const double* __restrict__ anchor) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  int key[3] = {-1, -1, -1};
+  if (k < a.n_nodes) {
+    const int p = a.node_particle[k];
+    const BoxDev& B = a.boxes[a.particle_box[p]];
+    double pos[3];
+    node_position(a, x, anchor, k, p, pos);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) key[d] = home_list(a, B, d, pos);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int slot = wave_append(a.tile_cursor, key[d]);
+    if (key[d] >= 0 && slot < a.list_cap) a.bin_list[slot] = k;
   }
 }
 
 // Exclusive scan of tile_count into tile_off (n + 1 entries) with one
-// workgroup; zeroes the cursors; flags a list that exceeds its capacity.
+// workgroup; starts every cursor at its list's offset; flags a total above
+// the list capacity (which holds exactly one entry per node and component).
 __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restrict__ cnt, int32_t* __restrict__ off,
                                                int32_t* __restrict__ cursor, int64_t cap,
                                                unsigned long long* status) {
@@ -328,8 +270,8 @@ __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restr
   int32_t run = part[tid] - s;
   for (int i = b; i < e; ++i) {
     off[i] = run;
+    cursor[i] = run;
     run += cnt[i];
-    cursor[i] = 0;
   }
   if (tid == nt - 1) {
     off[n] = part[nt - 1];
@@ -350,21 +292,9 @@ struct FixedAcc<double> {
 };
 
 constexpr int kTileThreads = 512;  // threads of a spread-tile workgroup (8 wavefronts)
-constexpr int kChunksPerWave = 2;  // chunks filtered per wavefront per round
 
-// LDS work queue of one spread tile: what the accumulation needs of a node,
-// gathered by the filter pass with chunk-coalesced global loads.
-template <typename T>
-struct TileQueue {
-  // one filter round adds at most (waves x kChunksPerWave x 64) entries to a carried remainder
-  static constexpr int kCap = (kTileThreads / kWave) * kChunksPerWave * kWave + kTileThreads;
-  T tau[3][kCap];
-  T f[kCap];
-  int32_t lb[kCap];  // nearest node relative to the tile start: x | y << 8 | z << 16
-};
-
-// Home-tile accumulation: workgroup (tile, component) takes every node whose
-// nearest lattice node lies in the tile and accumulates all 27 of its
+// Home-tile accumulation: workgroup (tile, component) takes the nodes of its
+// list (nearest lattice node in the tile) and accumulates all 27 of their
 // contributions into an LDS region covering the tile plus a one-cell halo
 // (64-bit fixed point: exact, order-independent sums).  The region interior
 // is written straight to the grid, the halo shell to scratch for the merge.
@@ -373,10 +303,8 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
                                                               const double* __restrict__ anchor,
                                                               const T* __restrict__ F, T* __restrict__ grid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ TileQueue<T> Q;
-  __shared__ int qn;
   __shared__ double wm[16];
-  __shared__ int wn[16];
+  __shared__ int wb[16];
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);
   constexpr int NW = FixedAcc<T>::kWords;
   const int tile = blockIdx.x, d = blockIdx.y;
@@ -390,153 +318,108 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   int ex[3];
   for (int i = 0; i < 3; ++i) ex[i] = min(a.tile[i], B.n[i] - c0[i]);
   const int rx = ex[0] + 2, ry = ex[1] + 2, rz = ex[2] + 2, nreg = rx * ry * rz;
-  const int64_t off = a.tile_off[L];
-  int cnt = a.tile_count[L];
-  if (off >= a.pair_cap) cnt = 0;
-  else if (off + cnt > a.pair_cap) cnt = (int)(a.pair_cap - off);
+  const int32_t* list = a.bin_list + a.tile_off[L];
+  const int cnt = a.tile_count[L];
   T* g = grid + d * a.total_cells + B.cell_off;
   T* halo = reinterpret_cast<T*>(a.halo) + (int64_t)L * a.region_cells;
   const int64_t NN = a.n_nodes;
+  const T* Fd = F + d * NN;
 
-  // fixed-point scale from the largest |F| and the number of candidate nodes
+  // fixed-point scale from the largest |F| of the list and its length; a non-finite force
+  // cannot be held in fixed point and poisons (NaN) the tile's whole region instead
   double m = 0.0;
-  int np = 0;
+  bool bad = false;
   for (int e = tid; e < cnt; e += nt) {
-    const int c = a.pair_list[off + e];
-    m = fmax(m, a.chunk_maxF[3 * c + d]);
-    np += a.chunk_len[c];
+    const double v = fabs((double)Fd[list[e]]);
+    bad |= !(v <= DBL_MAX);
+    m = fmax(m, v);
   }
   m = wave_max(m);
-  np = wave_sum(np);
+  const bool wbad = __ballot(bad) != 0ull;
   if (lane == 0) {
     wm[wave] = m;
-    wn[wave] = np;
+    wb[wave] = wbad ? 1 : 0;
   }
   for (int i = tid; i < NW * nreg; i += nt) acc[i] = 0ull;
   __syncthreads();
   m = 0.0;
-  np = 0;
+  bool poison = false;
   for (int w = 0; w < nwaves; ++w) {
     m = fmax(m, wm[w]);
-    np += wn[w];
+    poison |= wb[w] != 0;
   }
-  const bool active = cnt > 0 && m > 0.0 && isfinite(m);
+  const bool active = cnt > 0 && m > 0.0 && !poison;
   int sc = 0;
   if (active) {
-    // one contribution is at most 4 max|F| (sum of |phi| <= 4), a cell sum at most np times that:
+    // one contribution is at most 4 max|F| (sum of |phi| <= 4), a cell sum at most cnt times that:
     // keep every contribution below 2^50 and every sum below 2^62
     int e1, e2;
     frexp(4.0 * m, &e1);
-    frexp(4.0 * (double)np * m, &e2);
+    frexp(4.0 * (double)cnt * m, &e2);
     sc = min(50 - e1, 62 - e2);
     const double scale = ldexp(1.0, sc);
-    if (tid == 0) qn = 0;
-    __syncthreads();
-    for (int e0 = 0; e0 < cnt; e0 += nwaves * kChunksPerWave) {
-      // filter: queue the nodes whose nearest lattice node lies in this tile
-      for (int j = 0; j < kChunksPerWave; ++j) {
-        const int e = e0 + wave * kChunksPerWave + j;
-        if (e >= cnt) break;
-        const int c = a.pair_list[off + e];
-        const int len = a.chunk_len[c];
-        bool pass = false;
-        double tau[3];
-        int32_t base[3];
-        int k = 0;
-        if (lane < len) {
-          k = a.chunk_node0[c] + lane;
-          double pos[3];
-          node_position(a, x, anchor, k, a.chunk_particle[c], pos);
-          nearest_node(B, d, pos, base, tau);
-          pass = (unsigned)(base[0] - c0[0]) < (unsigned)ex[0] && (unsigned)(base[1] - c0[1]) < (unsigned)ex[1] &&
-                 (unsigned)(base[2] - c0[2]) < (unsigned)ex[2];
-        }
-        const unsigned long long mask = __ballot(pass);
-        int qb = 0;
-        if (lane == 0 && mask) qb = atomicAdd(&qn, (int)__popcll(mask));
-        qb = __shfl(qb, 0, kWave);
-        if (pass) {
-          const int q = qb + (int)__popcll(mask & ((1ull << lane) - 1ull));
-          Q.tau[0][q] = (T)tau[0];
-          Q.tau[1][q] = (T)tau[1];
-          Q.tau[2][q] = (T)tau[2];
-          Q.f[q] = F[d * NN + k];
-          Q.lb[q] = (base[0] - c0[0]) | ((base[1] - c0[1]) << 8) | ((base[2] - c0[2]) << 16);
-        }
+    for (int e = tid; e < cnt; e += nt) {
+      const int k = list[e];
+      double pos[3], tau64[3];
+      int32_t base[3];
+      node_position(a, x, anchor, k, a.node_particle[k], pos);
+      nearest_node(B, d, pos, base, tau64);
+      if ((unsigned)(base[0] - c0[0]) >= (unsigned)ex[0] || (unsigned)(base[1] - c0[1]) >= (unsigned)ex[1] ||
+          (unsigned)(base[2] - c0[2]) >= (unsigned)ex[2]) {
+        atomicAdd(a.status + 3, 1ull);  // positions changed since binning: the node is skipped, not misplaced
+        continue;
       }
-      __syncthreads();
-      // accumulate whole workgroup-size batches (everything in the last round); carry the rest
-      const int nq = qn;
-      const bool last = e0 + nwaves * kChunksPerWave >= cnt;
-      const int full = last ? nq : (nq / nt) * nt;
-      for (int qi = tid; qi < full; qi += nt) {
-        const T tau[3] = {Q.tau[0][qi], Q.tau[1][qi], Q.tau[2][qi]};
-        const int lb = Q.lb[qi];
-        T W[27], cf[4];
-        mls_weights<T>(tau, W, cf);
-        const double fs = (double)Q.f[qi] * scale;
-        // region cell of stencil node m: local base + m (the region starts one cell before the tile)
-        const int r0 = (((lb >> 16) & 0xff) * ry + ((lb >> 8) & 0xff)) * rx + (lb & 0xff);
+      const T tau[3] = {(T)tau64[0], (T)tau64[1], (T)tau64[2]};
+      T W[27], cf[4];
+      mls_weights<T>(tau, W, cf);
+      const double fs = (double)Fd[k] * scale;
+      // region cell of stencil node m: local base + m (the region starts one cell before the tile)
+      const int r0 = ((base[2] - c0[2]) * ry + (base[1] - c0[1])) * rx + (base[0] - c0[0]);
 #pragma unroll
-        for (int mz = 0; mz < 3; ++mz) {
-          const T vz = cf[0] + cf[3] * (T(mz - 1) - tau[2]);
+      for (int mz = 0; mz < 3; ++mz) {
+        const T vz = cf[0] + cf[3] * (T(mz - 1) - tau[2]);
 #pragma unroll
-          for (int my = 0; my < 3; ++my) {
-            const T vyz = vz + cf[2] * (T(my - 1) - tau[1]);
-            const int row = r0 + (mz * ry + my) * rx;
+        for (int my = 0; my < 3; ++my) {
+          const T vyz = vz + cf[2] * (T(my - 1) - tau[1]);
+          const int row = r0 + (mz * ry + my) * rx;
 #pragma unroll
-            for (int mx = 0; mx < 3; ++mx) {
-              const T phi = W[(mz * 3 + my) * 3 + mx] * (vyz + cf[1] * (T(mx - 1) - tau[0]));
-              const double q = (double)phi * fs;
-              const long long qh = round_to_i64(q);
-              atomicAdd(acc + row + mx, (unsigned long long)qh);
-              if (NW == 2) {
-                const long long ql = round_to_i64((q - (double)qh) * 0x1p40);
-                atomicAdd(acc + nreg + row + mx, (unsigned long long)ql);
-              }
+          for (int mx = 0; mx < 3; ++mx) {
+            const T phi = W[(mz * 3 + my) * 3 + mx] * (vyz + cf[1] * (T(mx - 1) - tau[0]));
+            const double q = (double)phi * fs;
+            const long long qh = round_to_i64(q);
+            atomicAdd(acc + row + mx, (unsigned long long)qh);
+            if (NW == 2) {
+              const long long ql = round_to_i64((q - (double)qh) * 0x1p40);
+              atomicAdd(acc + nreg + row + mx, (unsigned long long)ql);
             }
           }
         }
       }
-      __syncthreads();
-      const int rem = nq - full;  // < nt and, when positive, full >= nt: no overlap
-      if (tid < rem) {
-        const int src = full + tid;
-        Q.tau[0][tid] = Q.tau[0][src];
-        Q.tau[1][tid] = Q.tau[1][src];
-        Q.tau[2][tid] = Q.tau[2][src];
-        Q.f[tid] = Q.f[src];
-        Q.lb[tid] = Q.lb[src];
-      }
-      __syncthreads();
-      if (tid == 0) qn = rem;
-      __syncthreads();
     }
   }
-  // interior -> grid (final unless a neighbour's halo adds to it), halo shell -> scratch; one region
-  // row (fixed iy, iz) per wavefront at a time, so no per-cell division
+  __syncthreads();
+  // interior -> grid (final unless a neighbour's halo adds to it), halo shell -> scratch.  Region
+  // index r -> (ix, iy, iz) by float reciprocals: (r + 1/2) / d is at least 1/(2d) away from an
+  // integer, far above the rounding of these small quotients, so the truncation is exact.
   const double inv = ldexp(1.0, -sc);
-  for (int row = wave; row < ry * rz; row += nwaves) {
-    const int iy = row % ry, iz = row / ry;
-    const bool row_inside = iy >= 1 && iy <= ex[1] && iz >= 1 && iz <= ex[2];
-    // grid offset of the row's first interior cell (only formed for rows inside the tile)
-    const uint32_t rowbase =
-        row_inside ? (uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0]) : 0u;
-    for (int ix = lane; ix < rx; ix += kWave) {
-      const int r = row * rx + ix;
-      T v = T(0);
-      if (active) {
-        double w = (double)(long long)acc[r];
-        if (NW == 2) w += (double)(long long)acc[nreg + r] * 0x1p-40;
-        v = (T)(w * inv);
-      }
-      if (row_inside && ix >= 1 && ix <= ex[0])
-        g[rowbase + (uint32_t)(ix - 1)] = v;
-      else if (active)
-        halo[r] = v;
+  const float inv_rxy = frcp((float)(rx * ry)), inv_rx = frcp((float)rx);
+  for (int r = tid; r < nreg; r += nt) {
+    const int iz = (int)(((float)r + 0.5f) * inv_rxy);
+    const int rr = r - iz * rx * ry;
+    const int iy = (int)(((float)rr + 0.5f) * inv_rx);
+    const int ix = rr - iy * rx;
+    T v = poison ? (T)__builtin_nan("") : T(0);
+    if (active) {
+      double w = (double)(long long)acc[r];
+      if (NW == 2) w += (double)(long long)acc[nreg + r] * 0x1p-40;
+      v = (T)(w * inv);
     }
+    if (ix >= 1 && ix <= ex[0] && iy >= 1 && iy <= ex[1] && iz >= 1 && iz <= ex[2])
+      g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix - 1)] = v;
+    else if (active || poison)
+      halo[r] = v;
   }
-  if (tid == 0) a.tile_flag[L] = active ? 1 : 0;
+  if (tid == 0) a.tile_flag[L] = (active || poison) ? 1 : 0;
 }
 
 // Merge: every tile adds, to its border cells, the halo values that its 26
@@ -680,26 +563,29 @@ hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const
   hipError_t e = fill(a.tile_count, (int64_t)nl, 0, st);
   P.timer->end(st);
   if (e != hipSuccess) return e;
-  const dim3 cg((unsigned)((a.n_chunks + 3) / 4)), cb(256);
-  if (a.n_chunks) {
-    P.timer->begin(K_CHUNK_COUNT, st);
+  const dim3 ng = node_grid(a.n_nodes, 256), nb(256);
+  if (a.n_nodes) {
+    P.timer->begin(K_BIN_COUNT, st);
     if (dtype == 0)
-      hipLaunchKernelGGL(k_chunk_count<float>, cg, cb, 0, st, a, (const float*)x, anchor, (const float*)F);
+      hipLaunchKernelGGL(k_bin_count<float>, ng, nb, 0, st, a, (const float*)x, anchor);
     else
-      hipLaunchKernelGGL(k_chunk_count<double>, cg, cb, 0, st, a, (const double*)x, anchor, (const double*)F);
+      hipLaunchKernelGGL(k_bin_count<double>, ng, nb, 0, st, a, (const double*)x, anchor);
     P.timer->end(st);
   }
   P.timer->begin(K_SCAN, st);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nl, a.tile_count, a.tile_off, a.tile_cursor, a.pair_cap,
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nl, a.tile_count, a.tile_off, a.tile_cursor, a.list_cap,
                      a.status);
   P.timer->end(st);
-  if (a.n_chunks) {
-    P.timer->begin(K_CHUNK_FILL, st);
-    hipLaunchKernelGGL(k_chunk_fill, dim3((unsigned)((3 * a.n_chunks + 255) / 256)), dim3(256), 0, st, a);
+  if (a.n_nodes) {
+    P.timer->begin(K_BIN_FILL, st);
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_bin_fill<float>, ng, nb, 0, st, a, (const float*)x, anchor);
+    else
+      hipLaunchKernelGGL(k_bin_fill<double>, ng, nb, 0, st, a, (const double*)x, anchor);
     P.timer->end(st);
   }
   const dim3 g((unsigned)a.n_tiles, 3);
-  P.timer->begin(K_SPREAD_TILE, st);
+  P.timer->begin(K_SPREAD_HOME, st);
   if (dtype == 0)
     hipLaunchKernelGGL(k_spread_home<float>, g, dim3(kTileThreads), spread_tile_lds_bytes(P, 0), st, a,
                        (const float*)x, anchor, (const float*)F, (float*)grid);

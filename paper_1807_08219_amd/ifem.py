@@ -27,7 +27,7 @@ IFEM_SPREAD_TILED = 0
 IFEM_SPREAD_ATOMIC = 1
 IFEM_OPT_SPREAD_MODE = 1
 IFEM_OPT_KERNEL_TIMING = 2
-KERNEL_SLOTS = {0: "k_forces", 1: "k_chunk_count", 2: "k_scan", 3: "k_chunk_fill", 4: "k_spread_tile",
+KERNEL_SLOTS = {0: "k_forces", 1: "k_bin_count", 2: "k_scan", 3: "k_bin_fill", 4: "k_spread_home",
                 5: "k_spread_atomic", 6: "k_interp", 7: "k_fill", 8: "k_spread_merge"}
 
 EXPORTED = [

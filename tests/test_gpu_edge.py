@@ -1,0 +1,187 @@
+"""Edge cases through the C ABI: empty input, degenerate and inverted elements, lattice-node and seam points."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_08219_amd import ifem
+from paper_1807_08219_amd.inputs import meshes, scenes
+from paper_1807_08219_amd.inputs.scenes import Box, Particle, assemble
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def cu(a, dt):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / (nb if nb > 0 else 1.0))
+
+
+def test_empty_scene_gives_zero_grid():
+    say("[gpu] empty scene")
+    sc = assemble("empty", [Box((9, 8, 7), 0.5, (0.0, 0.0, 0.0))], [])
+    plan = ifem.Plan(sc)
+    x = torch.zeros((3, 0), dtype=torch.float64, device="cuda")
+    F = torch.zeros((3, 0), dtype=torch.float64, device="cuda")
+    G = torch.full((3, sc.total_cells), 7.0, dtype=torch.float64, device="cuda")
+    for mode in (ifem.IFEM_SPREAD_TILED, ifem.IFEM_SPREAD_ATOMIC):
+        plan.set(ifem.IFEM_OPT_SPREAD_MODE, mode)
+        G.fill_(7.0)
+        plan.spread(ifem.IFEM_F64, x, None, F, G)
+        torch.cuda.synchronize()
+        assert float(G.abs().max()) == 0.0
+    plan.element_forces(ifem.IFEM_F64, x, None, F, None)
+    plan.interp(ifem.IFEM_F64, x, None, G, F)
+    assert plan.status() == [0, 0, 0, 0]
+    plan.close()
+
+
+def _degenerate_scene():
+    """A capsule with one collapsed triangle and a solid with one inverted tetrahedron."""
+    rng = np.random.default_rng(3)
+    X, tris = meshes.icosphere(3)
+    x = X * 1.1 + [2.5, 2.5, 2.5]
+    t = tris[10]
+    x[t[1]] = x[t[0]]  # triangle 10 collapses (its other neighbours stay valid)
+    Xs, tets = meshes.ellipsoid_tets(2, 2, 2, (1.0, 0.9, 0.8))
+    xs = Xs.copy()
+    # reflect the last node of tetrahedron 0 through the plane of its other three: that tetrahedron inverts
+    a, b, c, d = (Xs[i] for i in tets[0])
+    nrm = np.cross(b - a, c - a)
+    nrm /= np.linalg.norm(nrm)
+    xs[tets[0][3]] = d - 2.0 * np.dot(d - a, nrm) * nrm
+    xs += [6.0, 2.5, 2.5]
+    box = Box((18, 10, 10), 0.5, (0.0, 0.0, 0.0))
+    parts = [Particle(X=X, x=x, tri=tris, law=scenes.LAW_TRI_NEOHOOKE, mu=1.0),
+             Particle(X=Xs, x=xs, tet=tets, law=scenes.LAW_TET_NEOHOOKE, mu=1.0, mu2=50.0)]
+    del rng
+    return assemble("degenerate", [box], parts)
+
+
+@pytest.mark.parametrize("dtype", [ifem.IFEM_F64, ifem.IFEM_F32])
+def test_degenerate_and_inverted_elements_are_counted_and_zeroed(dtype):
+    say(f"[gpu] degenerate/inverted elements dtype {dtype}")
+    sc = _degenerate_scene()
+    Fo, cnt = oracle.forces(sc)
+    assert cnt[0] >= 3  # the two triangles on the collapsed edge and at least one inverted tetrahedron
+    plan = ifem.Plan(sc)
+    if dtype == ifem.IFEM_F64:
+        x, a, tdt = cu(sc.x64, torch.float64), None, torch.float64
+    else:
+        x, a, tdt = cu(sc.x32, torch.float32), cu(sc.anchor, torch.float64), torch.float32
+    F = torch.empty((3, sc.n_nodes), dtype=tdt, device="cuda")
+    plan.element_forces(dtype, x, a, F, None)
+    st = plan.status()
+    assert st[0] == cnt[0] and st[1] == 0
+    e = rel(F.cpu().numpy(), Fo)
+    say(f"    forces rel err {e:.3e}")
+    assert e <= (1e-12 if dtype == ifem.IFEM_F64 else 2e-5)
+    plan.close()
+
+
+def test_nonfinite_position_is_flagged_not_fatal():
+    say("[gpu] non-finite position")
+    sc = scenes.small_capsule(kb=0.2, nu=3)
+    x = sc.x64.copy()
+    x[0, 5] = np.nan
+    plan = ifem.Plan(sc)
+    F = torch.empty((3, sc.n_nodes), dtype=torch.float64, device="cuda")
+    plan.element_forces(ifem.IFEM_F64, cu(x, torch.float64), None, F, None)
+    st = plan.status()
+    Fo, cnt = oracle.forces(sc, x=x)
+    assert st[0] == cnt[0] > 0  # the triangles around the node are rejected on both sides
+    assert st[1] > 0 and cnt[1] > 0  # bending spreads the NaN to the one-ring: reported, not hidden
+    finite = np.isfinite(Fo)
+    got = F.cpu().numpy()
+    assert np.array_equal(np.isfinite(got), finite)
+    assert rel(got[finite], Fo[finite]) <= 1e-12
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [ifem.IFEM_F64, ifem.IFEM_F32])
+def test_points_on_lattice_nodes_and_on_the_periodic_seam(dtype):
+    say(f"[gpu] lattice-node and seam points dtype {dtype}")
+    box = Box((12, 9, 10), 0.25, (0.0, 0.0, 0.0))
+    L = np.array(box.length)
+    pts = []
+    for comp in range(3):  # exactly on nodes of each staggered lattice
+        s = np.array([0.5, 0.5, 0.5])
+        s[comp] = 0.0
+        pts.append((np.array([3, 4, 5]) + s) * box.h)
+    eps = 2.0 ** -30
+    pts += [np.array([L[0] - eps, 1.0, 1.0]), np.array([0.0, L[1] - eps, 0.5]), np.array([eps, 0.3, L[2] - eps]),
+            np.array([L[0] - box.h / 2, L[1] - box.h / 2, L[2] - box.h / 2]), np.array([0.0, 0.0, 0.0])]
+    pts = np.array(pts)
+    sc = assemble("pts", [box], [Particle(X=pts.copy(), x=pts.copy())])
+    sc.x64 = pts.T.copy()
+    sc.anchor = np.zeros((1, 3))
+    sc.x32 = pts.T.astype(np.float32)
+    if dtype == ifem.IFEM_F32:
+        sc.x64 = sc.x32.astype(np.float64)
+    rng = np.random.default_rng(2)
+    Fin = rng.normal(size=(3, sc.n_nodes))
+    u = rng.normal(size=(3, sc.total_cells))
+    if dtype == ifem.IFEM_F32:
+        Fin = Fin.astype(np.float32).astype(np.float64)
+        u = u.astype(np.float32).astype(np.float64)
+    plan = ifem.Plan(sc)
+    tdt = torch.float64 if dtype == ifem.IFEM_F64 else torch.float32
+    if dtype == ifem.IFEM_F64:
+        x, a = cu(sc.x64, torch.float64), None
+    else:
+        x, a = cu(sc.x32, torch.float32), cu(sc.anchor, torch.float64)
+    tol = 1e-12 if dtype == ifem.IFEM_F64 else 1e-5
+    Go = oracle.spread(sc, Fin)
+    vo = oracle.interp(sc, u)
+    for mode in (ifem.IFEM_SPREAD_TILED, ifem.IFEM_SPREAD_ATOMIC):
+        plan.set(ifem.IFEM_OPT_SPREAD_MODE, mode)
+        G = torch.empty((3, sc.total_cells), dtype=tdt, device="cuda")
+        plan.spread(dtype, x, a, cu(Fin, tdt), G)
+        torch.cuda.synchronize()
+        assert rel(G.cpu().numpy(), Go) <= tol
+    v = torch.empty((3, sc.n_nodes), dtype=tdt, device="cuda")
+    plan.interp(dtype, x, a, cu(u, tdt), v)
+    assert rel(v.cpu().numpy(), vo) <= tol
+    assert plan.status() == [0, 0, 0, 0]
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [ifem.IFEM_F64, ifem.IFEM_F32])
+def test_nonfinite_force_poisons_its_home_tile_only(dtype):
+    say(f"[gpu] non-finite force in spread dtype {dtype}")
+    sc = scenes.small_mixed()
+    rng = np.random.default_rng(5)
+    Fin = rng.normal(size=(3, sc.n_nodes))
+    k = sc.n_nodes // 3
+    Fin[1, k] = np.nan
+    Go = oracle.spread(sc, Fin)
+    plan = ifem.Plan(sc)
+    tdt = torch.float64 if dtype == ifem.IFEM_F64 else torch.float32
+    if dtype == ifem.IFEM_F64:
+        x, a = cu(sc.x64, torch.float64), None
+    else:
+        x, a = cu(sc.x32, torch.float32), cu(sc.anchor, torch.float64)
+        Fin = Fin.astype(np.float32).astype(np.float64)
+        Go = oracle.spread(sc, Fin)  # x64 is anchor + x32 exactly
+    G = torch.empty((3, sc.total_cells), dtype=tdt, device="cuda")
+    plan.spread(dtype, x, a, cu(Fin, tdt), G)
+    got = G.cpu().numpy().astype(np.float64)
+    nan_o, nan_g = np.isnan(Go), np.isnan(got)
+    assert nan_o.any() and not nan_o[[0, 2]].any()
+    assert not (nan_o & ~nan_g).any()  # every NaN of the definition is NaN here
+    assert not nan_g[[0, 2]].any()  # the other components are untouched
+    # the poisoned cells stay within one tile plus its halo (at most (16 + 2)^3 cells)
+    assert nan_g[1].sum() <= 18 ** 3
+    fin = ~nan_g
+    assert rel(got[fin], Go[fin]) <= (1e-12 if dtype == ifem.IFEM_F64 else 1e-5)
+    plan.close()
