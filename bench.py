@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--tile", type=str, default=None, help="spread tile, e.g. 32,16,8 (powers of two)")
+    ap.add_argument("--block-forces", type=int, default=None, help="threads per particle workgroup")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is a design "
@@ -142,7 +144,11 @@ def main():
     log(f"scene {sc.name}: {sc.n_particles} particles, {sc.n_nodes} nodes, {sc.n_tris} tris, {sc.n_tets} tets, "
         f"{sc.total_cells} cells ({time.time() - t0:.1f} s)")
     t0 = time.time()
-    plan = ifem.Plan(sc)
+    tuning = None
+    if args.tile is not None or args.block_forces is not None:
+        tuning = {"tile": [int(v) for v in args.tile.split(",")] if args.tile else [64, 8, 8],
+                  "block_forces": args.block_forces or 512}
+    plan = ifem.Plan(sc, tuning=tuning)
     log(f"plan created ({time.time() - t0:.1f} s), info {plan.info()}")
     u64 = fields.scene_velocity(sc, device=dev, dtype=torch.float64, shear_rate=1.0 if args.config == 3 else 0.0)
     u32 = u64.to(torch.float32)
@@ -234,21 +240,21 @@ def main():
         F64 = torch.empty((3, sc.n_nodes), dtype=torch.float64, device=dev)
         G64 = torch.empty((3, sc.total_cells), dtype=torch.float64, device=dev)
         v64 = torch.empty((3, sc.n_nodes), dtype=torch.float64, device=dev)
-        plan.set(ifem.IFEM_OPT_SPREAD_MODE, ifem.IFEM_SPREAD_ATOMIC)
         ph64 = [lambda: plan.element_forces(ifem.IFEM_F64, x64, None, F64, red),
                 lambda: plan.spread(ifem.IFEM_F64, x64, None, F64, G64),
                 lambda: plan.interp(ifem.IFEM_F64, x64, None, u64, v64)]
-        for _ in range(1):
+        for mode, key, label in ((ifem.IFEM_SPREAD_TILED, "fp64", "tiled fixed-point spread"),
+                                 (ifem.IFEM_SPREAD_ATOMIC, "fp64_plain", "global atomics")):
+            plan.set(ifem.IFEM_OPT_SPREAD_MODE, mode)
             for f in ph64:
                 f()
-        torch.cuda.synchronize()
-        wall64, per64 = timed(None, args.fp64_steps, ph64)
-        ms64 = wall64 * 1e3 / args.fp64_steps
-        log(f"fp64 plain: {ms64:.3f} ms/step, phases {per64.mean(axis=0).round(4).tolist()} ms")
-        out["fp64_plain"] = {"value": round(sc.n_nodes / (ms64 * 1e-3), 1), "unit": "nodes/s",
-                             "ms_per_step": round(ms64, 4), "steps": args.fp64_steps,
-                             "phases_ms": per64.mean(axis=0).round(4).tolist(), "spread": "global atomics"}
-        out["speedup_fp32_vs_fp64_plain"] = round(ms64 / ms_step, 3)
+            torch.cuda.synchronize()
+            wall64, per64 = timed(None, args.fp64_steps, ph64)
+            ms64 = wall64 * 1e3 / args.fp64_steps
+            log(f"{key} ({label}): {ms64:.3f} ms/step, phases {per64.mean(axis=0).round(4).tolist()} ms")
+            out[key] = {"value": round(sc.n_nodes / (ms64 * 1e-3), 1), "unit": "nodes/s", "ms_per_step": round(ms64, 4),
+                        "steps": args.fp64_steps, "phases_ms": per64.mean(axis=0).round(4).tolist(), "spread": label}
+            out["speedup_fp32_vs_" + key] = round(ms64 / ms_step, 3)
         plan.set(ifem.IFEM_OPT_SPREAD_MODE, ifem.IFEM_SPREAD_TILED)
         del F64, G64, v64, x64
 

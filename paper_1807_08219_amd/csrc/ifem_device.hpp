@@ -84,16 +84,16 @@ __device__ __forceinline__ double sqrt_refined(double x) {
 // units (h = 1).  tau = t - base is the point's offset from its nearest node
 // (each component in [-1/2, 1/2]); stencil node m in {-1,0,1}^3 sits at
 // xi_m = m - tau from the point.  W_m = W(|xi_m| / sqrt 3) with the cubic
-// spline W(r) = 2/3 - 4 r^2 + 4 r^3 (r <= 1/2), 4/3 (1 - r)^3 (1/2 < r <= 1),
-// evaluated from R^2 = |xi|^2 as 2/3 + R^2 (-4/3 + 4/(3 sqrt 3) R) when
-// R^2 <= 3/4 and 4/3 max(1 - R/sqrt 3, 0)^3 otherwise.
+// spline W(r) = 2/3 - 4 r^2 + 4 r^3 (r <= 1/2), 4/3 (1 - r)^3 (1/2 < r <= 1).
 // The weighted normal equations A c = e_1, A = sum_m W_m p_m p_m^T,
 // p_m = (1, xi_m), give phi_m = W_m (c0 + c1 xi_mx + c2 xi_my + c3 xi_mz).
-// Output: W[27] (m_x fastest), c[4]; returns false if A is singular.
+// phi does not change when every W_m is scaled by one factor (c scales by its
+// inverse), so the weights are taken as 3/4 W: with R = |xi| and
+// s0 = 1 - R / sqrt 3, that is 1/2 - R^2 s0 (R^2 <= 3/4) and max(s0, 0)^3.
+// Output: the scaled W[27] (m_x fastest), c[4]; returns false if A is singular.
 template <typename T>
 __device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
   const T kInvSqrt3 = T(0.57735026918962576451);
-  const T kC3 = T(0.76980035891950101935);  // 4 / (3 sqrt 3)
   T ax[3], ay[3], az[3], qx[3], qy[3], qz[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -104,38 +104,54 @@ __device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
     qy[i] = ay[i] * ay[i];
     qz[i] = az[i] * az[i];
   }
-  // moments of the weights, accumulated along x first then y, z
+  // moments of the weights: along x within a row, rows into a plane, planes into the total
   T S0 = 0, Sx = 0, Sy = 0, Sz = 0, Sxx = 0, Syy = 0, Szz = 0, Sxy = 0, Sxz = 0, Syz = 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
+    T P0 = 0, Px = 0, Py = 0, Pxx = 0, Pyy = 0, Pxy = 0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const T qyz = qy[j] + qz[k];
       T w0 = 0, w1 = 0, w2 = 0;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
+        // |tau| <= 1/2 bounds q by the number of off-centre offsets: the centre node always takes the
+        // inner piece (q <= 3/4), a corner the outer one (q >= 3/4), and only nodes with two or three
+        // off-centre offsets can leave the support (q > 3); these are compile-time facts after unrolling
+        const int noff = (i != 1) + (j != 1) + (k != 1);
         const T q = qx[i] + qyz;
-        const T R = fsqrt(q);
-        const T s = fmax(T(1) - R * kInvSqrt3, T(0));
-        const T outer = (s * s) * (s * T(4.0 / 3.0));
-        const T inner = q * (R * kC3 - T(4.0 / 3.0)) + T(2.0 / 3.0);
-        const T w = q <= T(0.75) ? inner : outer;
+        const T s0 = T(1) - fsqrt(q) * kInvSqrt3;
+        const T inner = T(0.5) - q * s0;
+        T w;
+        if (noff == 0) {
+          w = inner;
+        } else {
+          const T sc = noff >= 2 ? fmax(s0, T(0)) : s0;
+          const T outer = (sc * sc) * sc;
+          w = noff == 3 ? outer : (q <= T(0.75) ? inner : outer);
+        }
         W[(k * 3 + j) * 3 + i] = w;
         w0 += w;
         w1 += w * ax[i];
         w2 += w * qx[i];
       }
-      S0 += w0;
-      Sx += w1;
-      Sxx += w2;
-      Sy += w0 * ay[j];
-      Syy += w0 * qy[j];
-      Sz += w0 * az[k];
-      Szz += w0 * qz[k];
-      Sxy += w1 * ay[j];
-      Sxz += w1 * az[k];
-      Syz += w0 * ay[j] * az[k];
+      P0 += w0;
+      Px += w1;
+      Pxx += w2;
+      Py += w0 * ay[j];
+      Pyy += w0 * qy[j];
+      Pxy += w1 * ay[j];
     }
+    S0 += P0;
+    Sx += Px;
+    Sxx += Pxx;
+    Sy += Py;
+    Syy += Pyy;
+    Sxy += Pxy;
+    Sz += P0 * az[k];
+    Szz += P0 * qz[k];
+    Sxz += Px * az[k];
+    Syz += Py * az[k];
   }
   // Schur complement on the 3x3 second-moment block Q: y = Q^-1 s,
   // c0 = 1 / (S0 - s.y), (c1, c2, c3) = -c0 y.

@@ -357,7 +357,7 @@ __device__ __forceinline__ void block_sum(double v[NV], double* lds /*[NV][16]*/
 // every element and one-ring read hits LDS; otherwise they are read through
 // the caches (particles too large for the staging copy).
 template <typename T, bool POS_LDS>
-__global__ void __launch_bounds__(256) k_forces(const ForceArgs a, const T* __restrict__ x,
+__global__ void __launch_bounds__(512) k_forces(const ForceArgs a, const T* __restrict__ x,
                                                  const double* __restrict__ anchor, T* __restrict__ fout,
                                                  double* __restrict__ red) {
   extern __shared__ __align__(16) unsigned char smem_raw[];

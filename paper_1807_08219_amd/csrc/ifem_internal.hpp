@@ -38,19 +38,19 @@ struct TransferArgs {
   const int32_t* particle_box;    // [n_p]
   const BoxDev* boxes;            // [n_boxes]
   const int32_t* tile_box;        // [n_tiles]
-  int32_t* tile_count;            // [3 n_tiles] nodes whose nearest lattice node is in the tile, per component
+  int32_t* tile_count;            // [3 n_tiles] list lengths: nodes whose stencil the tile takes, per component
   int32_t* tile_off;              // [3 n_tiles + 1]
   int32_t* tile_cursor;           // [3 n_tiles]
-  int32_t* bin_list;              // [list_cap = 3 n_nodes] node ids, grouped by (component, tile)
+  int32_t* bin_list;              // [list_cap] node ids, grouped by (component, tile)
   int32_t* tile_flag;             // [3 n_tiles] 1 if the tile wrote a halo shell this call
-  void* halo;                     // [3 n_tiles][region_cells] halo-shell values (float or double)
+  void* halo;                     // [3 n_tiles][region_cells] y/z halo rows (float or double)
   unsigned long long* status;
   int64_t list_cap;
   int64_t total_cells;
   int32_t n_nodes, n_boxes, n_tiles;
   int32_t tile[3];        // cells per tile and axis (powers of two)
   int32_t tile_shift[3];  // log2 of tile
-  int32_t region_cells;   // (tile_x + 2)(tile_y + 2)(tile_z + 2)
+  int32_t region_cells;   // (tile_x + 1)(tile_y + 2)(tile_z + 2): rows of tile_x cells and one pad cell
 };
 
 // Kernel slots of the per-kernel event timer.

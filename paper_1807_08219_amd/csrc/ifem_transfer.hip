@@ -10,7 +10,7 @@
 //  tiled spread         deterministic and free of global float atomics:
 //    k_bin_count<T>     per (node, component): counts the node in the list
 //                       of the tile holding its nearest lattice node;
-//    k_scan             exclusive scan of the counts (single workgroup);
+//    k_scan             list offsets from the counts (single workgroup);
 //    k_bin_fill<T>      writes every node into its lists;
 //    k_spread_home<T>   one workgroup per (component, tile): accumulates all
 //                       contributions of the tile's list in an LDS region
@@ -170,19 +170,41 @@ __global__ void __launch_bounds__(256) k_spread_atomic(const TransferArgs a, con
 }
 
 // ------------------------------------------------------------------ tiled spread: binning
-// Every (node, component) belongs to exactly one list: the tile holding its
-// nearest lattice node.  Count, scan and fill build the lists; the atomics
-// on the list counters are aggregated per wavefront (one per distinct list
-// among 64 consecutive nodes, which lie close together on one surface).
-// Home list of a node for one component: the (component, tile) that holds
-// its nearest lattice node.  The count and fill passes both call this, on the
-// same inputs, so they agree bit for bit.
-__device__ __forceinline__ int home_list(const TransferArgs& a, const BoxDev& B, int d, const double pos[3]) {
+// A (node, component) belongs to the list of the tile holding its nearest
+// lattice node and, when that node lies on the tile's first or last x layer,
+// also to the list of the x-neighbour tile that its stencil reaches into.
+// Each tile thus sees every contribution that lands inside its x range (no
+// halo along x) and keeps a one-cell halo along y and z only, whose rows are
+// contiguous in memory.  Count, scan and fill build the lists; the atomics on
+// the list counters are aggregated per wavefront (one per distinct list among
+// 64 consecutive nodes, which lie close together on one surface).
+constexpr int kListsPerEntry = 3;
+
+// Lists of a node for one component: keys[0] the home tile, keys[1] and
+// keys[2] the left and right x-neighbours when reached (else -1; a tile that
+// equals an earlier key is not repeated).  The count and fill passes both call
+// this on the same inputs, so they agree bit for bit.
+__device__ __forceinline__ void node_lists(const TransferArgs& a, const BoxDev& B, int d, const double pos[3],
+                                           int keys[kListsPerEntry]) {
   int32_t base[3];
   double tau[3];
   nearest_node(B, d, pos, base, tau);
   const int tx = base[0] >> a.tile_shift[0], ty = base[1] >> a.tile_shift[1], tz = base[2] >> a.tile_shift[2];
-  return d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0] + tx;
+  const int row = d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0];
+  const int c0x = tx << a.tile_shift[0];
+  const int exx = min(a.tile[0], B.n[0] - c0x);
+  int left = -1, right = -1;
+  if (base[0] == c0x) {
+    const int t = tx == 0 ? B.ntile[0] - 1 : tx - 1;
+    if (t != tx) left = t;
+  }
+  if (base[0] == c0x + exx - 1) {
+    const int t = tx == B.ntile[0] - 1 ? 0 : tx + 1;
+    if (t != tx && t != left) right = t;
+  }
+  keys[0] = row + tx;
+  keys[1] = left >= 0 ? row + left : -1;
+  keys[2] = right >= 0 ? row + right : -1;
 }
 
 // Adds one entry per active lane (key >= 0) to counter[key] with one atomic
@@ -207,75 +229,91 @@ __device__ __forceinline__ int wave_append(int32_t* __restrict__ counter, int ke
 }
 
 // Count pass: one thread per node; every (node, component) counts once in
-// its home list.
+// each of its lists.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_count(const TransferArgs a, const T* __restrict__ x,
                                                    const double* __restrict__ anchor) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  int key[3] = {-1, -1, -1};
+  int key[3][kListsPerEntry];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int j = 0; j < kListsPerEntry; ++j) key[d][j] = -1;
   if (k < a.n_nodes) {
     const int p = a.node_particle[k];
     const BoxDev& B = a.boxes[a.particle_box[p]];
     double pos[3];
     node_position(a, x, anchor, k, p, pos);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) key[d] = home_list(a, B, d, pos);
+    for (int d = 0; d < 3; ++d) node_lists(a, B, d, pos, key[d]);
   }
 #pragma unroll
-  for (int d = 0; d < 3; ++d) (void)wave_append(a.tile_count, key[d]);
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int j = 0; j < kListsPerEntry; ++j) (void)wave_append(a.tile_count, key[d][j]);
 }
 
-// Fill pass: the same keys; each (node, component) takes a slot of its home
-// list from the cursor (initialised to the list's offset by the scan).
+// Fill pass: the same keys; each (node, component) takes a slot of each of
+// its lists from the cursors (initialised to the lists' offsets by the scan).
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_fill(const TransferArgs a, const T* __restrict__ x,
                                                   const double* __restrict__ anchor) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  int key[3] = {-1, -1, -1};
+  int key[3][kListsPerEntry];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int j = 0; j < kListsPerEntry; ++j) key[d][j] = -1;
   if (k < a.n_nodes) {
     const int p = a.node_particle[k];
     const BoxDev& B = a.boxes[a.particle_box[p]];
     double pos[3];
     node_position(a, x, anchor, k, p, pos);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) key[d] = home_list(a, B, d, pos);
+    for (int d = 0; d < 3; ++d) node_lists(a, B, d, pos, key[d]);
   }
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int slot = wave_append(a.tile_cursor, key[d]);
-    if (key[d] >= 0 && slot < a.list_cap) a.bin_list[slot] = k;
-  }
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int j = 0; j < kListsPerEntry; ++j) {
+      const int slot = wave_append(a.tile_cursor, key[d][j]);
+      if (key[d][j] >= 0 && slot < a.list_cap) a.bin_list[slot] = k;
+    }
 }
 
-// Exclusive scan of tile_count into tile_off (n + 1 entries) with one
-// workgroup; starts every cursor at its list's offset; flags a total above
-// the list capacity (which holds exactly one entry per node and component).
+// List placement: any disjoint placement of the lists works, so thread t takes
+// the counts t, t + nt, t + 2 nt, ... (coalesced loads), the thread totals are
+// scanned across the workgroup, and each thread lays its lists out one after
+// another from its prefix.  Every cursor starts at its list's offset; a total
+// above the list capacity is flagged.
 __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restrict__ cnt, int32_t* __restrict__ off,
                                                int32_t* __restrict__ cursor, int64_t cap,
                                                unsigned long long* status) {
-  __shared__ int32_t part[1024];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int chunk = (n + nt - 1) / nt;
-  const int b = tid * chunk, e = min(n, b + chunk);
+  __shared__ int32_t wsum[1024 / kWave];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), wave = tid / kWave;
   int32_t s = 0;
-  for (int i = b; i < e; ++i) s += cnt[i];
-  part[tid] = s;
-  __syncthreads();
-  for (int o = 1; o < nt; o <<= 1) {  // Hillis-Steele inclusive scan of the per-thread sums
-    const int32_t v = tid >= o ? part[tid - o] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  for (int i = tid; i < n; i += nt) s += cnt[i];
+  // inclusive scan of the thread totals: within each wavefront, then across the wavefront totals
+  int32_t incl = s;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t v = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += v;
   }
-  int32_t run = part[tid] - s;
-  for (int i = b; i < e; ++i) {
+  if (lane == kWave - 1) wsum[wave] = incl;
+  __syncthreads();
+  int32_t before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  int32_t run = before + incl - s;
+  for (int i = tid; i < n; i += nt) {
+    const int32_t c = cnt[i];
     off[i] = run;
     cursor[i] = run;
-    run += cnt[i];
+    run += c;
   }
   if (tid == nt - 1) {
-    off[n] = part[nt - 1];
-    if ((int64_t)part[nt - 1] > cap) atomicAdd(status + 3, 1ull);
+    off[n] = run;
+    if ((int64_t)run > cap) atomicAdd(status + 3, 1ull);
   }
 }
 
@@ -293,11 +331,11 @@ struct FixedAcc<double> {
 
 constexpr int kTileThreads = 512;  // threads of a spread-tile workgroup (8 wavefronts)
 
-// Home-tile accumulation: workgroup (tile, component) takes the nodes of its
-// list (nearest lattice node in the tile) and accumulates all 27 of their
-// contributions into an LDS region covering the tile plus a one-cell halo
+// Tile accumulation: workgroup (tile, component) takes the nodes of its list
+// and accumulates every contribution that lands inside the tile's x range
+// into an LDS region covering the tile plus a one-cell halo along y and z
 // (64-bit fixed point: exact, order-independent sums).  The region interior
-// is written straight to the grid, the halo shell to scratch for the merge.
+// is written straight to the grid, the y/z halo rows to scratch for the merge.
 template <typename T>
 __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs a, const T* __restrict__ x,
                                                               const double* __restrict__ anchor,
@@ -317,7 +355,9 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   const int c0[3] = {tx * a.tile[0], ty * a.tile[1], tz * a.tile[2]};
   int ex[3];
   for (int i = 0; i < 3; ++i) ex[i] = min(a.tile[i], B.n[i] - c0[i]);
-  const int rx = ex[0] + 2, ry = ex[1] + 2, rz = ex[2] + 2, nreg = rx * ry * rz;
+  // region rows hold ex_x cells plus one pad cell: an odd pitch of 64-bit words spreads the rows and
+  // planes of the stencil over the LDS banks, and the pad takes the zero adds of masked columns
+  const int rx = ex[0] + 1, ry = ex[1] + 2, rz = ex[2] + 2, nreg = rx * ry * rz;
   const int32_t* list = a.bin_list + a.tile_off[L];
   const int cnt = a.tile_count[L];
   T* g = grid + d * a.total_cells + B.cell_off;
@@ -358,14 +398,35 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     frexp(4.0 * (double)cnt * m, &e2);
     sc = min(50 - e1, 62 - e2);
     const double scale = ldexp(1.0, sc);
-    for (int e = tid; e < cnt; e += nt) {
+    // entry order: qi -> (qi * stride) mod cnt with a prime stride that does not divide cnt (a
+    // permutation), so that the lanes of a wavefront take nodes far apart in the list, i.e. far apart
+    // on the surface, and rarely add to the same LDS cell in one instruction
+    int stride = 1;
+    if (cnt % 97) stride = 97;
+    else if (cnt % 89) stride = 89;
+    else if (cnt % 83) stride = 83;
+    const int step = (int)(((int64_t)nt * stride) % cnt);
+    int e = (int)(((int64_t)tid * stride) % cnt);
+    for (int qi = tid; qi < cnt; qi += nt) {
       const int k = list[e];
+      e += step;
+      if (e >= cnt) e -= cnt;
       double pos[3], tau64[3];
       int32_t base[3];
       node_position(a, x, anchor, k, a.node_particle[k], pos);
       nearest_node(B, d, pos, base, tau64);
-      if ((unsigned)(base[0] - c0[0]) >= (unsigned)ex[0] || (unsigned)(base[1] - c0[1]) >= (unsigned)ex[1] ||
-          (unsigned)(base[2] - c0[2]) >= (unsigned)ex[2]) {
+      // stencil columns wrapped onto the box, relative to the tile: kept when inside [0, ex_x)
+      int lx[3];
+      bool xin[3];
+#pragma unroll
+      for (int mx = 0; mx < 3; ++mx) {
+        int gx = base[0] + mx - 1;
+        gx = gx < 0 ? gx + B.n[0] : (gx >= B.n[0] ? gx - B.n[0] : gx);
+        lx[mx] = gx - c0[0];
+        xin[mx] = (unsigned)lx[mx] < (unsigned)ex[0];
+      }
+      if ((unsigned)(base[1] - c0[1]) >= (unsigned)ex[1] || (unsigned)(base[2] - c0[2]) >= (unsigned)ex[2] ||
+          !(xin[0] || xin[1] || xin[2])) {
         atomicAdd(a.status + 3, 1ull);  // positions changed since binning: the node is skipped, not misplaced
         continue;
       }
@@ -373,8 +434,17 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
       T W[27], cf[4];
       mls_weights<T>(tau, W, cf);
       const double fs = (double)Fd[k] * scale;
-      // region cell of stencil node m: local base + m (the region starts one cell before the tile)
-      const int r0 = ((base[2] - c0[2]) * ry + (base[1] - c0[1])) * rx + (base[0] - c0[0]);
+      // a column outside the tile adds zero to the row's pad cell (its contribution belongs to the
+      // x-neighbour, which holds this node in its list too)
+      double fsx[3];
+      int cx[3];
+#pragma unroll
+      for (int mx = 0; mx < 3; ++mx) {
+        fsx[mx] = xin[mx] ? fs : 0.0;
+        cx[mx] = xin[mx] ? lx[mx] : ex[0];
+      }
+      // region row of stencil rows (my, mz): the region starts one cell before the tile in y and z
+      const int r0 = ((base[2] - c0[2]) * ry + (base[1] - c0[1])) * rx;
 #pragma unroll
       for (int mz = 0; mz < 3; ++mz) {
         const T vz = cf[0] + cf[3] * (T(mz - 1) - tau[2]);
@@ -385,12 +455,12 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
 #pragma unroll
           for (int mx = 0; mx < 3; ++mx) {
             const T phi = W[(mz * 3 + my) * 3 + mx] * (vyz + cf[1] * (T(mx - 1) - tau[0]));
-            const double q = (double)phi * fs;
+            const double q = (double)phi * fsx[mx];
             const long long qh = round_to_i64(q);
-            atomicAdd(acc + row + mx, (unsigned long long)qh);
+            atomicAdd(acc + row + cx[mx], (unsigned long long)qh);
             if (NW == 2) {
               const long long ql = round_to_i64((q - (double)qh) * 0x1p40);
-              atomicAdd(acc + nreg + row + mx, (unsigned long long)ql);
+              atomicAdd(acc + nreg + row + cx[mx], (unsigned long long)ql);
             }
           }
         }
@@ -398,37 +468,57 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     }
   }
   __syncthreads();
-  // interior -> grid (final unless a neighbour's halo adds to it), halo shell -> scratch.  Region
-  // index r -> (ix, iy, iz) by float reciprocals: (r + 1/2) / d is at least 1/(2d) away from an
-  // integer, far above the rounding of these small quotients, so the truncation is exact.
+  // interior -> grid (final unless a neighbour's halo adds to it), y/z halo rows -> scratch.  Each
+  // thread walks r = tid, tid + nt, ... keeping (ix, iy, iz) and the grid offset up to date with
+  // adds and carries only.  Grid offsets use 32-bit wrap-around arithmetic: exact for the interior
+  // cells, the only ones stored to the grid.
   const double inv = ldexp(1.0, -sc);
-  const float inv_rxy = frcp((float)(rx * ry)), inv_rx = frcp((float)rx);
+  const int rxy = rx * ry;
+  const uint32_t nx = (uint32_t)B.n[0], nxy = (uint32_t)B.n[0] * (uint32_t)B.n[1];
+  int iz = tid / rxy, iy = (tid - iz * rxy) / rx, ix = tid - iz * rxy - iy * rx;
+  const int sz = nt / rxy, sy = (nt - sz * rxy) / rx, sx = nt - sz * rxy - sy * rx;
+  uint32_t goff = (uint32_t)(c0[2] - 1 + iz) * nxy + (uint32_t)(c0[1] - 1 + iy) * nx + (uint32_t)(c0[0] + ix);
+  const uint32_t gstep = (uint32_t)sz * nxy + (uint32_t)sy * nx + (uint32_t)sx;
+  const uint32_t carry_x = nx - (uint32_t)rx, carry_y = nxy - (uint32_t)ry * nx;
+  const bool halo_on = active || poison;
   for (int r = tid; r < nreg; r += nt) {
-    const int iz = (int)(((float)r + 0.5f) * inv_rxy);
-    const int rr = r - iz * rx * ry;
-    const int iy = (int)(((float)rr + 0.5f) * inv_rx);
-    const int ix = rr - iy * rx;
     T v = poison ? (T)__builtin_nan("") : T(0);
     if (active) {
       double w = (double)(long long)acc[r];
       if (NW == 2) w += (double)(long long)acc[nreg + r] * 0x1p-40;
       v = (T)(w * inv);
     }
-    if (ix >= 1 && ix <= ex[0] && iy >= 1 && iy <= ex[1] && iz >= 1 && iz <= ex[2])
-      g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix - 1)] = v;
-    else if (active || poison)
-      halo[r] = v;
+    const bool cell = ix < ex[0];  // not the pad
+    const bool in = cell && (unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2];
+    T* dst = in ? g + goff : halo + r;
+    if (in || (cell && halo_on)) *dst = v;
+    ix += sx;
+    iy += sy;
+    iz += sz;
+    goff += gstep;
+    if (ix >= rx) {
+      ix -= rx;
+      iy += 1;
+      goff += carry_x;
+    }
+    if (iy >= ry) {
+      iy -= ry;
+      iz += 1;
+      goff += carry_y;
+    }
   }
   if (tid == 0) a.tile_flag[L] = (active || poison) ? 1 : 0;
 }
 
-// Merge: every tile adds, to its border cells, the halo values that its 26
-// neighbours (periodic; possibly itself) accumulated for them, in a fixed order.
+// Merge: every tile adds, to its y/z border rows, the halo rows that its 8
+// neighbours in the y-z plane (periodic; possibly itself) accumulated for
+// them, in a fixed order.  Tiles that are neighbours in y or z share their x
+// range, so every row is a contiguous run of ex_x cells on both sides.
 template <typename T>
 __global__ void __launch_bounds__(256) k_spread_merge(const TransferArgs a, T* __restrict__ grid) {
-  __shared__ int nbL[27];
-  __shared__ int nbflag[27];
-  __shared__ int nbex[27][3];
+  __shared__ int nbL[9];
+  __shared__ int nbflag[9];
+  __shared__ int nbe[9][2];  // neighbour extents along y and z
   __shared__ int any;
   const int tile = blockIdx.x, d = blockIdx.y, tid = threadIdx.x;
   const BoxDev B = a.boxes[a.tile_box[tile]];
@@ -436,68 +526,59 @@ __global__ void __launch_bounds__(256) k_spread_merge(const TransferArgs a, T* _
   const int t[3] = {tl % B.ntile[0], (tl / B.ntile[0]) % B.ntile[1], tl / (B.ntile[0] * B.ntile[1])};
   if (tid == 0) any = 0;
   __syncthreads();
-  if (tid < 27) {
-    const int o[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
-    int nb[3];
-    for (int ax = 0; ax < 3; ++ax) {
-      nb[ax] = t[ax] + o[ax];
-      if (nb[ax] < 0) nb[ax] += B.ntile[ax];
-      if (nb[ax] >= B.ntile[ax]) nb[ax] -= B.ntile[ax];
-      nbex[tid][ax] = min(a.tile[ax], B.n[ax] - nb[ax] * a.tile[ax]);
+  if (tid < 9) {
+    const int o[2] = {tid % 3 - 1, tid / 3 - 1};  // (oy, oz)
+    int nb[2];
+    for (int ax = 0; ax < 2; ++ax) {
+      nb[ax] = t[ax + 1] + o[ax];
+      if (nb[ax] < 0) nb[ax] += B.ntile[ax + 1];
+      if (nb[ax] >= B.ntile[ax + 1]) nb[ax] -= B.ntile[ax + 1];
+      nbe[tid][ax] = min(a.tile[ax + 1], B.n[ax + 1] - nb[ax] * a.tile[ax + 1]);
     }
-    const int Ln = d * a.n_tiles + B.tile_base + (nb[2] * B.ntile[1] + nb[1]) * B.ntile[0] + nb[0];
+    const int Ln = d * a.n_tiles + B.tile_base + (nb[1] * B.ntile[1] + nb[0]) * B.ntile[0] + t[0];
     nbL[tid] = Ln;
-    const int f = tid == 13 ? 0 : a.tile_flag[Ln];  // 13 = the tile itself, already in the grid
+    const int f = tid == 4 ? 0 : a.tile_flag[Ln];  // 4 = the tile itself, already in the grid
     nbflag[tid] = f;
     if (f) atomicOr(&any, 1);
   }
   __syncthreads();
   if (!any) return;
   const int c0[3] = {t[0] * a.tile[0], t[1] * a.tile[1], t[2] * a.tile[2]};
-  const int ex[3] = {nbex[13][0], nbex[13][1], nbex[13][2]};
+  const int exx = min(a.tile[0], B.n[0] - c0[0]);
+  const int ey = nbe[4][0], ez = nbe[4][1];
   T* g = grid + d * a.total_cells + B.cell_off;
   const T* halo = reinterpret_cast<const T*>(a.halo);
-  // border cells only: the two z faces, then the two y faces without z-face cells, then the two x
-  // faces without y/z-face cells (each border cell exactly once, rows along x stay coalesced)
-  const int inz = max(ex[2] - 2, 0), iny = max(ex[1] - 2, 0);
-  const int zf = ex[2] > 1 ? 2 : 1, yf = ex[1] > 1 ? 2 : 1, xf = ex[0] > 1 ? 2 : 1;
-  const int nzc = zf * ex[0] * ex[1], nyc = yf * ex[0] * inz, nxc = xf * iny * inz;
-  const int total = nzc + nyc + nxc;
-  for (int bi = tid; bi < total; bi += blockDim.x) {
-    int i[3];
-    if (bi < nzc) {
-      const int f = bi / (ex[0] * ex[1]), r = bi - f * ex[0] * ex[1];
-      i[0] = r % ex[0];
-      i[1] = r / ex[0];
-      i[2] = f ? ex[2] - 1 : 0;
-    } else if (bi < nzc + nyc) {
-      const int b = bi - nzc, f = b / (ex[0] * inz), r = b - f * ex[0] * inz;
-      i[0] = r % ex[0];
-      i[1] = f ? ex[1] - 1 : 0;
-      i[2] = 1 + r / ex[0];
+  // border rows: the z faces (all y), then the y faces without the z-face rows
+  const int zf = ez > 1 ? 2 : 1, yf = ey > 1 ? 2 : 1, inz = max(ez - 2, 0);
+  const int nzr = zf * ey, nrows = nzr + yf * inz;
+  // lanes cover rows of the power-of-two tile width; lanes past the tile's extent idle
+  const int sh = a.tile_shift[0];
+  const int rpp = a.tile[0] >= 256 ? 1 : 256 / a.tile[0];  // rows per workgroup pass
+  const int ix = tid & (a.tile[0] - 1), lrow = tid >> sh;
+  if (ix >= exx || lrow >= rpp) return;  // no barrier follows
+  for (int row = lrow; row < nrows; row += rpp) {
+    int iy, iz;
+    if (row < nzr) {
+      const int f = row >= ey ? 1 : 0;
+      iy = row - f * ey;
+      iz = f ? ez - 1 : 0;
     } else {
-      const int b = bi - nzc - nyc, f = b / (iny * inz), r = b - f * iny * inz;
-      i[0] = f ? ex[0] - 1 : 0;
-      i[1] = 1 + r % iny;
-      i[2] = 1 + r / iny;
+      const int b = row - nzr, f = b >= inz ? 1 : 0;
+      iz = 1 + b - f * inz;
+      iy = f ? ey - 1 : 0;
     }
-    const uint32_t cell = (uint32_t)(((c0[2] + i[2]) * B.n[1] + (c0[1] + i[1])) * B.n[0] + c0[0] + i[0]);
+    const uint32_t cell = (uint32_t)(((c0[2] + iz) * B.n[1] + (c0[1] + iy)) * B.n[0] + c0[0] + ix);
     T v = g[cell];
     for (int oz = -1; oz <= 1; ++oz) {
-      if ((oz == -1 && i[2] != 0) || (oz == 1 && i[2] != ex[2] - 1)) continue;
+      if ((oz == -1 && iz != 0) || (oz == 1 && iz != ez - 1)) continue;
       for (int oy = -1; oy <= 1; ++oy) {
-        if ((oy == -1 && i[1] != 0) || (oy == 1 && i[1] != ex[1] - 1)) continue;
-        for (int ox = -1; ox <= 1; ++ox) {
-          if ((ox == -1 && i[0] != 0) || (ox == 1 && i[0] != ex[0] - 1)) continue;
-          const int nbi = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1);
-          if (!nbflag[nbi]) continue;
-          // region coordinates of this cell in the neighbour: -1 -> its last+1, +1 -> 0, 0 -> i + 1
-          const int r[3] = {ox == -1 ? nbex[nbi][0] + 1 : (ox == 1 ? 0 : i[0] + 1),
-                            oy == -1 ? nbex[nbi][1] + 1 : (oy == 1 ? 0 : i[1] + 1),
-                            oz == -1 ? nbex[nbi][2] + 1 : (oz == 1 ? 0 : i[2] + 1)};
-          const int rxn = nbex[nbi][0] + 2, ryn = nbex[nbi][1] + 2;
-          v += halo[(int64_t)nbL[nbi] * a.region_cells + (r[2] * ryn + r[1]) * rxn + r[0]];
-        }
+        if ((oy == -1 && iy != 0) || (oy == 1 && iy != ey - 1)) continue;
+        const int nbi = (oz + 1) * 3 + (oy + 1);
+        if (!nbflag[nbi]) continue;
+        // region coordinates of this cell in the neighbour: -1 -> its last+1, +1 -> 0, 0 -> i + 1
+        const int ry = oy == -1 ? nbe[nbi][0] + 1 : (oy == 1 ? 0 : iy + 1);
+        const int rz = oz == -1 ? nbe[nbi][1] + 1 : (oz == 1 ? 0 : iz + 1);
+        v += halo[(int64_t)nbL[nbi] * a.region_cells + (rz * (nbe[nbi][0] + 2) + ry) * (exx + 1) + ix];
       }
     }
     g[cell] = v;

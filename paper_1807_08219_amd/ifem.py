@@ -147,8 +147,8 @@ class Plan:
         tp = None
         if tuning is not None:
             t = ifem_tuning()
-            t.tile[:] = list(tuning.get("tile", (16, 16, 16)))
-            t.block_forces = int(tuning.get("block_forces", 256))
+            t.tile[:] = list(tuning.get("tile", (64, 8, 8)))
+            t.block_forces = int(tuning.get("block_forces", 512))
             t.block_points = int(tuning.get("block_points", 256))
             tp = C.byref(t)
         h = C.c_void_p()

@@ -55,11 +55,14 @@ def _degenerate_scene():
     x[t[1]] = x[t[0]]  # triangle 10 collapses (its other neighbours stay valid)
     Xs, tets = meshes.ellipsoid_tets(2, 2, 2, (1.0, 0.9, 0.8))
     xs = Xs.copy()
-    # reflect the last node of tetrahedron 0 through the plane of its other three: that tetrahedron inverts
-    a, b, c, d = (Xs[i] for i in tets[0])
+    # push a node of the fewest tetrahedra 1.2 times its distance through the opposite face of its first
+    # tetrahedron: the tetrahedra at that node invert, the others keep their shape (well-conditioned)
+    node = int(np.argmin(np.bincount(tets.ravel(), minlength=len(Xs))))
+    t = tets[np.where((tets == node).any(axis=1))[0][0]]
+    a, b, c = (Xs[i] for i in t if i != node)
     nrm = np.cross(b - a, c - a)
     nrm /= np.linalg.norm(nrm)
-    xs[tets[0][3]] = d - 2.0 * np.dot(d - a, nrm) * nrm
+    xs[node] = Xs[node] - 1.2 * np.dot(Xs[node] - a, nrm) * nrm
     xs += [6.0, 2.5, 2.5]
     box = Box((18, 10, 10), 0.5, (0.0, 0.0, 0.0))
     parts = [Particle(X=X, x=x, tri=tris, law=scenes.LAW_TRI_NEOHOOKE, mu=1.0),
@@ -180,8 +183,10 @@ def test_nonfinite_force_poisons_its_home_tile_only(dtype):
     assert nan_o.any() and not nan_o[[0, 2]].any()
     assert not (nan_o & ~nan_g).any()  # every NaN of the definition is NaN here
     assert not nan_g[[0, 2]].any()  # the other components are untouched
-    # the poisoned cells stay within one tile plus its halo (at most (16 + 2)^3 cells)
-    assert nan_g[1].sum() <= 18 ** 3
+    # the poisoned cells stay within the tiles whose lists hold the node (its home tile and at most one
+    # x-neighbour) plus their y/z halos
+    tx, ty, tz = plan.info()[3:6]
+    assert nan_g[1].sum() <= 2 * tx * (ty + 2) * (tz + 2)
     fin = ~nan_g
     assert rel(got[fin], Go[fin]) <= (1e-12 if dtype == ifem.IFEM_F64 else 1e-5)
     plan.close()

@@ -195,3 +195,26 @@ def test_adjoint_identity_on_gpu(runs):
     v = r.interp(ifem.IFEM_F64, u)
     for d in range(3):
         assert np.dot(G[d], u[d]) == pytest.approx(np.dot(F[d], v[d]), rel=1e-12)
+
+
+TILES = [(4, 4, 4), (8, 4, 16), (16, 8, 4), (4, 16, 8), (64, 8, 8)]
+
+
+@pytest.mark.parametrize("tile", TILES, ids=lambda t: "x".join(map(str, t)))
+@pytest.mark.parametrize("name", ["mixed_two_boxes", "config2_rbc_2562"])
+@pytest.mark.parametrize("dtype", [ifem.IFEM_F64, ifem.IFEM_F32])
+def test_tiled_spread_any_tile_shape(name, tile, dtype):
+    """Several x-tiles per box (nodes on tile x-faces go to both x-neighbours' lists), ragged last
+    tiles, and a one-cell-wide last tile between two others (13 cells in 4-cell tiles)."""
+    sc = SCENES[name]()
+    say(f"[gpu] tiled spread {name} tile {tile} dtype {dtype}")
+    r = Run(sc, tuning={"tile": list(tile)})
+    F = fields.random_forces(sc, seed=12)
+    if dtype == ifem.IFEM_F32:
+        F = F.astype(np.float32).astype(np.float64)
+    G = r.spread(dtype, F)
+    e = rel(G, oracle.spread(sc, F))
+    say(f"    grid rel err {e:.3e}")
+    assert e <= (F64_TOL if dtype == ifem.IFEM_F64 else F32_TRANSFER_TOL)
+    assert r.plan.status() == [0, 0, 0, 0]
+    r.plan.close()
