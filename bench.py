@@ -37,7 +37,8 @@ def log(msg):
 #   [27 stencil nodes x 14 (distance, spline, moments) + 9 x 20 (moment sums)
 #    + 60 (4x4 solve) + 27 x 5 (weight and multiply-add)].
 MLS_FLOPS = 27 * 14 + 9 * 20 + 60 + 27 * 5
-VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (fma) x 2.4 GHz, non-packed float32
+VALU_PEAK_TFLOPS = 157.3  # MI355X float32 vector peak (packed issue); 256 CU x 2.4 GHz x 256 flop/cycle
+VALU_NONPACKED_TFLOPS = 78.6  # the same without packed float32 issue, which this build does not use
 HBM_PEAK_GBS = 8000.0
 
 
@@ -126,6 +127,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="spread tile, e.g. 32,16,8 (powers of two)")
     ap.add_argument("--block-forces", type=int, default=None, help="threads per particle workgroup")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="bytes of a plain device copy made before the steps (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is a design "
@@ -183,6 +186,13 @@ def main():
         per = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in ev])  # ms
         return wall, per
 
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"calibration copy of {args.copy_calibration} bytes done")
     plan.set(ifem.IFEM_OPT_SPREAD_MODE, ifem.IFEM_SPREAD_TILED)
     for _ in range(args.warmup):
         step32()
@@ -222,6 +232,7 @@ def main():
         "algorithmic_bytes": int(bytes_dom) if bytes_dom else None,
         "algorithmic_flops": int(flops_dom) if flops_dom else None,
         "hbm_frac": round(hbm_frac, 4), "alu_frac": round(alu_frac, 4),
+        "alu_frac_nonpacked": round(tfs / VALU_NONPACKED_TFLOPS, 4) if tfs else None,
         "step_hbm_frac": round(step_bytes(sc, False) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels_ms": {k: round(v[0], 4) for k, v in kavg.items()},
     })

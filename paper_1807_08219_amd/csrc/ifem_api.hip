@@ -343,7 +343,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     B.tile_base = (int32_t)tile_box.size();
     total_cells += (int64_t)B.n[0] * B.n[1] * B.n[2];
     const int64_t nt = (int64_t)B.ntile[0] * B.ntile[1] * B.ntile[2];
-    if ((int64_t)tile_box.size() + nt > (1 << 30)) return fail(IFEM_ERR_UNSUPPORTED, "too many tiles");
+    if ((int64_t)tile_box.size() + nt > (1 << 28)) return fail(IFEM_ERR_UNSUPPORTED, "too many tiles");
     tile_box.insert(tile_box.end(), (size_t)nt, b);
   }
 

@@ -79,6 +79,18 @@ __device__ __forceinline__ double sqrt_refined(double x) {
   return __builtin_fma(0.5 * __builtin_fma(-y, y, x), r, y);
 }
 
+// ------------------------------------------------------------------ launch order
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  xcd_remap turns the hardware workgroup id into a logical
+// one such that every XCD runs one contiguous range of logical workgroups, so
+// neighbouring work (nodes of one particle, the components of one tile) shares
+// an L2.  It is a bijection on [0, n) for any n.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+  const int q = n / kXcds, r = n % kXcds, xcd = bid % kXcds;
+  return xcd * q + (xcd < r ? xcd : r) + bid / kXcds;
+}
+
 // ------------------------------------------------------------------ MLS weights
 // Linear moving-least-squares weights on one 27-node stencil, in lattice
 // units (h = 1).  tau = t - base is the point's offset from its nearest node

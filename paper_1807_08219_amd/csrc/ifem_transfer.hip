@@ -74,7 +74,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_interp(const TransferArgs a, const T* __restrict__ x,
                                                 const double* __restrict__ anchor, const T* __restrict__ grid,
                                                 T* __restrict__ v) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= a.n_nodes) return;
   const int p = a.node_particle[k];
   const BoxDev B = a.boxes[a.particle_box[p]];
@@ -207,78 +207,83 @@ __device__ __forceinline__ void node_lists(const TransferArgs& a, const BoxDev& 
   keys[2] = right >= 0 ? row + right : -1;
 }
 
-// Adds one entry per active lane (key >= 0) to counter[key] with one atomic
-// per distinct key in the wavefront; returns each lane's slot (the counter's
-// old value plus the lane's rank among the lanes with its key).  Every lane
-// of the wavefront must call it.
-__device__ __forceinline__ int wave_append(int32_t* __restrict__ counter, int key) {
+// Groups the active lanes (key >= 0) of a wavefront by key: every lane gets
+// the lane of its group's leader and its rank in the group; the leader also
+// gets the group size (0 elsewhere).  Ballots and lane reads only, no memory
+// traffic, so the atomics that follow can all be in flight at once.  Every
+// lane of the wavefront must call it.
+__device__ __forceinline__ void wave_groups(int key, int& leader, int& rank, int& size) {
   const int lane = threadIdx.x & (kWave - 1);
   unsigned long long todo = __ballot(key >= 0);
-  int slot = 0;
+  leader = lane;
+  rank = 0;
+  size = 0;
   while (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    const int kl = __builtin_amdgcn_readlane(key, leader);
+    const int l = __ffsll((long long)todo) - 1;
+    const int kl = __builtin_amdgcn_readlane(key, l);
     const unsigned long long m = __ballot(key == kl) & todo;
-    int b = 0;
-    if (lane == leader) b = atomicAdd(counter + kl, (int)__popcll(m));
-    b = __builtin_amdgcn_readlane(b, leader);
-    if (key == kl) slot = b + (int)__popcll(m & ((1ull << lane) - 1ull));
+    if (key == kl) {
+      leader = l;
+      rank = (int)__popcll(m & ((1ull << lane) - 1ull));
+    }
+    if (lane == l) size = (int)__popcll(m);
     todo &= ~m;
   }
-  return slot;
+}
+
+// The lists of one node, all components: keys[d * kListsPerEntry + j].
+template <typename T>
+__device__ __forceinline__ void all_lists(const TransferArgs& a, const T* __restrict__ x,
+                                          const double* __restrict__ anchor, int k, int keys[3 * kListsPerEntry]) {
+#pragma unroll
+  for (int i = 0; i < 3 * kListsPerEntry; ++i) keys[i] = -1;
+  if (k < a.n_nodes) {
+    const int p = a.node_particle[k];
+    const BoxDev& B = a.boxes[a.particle_box[p]];
+    double pos[3];
+    node_position(a, x, anchor, k, p, pos);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) node_lists(a, B, d, pos, keys + d * kListsPerEntry);
+  }
 }
 
 // Count pass: one thread per node; every (node, component) counts once in
-// each of its lists.
+// each of its lists, one atomic per distinct list per wavefront.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_count(const TransferArgs a, const T* __restrict__ x,
                                                    const double* __restrict__ anchor) {
+  constexpr int NK = 3 * kListsPerEntry;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  int key[3][kListsPerEntry];
+  int key[NK];
+  all_lists(a, x, anchor, k, key);
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int j = 0; j < kListsPerEntry; ++j) key[d][j] = -1;
-  if (k < a.n_nodes) {
-    const int p = a.node_particle[k];
-    const BoxDev& B = a.boxes[a.particle_box[p]];
-    double pos[3];
-    node_position(a, x, anchor, k, p, pos);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) node_lists(a, B, d, pos, key[d]);
+  for (int i = 0; i < NK; ++i) {
+    int leader, rank, size;
+    wave_groups(key[i], leader, rank, size);
+    if (size > 0) atomicAdd(a.tile_count + key[i], size);
   }
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int j = 0; j < kListsPerEntry; ++j) (void)wave_append(a.tile_count, key[d][j]);
 }
 
-// Fill pass: the same keys; each (node, component) takes a slot of each of
-// its lists from the cursors (initialised to the lists' offsets by the scan).
+// Fill pass: the same keys; each group's leader takes a run of slots from the
+// list's cursor (initialised to the list's offset by the scan) and the group
+// members write the node id into it.  All atomics of a wavefront are issued
+// before any result is used.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_fill(const TransferArgs a, const T* __restrict__ x,
                                                   const double* __restrict__ anchor) {
+  constexpr int NK = 3 * kListsPerEntry;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  int key[3][kListsPerEntry];
+  int key[NK], leader[NK], rank[NK], size[NK], base[NK];
+  all_lists(a, x, anchor, k, key);
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
+  for (int i = 0; i < NK; ++i) wave_groups(key[i], leader[i], rank[i], size[i]);
 #pragma unroll
-    for (int j = 0; j < kListsPerEntry; ++j) key[d][j] = -1;
-  if (k < a.n_nodes) {
-    const int p = a.node_particle[k];
-    const BoxDev& B = a.boxes[a.particle_box[p]];
-    double pos[3];
-    node_position(a, x, anchor, k, p, pos);
+  for (int i = 0; i < NK; ++i) base[i] = size[i] > 0 ? atomicAdd(a.tile_cursor + key[i], size[i]) : 0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) node_lists(a, B, d, pos, key[d]);
+  for (int i = 0; i < NK; ++i) {
+    const int slot = __shfl(base[i], leader[i], kWave) + rank[i];
+    if (key[i] >= 0 && slot < a.list_cap) a.bin_list[slot] = k;
   }
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int j = 0; j < kListsPerEntry; ++j) {
-      const int slot = wave_append(a.tile_cursor, key[d][j]);
-      if (key[d][j] >= 0 && slot < a.list_cap) a.bin_list[slot] = k;
-    }
 }
 
 // List placement: any disjoint placement of the lists works, so thread t takes
@@ -345,7 +350,7 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   __shared__ int wb[16];
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);
   constexpr int NW = FixedAcc<T>::kWords;
-  const int tile = blockIdx.x, d = blockIdx.y;
+  const int w = xcd_remap(blockIdx.x, gridDim.x), tile = w / 3, d = w - 3 * tile;  // the 3 components of a tile adjacent
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int nwaves = nt / kWave;
   const int L = d * a.n_tiles + tile;
@@ -520,7 +525,7 @@ __global__ void __launch_bounds__(256) k_spread_merge(const TransferArgs a, T* _
   __shared__ int nbflag[9];
   __shared__ int nbe[9][2];  // neighbour extents along y and z
   __shared__ int any;
-  const int tile = blockIdx.x, d = blockIdx.y, tid = threadIdx.x;
+  const int w = xcd_remap(blockIdx.x, gridDim.x), tile = w / 3, d = w - 3 * tile, tid = threadIdx.x;
   const BoxDev B = a.boxes[a.tile_box[tile]];
   const int tl = tile - B.tile_base;
   const int t[3] = {tl % B.ntile[0], (tl / B.ntile[0]) % B.ntile[1], tl / (B.ntile[0] * B.ntile[1])};
@@ -665,7 +670,7 @@ hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const
       hipLaunchKernelGGL(k_bin_fill<double>, ng, nb, 0, st, a, (const double*)x, anchor);
     P.timer->end(st);
   }
-  const dim3 g((unsigned)a.n_tiles, 3);
+  const dim3 g((unsigned)(3 * a.n_tiles));  // (tile, component) pairs, components fastest
   P.timer->begin(K_SPREAD_HOME, st);
   if (dtype == 0)
     hipLaunchKernelGGL(k_spread_home<float>, g, dim3(kTileThreads), spread_tile_lds_bytes(P, 0), st, a,
