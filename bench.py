@@ -248,6 +248,27 @@ def main():
     st = plan.status()
     out["device_status"] = st
 
+    # the same step captured once as a HIP graph and replayed (no host launch work per step)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step32()
+    torch.cuda.current_stream().wait_stream(side)
+    with torch.cuda.graph(graph):
+        step32()
+    graph.replay()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t_start) * 1e3 / args.steps
+    log(f"fp32 graph replay: {ms_graph:.3f} ms/step")
+    out["graph_replay"] = {"ms_per_step": round(ms_graph, 4), "value": round(sc.n_nodes / (ms_graph * 1e-3), 1),
+                           "steps": args.steps}
+    del graph
+
     if not args.no_fp64:
         x64 = torch.as_tensor(sc.x64, device=dev)
         F64 = torch.empty((3, sc.n_nodes), dtype=torch.float64, device=dev)

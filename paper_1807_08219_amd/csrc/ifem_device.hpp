@@ -13,13 +13,18 @@ namespace ifem {
 constexpr int kWave = 64;
 
 // ------------------------------------------------------------------ error-free transformations
+// Every operation below must round on its own: with the default fp-contract
+// the compiler would fuse the sum s + a*b of an inlined caller into one FMA,
+// which breaks TwoSum's error term and leaves g - G with plain float error.
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
   s = a + b;
   float bb = s - a;
   e = (a - (s - bb)) + (b - bb);
 }
 __device__ __forceinline__ void two_diff(float a, float b, float& s, float& e) { two_sum(a, -b, s, e); }
 __device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
+#pragma clang fp contract(off)
   p = a * b;
   e = __builtin_fmaf(a, b, -p);
 }
@@ -28,6 +33,7 @@ __device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
 // unevaluated float-float sum (s, e) accurate to ~u^2 |a||b|.
 __device__ __forceinline__ void dot3_ff(const float ah[3], const float al[3], const float bh[3], const float bl[3],
                                         float& s, float& e) {
+#pragma clang fp contract(off)
   float p, ep, t, et;
   two_prod(ah[0], bh[0], s, e);
   two_prod(ah[1], bh[1], p, ep);
@@ -46,6 +52,7 @@ __device__ __forceinline__ void dot3_ff(const float ah[3], const float al[3], co
 // (g_s + g_e) - G for a float64 reference value G: exact leading difference
 // (Sterbenz) plus the low parts.
 __device__ __forceinline__ float diff_ff(float gs, float ge, double G) {
+#pragma clang fp contract(off)
   float Gh = (float)G;
   float Gl = (float)(G - (double)Gh);
   return (gs - Gh) + (ge - Gl);

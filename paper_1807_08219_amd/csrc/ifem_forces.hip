@@ -208,11 +208,13 @@ __device__ __forceinline__ bool tet_element(const T xs[4][3], const double G[6],
                  dh[0][1] * (dh[1][0] * dh[2][2] - dh[1][2] * dh[2][0]) +
                  dh[0][2] * (dh[1][0] * dh[2][1] - dh[1][1] * dh[2][0]);
   const bool ok = detD > T(0);
-  // current metric g = G + Delta and its inverse
-  T g[6];
-  for (int k = 0; k < 6; ++k) g[k] = (T)G[k] + D[k];
+  // current metric g = G + Delta and its inverse, formed in float64 (the inverse of a tetrahedron's
+  // metric loses cond(g) ulps; at float32 that would dominate the force error of stiff elements)
+  double gd[6], gid[6];
+  for (int k = 0; k < 6; ++k) gd[k] = G[k] + (double)D[k];
+  sym3_inverse<double>(gd, gid);
   T gi[6];
-  sym3_inverse<T>(g, gi);
+  for (int k = 0; k < 6; ++k) gi[k] = (T)gid[k];
   // S = lam/2 (J^2 - 1) g^-1 + mu g^-1 Delta G^-1
   T DG[3][3];  // Delta G^-1
   for (int a = 0; a < 3; ++a)

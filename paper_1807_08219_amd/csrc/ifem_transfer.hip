@@ -473,44 +473,33 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     }
   }
   __syncthreads();
-  // interior -> grid (final unless a neighbour's halo adds to it), y/z halo rows -> scratch.  Each
-  // thread walks r = tid, tid + nt, ... keeping (ix, iy, iz) and the grid offset up to date with
-  // adds and carries only.  Grid offsets use 32-bit wrap-around arithmetic: exact for the interior
-  // cells, the only ones stored to the grid.
+  // interior -> grid (final unless a neighbour's halo adds to it), y/z halo rows -> scratch.  A
+  // wavefront takes 64 / tile_x region rows at a time (lane -> row of the group, x), so the row is
+  // decoded once per row; (row + 1/2) / ry is at least 1/(2 ry) away from an integer, far above the
+  // rounding of this small quotient, so the truncation is exact.
   const double inv = ldexp(1.0, -sc);
-  const int rxy = rx * ry;
-  const uint32_t nx = (uint32_t)B.n[0], nxy = (uint32_t)B.n[0] * (uint32_t)B.n[1];
-  int iz = tid / rxy, iy = (tid - iz * rxy) / rx, ix = tid - iz * rxy - iy * rx;
-  const int sz = nt / rxy, sy = (nt - sz * rxy) / rx, sx = nt - sz * rxy - sy * rx;
-  uint32_t goff = (uint32_t)(c0[2] - 1 + iz) * nxy + (uint32_t)(c0[1] - 1 + iy) * nx + (uint32_t)(c0[0] + ix);
-  const uint32_t gstep = (uint32_t)sz * nxy + (uint32_t)sy * nx + (uint32_t)sx;
-  const uint32_t carry_x = nx - (uint32_t)rx, carry_y = nxy - (uint32_t)ry * nx;
+  const int lrow = lane >> a.tile_shift[0], ix = lane & (a.tile[0] - 1);
+  const int rpw = kWave >> a.tile_shift[0];  // tiles are at most 64 cells wide
+  const int nrows = ry * rz;
+  const float inv_ry = frcp((float)ry);
   const bool halo_on = active || poison;
-  for (int r = tid; r < nreg; r += nt) {
-    T v = poison ? (T)__builtin_nan("") : T(0);
+  const T fillv = poison ? (T)__builtin_nan("") : T(0);
+  for (int row0 = wave * rpw; row0 < nrows; row0 += nwaves * rpw) {
+    const int row = row0 + lrow;
+    if (row >= nrows || ix >= ex[0]) continue;
+    const int iz = (int)(((float)row + 0.5f) * inv_ry);
+    const int iy = row - iz * ry;
+    const int r = row * rx + ix;
+    T v = fillv;
     if (active) {
       double w = (double)(long long)acc[r];
       if (NW == 2) w += (double)(long long)acc[nreg + r] * 0x1p-40;
       v = (T)(w * inv);
     }
-    const bool cell = ix < ex[0];  // not the pad
-    const bool in = cell && (unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2];
-    T* dst = in ? g + goff : halo + r;
-    if (in || (cell && halo_on)) *dst = v;
-    ix += sx;
-    iy += sy;
-    iz += sz;
-    goff += gstep;
-    if (ix >= rx) {
-      ix -= rx;
-      iy += 1;
-      goff += carry_x;
-    }
-    if (iy >= ry) {
-      iy -= ry;
-      iz += 1;
-      goff += carry_y;
-    }
+    if ((unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2])
+      g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix)] = v;
+    else if (halo_on)
+      halo[r] = v;
   }
   if (tid == 0) a.tile_flag[L] = (active || poison) ? 1 : 0;
 }
