@@ -75,15 +75,23 @@ __device__ __forceinline__ double wave_max(double v) {
 // float32: the hardware square root and reciprocal (about 1 ulp); float64:
 // the correctly rounded operations.
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
-// float64 square root of a positive normal number: the hardware estimate
-// (relative error about 2^-29) refined by one Newton step to about 2^-56.
-__device__ __forceinline__ double sqrt_refined(double x) {
+// float64 square root: the hardware estimate (relative error about 2^-29)
+// refined by one Newton step to about 2^-56; exactly 0 at 0.
+__device__ __forceinline__ double fsqrt(double x) {
   const double y = __builtin_amdgcn_sqrt(x);
   const double r = __builtin_amdgcn_rcp(y);
-  return __builtin_fma(0.5 * __builtin_fma(-y, y, x), r, y);
+  const double s = __builtin_fma(0.5 * __builtin_fma(-y, y, x), r, y);
+  return x > 0.0 ? s : y;
+}
+// float64 reciprocal: the hardware estimate refined by two Newton steps
+// (e = 1 - x r, r += r e; each step squares the relative error).
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
 }
 
 // ------------------------------------------------------------------ launch order
@@ -189,9 +197,9 @@ __device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
   const bool ok = detQ > T(0) && schur > T(0);
   const T c0 = ok ? frcp(schur) : T(0);
   c[0] = c0;
-  c[1] = -c0 * y0;
-  c[2] = -c0 * y1;
-  c[3] = -c0 * y2;
+  c[1] = ok ? -c0 * y0 : T(0);
+  c[2] = ok ? -c0 * y1 : T(0);
+  c[3] = ok ? -c0 * y2 : T(0);
   return ok;
 }
 

@@ -264,6 +264,17 @@ __device__ __forceinline__ double atan2_t<double>(double y, double x) {
   return atan2(y, x);
 }
 
+// |v| and 1 / |v| from |v|^2: one reciprocal square root in float32, refined
+// square root and reciprocal in float64.
+__device__ __forceinline__ void norm_and_inverse(float n2, float& n, float& inv) {
+  inv = __builtin_amdgcn_rsqf(n2);
+  n = n2 * inv;
+}
+__device__ __forceinline__ void norm_and_inverse(double n2, double& n, double& inv) {
+  n = fsqrt(n2);
+  inv = frcp(n);
+}
+
 template <typename T, bool WITH_LAP>
 __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__ ring, int rb, int re, const T* xx,
                                               const T* xy, const T* xz, const T* g, RingGeom<T>& R) {
@@ -283,23 +294,24 @@ __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__
     // triangle (k, ja, jb): wedge from the previous neighbour to this one
     const T w[3] = {xx[jb] - xk[0], xy[jb] - xk[1], xz[jb] - xk[2]};
     const T cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
-    const T s = fsqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);  // twice the area
+    T s, inv;  // twice the area and its reciprocal
+    norm_and_inverse(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2], s, inv);
     const T uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
     const T ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
     // with e = w - u (edge ja -> jb): u.e = uw - uu, w.e = ww - uw
     const T ue = uw - uu, we = ww - uw;
-    const T inv = frcp(s);
     const T cot_a = -ue * inv;  // angle at ja, opposite edge (k, jb)
     const T cot_b = we * inv;   // angle at jb, opposite edge (k, ja)
     for (int c = 0; c < 3; ++c) {
       R.K[c] -= cot_b * u[c] + cot_a * w[c];
       R.N[c] += T(0.5) * cr[c];
     }
-    if (WITH_LAP) {  // the angle at k enters through the argument of a running complex product
-      const T inv_m = frcp(fmax(fabs(uw), s));  // rescale each factor to keep the product in range
-      const T ar = uw * inv_m, ai = s * inv_m;
-      const T zr = R.zr * ar - R.zi * ai;
-      R.zi = R.zr * ai + R.zi * ar;
+    if (WITH_LAP) {
+      // the angle at k enters through the argument of a running complex product: uw + i s has the
+      // argument of the angle, and so has (uw + i s) / s = cot + i, whose modulus 1 / sin stays small
+      const T cot_k = uw * inv;
+      const T zr = R.zr * cot_k - R.zi;
+      R.zi = R.zr + R.zi * cot_k;
       R.zr = zr;
     }
     const bool obt_k = uw < T(0), obt_a = ue > T(0), obt_b = we < T(0);
@@ -443,7 +455,7 @@ __global__ void __launch_bounds__(512) k_forces(const ForceArgs a, const T* __re
         r[0] += cone;
         for (int cc = 0; cc < 3; ++cc) r[2 + cc] += cone * (q[0][cc] + q[1][cc] + q[2][cc]) * 0.25;
         const double n2 = nx * nx + ny * ny + nz * nz;
-        r[1] += n2 > 0.0 ? 0.5 * sqrt_refined(n2) : 0.0;
+        r[1] += 0.5 * fsqrt(n2);
       }
     }
     __syncthreads();
