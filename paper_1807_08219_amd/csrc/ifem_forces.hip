@@ -103,6 +103,27 @@ __device__ __forceinline__ void metric_delta(const double xs[][3], int ne, doubl
       Delta[k] = (dh[a][0] * dh[b][0] + dh[a][1] * dh[b][1] + dh[a][2] * dh[b][2]) - Gref[k];
 }
 
+// Delta = g - G returned in float64: the float-float Gram sum (s, e) minus the
+// float64 reference, with no rounding of Delta to float (s - G is exact by
+// Sterbenz for strains below 100 %).  The float64 path forms it directly.
+__device__ __forceinline__ void metric_delta_f64(const float xs[][3], int ne, float (*dh)[3], float (*dl)[3],
+                                                 const double* Gref, double* Delta) {
+  for (int a = 0; a < ne; ++a)
+    for (int c = 0; c < 3; ++c) two_diff(xs[a + 1][c], xs[0][c], dh[a][c], dl[a][c]);
+  int k = 0;
+  for (int a = 0; a < ne; ++a)
+    for (int b = a; b < ne; ++b, ++k) {
+      float s, e;
+      dot3_ff(dh[a], dl[a], dh[b], dl[b], s, e);
+      Delta[k] = ((double)s - Gref[k]) + (double)e;
+    }
+}
+
+__device__ __forceinline__ void metric_delta_f64(const double xs[][3], int ne, double (*dh)[3], double (*dl)[3],
+                                                 const double* Gref, double* Delta) {
+  metric_delta(xs, ne, dh, dl, Gref, Delta);
+}
+
 // ------------------------------------------------------------------ membrane element
 // Returns false (and zero forces) when the current triangle is collapsed (I2 <= 0).
 template <typename T>
@@ -180,61 +201,64 @@ __device__ __forceinline__ T symget(const T s[6], int a, int b) {
 }
 
 // Returns false (and zero forces) for an inverted element (det D <= 0).
+// Only the Gram matrix comes from the working precision (float-float in the
+// float32 path, exact to about u^2 |g|); Delta, the stress and the forces are
+// formed in float64 from the exact edges.  Near-incompressible solids turn
+// any rounding of Delta into a large volumetric stress error (lambda / mu
+// times it), flat tetrahedra have ill-conditioned metrics, and the few
+// tetrahedra of a suspension make the float64 cost small.
 template <typename T>
-__device__ __forceinline__ bool tet_element(const T xs[4][3], const double G[6], double V0, T mu, T lam, T f[4][3]) {
-  T dh[3][3], dl[3][3], D[6];
-  metric_delta(xs, 3, dh, dl, G, D);
-  double Gid[6];
-  {
-    double gi[6];
-    sym3_inverse<double>(G, gi);
-    for (int k = 0; k < 6; ++k) Gid[k] = gi[k];
-  }
-  T Gi[6];
-  for (int k = 0; k < 6; ++k) Gi[k] = (T)Gid[k];
+__device__ __forceinline__ bool tet_element(const T xs[4][3], const double G[6], double V0, T mu_t, T lam_t,
+                                            T f[4][3]) {
+  T dh[3][3], dl[3][3];
+  double D[6];
+  metric_delta_f64(xs, 3, dh, dl, G, D);
+  double e[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) e[a][c] = (double)dh[a][c] + (sizeof(T) == 4 ? (double)dl[a][c] : 0.0);
+  const double mu = (double)mu_t, lam = (double)lam_t;
+  double Gi[6];
+  sym3_inverse<double>(G, Gi);
   // M = G^-1 Delta (full 3x3)
-  T M[3][3];
+  double M[3][3];
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
       M[a][b] = symget(Gi, a, 0) * symget(D, 0, b) + symget(Gi, a, 1) * symget(D, 1, b) + symget(Gi, a, 2) * symget(D, 2, b);
-  const T e1 = M[0][0] + M[1][1] + M[2][2];
-  const T e2 = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) + (M[0][0] * M[2][2] - M[0][2] * M[2][0]) +
-               (M[1][1] * M[2][2] - M[1][2] * M[2][1]);
-  const T e3 = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
-               M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
-  const T J2m1 = e1 + e2 + e3;
+  const double e1 = M[0][0] + M[1][1] + M[2][2];
+  const double e2 = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) + (M[0][0] * M[2][2] - M[0][2] * M[2][0]) +
+                    (M[1][1] * M[2][2] - M[1][2] * M[2][1]);
+  const double e3 = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                    M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                    M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  const double J2m1 = e1 + e2 + e3;
   // orientation of the current element
-  const T detD = dh[0][0] * (dh[1][1] * dh[2][2] - dh[1][2] * dh[2][1]) -
-                 dh[0][1] * (dh[1][0] * dh[2][2] - dh[1][2] * dh[2][0]) +
-                 dh[0][2] * (dh[1][0] * dh[2][1] - dh[1][1] * dh[2][0]);
-  const bool ok = detD > T(0);
-  // current metric g = G + Delta and its inverse, formed in float64 (the inverse of a tetrahedron's
-  // metric loses cond(g) ulps; at float32 that would dominate the force error of stiff elements)
-  double gd[6], gid[6];
-  for (int k = 0; k < 6; ++k) gd[k] = G[k] + (double)D[k];
-  sym3_inverse<double>(gd, gid);
-  T gi[6];
-  for (int k = 0; k < 6; ++k) gi[k] = (T)gid[k];
+  const double detD = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                      e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                      e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+  const bool ok = detD > 0.0;
+  // current metric g = G + Delta and its inverse
+  double gd[6], gi[6];
+  for (int k = 0; k < 6; ++k) gd[k] = G[k] + D[k];
+  sym3_inverse<double>(gd, gi);
   // S = lam/2 (J^2 - 1) g^-1 + mu g^-1 Delta G^-1
-  T DG[3][3];  // Delta G^-1
+  double DG[3][3];  // Delta G^-1
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
       DG[a][b] = symget(D, a, 0) * symget(Gi, 0, b) + symget(D, a, 1) * symget(Gi, 1, b) + symget(D, a, 2) * symget(Gi, 2, b);
-  T S[3][3];
-  const T kv = T(0.5) * lam * J2m1;
+  double S[3][3];
+  const double kv = 0.5 * lam * J2m1;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
       S[a][b] = kv * symget(gi, a, b) +
                 mu * (symget(gi, a, 0) * DG[0][b] + symget(gi, a, 1) * DG[1][b] + symget(gi, a, 2) * DG[2][b]);
-  const T v0 = (T)V0;
   for (int c = 0; c < 3; ++c) {
-    T s0 = 0;
+    double s0 = 0.0;
     for (int a = 0; a < 3; ++a) {
-      const T fa = ok ? -v0 * (dh[0][c] * S[0][a] + dh[1][c] * S[1][a] + dh[2][c] * S[2][a]) : T(0);
-      f[a + 1][c] = fa;
+      const double fa = ok ? -V0 * (e[0][c] * S[0][a] + e[1][c] * S[1][a] + e[2][c] * S[2][a]) : 0.0;
+      f[a + 1][c] = (T)fa;
       s0 += fa;
     }
-    f[0][c] = -s0;
+    f[0][c] = (T)(-s0);
   }
   return ok;
 }

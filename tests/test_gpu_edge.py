@@ -88,7 +88,7 @@ def test_degenerate_and_inverted_elements_are_counted_and_zeroed(dtype):
     assert st[0] == cnt[0] and st[1] == 0
     e = rel(F.cpu().numpy(), Fo)
     say(f"    forces rel err {e:.3e}")
-    assert e <= (1e-12 if dtype == ifem.IFEM_F64 else 2e-5)
+    assert e <= (1e-12 if dtype == ifem.IFEM_F64 else 1e-5)
     plan.close()
 
 
@@ -143,7 +143,7 @@ def test_points_on_lattice_nodes_and_on_the_periodic_seam(dtype):
         x, a = cu(sc.x64, torch.float64), None
     else:
         x, a = cu(sc.x32, torch.float32), cu(sc.anchor, torch.float64)
-    tol = 1e-12 if dtype == ifem.IFEM_F64 else 1e-5
+    tol = 1e-12 if dtype == ifem.IFEM_F64 else 1e-6
     Go = oracle.spread(sc, Fin)
     vo = oracle.interp(sc, u)
     for mode in (ifem.IFEM_SPREAD_TILED, ifem.IFEM_SPREAD_ATOMIC):
@@ -188,5 +188,5 @@ def test_nonfinite_force_poisons_its_home_tile_only(dtype):
     tx, ty, tz = plan.info()[3:6]
     assert nan_g[1].sum() <= 2 * tx * (ty + 2) * (tz + 2)
     fin = ~nan_g
-    assert rel(got[fin], Go[fin]) <= (1e-12 if dtype == ifem.IFEM_F64 else 1e-5)
+    assert rel(got[fin], Go[fin]) <= (1e-12 if dtype == ifem.IFEM_F64 else 1e-6)
     plan.close()

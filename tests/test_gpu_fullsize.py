@@ -18,9 +18,9 @@ from paper_1807_08219_amd.inputs import fields, scenes
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-F32_ELASTIC_TOL = 2e-5
-F32_BENDING_TOL = 2e-3
-F32_TRANSFER_TOL = 1e-5
+F32_ELASTIC_TOL = 1e-5     # normwise, elastic membrane/solid forces (~160 u32)
+F32_BENDING_TOL = 2e-5     # normwise, forces of scenes with Helfrich bending
+F32_TRANSFER_TOL = 1e-6    # normwise, spread grid and interpolated velocity (~16 u32)
 
 
 def say(msg):
