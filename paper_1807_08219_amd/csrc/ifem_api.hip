@@ -413,6 +413,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_list, (size_t)std::max<int64_t>(list_cap, 1)));
   const int region_cells = (tn.tile[0] + 1) * (tn.tile[1] + 2) * (tn.tile[2] + 2);
   HIP_TRY(mem.alloc(&d_flag, (size_t)3 * n_tiles));
+  uint32_t* d_fmax;
+  HIP_TRY(mem.alloc(&d_fmax, (size_t)3 * n_tiles));
   HIP_TRY(mem.alloc(&d_halo, (size_t)3 * n_tiles * region_cells));  // sized for float64
   plan->workspace_bytes = (int64_t)(12 * (int64_t)n_tiles + 1 + list_cap) * 4 + (int64_t)3 * n_tiles * region_cells * 8;
 
@@ -455,6 +457,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ta.tile_cursor = d_cur;
   ta.bin_list = d_list;
   ta.tile_flag = d_flag;
+  ta.tile_fmax = d_fmax;
   ta.halo = d_halo;
   ta.region_cells = region_cells;
   ta.status = d_status;

@@ -43,6 +43,7 @@ struct TransferArgs {
   int32_t* tile_cursor;           // [3 n_tiles]
   int32_t* bin_list;              // [list_cap] node ids, grouped by (component, tile)
   int32_t* tile_flag;             // [3 n_tiles] 1 if the tile wrote a halo shell this call
+  uint32_t* tile_fmax;            // [3 n_tiles] bound on |F| of each list, float32 bits (atomic max)
   void* halo;                     // [3 n_tiles][region_cells] y/z halo rows (float or double)
   unsigned long long* status;
   int64_t list_cap;

@@ -248,19 +248,36 @@ __device__ __forceinline__ void all_lists(const TransferArgs& a, const T* __rest
 }
 
 // Count pass: one thread per node; every (node, component) counts once in
-// each of its lists, one atomic per distinct list per wavefront.
+// each of its lists, one atomic per distinct list per wavefront.  The same
+// atomics raise each list's bound on |F| to the wavefront's largest |F| of
+// that component (float bits of non-negative values order like the values,
+// NaN above infinity); the bound sets the list's fixed-point scale.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_count(const TransferArgs a, const T* __restrict__ x,
-                                                   const double* __restrict__ anchor) {
+                                                   const double* __restrict__ anchor, const T* __restrict__ F) {
   constexpr int NK = 3 * kListsPerEntry;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   int key[NK];
   all_lists(a, x, anchor, k, key);
+  uint32_t fm[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    uint32_t v = k < a.n_nodes ? __float_as_uint(fabsf((float)F[d * (int64_t)a.n_nodes + k])) : 0u;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      const uint32_t w = __shfl_xor(v, o, kWave);
+      v = w > v ? w : v;
+    }
+    fm[d] = v;
+  }
 #pragma unroll
   for (int i = 0; i < NK; ++i) {
     int leader, rank, size;
     wave_groups(key[i], leader, rank, size);
-    if (size > 0) atomicAdd(a.tile_count + key[i], size);
+    if (size > 0) {
+      atomicAdd(a.tile_count + key[i], size);
+      atomicMax(a.tile_fmax + key[i], fm[i / kListsPerEntry]);
+    }
   }
 }
 
@@ -346,8 +363,6 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
                                                               const double* __restrict__ anchor,
                                                               const T* __restrict__ F, T* __restrict__ grid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double wm[16];
-  __shared__ int wb[16];
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);
   constexpr int NW = FixedAcc<T>::kWords;
   const int w = xcd_remap(blockIdx.x, gridDim.x), tile = w / 3, d = w - 3 * tile;  // the 3 components of a tile adjacent
@@ -370,29 +385,12 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   const int64_t NN = a.n_nodes;
   const T* Fd = F + d * NN;
 
-  // fixed-point scale from the largest |F| of the list and its length; a non-finite force
-  // cannot be held in fixed point and poisons (NaN) the tile's whole region instead
-  double m = 0.0;
-  bool bad = false;
-  for (int e = tid; e < cnt; e += nt) {
-    const double v = fabs((double)Fd[list[e]]);
-    bad |= !(v <= DBL_MAX);
-    m = fmax(m, v);
-  }
-  m = wave_max(m);
-  const bool wbad = __ballot(bad) != 0ull;
-  if (lane == 0) {
-    wm[wave] = m;
-    wb[wave] = wbad ? 1 : 0;
-  }
+  // fixed-point scale from the bound on |F| of the list (raised by the count pass) and its length; a
+  // non-finite force cannot be held in fixed point and poisons (NaN) the tile's whole region instead
+  const double m = (double)__uint_as_float(a.tile_fmax[L]);
+  const bool poison = cnt > 0 && !(m <= DBL_MAX);
   for (int i = tid; i < NW * nreg; i += nt) acc[i] = 0ull;
   __syncthreads();
-  m = 0.0;
-  bool poison = false;
-  for (int w = 0; w < nwaves; ++w) {
-    m = fmax(m, wm[w]);
-    poison |= wb[w] != 0;
-  }
   const bool active = cnt > 0 && m > 0.0 && !poison;
   int sc = 0;
   if (active) {
@@ -636,15 +634,16 @@ hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const
   const int nl = 3 * a.n_tiles;
   P.timer->begin(K_FILL, st);
   hipError_t e = fill(a.tile_count, (int64_t)nl, 0, st);
+  if (e == hipSuccess) e = fill(a.tile_fmax, (int64_t)nl, 0u, st);
   P.timer->end(st);
   if (e != hipSuccess) return e;
   const dim3 ng = node_grid(a.n_nodes, 256), nb(256);
   if (a.n_nodes) {
     P.timer->begin(K_BIN_COUNT, st);
     if (dtype == 0)
-      hipLaunchKernelGGL(k_bin_count<float>, ng, nb, 0, st, a, (const float*)x, anchor);
+      hipLaunchKernelGGL(k_bin_count<float>, ng, nb, 0, st, a, (const float*)x, anchor, (const float*)F);
     else
-      hipLaunchKernelGGL(k_bin_count<double>, ng, nb, 0, st, a, (const double*)x, anchor);
+      hipLaunchKernelGGL(k_bin_count<double>, ng, nb, 0, st, a, (const double*)x, anchor, (const double*)F);
     P.timer->end(st);
   }
   P.timer->begin(K_SCAN, st);
