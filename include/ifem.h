@@ -191,12 +191,11 @@ ifem_status ifem_element_forces(ifem_plan plan, int32_t dtype, const void* x, co
  * The grid holds forces (its sum equals the Lagrangian total), not densities.
  * IFEM_SPREAD_TILED (default) sums in 64-bit fixed point per lattice tile:
  * bitwise reproducible, no global float atomics.  A non-finite force
- * component (or a float64 one beyond the float32 range, 3.4e38, which the
- * per-tile bound on |F| is kept in) cannot be held in fixed point: it turns
- * the tiles that take its
- * stencil (its home tile and at most one x-neighbour), plus their one-cell
- * y/z halos, into NaN for that component (the plain IFEM_SPREAD_ATOMIC mode
- * spreads it to the 27 stencil cells only). */
+ * component, or a float64 one beyond the float32 range (3.4e38, the range of
+ * the per-tile bound on |F|), cannot be held in fixed point: it turns the
+ * tiles that take its stencil (its home tile and at most one x-neighbour),
+ * plus their one-cell y/z halos, into NaN for that component (the plain
+ * IFEM_SPREAD_ATOMIC mode spreads it to the 27 stencil cells only). */
 ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F,
                         void* grid, void* stream);
 
