@@ -274,7 +274,6 @@ struct RingGeom {
   T K[3];      // sum (cot a + cot b)(x_k - x_j)
   T N[3];      // sum of face area vectors
   T zr, zi;    // product of (u.w + i |u x w|) over the fan: its argument is sum(theta) - 2 pi
-  T lap;       // sum (cot a + cot b)(g_j - g_k) for a nodal field g
 };
 
 template <typename T>
@@ -299,20 +298,19 @@ __device__ __forceinline__ void norm_and_inverse(double n2, double& n, double& i
   inv = frcp(n);
 }
 
-template <typename T, bool WITH_LAP>
+// One-ring quantities of node k for the curvature pass: mixed area, the
+// cotangent sum K, the area-vector sum N and the angle product z.
+template <typename T>
 __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__ ring, int rb, int re, const T* xx,
-                                              const T* xy, const T* xz, const T* g, RingGeom<T>& R) {
+                                              const T* xy, const T* xz, RingGeom<T>& R) {
   const T xk[3] = {xx[k], xy[k], xz[k]};
   R.A = 0;
   R.zr = 1;
   R.zi = 0;
-  R.lap = 0;
   for (int c = 0; c < 3; ++c) R.K[c] = R.N[c] = 0;
-  const T gk = WITH_LAP ? g[k] : T(0);
   int ja = ring[re - 1];
   T u[3] = {xx[ja] - xk[0], xy[ja] - xk[1], xz[ja] - xk[2]};
   T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  T ga = WITH_LAP ? g[ja] : T(0);
   for (int r = rb; r < re; ++r) {
     const int jb = ring[r];
     // triangle (k, ja, jb): wedge from the previous neighbour to this one
@@ -330,25 +328,51 @@ __device__ __forceinline__ void ring_geometry(int k, const int32_t* __restrict__
       R.K[c] -= cot_b * u[c] + cot_a * w[c];
       R.N[c] += T(0.5) * cr[c];
     }
-    if (WITH_LAP) {
-      // the angle at k enters through the argument of a running complex product: uw + i s has the
-      // argument of the angle, and so has (uw + i s) / s = cot + i, whose modulus 1 / sin stays small
-      const T cot_k = uw * inv;
-      const T zr = R.zr * cot_k - R.zi;
-      R.zi = R.zr + R.zi * cot_k;
-      R.zr = zr;
-    }
+    // the angle at k enters through the argument of a running complex product: uw + i s has the
+    // argument of the angle, and so has (uw + i s) / s = cot + i, whose modulus 1 / sin stays small
+    const T cot_k = uw * inv;
+    const T zr = R.zr * cot_k - R.zi;
+    R.zi = R.zr + R.zi * cot_k;
+    R.zr = zr;
     const bool obt_k = uw < T(0), obt_a = ue > T(0), obt_b = we < T(0);
     if (!(obt_k || obt_a || obt_b))
       R.A += T(0.125) * (uu * cot_b + ww * cot_a);
     else
       R.A += obt_k ? T(0.25) * s : T(0.125) * s;
-    if (WITH_LAP) {
-      const T gb = g[jb];
-      R.lap += cot_b * (ga - gk) + cot_a * (gb - gk);
-      ga = gb;
-    }
     ja = jb;
+    for (int c = 0; c < 3; ++c) u[c] = w[c];
+    uu = ww;
+  }
+}
+
+// One-ring quantities of node k for the Laplacian pass: the area-vector sum N
+// (the same operations as ring_geometry, so the same normal) and the
+// cotangent sum of g_j - g_k.
+template <typename T>
+__device__ __forceinline__ void ring_laplacian(int k, const int32_t* __restrict__ ring, int rb, int re, const T* xx,
+                                               const T* xy, const T* xz, const T* g, T N[3], T& lap) {
+  const T xk[3] = {xx[k], xy[k], xz[k]};
+  const T gk = g[k];
+  N[0] = N[1] = N[2] = 0;
+  lap = 0;
+  int ja = ring[re - 1];
+  T u[3] = {xx[ja] - xk[0], xy[ja] - xk[1], xz[ja] - xk[2]};
+  T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  T ga = g[ja];
+  for (int r = rb; r < re; ++r) {
+    const int jb = ring[r];
+    const T w[3] = {xx[jb] - xk[0], xy[jb] - xk[1], xz[jb] - xk[2]};
+    const T cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    T s, inv;
+    norm_and_inverse(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2], s, inv);
+    const T uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+    const T ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const T cot_a = -(uw - uu) * inv;
+    const T cot_b = (ww - uw) * inv;
+    for (int c = 0; c < 3; ++c) N[c] += T(0.5) * cr[c];
+    const T gb = g[jb];
+    lap += cot_b * (ga - gk) + cot_a * (gb - gk);
+    ga = gb;
     for (int c = 0; c < 3; ++c) u[c] = w[c];
     uu = ww;
   }
@@ -525,35 +549,39 @@ __global__ void __launch_bounds__(512) k_forces(const ForceArgs a, const T* __re
     }
     __syncthreads();
   }
-  // --- Helfrich bending: F = 2 kb [Lap(kH - kH0) + 2 (kH - kH0)(kH^2 - kG + kH0 kH)] n A
+  // --- Helfrich bending: F = 2 kb [Lap(kH - kH0) + 2 (kH - kH0)(kH^2 - kG + kH0 kH)] n A.  The
+  // curvature pass adds the second term; with Lap f = (1 / 2A) sum (cot a + cot b)(f_j - f_k), the
+  // first is kb n sum (cot a + cot b)(g_j - g_k), g = kH - kH0, added by the Laplacian pass.
   const double kbp = a.kb[p];
   if (kbp != 0.0 && a.ring_start != nullptr) {
     const int* rs = a.ring_start + n0;
     const T kH0 = (T)(-0.5 * a.c0[p]);
+    const T kb = (T)kbp;
     for (int k = tid; k < nn; k += nt) {
       if (rs[k + 1] - rs[k] < 3) {  // node without a closed fan: no curvature
         kh[k] = 0;
         continue;
       }
       RingGeom<T> R;
-      ring_geometry<T, false>(k, a.ring, rs[k], rs[k + 1], xx, xy, xz, nullptr, R);
+      ring_geometry<T>(k, a.ring, rs[k], rs[k + 1], xx, xy, xz, R);
       T kH, kG, nv[3];
-      ring_curvature(R, false, kH, kG, nv);
-      kh[k] = kH - kH0;
+      ring_curvature(R, true, kH, kG, nv);
+      const T gk = kH - kH0;
+      kh[k] = gk;
+      const T s2 = T(4) * kb * gk * (kH * kH - kG + kH0 * kH) * R.A;
+      acc[k] += s2 * nv[0];
+      acc[a.cap + k] += s2 * nv[1];
+      acc[2 * a.cap + k] += s2 * nv[2];
     }
     __syncthreads();
     for (int k = tid; k < nn; k += nt) {
       if (rs[k + 1] - rs[k] < 3) continue;
-      RingGeom<T> R;
-      ring_geometry<T, true>(k, a.ring, rs[k], rs[k + 1], xx, xy, xz, kh, R);
-      T kH, kG, nv[3];
-      ring_curvature(R, true, kH, kG, nv);
-      const T gk = kh[k];
-      const T lap = R.lap / (T(2) * R.A);
-      const T s = T(2) * (T)kbp * (lap + T(2) * gk * (kH * kH - kG + kH0 * kH)) * R.A;
-      acc[k] += s * nv[0];
-      acc[a.cap + k] += s * nv[1];
-      acc[2 * a.cap + k] += s * nv[2];
+      T N[3], lap;
+      ring_laplacian<T>(k, a.ring, rs[k], rs[k + 1], xx, xy, xz, kh, N, lap);
+      const T s1 = kb * lap * frcp(fsqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]));
+      acc[k] += s1 * N[0];
+      acc[a.cap + k] += s1 * N[1];
+      acc[2 * a.cap + k] += s1 * N[2];
     }
     __syncthreads();
   }
