@@ -57,6 +57,7 @@ def lib():
         L.orc_laplacian.argtypes = [_D, C.c_long, C.c_int, C.c_int, _I, C.c_long, C.c_int, C.c_int, _D, _D, _D]
         L.orc_spread.argtypes = [C.c_int, _D, _D, _I, _I, _D, _D, _L, C.c_int64, _D]
         L.orc_interp.argtypes = [C.c_int, _D, _I, _I, _D, _D, _L, C.c_int64, _D, _D]
+        L.orc_volume_correct.argtypes = [C.c_int, _D, C.c_int, _I, _I, _I, C.c_int, _I, _D, _D, _D]
         _lib = L
     return _lib
 
@@ -186,3 +187,18 @@ def interp(scene, grid, x=None, box_of_point=None):
     v = np.zeros((3, x.shape[1]))
     lib().orc_interp(x.shape[1], x, bop, n, h, o, off, scene.total_cells, _c(grid, np.float64), v)
     return v
+
+
+def volume_correct(scene, V0=None, x=None):
+    """Membrane volume correction of Sec. II.E: (x_out [3][n_nodes], Lambda [n_particles], non-converged count).
+
+    V0 defaults to each particle's volume in the reference configuration."""
+    x = scene.x64 if x is None else x
+    if V0 is None:
+        V0 = reduce(scene, x=scene.X_ref)[:, 0]
+    out = np.zeros((3, scene.n_nodes))
+    lam = np.zeros(scene.n_particles)
+    ns, ts, qs, tri, ntri, tet, ntet = _scene_args(scene)
+    bad = lib().orc_volume_correct(scene.n_nodes, _c(x, np.float64), scene.n_particles, ns, ts, tri, ntri,
+                                   _c(scene.law, np.int32), _c(V0, np.float64), out, lam)
+    return out, lam, bad
