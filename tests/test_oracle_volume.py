@@ -129,3 +129,24 @@ def test_no_drift_and_solids_untouched():
         else:
             t = mixed.tri[:, mixed.tri_start[p]:mixed.tri_start[p + 1]].T
             assert np_volume(out, t) == pytest.approx(np_volume(mixed.X_ref, t), rel=1e-13)
+
+
+def test_correction_is_the_shortest_along_any_direction():
+    # the cost function of Sec. II.E: among displacements mu w that restore V0 along random
+    # directions w, none is shorter than Lambda alpha (to second order in the drift)
+    sc, tris = _drifted(nu=4, rel=2e-3)
+    V0 = np_volume(sc.X_ref, tris)
+    out, lam, _ = oracle.volume_correct(sc)
+    best = np.linalg.norm(out - sc.x64)
+    rng = np.random.default_rng(17)
+    alpha = (out - sc.x64) / lam[0]
+    for trial in range(20):
+        w = rng.normal(size=sc.x64.shape) + (3.0 if trial % 2 else 0.0) * alpha / np.abs(alpha).max()
+        # V(x + mu w) - V0 is a cubic in mu: fit it from four evaluations, take the smallest root
+        s = 1e-2 / np.abs(w).max()
+        Ms = np.array([-2 * s, -s, s, 2 * s])
+        vals = np.array([np_volume(sc.x64 + m * w, tris) - V0 for m in Ms])
+        roots = np.roots(np.linalg.solve(np.vander(Ms, 4), vals))
+        real = roots[np.abs(roots.imag) <= 1e-9 * np.abs(roots).max()].real
+        mu = real[np.argmin(np.abs(real))]
+        assert np.linalg.norm(mu * w) >= best * (1 - 1e-3)
