@@ -41,6 +41,7 @@ MLS_FLOPS = 27 * 14 + 9 * 20 + 60 + 27 * 5
 VALU_PEAK_TFLOPS = 157.3  # MI355X float32 vector peak (packed issue); 256 CU x 2.4 GHz x 256 flop/cycle
 VALU_NONPACKED_TFLOPS = 78.6  # the same without packed float32 issue, which this build does not use
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X float64 vector peak
 
 
 def algorithmic(sc, fp64: bool):
@@ -59,6 +60,22 @@ def algorithmic(sc, fp64: bool):
         "k_bin_count": (sc.n_nodes * vec, None),
         "k_bin_fill": (sc.n_nodes * vec + 3 * sc.n_nodes * 4, None),
     }
+
+
+def volume_algorithmic(sc, fp64: bool):
+    """Algorithmic bytes and float64 flops of one membrane volume correction (Sec. II.E).
+
+    Bytes: positions read and written once (2 x 12 B per node in float32, 2 x 24 B in float64) and
+    the connectivity once (12 B per triangle: its three corners, which are also the one-ring
+    entries of the three nodes).  Flops, as the kernel evaluates the face sums node by node over
+    one-rings (3 entries per triangle): per ring entry an edge vector (3), a cross product (9) and
+    its sum (3) for alpha, a cross product of alpha values (9) and its sum (3) for beta: 27; per
+    node alpha's scaling (3), |alpha|^2 and x.alpha (15), alpha.beta and x.beta (12) and the
+    update x + L alpha (6): 36."""
+    vec = 24 if fp64 else 12
+    mem = sc.tri_start[1:] != sc.tri_start[:-1]
+    nodes = int(np.diff(sc.node_start)[mem].sum())
+    return sc.n_nodes * 2 * vec + sc.n_tris * 12, sc.n_tris * 3 * 27 + nodes * 36
 
 
 def step_bytes(sc, fp64: bool):
@@ -116,6 +133,47 @@ def cpu_baseline(sc, u64, budget_s: float):
                       f"spread onto the full grid, interpolation; {t_total:.1f} s single-threaded FP64"}
 
 
+def bench_volume(plan, sc, steps, dev, stream):
+    """Membrane volume correction (Sec. II.E) of positions whose volumes drifted by up to 0.1 %:
+    float32 offsets and float64 positions, kernel time from the library's event timer."""
+    import torch
+
+    from paper_1807_08219_amd import ifem
+    from paper_1807_08219_amd.inputs import scenes
+
+    dr = scenes.with_volume_drift(sc, rel=1e-3, seed=5)
+    res = {"workload": f"{sc.name}, membrane volumes drifted by U(-0.1 %, 0.1 %)"}
+    for dt, key, xin in ((ifem.IFEM_F32, "f32", dr.x32), (ifem.IFEM_F64, "f64", dr.x64)):
+        x = torch.as_tensor(xin, device=dev)
+        xo = torch.empty_like(x)
+        lam = torch.empty(sc.n_particles, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            plan.volume_correct(dt, x, xo, lambda_out=lam)
+        torch.cuda.synchronize()
+        plan.set(ifem.IFEM_OPT_KERNEL_TIMING, steps + 8)
+        plan.kernel_times(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.volume_correct(dt, x, xo, lambda_out=lam)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        kt = plan.kernel_times(reset=True)
+        plan.set(ifem.IFEM_OPT_KERNEL_TIMING, 0)
+        ms = kt["k_volume"][0] / kt["k_volume"][1]
+        nbytes, flops = volume_algorithmic(sc, key == "f64")
+        gbs, tfs = nbytes / (ms * 1e-3) / 1e9, flops / (ms * 1e-3) / 1e12
+        res[key] = {"ms": round(ms, 4), "wall_ms": round(wall, 4), "value": round(sc.n_nodes / (ms * 1e-3), 1),
+                    "unit": "nodes/s",
+                    "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(nbytes),
+                                 "fp64_tflops": round(tfs, 3), "fp64_frac": round(tfs / FP64_PEAK_TFLOPS, 4)},
+                    "multiplier_range": [float(lam.min()), float(lam.max())]}
+        log(f"volume correction {key}: {ms:.4f} ms ({gbs:.0f} GB/s algorithmic, {tfs:.2f} fp64 TFLOP/s)")
+        del x, xo
+    res["device_status"] = plan.status()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +184,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="spread tile, e.g. 32,16,8 (powers of two)")
     ap.add_argument("--block-forces", type=int, default=None, help="threads per particle workgroup")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -268,6 +327,9 @@ def main():
     out["graph_replay"] = {"ms_per_step": round(ms_graph, 4), "value": round(sc.n_nodes / (ms_graph * 1e-3), 1),
                            "steps": args.steps}
     del graph
+
+    if not args.no_volume:
+        out["volume_correct"] = bench_volume(plan, sc, args.steps, dev, stream)
 
     if not args.no_fp64:
         x64 = torch.as_tensor(sc.x64, device=dev)

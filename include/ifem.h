@@ -14,16 +14,20 @@
  *   ifem_interp          v_k = sum_J phi_J(x_J - x_k) v_J back to the nodes
  *                        (Sec. II.C interpolation operator);
  *
+ * and, after the positions are advanced, the membrane volume correction of
+ * Sec. II.E (ifem_volume_correct),
+ *
  * with phi the linear moving-least-squares weights of Sec. II.C (27-node
  * stencil around the nearest lattice node, cubic-spline weight, support
  * sqrt(3) h).
  *
  * Conventions
  * -----------
- * Every array passed to the three step calls is DEVICE memory owned by the
+ * Every array passed to the step calls is DEVICE memory owned by the
  * caller; the library never frees or reallocates it.  Inputs are not
  * modified; outputs are overwritten (never accumulated).  An output may not
- * alias an input: that is rejected with IFEM_ERR_INVALID_ARG.
+ * alias an input (except the in-place volume correction): that is rejected
+ * with IFEM_ERR_INVALID_ARG.
  *
  * Layouts (structure of arrays, 32-bit indices):
  *   positions, forces, velocities   [3][n_nodes]  (component-major)
@@ -64,7 +68,9 @@
  *   counts[2]  points whose MLS moment matrix was singular (weights zero);
  *   counts[3]  nodes a tiled spread skipped because their nearest lattice
  *              node moved between binning and accumulation (positions
- *              written concurrently with the call); 0 in normal use.
+ *              written concurrently with the call); 0 in normal use;
+ *   counts[4]  membranes whose volume-correction multiplier did not converge
+ *              (ifem_volume_correct; their nodes are moved by the last iterate).
  */
 #ifndef IFEM_H
 #define IFEM_H
@@ -115,7 +121,8 @@ enum {
   IFEM_KERNEL_SPREAD_MERGE = 8,  /* spread: neighbour halos added to tile border cells  */
   IFEM_KERNEL_SPREAD_ATOMIC = 5, /* spread: plain global-atomic baseline                */
   IFEM_KERNEL_INTERP = 6,        /* interpolation                                       */
-  IFEM_KERNEL_FILL = 7           /* zero fills                                          */
+  IFEM_KERNEL_FILL = 7,          /* zero fills                                          */
+  IFEM_KERNEL_VOLUME = 9         /* membrane volume correction                          */
 };
 
 /* Mesh description, HOST memory, read once by ifem_plan_create. */
@@ -203,6 +210,34 @@ ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const doub
 ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* grid_u,
                         void* v_out, void* stream);
 
+/* Membrane volume conservation (Sec. II.E, conservation of volume for
+ * membranes), applied to positions after they have been advanced.  For every
+ * membrane the nodes move by dx_I = L alpha_I: alpha_I = -(1/2) dV/dx_I is the
+ * stationary direction of the section's cost function (sum of squared nodal
+ * displacements plus a multiplier times the volume error), and L is the real
+ * root of smallest magnitude of the cubic A L^3 + B L^2 + C L + D = 0 with the
+ * section's coefficients, D = V(x) - V0, so that the enclosed volume after the
+ * move equals V0.  L is found by Newton's iteration from 0 (counts[4] of
+ * ifem_plan_status counts membranes where it did not converge).  Everything is
+ * computed in float64.  Solids (tetrahedral particles) are copied unchanged.
+ *   x           [3][n_nodes] positions (see dtype), device.  IFEM_F32: float32
+ *               offsets from the caller's per-particle anchors; the correction
+ *               does not depend on the anchors (volume and alpha are unchanged by
+ *               a translation of a closed surface), so none is passed, and x_out
+ *               holds offsets from the same anchors.
+ *   V0          [n_particles] float64 target volumes, device, or NULL for the
+ *               volumes of the reference configuration X_ref (computed by
+ *               ifem_plan_create); entries of solids are ignored.
+ *   x_out       [3][n_nodes] corrected positions, same dtype.  x_out == x
+ *               corrects in place; any other overlap with an input is rejected.
+ *   lambda_out  [n_particles] float64 multipliers L (0 for solids), or NULL.
+ * Returns IFEM_ERR_UNSUPPORTED if a membrane's triangles do not form a closed,
+ * consistently oriented surface (its enclosed volume is then undefined), or if
+ * the largest particle exceeds 6784 nodes (its float64 alpha sums must fit one
+ * workgroup's LDS). */
+ifem_status ifem_volume_correct(ifem_plan plan, int32_t dtype, const void* x, const double* V0, void* x_out,
+                                double* lambda_out, void* stream);
+
 /* Synchronise `stream` and the timer's events; total_ms[i] and launches[i]
  * receive the summed duration and number of launches of kernel slot i
  * (IFEM_KERNEL_*) recorded since the last reset; launches[15] counts launches
@@ -210,14 +245,14 @@ ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const doub
 ifem_status ifem_plan_kernel_times(ifem_plan plan, void* stream, double total_ms[16], int64_t launches[16],
                                    int32_t reset);
 
-/* Synchronise `stream`, copy the device status counters into counts[4] and,
+/* Synchronise `stream`, copy the device status counters into counts[5] and,
  * if reset != 0, clear them. */
-ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[4], int32_t reset);
+ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[5], int32_t reset);
 
 /* Thread-local description of the last non-OK return ("" if none). */
 const char* ifem_last_error(void);
 
-/* Library version, e.g. 10000 for 1.0.0. */
+/* Library version, e.g. 10100 for 1.1.0. */
 int32_t ifem_version(void);
 
 #ifdef __cplusplus

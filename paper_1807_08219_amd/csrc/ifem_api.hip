@@ -62,6 +62,7 @@ struct ifem_plan_s {
   ifem_tuning tune{};
   int spread_mode = IFEM_SPREAD_TILED;
   int64_t workspace_bytes = 0;
+  int32_t open_surface = -1;  // first membrane whose faces do not close, or -1
 };
 
 // ------------------------------------------------------------------ host-side mesh preprocessing
@@ -135,10 +136,12 @@ ifem_status build_coloured(const int32_t* conn, int n_all, int n_p, const int32_
   return IFEM_OK;
 }
 
-// Ordered one-ring of every node of the bending particles: neighbours
-// j_1..j_v with (k, j_i, j_{i+1}) counter-clockwise triangles of the mesh.
+// Ordered one-ring of every node of the selected particles (bending, and the
+// volume correction): neighbours j_1..j_v with (k, j_i, j_{i+1})
+// counter-clockwise triangles of the mesh.  On failure *bad_node is the node
+// whose fan is open, non-manifold or pinched.
 ifem_status build_rings(const ifem_mesh_desc& m, const std::vector<char>& bend, std::vector<int32_t>& rstart,
-                        std::vector<int32_t>& ring) {
+                        std::vector<int32_t>& ring, int* bad_node) {
   const int nN = m.n_nodes, nT = m.n_tris;
   std::vector<int32_t> wcount(nN + 1, 0);
   for (int p = 0; p < m.n_particles; ++p) {
@@ -171,6 +174,7 @@ ifem_status build_rings(const ifem_mesh_desc& m, const std::vector<char>& bend, 
     const int b = wcount[k], e = wcount[k + 1], v = e - b;
     if (v == 0) continue;
     const int node0 = m.node_start[node_p[k]];
+    *bad_node = k;
     if (v < 3) return fail(IFEM_ERR_UNSUPPORTED, "node %d has %d incident triangles; bending needs a closed surface", k, v);
     int j = wa[b];
     for (int step = 0; step < v; ++step) {
@@ -183,6 +187,8 @@ ifem_status build_rings(const ifem_mesh_desc& m, const std::vector<char>& bend, 
         }
       if (hits != 1) return fail(IFEM_ERR_UNSUPPORTED, "non-manifold or open one-ring at node %d", k);
       j = nxt;
+      if (j == wa[b] && step + 1 < v)
+        return fail(IFEM_ERR_UNSUPPORTED, "node %d joins two fans of triangles (pinched surface)", k);
     }
     if (j != wa[b]) return fail(IFEM_ERR_UNSUPPORTED, "one-ring of node %d does not close", k);
   }
@@ -269,10 +275,44 @@ hipError_t upload(DeviceBuffers& mem, T** dst, const T* src, size_t n, hipStream
 
 }  // namespace
 
+namespace {
+
+// First particle whose triangles do not form a closed, consistently oriented
+// surface (every directed edge once and its reverse once), or -1.  The
+// enclosed volume, and so the volume correction, is defined only for those.
+int first_open_surface(const ifem_mesh_desc& m) {
+  std::vector<int32_t> start, fill, nb;
+  for (int p = 0; p < m.n_particles; ++p) {
+    const int t0 = m.tri_start[p], t1 = m.tri_start[p + 1];
+    if (t1 == t0) continue;
+    const int n0 = m.node_start[p], nn = m.node_start[p + 1] - n0;
+    start.assign((size_t)nn + 1, 0);
+    for (int t = t0; t < t1; ++t)
+      for (int v = 0; v < 3; ++v) ++start[m.tri[v * m.n_tris + t] - n0 + 1];
+    for (int i = 0; i < nn; ++i) start[i + 1] += start[i];
+    fill.assign(start.begin(), start.end() - 1);
+    nb.resize(start[nn]);
+    for (int t = t0; t < t1; ++t)
+      for (int v = 0; v < 3; ++v) nb[fill[m.tri[v * m.n_tris + t] - n0]++] = m.tri[((v + 1) % 3) * m.n_tris + t] - n0;
+    for (int a = 0; a < nn; ++a)
+      for (int i = start[a]; i < start[a + 1]; ++i) {
+        const int b = nb[i];
+        for (int j = start[a]; j < i; ++j)
+          if (nb[j] == b) return p;  // the directed edge a -> b twice
+        bool rev = false;
+        for (int j = start[b]; j < start[b + 1] && !rev; ++j) rev = nb[j] == a;
+        if (!rev) return p;  // a boundary edge or an orientation flip
+      }
+  }
+  return -1;
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
-int32_t ifem_version(void) { return 10000; }
+int32_t ifem_version(void) { return 10100; }
 
 const char* ifem_last_error(void) { return g_last_error.c_str(); }
 
@@ -315,10 +355,30 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     any_bend = any_bend || bend[p];
     cap = std::max(cap, m.node_start[p + 1] - m.node_start[p]);
   }
+  // one-rings for bending, and for every membrane when all are closed (the volume correction)
+  int open_surface = first_open_surface(m);
+  std::vector<char> ringset(bend);
+  bool any_ring = any_bend;
+  if (open_surface < 0)
+    for (int p = 0; p < m.n_particles; ++p)
+      if (m.tri_start[p + 1] > m.tri_start[p]) ringset[p] = 1, any_ring = true;
   std::vector<int32_t> rstart, ring;
-  if (any_bend) {
-    s = build_rings(m, bend, rstart, ring);
-    if (s != IFEM_OK) return s;
+  if (any_ring) {
+    int bad_node = -1;
+    s = build_rings(m, ringset, rstart, ring, &bad_node);
+    if (s != IFEM_OK) {
+      int pb = 0;
+      while (m.node_start[pb + 1] <= bad_node) ++pb;
+      if (bend[pb]) return s;  // a bending surface must close
+      open_surface = pb;       // only the volume correction is out of reach
+      any_ring = any_bend;
+      rstart.clear();
+      ring.clear();
+      if (any_bend) {
+        s = build_rings(m, bend, rstart, ring, &bad_node);
+        if (s != IFEM_OK) return s;
+      }
+    }
   }
   if ((size_t)(3 + (any_bend ? 1 : 0)) * cap * sizeof(double) > kLdsLimit)
     return fail(IFEM_ERR_UNSUPPORTED, "a particle with %d nodes does not fit one workgroup's LDS", cap);
@@ -350,6 +410,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   // --- device upload
   ifem_plan plan = new ifem_plan_s();
   plan->tune = tn;
+  plan->open_surface = open_surface;
   PlanDev& P = plan->P;
   P.timer = &plan->timer;
   P.n_particles = m.n_particles;
@@ -365,7 +426,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   int32_t *d_tet_src, *d_tet_glob, *d_tet_local, *d_tet_pcol, *d_tet_colb, *d_rstart = nullptr, *d_ring = nullptr;
   int32_t *d_np, *d_tile_box, *d_cnt, *d_off, *d_cur, *d_list, *d_flag;
   double* d_halo;
-  double *d_mu, *d_mu2, *d_kb, *d_c0, *d_tri_ref, *d_tet_ref, *d_X;
+  double *d_mu, *d_mu2, *d_kb, *d_c0, *d_tri_ref, *d_tet_ref, *d_X, *d_vref;
   BoxDev* d_boxes;
   unsigned long long* d_status;
   const int np = m.n_particles;
@@ -388,7 +449,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(upload(mem, &d_tet_local, tet_local.data(), tet_local.size(), st));
   HIP_TRY(upload(mem, &d_tet_pcol, tet_pcol.data(), tet_pcol.size(), st));
   HIP_TRY(upload(mem, &d_tet_colb, tet_colb.data(), tet_colb.size(), st));
-  if (any_bend) {
+  if (any_ring) {
     HIP_TRY(upload(mem, &d_rstart, rstart.data(), rstart.size(), st));
     HIP_TRY(upload(mem, &d_ring, ring.data(), ring.size(), st));
   }
@@ -398,7 +459,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(upload(mem, &d_X, m.X_ref, (size_t)3 * m.n_nodes, st));
   HIP_TRY(mem.alloc(&d_tri_ref, (size_t)4 * m.n_tris));
   HIP_TRY(mem.alloc(&d_tet_ref, (size_t)7 * m.n_tets));
-  HIP_TRY(mem.alloc(&d_status, 4));
+  HIP_TRY(mem.alloc(&d_status, 5));
+  HIP_TRY(mem.alloc(&d_vref, (size_t)np));
   const int n_tiles = (int)tile_box.size();
   // a (node, component) sits in its home list and at most one x-neighbour's, or both neighbours' when
   // a box ends in a one-cell-wide tile between two others
@@ -425,6 +487,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   P.tet_global = d_tet_glob;
   P.tet_ref = d_tet_ref;
   P.status = d_status;
+  P.vref = d_vref;
   ForceArgs& fa = P.fargs;
   fa.node_start = d_ns;
   fa.law = d_law;
@@ -447,6 +510,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   fa.n_tris = m.n_tris;
   fa.n_tets = m.n_tets;
   fa.cap = cap;
+  fa.has_bending = any_bend ? 1 : 0;
   TransferArgs& ta = P.targs;
   ta.node_particle = d_np;
   ta.particle_box = d_box;
@@ -472,9 +536,10 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   }
 
   // --- reference metrics on the device (float64), degeneracy check
-  HIP_TRY(launch_fill_u64(d_status, 4, st));
+  HIP_TRY(launch_fill_u64(d_status, 5, st));
   HIP_TRY(launch_ref_setup(P, d_X, st));
-  unsigned long long hs[4];
+  HIP_TRY(launch_ref_volume(P, d_X, d_vref, st));
+  unsigned long long hs[5];
   HIP_TRY(hipMemcpyAsync(hs, d_status, sizeof hs, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (hs[3] != 0) {
@@ -482,9 +547,10 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     delete plan;
     return fail(IFEM_ERR_DEGENERATE, "%llu reference elements have non-positive area or volume", hs[3]);
   }
-  HIP_TRY(launch_fill_u64(d_status, 4, st));
+  HIP_TRY(launch_fill_u64(d_status, 5, st));
   HIP_TRY(prepare_force_kernels(P));
   HIP_TRY(prepare_transfer_kernels(P));
+  HIP_TRY(prepare_volume_kernels(P));
   HIP_TRY(hipStreamSynchronize(st));
   *out = plan;
   return ok();
@@ -620,6 +686,24 @@ ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const doub
   return launched(launch_interp(P, dtype, x, anchor, grid_u, v_out, plan->tune.block_points, (hipStream_t)stream));
 }
 
+ifem_status ifem_volume_correct(ifem_plan plan, int32_t dtype, const void* x, const double* V0, void* x_out,
+                                double* lambda_out, void* stream) {
+  if (!plan) return fail(IFEM_ERR_INVALID_ARG, "plan is NULL");
+  if (dtype != IFEM_F32 && dtype != IFEM_F64) return fail(IFEM_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+  const PlanDev& P = plan->P;
+  if (P.n_nodes > 0 && (!x || !x_out)) return fail(IFEM_ERR_INVALID_ARG, "x or x_out is NULL");
+  if (plan->open_surface >= 0)
+    return fail(IFEM_ERR_UNSUPPORTED, "particle %d: the volume correction needs a closed, consistently oriented surface",
+                plan->open_surface);
+  if (!volume_fits(P))
+    return fail(IFEM_ERR_UNSUPPORTED, "a particle with %d nodes is too large for the volume correction's LDS", P.cap);
+  const size_t nb = (size_t)3 * P.n_nodes * (dtype == IFEM_F32 ? 4 : 8), pb = (size_t)P.n_particles * 8;
+  if ((x_out != x && overlaps(x_out, nb, x, nb)) || overlaps(x_out, nb, V0, pb) || overlaps(lambda_out, pb, x, nb) ||
+      overlaps(lambda_out, pb, x_out, nb) || overlaps(lambda_out, pb, V0, pb))
+    return fail(IFEM_ERR_INVALID_ARG, "outputs alias inputs (only x_out == x is allowed)");
+  return launched(launch_volume(P, dtype, x, V0, x_out, lambda_out, (hipStream_t)stream));
+}
+
 ifem_status ifem_plan_kernel_times(ifem_plan plan, void* stream, double total_ms[16], int64_t launches[16],
                                    int32_t reset) {
   if (!plan || !total_ms || !launches) return fail(IFEM_ERR_INVALID_ARG, "NULL argument");
@@ -643,16 +727,16 @@ ifem_status ifem_plan_kernel_times(ifem_plan plan, void* stream, double total_ms
   return ok();
 }
 
-ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[4], int32_t reset) {
+ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[5], int32_t reset) {
   if (!plan || !counts) return fail(IFEM_ERR_INVALID_ARG, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  unsigned long long hs[4];
+  unsigned long long hs[5];
   hipError_t e = hipMemcpyAsync(hs, plan->P.status, sizeof hs, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "status read failed: %s", hipGetErrorString(e));
-  for (int i = 0; i < 4; ++i) counts[i] = (int64_t)hs[i];
+  for (int i = 0; i < 5; ++i) counts[i] = (int64_t)hs[i];
   if (reset) {
-    e = launch_fill_u64(plan->P.status, 4, st);
+    e = launch_fill_u64(plan->P.status, 5, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "status reset failed: %s", hipGetErrorString(e));
   }

@@ -71,6 +71,23 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Block-wide deterministic sum of NV doubles (shuffle tree per wave, then waves in order).
+template <int NV>
+__device__ __forceinline__ void block_sum(double v[NV], double* lds /*[NV][16]*/) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0)
+    for (int i = 0; i < NV; ++i) lds[i * 16 + wave] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += lds[i * 16 + w];
+      v[i] = s;
+    }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ fast elementary functions
 // float32: the hardware square root and reciprocal (about 1 ulp); float64:
 // the correctly rounded operations.

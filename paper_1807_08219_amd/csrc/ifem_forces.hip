@@ -398,23 +398,6 @@ __device__ __forceinline__ void load_pos(const T* __restrict__ x, int64_t N, int
   out[2] = x[2 * N + i];
 }
 
-// Block-wide deterministic sum of NV doubles (shuffle tree per wave, then waves in order).
-template <int NV>
-__device__ __forceinline__ void block_sum(double v[NV], double* lds /*[NV][16]*/) {
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  if (lane == 0)
-    for (int i = 0; i < NV; ++i) lds[i * 16 + wave] = v[i];
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int i = 0; i < NV; ++i) {
-      double s = 0.0;
-      for (int w = 0; w < nw; ++w) s += lds[i * 16 + w];
-      v[i] = s;
-    }
-  __syncthreads();
-}
-
 // POS_LDS: the particle's positions are staged in LDS once (coalesced) and
 // every element and one-ring read hits LDS; otherwise they are read through
 // the caches (particles too large for the staging copy).
@@ -444,7 +427,7 @@ __global__ void __launch_bounds__(512) k_forces(const ForceArgs a, const T* __re
   const T* xy = x + N + n0;
   const T* xz = x + 2 * N + n0;
   if (POS_LDS) {
-    T* px = kh + (a.ring_start ? a.cap : 0);  // [3][cap] after the curvature array
+    T* px = kh + (a.has_bending ? a.cap : 0);  // [3][cap] after the curvature array
     for (int i = tid; i < nn; i += nt) {
       px[i] = xx[i];
       px[a.cap + i] = xy[i];

@@ -26,10 +26,11 @@ struct ForceArgs {
   const int32_t* colb_tet;
   const int32_t* tet_local;  // [4][n_tets]
   const double* tet_ref;     // [7][n_tets] G11 G12 G13 G22 G23 G33 V0
-  const int32_t* ring_start; // [n_nodes + 1] or null (no bending anywhere)
+  const int32_t* ring_start; // [n_nodes + 1]: one-rings of bending and (when all close) membrane nodes, or null
   const int32_t* ring;       // one-ring neighbours, particle-local ids
   unsigned long long* status;
   int32_t n_nodes, n_tris, n_tets, cap;
+  int32_t has_bending;       // the force kernel's LDS holds a curvature array
 };
 
 // Everything the transfer kernels read.
@@ -65,6 +66,7 @@ enum KernelSlot {
   K_SPREAD_ATOMIC = 5,
   K_INTERP = 6,
   K_FILL = 7,
+  K_VOLUME = 9,
   K_NSLOTS = 16
 };
 
@@ -104,7 +106,8 @@ struct PlanDev {
   const int32_t* tet_src;
   const int32_t* tet_global;
   double* tet_ref;
-  unsigned long long* status;  // [4]
+  unsigned long long* status;  // [5]
+  double* vref;                // [n_p] enclosed volume of every membrane in the reference configuration
   ForceArgs fargs;
   TransferArgs targs;
   KernelTimer* timer;  // host object owned by the plan
@@ -116,6 +119,13 @@ hipError_t prepare_force_kernels(const PlanDev& P);
 size_t force_lds_bytes(const PlanDev& P, int dtype);
 hipError_t launch_forces(const PlanDev& P, int dtype, const void* x, const double* anchor, void* f, double* red,
                          int block, hipStream_t st);
+
+// ---- launchers (ifem_volume.hip)
+hipError_t prepare_volume_kernels(const PlanDev& P);
+bool volume_fits(const PlanDev& P);  // the largest particle's alpha sums fit one workgroup's LDS
+hipError_t launch_ref_volume(const PlanDev& P, const double* X, double* vref, hipStream_t st);
+hipError_t launch_volume(const PlanDev& P, int dtype, const void* x, const double* V0, void* x_out, double* lam,
+                         hipStream_t st);
 
 // ---- launchers (ifem_transfer.hip)
 hipError_t prepare_transfer_kernels(const PlanDev& P);

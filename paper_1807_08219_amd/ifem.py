@@ -28,11 +28,11 @@ IFEM_SPREAD_ATOMIC = 1
 IFEM_OPT_SPREAD_MODE = 1
 IFEM_OPT_KERNEL_TIMING = 2
 KERNEL_SLOTS = {0: "k_forces", 1: "k_bin_count", 2: "k_scan", 3: "k_bin_fill", 4: "k_spread_home",
-                5: "k_spread_atomic", 6: "k_interp", 7: "k_fill", 8: "k_spread_merge"}
+                5: "k_spread_atomic", 6: "k_interp", 7: "k_fill", 8: "k_spread_merge", 9: "k_volume"}
 
 EXPORTED = [
     "ifem_plan_create", "ifem_plan_destroy", "ifem_plan_set", "ifem_plan_info", "ifem_element_forces",
-    "ifem_spread", "ifem_interp", "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
+    "ifem_spread", "ifem_interp", "ifem_volume_correct", "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
 ]
 
 
@@ -78,6 +78,7 @@ def lib():
         L.ifem_element_forces.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_spread.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_interp.argtypes = [P, C.c_int32, P, P, P, P, P]
+        L.ifem_volume_correct.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_plan_status.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int32]
         L.ifem_plan_kernel_times.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.ifem_last_error.restype = C.c_char_p
@@ -179,7 +180,7 @@ class Plan:
         return list(out)
 
     def status(self, reset=True, stream=None):
-        out = (C.c_int64 * 4)()
+        out = (C.c_int64 * 5)()
         _check(lib().ifem_plan_status(self.handle, _stream(stream), out, int(bool(reset))))
         return list(out)
 
@@ -204,3 +205,8 @@ class Plan:
     def interp(self, dtype, x, anchor, grid_u, v_out, stream=None):
         _check(lib().ifem_interp(self.handle, dtype, _ptr(x), _ptr(anchor), _ptr(grid_u), _ptr(v_out),
                                  _stream(stream)))
+
+    def volume_correct(self, dtype, x, x_out, V0=None, lambda_out=None, stream=None):
+        """Membrane volume correction; x_out may be x itself (in place)."""
+        _check(lib().ifem_volume_correct(self.handle, dtype, _ptr(x), _ptr(V0), _ptr(x_out), _ptr(lambda_out),
+                                         _stream(stream)))

@@ -467,3 +467,33 @@ def subset(scene: Scene, particles) -> Scene:
         box=scene.box[particles], X_ref=np.ascontiguousarray(scene.X_ref[:, nodes]),
         x64=np.ascontiguousarray(scene.x64[:, nodes]), anchor=scene.anchor[particles],
         x32=np.ascontiguousarray(scene.x32[:, nodes]), seed=scene.seed, info=dict(scene.info))
+
+
+def with_volume_drift(scene: Scene, rel: float = 1e-3, seed: int = 0, roughness: float = 0.0) -> Scene:
+    """The scene with every membrane's current nodes scaled about their mean so that its enclosed
+    volume drifts by a factor 1 + d, d ~ U(-rel, rel) per membrane (the volume error a time step
+    leaves behind), plus optional N(0, roughness^2) noise per coordinate.  Solids are unchanged.
+    Anchors stay as they are; offsets and float64 positions are re-split so that
+    x64 == anchor + float64(x32) still holds exactly."""
+    rng = np.random.default_rng(seed)
+    x = scene.x64.T.copy()
+    for p in range(scene.n_particles):
+        if scene.tri_start[p + 1] == scene.tri_start[p]:
+            continue
+        s, e = scene.node_start[p], scene.node_start[p + 1]
+        c = x[s:e].mean(axis=0)
+        d = rng.uniform(-rel, rel)
+        x[s:e] = c + (1.0 + d) ** (1.0 / 3.0) * (x[s:e] - c)
+        if roughness:
+            x[s:e] += roughness * rng.normal(size=(e - s, 3))
+    x32 = np.zeros_like(scene.x32.T)
+    x64 = np.zeros_like(x)
+    for p in range(scene.n_particles):
+        s, e = scene.node_start[p], scene.node_start[p + 1]
+        a = scene.anchor[p]
+        off = (x[s:e] - a).astype(np.float32)
+        off[np.abs(off) < OFFSET_FLUSH] = 0.0
+        x32[s:e] = off
+        x64[s:e] = a + off.astype(np.float64)
+    return Scene(**{**scene.__dict__, "name": scene.name + "_drift", "x64": np.ascontiguousarray(x64.T),
+                    "x32": np.ascontiguousarray(x32.T)})

@@ -42,7 +42,7 @@ def test_empty_scene_gives_zero_grid():
         assert float(G.abs().max()) == 0.0
     plan.element_forces(ifem.IFEM_F64, x, None, F, None)
     plan.interp(ifem.IFEM_F64, x, None, G, F)
-    assert plan.status() == [0, 0, 0, 0]
+    assert plan.status() == [0, 0, 0, 0, 0]
     plan.close()
 
 
@@ -155,7 +155,7 @@ def test_points_on_lattice_nodes_and_on_the_periodic_seam(dtype):
     v = torch.empty((3, sc.n_nodes), dtype=tdt, device="cuda")
     plan.interp(dtype, x, a, cu(u, tdt), v)
     assert rel(v.cpu().numpy(), vo) <= tol
-    assert plan.status() == [0, 0, 0, 0]
+    assert plan.status() == [0, 0, 0, 0, 0]
     plan.close()
 
 

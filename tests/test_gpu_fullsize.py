@@ -14,6 +14,7 @@ import pytest
 import oracle
 from paper_1807_08219_amd import ifem
 from paper_1807_08219_amd.inputs import fields, scenes
+from volume_bars import U32, lambda_bars
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -175,3 +176,30 @@ def test_fullsize_fp64_plain_sampled(full):
         ref = np.array([Go[d, i] for d, i in idx])
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(Fin).max()
     plan.set(ifem.IFEM_OPT_SPREAD_MODE, ifem.IFEM_SPREAD_TILED)
+
+
+def test_fullsize_volume_correct_sampled(full):
+    # every membrane's volume drifted by up to 0.1 %, float32 offsets in and out (Sec. II.E)
+    cfg, sc, plan = full
+    dr = scenes.with_volume_drift(sc, rel=1e-3, seed=cfg)
+    x32 = cu(dr.x32, torch.float32)
+    out = torch.empty_like(x32)
+    lam = torch.empty(sc.n_particles, dtype=torch.float64, device="cuda")
+    say(f"[gpu] config {cfg}: volume correction fp32")
+    plan.volume_correct(ifem.IFEM_F32, x32, out, lambda_out=lam)
+    torch.cuda.synchronize()
+    assert plan.status()[4] == 0
+    got, lg = out.cpu().numpy().astype(np.float64), lam.cpu().numpy()
+    parts = np.unique(np.linspace(0, sc.n_particles - 1, 8).astype(int))
+    sub = scenes.subset(dr, parts)
+    xo, lo, bad = oracle.volume_correct(sub)
+    assert bad == 0
+    bars, _, xbar = lambda_bars(sub, xo, lo)
+    say(f"    sampled multipliers {lo}, |dL| / bar max {(np.abs(lg[parts] - lo) / np.maximum(bars, 1e-300)).max():.3g}")
+    assert np.all(np.abs(lg[parts] - lo) <= bars)
+    nodes = np.concatenate([np.arange(sc.node_start[p], sc.node_start[p + 1]) for p in parts])
+    ref = xo - sub.anchor[sub.node_particle()].T
+    assert np.all(np.abs(got[:, nodes] - ref) <= U32 * np.abs(ref) + xbar)
+    # solids keep their nodes bit for bit
+    solid = np.isin(sc.node_particle(), np.where(sc.law == scenes.LAW_TET_NEOHOOKE)[0])
+    assert np.array_equal(got[:, solid], dr.x32[:, solid].astype(np.float64))

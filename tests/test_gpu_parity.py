@@ -216,5 +216,5 @@ def test_tiled_spread_any_tile_shape(name, tile, dtype):
     e = rel(G, oracle.spread(sc, F))
     say(f"    grid rel err {e:.3e}")
     assert e <= (F64_TOL if dtype == ifem.IFEM_F64 else F32_TRANSFER_TOL)
-    assert r.plan.status() == [0, 0, 0, 0]
+    assert r.plan.status() == [0, 0, 0, 0, 0]
     r.plan.close()

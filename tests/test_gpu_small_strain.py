@@ -61,5 +61,5 @@ def test_fp32_forces_at_small_strain(law, eps):
     e = np.linalg.norm(got - Fo) / np.linalg.norm(Fo)
     print(f"    force rel err {e:.3e} (|F| {np.linalg.norm(Fo):.3e})", flush=True)
     assert e <= F32_ELASTIC_TOL
-    assert plan.status() == [0, 0, 0, 0]
+    assert plan.status() == [0, 0, 0, 0, 0]
     plan.close()
