@@ -58,6 +58,8 @@ def lib():
         L.orc_spread.argtypes = [C.c_int, _D, _D, _I, _I, _D, _D, _L, C.c_int64, _D]
         L.orc_interp.argtypes = [C.c_int, _D, _I, _I, _D, _D, _L, C.c_int64, _D, _D]
         L.orc_volume_correct.argtypes = [C.c_int, _D, C.c_int, _I, _I, _I, C.c_int, _I, _D, _D, _D]
+        L.orc_advance.argtypes = [C.c_int, _D, _D, C.c_void_p, C.c_double, _D]
+        L.orc_advance.restype = None
         _lib = L
     return _lib
 
@@ -202,3 +204,13 @@ def volume_correct(scene, V0=None, x=None):
     bad = lib().orc_volume_correct(scene.n_nodes, _c(x, np.float64), scene.n_particles, ns, ts, tri, ntri,
                                    _c(scene.law, np.int32), _c(V0, np.float64), out, lam)
     return out, lam, bad
+
+
+def advance(x, v, v_prev, dt):
+    """Adams-Bashforth update x + dt (3/2 v - 1/2 v_prev) of [3][n] arrays (forward Euler if v_prev is None)."""
+    x = _c(x, np.float64)
+    out = np.zeros_like(x)
+    vp = None if v_prev is None else _c(v_prev, np.float64)
+    lib().orc_advance(x.shape[1], x, _c(v, np.float64), None if vp is None else vp.ctypes.data_as(C.c_void_p),
+                      float(dt), out)
+    return out

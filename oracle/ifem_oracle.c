@@ -24,7 +24,8 @@
  *     (Sec. II.C, Interpolation Scheme);
  *   - per-particle volume (Sec. II.E volume formula), area and centroid;
  *   - the membrane volume correction (Sec. II.E, conservation of volume for
- *     membranes: the Lagrange-multiplier displacement and its cubic).
+ *     membranes: the Lagrange-multiplier displacement and its cubic);
+ *   - the second-order Adams-Bashforth update of the positions (Sec. III.A).
  *
  * Readings of the paper where it is silent or garbled are marked READING.
  */
@@ -737,4 +738,18 @@ int orc_volume_correct(int n_nodes, const double* x, int n_particles, const int*
     free(v);
   }
   return bad;
+}
+
+/* ------------------------------------------------------------ Lagrangian update (Sec. III.A, last step) */
+/* Second-order Adams-Bashforth update of the node positions with the
+ * interpolated velocities of this step and the previous one:
+ *   x^{n+1} = x^n + dt (3/2 v^n - 1/2 v^{n-1}).
+ * READING: the paper does not say how the first step starts; with no previous
+ * velocity (v_prev NULL) it is the forward Euler step x^n + dt v^n.  All arrays
+ * [3][n_nodes]. */
+void orc_advance(int n_nodes, const double* x, const double* v, const double* v_prev, double dt, double* x_out) {
+  for (long i = 0; i < 3L * n_nodes; ++i) {
+    const double rate = v_prev ? 1.5 * v[i] - 0.5 * v_prev[i] : v[i];
+    x_out[i] = x[i] + dt * rate;
+  }
 }
