@@ -174,6 +174,68 @@ def bench_volume(plan, sc, steps, dev, stream):
     return res
 
 
+def bench_loop(plan, sc, steps, dev, anchor, u32):
+    """The Lagrangian loop in float32: forces, spread, interpolation of the steady synthetic velocity,
+    Adams-Bashforth update and volume correction, two steps captured as one HIP graph."""
+    import torch
+
+    from paper_1807_08219_amd import ifem
+
+    x = torch.as_tensor(sc.x32, device=dev).clone()
+    F = torch.empty_like(x)
+    G = torch.empty((3, sc.total_cells), dtype=torch.float32, device=dev)
+    vA, vB = torch.empty_like(x), torch.empty_like(x)
+    dt = 0.05 * min(b.h for b in sc.boxes) / max(float(u32.abs().max()), 1e-30)  # 1/20 cell per step at most
+
+    def step(v_new, v_old, stream=None):
+        plan.element_forces(ifem.IFEM_F32, x, anchor, F, None, stream)
+        plan.spread(ifem.IFEM_F32, x, anchor, F, G, stream)
+        plan.interp(ifem.IFEM_F32, x, anchor, u32, v_new, stream)
+        plan.advance(ifem.IFEM_F32, x, v_new, x, v_prev=v_old, dt=dt, stream=stream)
+        plan.volume_correct(ifem.IFEM_F32, x, x, stream=stream)
+
+    step(vA, None)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        step(vB, vA, side)
+        step(vA, vB, side)
+        with torch.cuda.graph(graph, stream=side):
+            step(vB, vA, side)
+            step(vA, vB, side)
+    torch.cuda.current_stream().wait_stream(side)
+    graph.replay()
+    torch.cuda.synchronize()
+    pairs = max(1, steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(pairs):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / (2 * pairs)
+    del graph
+    # the update kernel alone (eager, event timer): float32 positions, two velocities
+    plan.set(ifem.IFEM_OPT_KERNEL_TIMING, steps + 8)
+    plan.kernel_times(reset=True)
+    for _ in range(steps):
+        plan.advance(ifem.IFEM_F32, x, vA, F, v_prev=vB, dt=dt)
+    kt = plan.kernel_times(reset=True)
+    plan.set(ifem.IFEM_OPT_KERNEL_TIMING, 0)
+    ms_adv = kt["k_advance"][0] / kt["k_advance"][1]
+    nbytes = 4 * 12 * sc.n_nodes
+    gbs = nbytes / (ms_adv * 1e-3) / 1e9
+    log(f"Lagrangian loop (graph, float32): {ms:.3f} ms/step; advance kernel {ms_adv:.4f} ms ({gbs:.0f} GB/s)")
+    st = plan.status()
+    return {"ms_per_step": round(ms, 4), "value": round(sc.n_nodes / (ms * 1e-3), 1), "unit": "nodes/s",
+            "steps": 2 * pairs, "dt": dt,
+            "step": "forces + spread + interp + Adams-Bashforth update + volume correction (float32, one graph)",
+            "advance": {"ms": round(ms_adv, 4), "roofline": {"bound": "hbm", "achieved": round(gbs, 2),
+                                                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                                            "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                                            "algorithmic_bytes": nbytes}},
+            "device_status": st}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +247,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
+    ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="spread tile, e.g. 32,16,8 (powers of two)")
     ap.add_argument("--block-forces", type=int, default=None, help="threads per particle workgroup")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -330,6 +393,8 @@ def main():
 
     if not args.no_volume:
         out["volume_correct"] = bench_volume(plan, sc, args.steps, dev, stream)
+    if not args.no_loop:
+        out["lagrangian_loop"] = bench_loop(plan, sc, args.steps, dev, anchor, u32)
 
     if not args.no_fp64:
         x64 = torch.as_tensor(sc.x64, device=dev)

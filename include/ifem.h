@@ -14,8 +14,9 @@
  *   ifem_interp          v_k = sum_J phi_J(x_J - x_k) v_J back to the nodes
  *                        (Sec. II.C interpolation operator);
  *
- * and, after the positions are advanced, the membrane volume correction of
- * Sec. II.E (ifem_volume_correct),
+ * and the end of a time step (Sec. III.A, last step): the second-order
+ * Adams-Bashforth update of the positions (ifem_advance) and the membrane
+ * volume correction of Sec. II.E (ifem_volume_correct),
  *
  * with phi the linear moving-least-squares weights of Sec. II.C (27-node
  * stencil around the nearest lattice node, cubic-spline weight, support
@@ -122,7 +123,8 @@ enum {
   IFEM_KERNEL_SPREAD_ATOMIC = 5, /* spread: plain global-atomic baseline                */
   IFEM_KERNEL_INTERP = 6,        /* interpolation                                       */
   IFEM_KERNEL_FILL = 7,          /* zero fills                                          */
-  IFEM_KERNEL_VOLUME = 9         /* membrane volume correction                          */
+  IFEM_KERNEL_VOLUME = 9,        /* membrane volume correction                          */
+  IFEM_KERNEL_ADVANCE = 10       /* Adams-Bashforth position update                     */
 };
 
 /* Mesh description, HOST memory, read once by ifem_plan_create. */
@@ -238,6 +240,21 @@ ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const doub
 ifem_status ifem_volume_correct(ifem_plan plan, int32_t dtype, const void* x, const double* V0, void* x_out,
                                 double* lambda_out, void* stream);
 
+/* Lagrangian update (Sec. III.A, last step of the algorithm): second-order
+ * Adams-Bashforth with the interpolated velocities of this step and the last,
+ *   x_out = x + dt (3/2 v - 1/2 v_prev),
+ * or the forward Euler step x + dt v when v_prev is NULL (the first step).
+ * Arithmetic is float64 in the order written, without fused multiply-add.
+ *   x, x_out     [3][n_nodes] positions (see dtype), device.  IFEM_F32: float32
+ *                offsets from the caller's anchors; x_out holds offsets from the
+ *                same anchors (the displacement is added in float64 and the
+ *                offset rounded once).  x_out == x updates in place.
+ *   v, v_prev    [3][n_nodes] velocities in the same dtype, device (v_prev may
+ *                be NULL); neither may overlap x_out.
+ *   dt           time step (finite). */
+ifem_status ifem_advance(ifem_plan plan, int32_t dtype, const void* x, const void* v, const void* v_prev, double dt,
+                         void* x_out, void* stream);
+
 /* Synchronise `stream` and the timer's events; total_ms[i] and launches[i]
  * receive the summed duration and number of launches of kernel slot i
  * (IFEM_KERNEL_*) recorded since the last reset; launches[15] counts launches
@@ -252,7 +269,7 @@ ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[5], in
 /* Thread-local description of the last non-OK return ("" if none). */
 const char* ifem_last_error(void);
 
-/* Library version, e.g. 10100 for 1.1.0. */
+/* Library version, e.g. 10200 for 1.2.0. */
 int32_t ifem_version(void);
 
 #ifdef __cplusplus

@@ -312,7 +312,7 @@ int first_open_surface(const ifem_mesh_desc& m) {
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
-int32_t ifem_version(void) { return 10100; }
+int32_t ifem_version(void) { return 10200; }
 
 const char* ifem_last_error(void) { return g_last_error.c_str(); }
 
@@ -702,6 +702,19 @@ ifem_status ifem_volume_correct(ifem_plan plan, int32_t dtype, const void* x, co
       overlaps(lambda_out, pb, x_out, nb) || overlaps(lambda_out, pb, V0, pb))
     return fail(IFEM_ERR_INVALID_ARG, "outputs alias inputs (only x_out == x is allowed)");
   return launched(launch_volume(P, dtype, x, V0, x_out, lambda_out, (hipStream_t)stream));
+}
+
+ifem_status ifem_advance(ifem_plan plan, int32_t dtype, const void* x, const void* v, const void* v_prev, double dt,
+                         void* x_out, void* stream) {
+  if (!plan) return fail(IFEM_ERR_INVALID_ARG, "plan is NULL");
+  if (dtype != IFEM_F32 && dtype != IFEM_F64) return fail(IFEM_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+  const PlanDev& P = plan->P;
+  if (P.n_nodes > 0 && (!x || !v || !x_out)) return fail(IFEM_ERR_INVALID_ARG, "x, v or x_out is NULL");
+  if (!std::isfinite(dt)) return fail(IFEM_ERR_INVALID_ARG, "dt is not finite");
+  const size_t nb = (size_t)3 * P.n_nodes * (dtype == IFEM_F32 ? 4 : 8);
+  if ((x_out != x && overlaps(x_out, nb, x, nb)) || overlaps(x_out, nb, v, nb) || overlaps(x_out, nb, v_prev, nb))
+    return fail(IFEM_ERR_INVALID_ARG, "x_out aliases an input (only x_out == x is allowed)");
+  return launched(launch_advance(P, dtype, x, v, v_prev, dt, x_out, (hipStream_t)stream));
 }
 
 ifem_status ifem_plan_kernel_times(ifem_plan plan, void* stream, double total_ms[16], int64_t launches[16],

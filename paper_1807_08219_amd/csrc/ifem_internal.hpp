@@ -67,6 +67,7 @@ enum KernelSlot {
   K_INTERP = 6,
   K_FILL = 7,
   K_VOLUME = 9,
+  K_ADVANCE = 10,
   K_NSLOTS = 16
 };
 
@@ -126,6 +127,10 @@ bool volume_fits(const PlanDev& P);  // the largest particle's alpha sums fit on
 hipError_t launch_ref_volume(const PlanDev& P, const double* X, double* vref, hipStream_t st);
 hipError_t launch_volume(const PlanDev& P, int dtype, const void* x, const double* V0, void* x_out, double* lam,
                          hipStream_t st);
+
+// ---- launchers (ifem_advance.hip)
+hipError_t launch_advance(const PlanDev& P, int dtype, const void* x, const void* v, const void* v_prev, double dt,
+                          void* x_out, hipStream_t st);
 
 // ---- launchers (ifem_transfer.hip)
 hipError_t prepare_transfer_kernels(const PlanDev& P);

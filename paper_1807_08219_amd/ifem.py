@@ -28,11 +28,12 @@ IFEM_SPREAD_ATOMIC = 1
 IFEM_OPT_SPREAD_MODE = 1
 IFEM_OPT_KERNEL_TIMING = 2
 KERNEL_SLOTS = {0: "k_forces", 1: "k_bin_count", 2: "k_scan", 3: "k_bin_fill", 4: "k_spread_home",
-                5: "k_spread_atomic", 6: "k_interp", 7: "k_fill", 8: "k_spread_merge", 9: "k_volume"}
+                5: "k_spread_atomic", 6: "k_interp", 7: "k_fill", 8: "k_spread_merge", 9: "k_volume",
+                10: "k_advance"}
 
 EXPORTED = [
     "ifem_plan_create", "ifem_plan_destroy", "ifem_plan_set", "ifem_plan_info", "ifem_element_forces",
-    "ifem_spread", "ifem_interp", "ifem_volume_correct", "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
+    "ifem_spread", "ifem_interp", "ifem_volume_correct", "ifem_advance", "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
 ]
 
 
@@ -79,6 +80,7 @@ def lib():
         L.ifem_spread.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_interp.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_volume_correct.argtypes = [P, C.c_int32, P, P, P, P, P]
+        L.ifem_advance.argtypes = [P, C.c_int32, P, P, P, C.c_double, P, P]
         L.ifem_plan_status.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int32]
         L.ifem_plan_kernel_times.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.ifem_last_error.restype = C.c_char_p
@@ -210,3 +212,8 @@ class Plan:
         """Membrane volume correction; x_out may be x itself (in place)."""
         _check(lib().ifem_volume_correct(self.handle, dtype, _ptr(x), _ptr(V0), _ptr(x_out), _ptr(lambda_out),
                                          _stream(stream)))
+
+    def advance(self, dtype, x, v, x_out, v_prev=None, dt=1.0, stream=None):
+        """Adams-Bashforth update x_out = x + dt (3/2 v - 1/2 v_prev) (forward Euler without v_prev)."""
+        _check(lib().ifem_advance(self.handle, dtype, _ptr(x), _ptr(v), _ptr(v_prev), float(dt), _ptr(x_out),
+                                  _stream(stream)))
