@@ -59,6 +59,10 @@ def lib():
         L.orc_interp.argtypes = [C.c_int, _D, _I, _I, _D, _D, _L, C.c_int64, _D, _D]
         L.orc_volume_correct.argtypes = [C.c_int, _D, C.c_int, _I, _I, _I, C.c_int, _I, _D, _D, _D]
         L.orc_advance.argtypes = [C.c_int, _D, _D, C.c_void_p, C.c_double, _D]
+        L.orc_interp_cells.argtypes = [C.c_int, _D, _I, _I, _D, _D, _L, C.c_int64, C.c_int, _D, _D]
+        L.orc_tet_fluid_element.argtypes = [_D, _D, _D, C.c_void_p, C.c_double, C.c_double, _D]
+        L.orc_fluid_forces.argtypes = [C.c_int, _D, _D, _D, C.c_void_p, C.c_int, _I, _I, C.c_int, C.c_double,
+                                       C.c_double, _D]
         L.orc_advance.restype = None
         _lib = L
     return _lib
@@ -214,3 +218,41 @@ def advance(x, v, v_prev, dt):
     lib().orc_advance(x.shape[1], x, _c(v, np.float64), None if vp is None else vp.ctypes.data_as(C.c_void_p),
                       float(dt), out)
     return out
+
+
+def _opt(a):
+    """(keep-alive array, void pointer) of an optional float64 array."""
+    if a is None:
+        return None, None
+    a = _c(a, np.float64)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def interp_cells(scene, grid, x=None, box_of_point=None):
+    """[ncomp][n_points] interpolation of cell-centred fields grid [ncomp][total_cells]."""
+    x, bop = _points(scene, scene.x64 if x is None else x, box_of_point)
+    n, h, o, off = _box_args(scene)
+    grid = _c(grid, np.float64)
+    out = np.zeros((grid.shape[0], x.shape[1]))
+    lib().orc_interp_cells(x.shape[1], x, bop, n, h, o, off, scene.total_cells, grid.shape[0], grid, out)
+    return out
+
+
+def tet_fluid_element(X, x, u, C, eta, G):
+    """Fluid-stress forces [4][3] of one tetrahedron; C [4][6] (xx, yy, zz, xy, xz, yz) or None."""
+    f = np.zeros((4, 3))
+    keep, cp = _opt(None if C is None else np.asarray(C).reshape(24))
+    st = lib().orc_tet_fluid_element(_c(X, np.float64), _c(x, np.float64), _c(u, np.float64), cp, float(eta),
+                                     float(G), f)
+    return f, st
+
+
+def fluid_forces(scene, u, C=None, eta=1.0, G=1.0, x=None):
+    """Fluid-stress nodal forces [3][n_nodes] of every solid and the number of skipped elements."""
+    x = scene.x64 if x is None else x
+    f = np.zeros((3, scene.n_nodes))
+    keep, cp = _opt(C)
+    bad = lib().orc_fluid_forces(scene.n_nodes, _c(scene.X_ref, np.float64), _c(x, np.float64), _c(u, np.float64), cp,
+                                 scene.n_particles, _c(scene.tet_start, np.int32), _c(scene.tet, np.int32),
+                                 scene.n_tets, float(eta), float(G), f)
+    return f, bad

@@ -25,7 +25,10 @@
  *   - per-particle volume (Sec. II.E volume formula), area and centroid;
  *   - the membrane volume correction (Sec. II.E, conservation of volume for
  *     membranes: the Lagrange-multiplier displacement and its cubic);
- *   - the second-order Adams-Bashforth update of the positions (Sec. III.A).
+ *   - the second-order Adams-Bashforth update of the positions (Sec. III.A);
+ *   - the interpolation of the conformation tensor to the nodes and the
+ *     fluid-stress (Newtonian and polymer) forces on solids (Sec. II.B,
+ *     Sec. III.A steps 1 and 4).
  *
  * Readings of the paper where it is silent or garbled are marked READING.
  */
@@ -542,11 +545,16 @@ static int solve4(double A[4][4], double b[4], double z[4]) {
   return 0;
 }
 
-static const double ORC_STAGGER[3][3] = {{0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0}};
+/* Lattice offsets in cells: rows 0..2 the MAC lattices of the three velocity
+ * components, row 3 the cell centres, where the six components of the
+ * conformation tensor live.  READING: the paper's grid is collocated; on this
+ * staggered grid the conformation, a cell quantity like the pressure, sits at
+ * the cell centres. */
+static const double ORC_STAGGER[4][3] = {{0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0}, {0.5, 0.5, 0.5}};
 
-/* MLS weights of one Lagrangian point p on the lattice of velocity component
- * `comp` of a periodic box (n cells per axis, spacing h, lattice nodes at
- * origin + (i + s) h with s the staggering of that component).
+/* MLS weights of one Lagrangian point p on lattice `comp` of a periodic box
+ * (n cells per axis, spacing h, lattice nodes at origin + (i + s) h with s the
+ * lattice's offset: velocity component comp = 0..2, cell centres comp = 3).
  *
  * Stencil: the lattice node nearest to p and the 26 nodes sharing a cell
  * with it.  READING (nearest-node rule, bit-specified so that every
@@ -752,4 +760,120 @@ void orc_advance(int n_nodes, const double* x, const double* v, const double* v_
     const double rate = v_prev ? 1.5 * v[i] - 0.5 * v_prev[i] : v[i];
     x_out[i] = x[i] + dt * rate;
   }
+}
+
+/* ------------------------------------------------------------ conformation interpolation (Sec. III.A step 4) */
+/* C_k = sum_J phi_J(x_J - x_k) C_J for each of ncomp cell-centred fields
+ * (the six components of the symmetric conformation tensor, in the order
+ * xx, yy, zz, xy, xz, yz), with the MLS weights of the cell-centre lattice.
+ * grid [ncomp][total_cells], out [ncomp][n_points]. */
+int orc_interp_cells(int n_points, const double* x, const int* box_of_point, const int* bn, const double* bh,
+                     const double* borig, const int64_t* cell_off, int64_t total_cells, int ncomp,
+                     const double* grid, double* out) {
+  int bad = 0;
+  for (int k = 0; k < n_points; ++k) {
+    int b = box_of_point[k];
+    const int* n = bn + 3 * b;
+    double p[3] = {x[k], x[n_points + k], x[2 * (size_t)n_points + k]};
+    int64_t base[3];
+    double phi[27];
+    const int singular = orc_mls(p, n, bh[b], borig + 3 * b, 3, base, phi);
+    bad += singular;
+    for (int c = 0; c < ncomp; ++c) {
+      double s = 0.0;
+      for (int mz = -1; mz <= 1; ++mz)
+        for (int my = -1; my <= 1; ++my)
+          for (int mx = -1; mx <= 1; ++mx) {
+            int64_t i = wrap(base[0] + mx, n[0]), j = wrap(base[1] + my, n[1]), kk = wrap(base[2] + mz, n[2]);
+            int64_t cell = cell_off[b] + (kk * n[1] + j) * n[0] + i;
+            s += phi[(mz + 1) * 9 + (my + 1) * 3 + (mx + 1)] * grid[c * (size_t)total_cells + cell];
+          }
+      out[c * (size_t)n_points + k] = singular ? NAN : s;
+    }
+  }
+  return bad;
+}
+
+/* ------------------------------------------------------------ fluid-stress forces on solids (Sec. II.B) */
+/* The fluid part of eq. FEM for one tetrahedron, split into its Newtonian and
+ * polymer parts:
+ *   L      = sum_k u_k (x) grad N_k F^-1               (velocity gradient),
+ *   P^fN   = eta J (L + L^T) F^-T,
+ *   P^fP   = J G (1/4 sum_k (C_k - I)) F^-T,
+ *   f_k    = +V0 (P^fN + P^fP) grad N_k,
+ * the sign of the fluid stress in F_k = -V0 (P^s - P^f) grad N_k.  eta is the
+ * Newtonian viscosity and G the polymer modulus eta_p / lambda (written
+ * eta (1 - beta) / lambda in the paper, with eta the total viscosity there).
+ * C [4][6] per node xx, yy, zz, xy, xz, yz, or NULL for a Newtonian fluid.
+ * Returns 1 (and zero forces) for a degenerate reference or J <= 0. */
+int orc_tet_fluid_element(const double X[4][3], const double x[4][3], const double u[4][3], const double* C,
+                          double eta, double G, double f[4][3]) {
+  memset(f, 0, 12 * sizeof(double));
+  double gradN[4][3];
+  const double V0 = tet_reference(X, gradN);
+  if (!(V0 > 0.0)) return 1;
+  double F[3][3], Fi[3][3];
+  tet_defgrad(x, gradN, F);
+  const double J = inv3(F, Fi);
+  if (!(J > 0.0)) return 1;
+  double L[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 4; ++k)
+        for (int l = 0; l < 3; ++l) s += u[k][i] * gradN[k][l] * Fi[l][j];
+      L[i][j] = s;
+    }
+  double P[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += (L[i][k] + L[k][i]) * Fi[j][k]; /* (L + L^T) F^-T */
+      P[i][j] = eta * J * s;
+    }
+  if (C) {
+    static const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    double Cb[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int l = 0; l < 3; ++l) {
+        double s = 0.0;
+        for (int k = 0; k < 4; ++k) s += (C[6 * k + sym[i][l]] - (i == l)) / 4.0;
+        Cb[i][l] = s;
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int l = 0; l < 3; ++l) s += Cb[i][l] * Fi[j][l];
+        P[i][j] += J * G * s;
+      }
+  }
+  for (int k = 0; k < 4; ++k)
+    for (int i = 0; i < 3; ++i) f[k][i] = V0 * (P[i][0] * gradN[k][0] + P[i][1] * gradN[k][1] + P[i][2] * gradN[k][2]);
+  return 0;
+}
+
+/* Fluid-stress nodal forces of every solid (sum of the element forces over its
+ * tetrahedra); membranes get none.  u [3][n_nodes], C [6][n_nodes] or NULL,
+ * f [3][n_nodes] overwritten.  Returns the number of skipped elements. */
+int orc_fluid_forces(int n_nodes, const double* X, const double* x, const double* u, const double* C, int n_particles,
+                     const int* tet_start, const int* tet, int n_tet, double eta, double G, double* f) {
+  memset(f, 0, sizeof(double) * 3 * (size_t)n_nodes);
+  int bad = 0;
+  for (int p = 0; p < n_particles; ++p)
+    for (int t = tet_start[p]; t < tet_start[p + 1]; ++t) {
+      int id[4];
+      double Xe[4][3], xe[4][3], ue[4][3], Ce[24], fe[4][3];
+      for (int v = 0; v < 4; ++v) {
+        id[v] = tet[v * n_tet + t];
+        pos(X, n_nodes, id[v], Xe[v]);
+        pos(x, n_nodes, id[v], xe[v]);
+        pos(u, n_nodes, id[v], ue[v]);
+        if (C)
+          for (int c = 0; c < 6; ++c) Ce[6 * v + c] = C[c * (size_t)n_nodes + id[v]];
+      }
+      bad += orc_tet_fluid_element(Xe, xe, ue, C ? Ce : NULL, eta, G, fe);
+      for (int v = 0; v < 4; ++v)
+        for (int i = 0; i < 3; ++i) f[i * (size_t)n_nodes + id[v]] += fe[v][i];
+    }
+  return bad;
 }

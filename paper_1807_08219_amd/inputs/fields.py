@@ -1,4 +1,5 @@
-"""Seeded synthetic Eulerian velocity fields on the staggered (MAC) lattices of each box.
+"""Seeded synthetic Eulerian fields: velocity on the staggered (MAC) lattices of each box, and the
+conformation tensor at the cell centres.
 
 The finite-volume fluid solve is not part of the coupling step; these fields
 stand in for its output.  Component ``d`` of box ``b`` is sampled at
@@ -19,7 +20,9 @@ import math
 import numpy as np
 import torch
 
-STAGGER = np.array([[0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]])
+# lattice offsets in cells: the three velocity components, then the cell centres (comp 3)
+STAGGER = np.array([[0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0], [0.5, 0.5, 0.5]])
+CONFORMATION = ("xx", "yy", "zz", "xy", "xz", "yz")
 
 
 def draw_modes(rng: np.random.Generator, n_modes: int = 8, kmax: int = 4, amp: float = 1.0):
@@ -93,3 +96,30 @@ def random_forces(scene, seed: int = 5, scale: float = 1.0) -> np.ndarray:
     """[3][n_nodes] float64 nodal force field for transfer tests that do not need element forces."""
     rng = np.random.default_rng(seed)
     return rng.normal(0.0, scale, size=(3, scene.n_nodes))
+
+
+def conformation_field(scene, seed: int | None = None, amp: float = 0.2, n_modes: int = 6, device="cpu",
+                       dtype=torch.float64):
+    """[6][total_cells] conformation tensor C = I + perturbation at the cell centres of every box
+    (components xx, yy, zz, xy, xz, yz).  Each component's perturbation is a sum of periodic Fourier
+    modes scaled so that its magnitude stays below ``amp``; with amp <= 1/3 every C is symmetric
+    positive definite (diagonal >= 1 - amp, off-diagonal row sums <= 2 amp)."""
+    rng = np.random.default_rng(scene.seed + 91 if seed is None else seed)
+    out = torch.empty((6, scene.total_cells), dtype=dtype, device=device)
+    off = scene.cell_offset
+    for b, box in enumerate(scene.boxes):
+        L = np.array(box.length)
+        nx, ny, nz = box.n
+        coords = [(torch.arange(n, dtype=torch.float64, device=device) + 0.5) * box.h for n in (nx, ny, nz)]
+        for c in range(6):
+            ks, amps, phases, _ = draw_modes(rng, n_modes)
+            amps = amps / max(amps.sum(), 1e-300) * amp * rng.uniform(0.5, 1.0)
+            kap = 2 * np.pi * ks / L[None, :]
+            f = torch.full((nz, ny, nx), 1.0 if c < 3 else 0.0, dtype=torch.float64, device=device)
+            for m in range(n_modes):
+                ex = torch.exp(1j * (kap[m, 0] * coords[0]).to(torch.complex128))
+                ey = torch.exp(1j * (kap[m, 1] * coords[1]).to(torch.complex128))
+                ez = torch.exp(1j * (kap[m, 2] * coords[2] + phases[m]).to(torch.complex128))
+                f += amps[m] * (ez[:, None, None] * ey[None, :, None] * ex[None, None, :]).real
+            out[c, off[b]:off[b + 1]] = f.reshape(-1).to(dtype)
+    return out
