@@ -236,6 +236,65 @@ def bench_loop(plan, sc, steps, dev, anchor, u32):
             "device_status": st}
 
 
+def _kernel_ms(plan, slot, fn, steps):
+    from paper_1807_08219_amd import ifem
+
+    fn()
+    plan.set(ifem.IFEM_OPT_KERNEL_TIMING, steps + 8)
+    plan.kernel_times(reset=True)
+    for _ in range(steps):
+        fn()
+    kt = plan.kernel_times(reset=True)
+    plan.set(ifem.IFEM_OPT_KERNEL_TIMING, 0)
+    return kt[slot][0] / kt[slot][1]
+
+
+def bench_viscoelastic(plan, sc, steps, dev, x32, anchor):
+    """Conformation interpolation (six cell-centred fields to every node) on the main workload, and
+    the fluid-stress forces of the solids of the 64-box workload (config 4), float32."""
+    import torch
+
+    from paper_1807_08219_amd import ifem
+    from paper_1807_08219_amd.inputs import fields, scenes
+
+    res = {}
+    Cg = fields.conformation_field(sc, device=dev, dtype=torch.float32)
+    Cn = torch.empty((6, sc.n_nodes), dtype=torch.float32, device=dev)
+    ms = _kernel_ms(plan, "k_interp_cells", lambda: plan.interp_cells(ifem.IFEM_F32, x32, anchor, Cg, Cn), steps)
+    nbytes = sc.n_nodes * (12 + 24) + sc.total_cells * 24
+    flops = sc.n_nodes * (27 * 14 + 9 * 20 + 60 + 27 * 4 + 6 * 27 * 2)
+    gbs, tfs = nbytes / (ms * 1e-3) / 1e9, flops / (ms * 1e-3) / 1e12
+    log(f"conformation interpolation: {ms:.4f} ms ({gbs:.0f} GB/s algorithmic, {tfs:.1f} TFLOP/s)")
+    res["interp_cells"] = {
+        "workload": f"{sc.name}, 6 conformation components at the cell centres", "ms": round(ms, 4),
+        "value": round(sc.n_nodes / (ms * 1e-3), 1), "unit": "nodes/s",
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(nbytes),
+                     "tflops": round(tfs, 2), "alu_frac_nonpacked": round(tfs / VALU_NONPACKED_TFLOPS, 4)}}
+    del Cg, Cn
+    s4 = scenes.make_config(4)
+    p4 = ifem.Plan(s4)
+    x4, a4 = torch.as_tensor(s4.x32, device=dev), torch.as_tensor(s4.anchor, device=dev)
+    C4 = torch.empty((6, s4.n_nodes), dtype=torch.float32, device=dev)
+    p4.interp_cells(ifem.IFEM_F32, x4, a4, fields.conformation_field(s4, device=dev, dtype=torch.float32), C4)
+    v4 = torch.randn((3, s4.n_nodes), dtype=torch.float32, device=dev)
+    f4 = torch.zeros((3, s4.n_nodes), dtype=torch.float32, device=dev)
+    ms = _kernel_ms(p4, "k_fluid", lambda: p4.fluid_forces(ifem.IFEM_F32, x4, v4, f4, C=C4, eta=1.0, G=0.5), steps)
+    solid = s4.law == scenes.LAW_TET_NEOHOOKE
+    sn = int(np.diff(s4.node_start)[solid].sum())
+    nbytes = s4.n_tets * 16 + sn * (12 + 12 + 24 + 24)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log(f"fluid-stress forces: {ms:.4f} ms for {s4.n_tets} tets ({gbs:.0f} GB/s algorithmic)")
+    res["fluid_forces"] = {
+        "workload": f"{s4.name}: {int(solid.sum())} solids, {s4.n_tets} tetrahedra, {sn} nodes", "ms": round(ms, 4),
+        "value": round(s4.n_tets / (ms * 1e-3), 1), "unit": "tets/s",
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(nbytes)}}
+    res["device_status"] = p4.status()
+    p4.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +307,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
+    ap.add_argument("--no-visco", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="spread tile, e.g. 32,16,8 (powers of two)")
     ap.add_argument("--block-forces", type=int, default=None, help="threads per particle workgroup")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -395,6 +455,8 @@ def main():
         out["volume_correct"] = bench_volume(plan, sc, args.steps, dev, stream)
     if not args.no_loop:
         out["lagrangian_loop"] = bench_loop(plan, sc, args.steps, dev, anchor, u32)
+    if not args.no_visco:
+        out["viscoelastic"] = bench_viscoelastic(plan, sc, args.steps, dev, x32, anchor)
 
     if not args.no_fp64:
         x64 = torch.as_tensor(sc.x64, device=dev)

@@ -14,6 +14,9 @@
  *   ifem_interp          v_k = sum_J phi_J(x_J - x_k) v_J back to the nodes
  *                        (Sec. II.C interpolation operator);
  *
+ * for viscoelastic suspensions, the interpolation of the conformation tensor
+ * to the nodes (ifem_interp_cells, Sec. III.A step 4) and the fluid-stress
+ * forces on solids (ifem_fluid_forces, Sec. II.B eq. FEM, Sec. III.A step 1);
  * and the end of a time step (Sec. III.A, last step): the second-order
  * Adams-Bashforth update of the positions (ifem_advance) and the membrane
  * volume correction of Sec. II.E (ifem_volume_correct),
@@ -26,9 +29,10 @@
  * -----------
  * Every array passed to the step calls is DEVICE memory owned by the
  * caller; the library never frees or reallocates it.  Inputs are not
- * modified; outputs are overwritten (never accumulated).  An output may not
- * alias an input (except the in-place volume correction): that is rejected
- * with IFEM_ERR_INVALID_ARG.
+ * modified; outputs are overwritten (never accumulated, except the
+ * documented in-out forces of ifem_fluid_forces).  An output may not alias an
+ * input (except in place where a call says so): that is rejected with
+ * IFEM_ERR_INVALID_ARG.
  *
  * Layouts (structure of arrays, 32-bit indices):
  *   positions, forces, velocities   [3][n_nodes]  (component-major)
@@ -124,7 +128,9 @@ enum {
   IFEM_KERNEL_INTERP = 6,        /* interpolation                                       */
   IFEM_KERNEL_FILL = 7,          /* zero fills                                          */
   IFEM_KERNEL_VOLUME = 9,        /* membrane volume correction                          */
-  IFEM_KERNEL_ADVANCE = 10       /* Adams-Bashforth position update                     */
+  IFEM_KERNEL_ADVANCE = 10,      /* Adams-Bashforth position update                     */
+  IFEM_KERNEL_INTERP_CELLS = 11, /* interpolation of cell-centred fields                */
+  IFEM_KERNEL_FLUID = 12         /* fluid-stress forces on solids                       */
 };
 
 /* Mesh description, HOST memory, read once by ifem_plan_create. */
@@ -240,6 +246,41 @@ ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const doub
 ifem_status ifem_volume_correct(ifem_plan plan, int32_t dtype, const void* x, const double* V0, void* x_out,
                                 double* lambda_out, void* stream);
 
+/* Interpolation of cell-centred fields to the nodes (Sec. III.A step 4: the
+ * conformation tensor C_k = sum_J phi_J(x_J - x_k) C_J).  The fields live at
+ * the cell centres origin + (i + 1/2, j + 1/2, k + 1/2) h of every box (the
+ * fourth lattice beside the three velocity lattices), with the same MLS
+ * weights and stencil rule.
+ *   grid  [ncomp][total_cells] (same dtype), device; for the conformation
+ *         ncomp = 6 in the order xx, yy, zz, xy, xz, yz.
+ *   out   [ncomp][n_nodes], overwritten.
+ *   ncomp 1..64.  Singular MLS systems are counted in counts[2]. */
+ifem_status ifem_interp_cells(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* grid,
+                              int32_t ncomp, void* out, void* stream);
+
+/* Fluid-stress forces on solids (Sec. II.B: the Newtonian and polymer parts of
+ * eq. FEM, F_k = -V0 (P^s - P^fN - P^fP) grad N_k; Sec. III.A step 1), ADDED
+ * to f_inout for the nodes of every tetrahedral particle (membrane nodes are
+ * left as they are).  Per element, with L the velocity gradient of the
+ * interpolated nodal velocities:
+ *   P^fN = eta J (L + L^T) F^-T,  P^fP = J G (C_avg - I) F^-T,
+ * C_avg the mean of the element's four nodal conformation tensors.  eta is the
+ * Newtonian viscosity, G the polymer modulus eta_p / lambda (eta (1 - beta) /
+ * lambda in the paper's notation, with eta the total viscosity there).  The
+ * kernel uses the equal current-configuration form V sigma grad_x N_k; float64
+ * arithmetic.  Inverted or flat elements contribute nothing (ifem_element_forces
+ * counts them).
+ *   x        [3][n_nodes] positions (see dtype; float32 offsets need no anchor:
+ *            the forces do not change under a translation), device.
+ *   v        [3][n_nodes] nodal velocities, same dtype.
+ *   C        [6][n_nodes] nodal conformation (xx, yy, zz, xy, xz, yz), same
+ *            dtype, or NULL for a Newtonian fluid (G is then unused).
+ *   eta, G   finite.
+ *   f_inout  [3][n_nodes] nodal forces, same dtype, read and written; it may
+ *            not overlap an input. */
+ifem_status ifem_fluid_forces(ifem_plan plan, int32_t dtype, const void* x, const void* v, const void* C, double eta,
+                              double G, void* f_inout, void* stream);
+
 /* Lagrangian update (Sec. III.A, last step of the algorithm): second-order
  * Adams-Bashforth with the interpolated velocities of this step and the last,
  *   x_out = x + dt (3/2 v - 1/2 v_prev),
@@ -269,7 +310,7 @@ ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[5], in
 /* Thread-local description of the last non-OK return ("" if none). */
 const char* ifem_last_error(void);
 
-/* Library version, e.g. 10200 for 1.2.0. */
+/* Library version, e.g. 10300 for 1.3.0. */
 int32_t ifem_version(void);
 
 #ifdef __cplusplus

@@ -312,7 +312,7 @@ int first_open_surface(const ifem_mesh_desc& m) {
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
-int32_t ifem_version(void) { return 10200; }
+int32_t ifem_version(void) { return 10300; }
 
 const char* ifem_last_error(void) { return g_last_error.c_str(); }
 
@@ -551,6 +551,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(prepare_force_kernels(P));
   HIP_TRY(prepare_transfer_kernels(P));
   HIP_TRY(prepare_volume_kernels(P));
+  HIP_TRY(prepare_fluid_kernels(P));
   HIP_TRY(hipStreamSynchronize(st));
   *out = plan;
   return ok();
@@ -715,6 +716,33 @@ ifem_status ifem_advance(ifem_plan plan, int32_t dtype, const void* x, const voi
   if ((x_out != x && overlaps(x_out, nb, x, nb)) || overlaps(x_out, nb, v, nb) || overlaps(x_out, nb, v_prev, nb))
     return fail(IFEM_ERR_INVALID_ARG, "x_out aliases an input (only x_out == x is allowed)");
   return launched(launch_advance(P, dtype, x, v, v_prev, dt, x_out, (hipStream_t)stream));
+}
+
+ifem_status ifem_interp_cells(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* grid,
+                              int32_t ncomp, void* out, void* stream) {
+  ifem_status s = check_common(plan, dtype, x, anchor);
+  if (s != IFEM_OK) return s;
+  const PlanDev& P = plan->P;
+  if (ncomp < 1 || ncomp > 64) return fail(IFEM_ERR_INVALID_ARG, "ncomp must be in [1, 64]");
+  const size_t es = dtype == IFEM_F32 ? 4 : 8, nb = (size_t)3 * P.n_nodes * es;
+  const size_t ob = (size_t)ncomp * P.n_nodes * es, gb = (size_t)ncomp * P.total_cells * es;
+  if (!grid || (P.n_nodes > 0 && !out)) return fail(IFEM_ERR_INVALID_ARG, "grid or out is NULL");
+  if (overlaps(out, ob, x, nb) || overlaps(out, ob, grid, gb) || overlaps(out, ob, anchor, (size_t)3 * P.n_particles * 8))
+    return fail(IFEM_ERR_INVALID_ARG, "out aliases an input");
+  return launched(launch_interp_cells(P, dtype, x, anchor, grid, ncomp, out, (hipStream_t)stream));
+}
+
+ifem_status ifem_fluid_forces(ifem_plan plan, int32_t dtype, const void* x, const void* v, const void* C, double eta,
+                              double G, void* f_inout, void* stream) {
+  if (!plan) return fail(IFEM_ERR_INVALID_ARG, "plan is NULL");
+  if (dtype != IFEM_F32 && dtype != IFEM_F64) return fail(IFEM_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+  const PlanDev& P = plan->P;
+  if (P.n_nodes > 0 && (!x || !v || !f_inout)) return fail(IFEM_ERR_INVALID_ARG, "x, v or f_inout is NULL");
+  if (!std::isfinite(eta) || !std::isfinite(G)) return fail(IFEM_ERR_INVALID_ARG, "eta and G must be finite");
+  const size_t es = dtype == IFEM_F32 ? 4 : 8, nb = (size_t)3 * P.n_nodes * es, cb = (size_t)6 * P.n_nodes * es;
+  if (overlaps(f_inout, nb, x, nb) || overlaps(f_inout, nb, v, nb) || overlaps(f_inout, nb, C, cb))
+    return fail(IFEM_ERR_INVALID_ARG, "f_inout aliases an input");
+  return launched(launch_fluid(P, dtype, x, v, C, eta, G, f_inout, (hipStream_t)stream));
 }
 
 ifem_status ifem_plan_kernel_times(ifem_plan plan, void* stream, double total_ms[16], int64_t launches[16],

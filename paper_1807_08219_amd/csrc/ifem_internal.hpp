@@ -68,6 +68,8 @@ enum KernelSlot {
   K_FILL = 7,
   K_VOLUME = 9,
   K_ADVANCE = 10,
+  K_INTERP_CELLS = 11,
+  K_FLUID = 12,
   K_NSLOTS = 16
 };
 
@@ -131,6 +133,13 @@ hipError_t launch_volume(const PlanDev& P, int dtype, const void* x, const doubl
 // ---- launchers (ifem_advance.hip)
 hipError_t launch_advance(const PlanDev& P, int dtype, const void* x, const void* v, const void* v_prev, double dt,
                           void* x_out, hipStream_t st);
+
+// ---- launchers (ifem_fluid.hip)
+hipError_t prepare_fluid_kernels(const PlanDev& P);
+hipError_t launch_interp_cells(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* grid,
+                               int ncomp, void* out, hipStream_t st);
+hipError_t launch_fluid(const PlanDev& P, int dtype, const void* x, const void* v, const void* C, double eta, double G,
+                        void* f, hipStream_t st);
 
 // ---- launchers (ifem_transfer.hip)
 hipError_t prepare_transfer_kernels(const PlanDev& P);

@@ -29,11 +29,12 @@ IFEM_OPT_SPREAD_MODE = 1
 IFEM_OPT_KERNEL_TIMING = 2
 KERNEL_SLOTS = {0: "k_forces", 1: "k_bin_count", 2: "k_scan", 3: "k_bin_fill", 4: "k_spread_home",
                 5: "k_spread_atomic", 6: "k_interp", 7: "k_fill", 8: "k_spread_merge", 9: "k_volume",
-                10: "k_advance"}
+                10: "k_advance", 11: "k_interp_cells", 12: "k_fluid"}
 
 EXPORTED = [
     "ifem_plan_create", "ifem_plan_destroy", "ifem_plan_set", "ifem_plan_info", "ifem_element_forces",
-    "ifem_spread", "ifem_interp", "ifem_volume_correct", "ifem_advance", "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
+    "ifem_spread", "ifem_interp", "ifem_volume_correct", "ifem_advance", "ifem_interp_cells", "ifem_fluid_forces",
+    "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
 ]
 
 
@@ -81,6 +82,8 @@ def lib():
         L.ifem_interp.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_volume_correct.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_advance.argtypes = [P, C.c_int32, P, P, P, C.c_double, P, P]
+        L.ifem_interp_cells.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P, P]
+        L.ifem_fluid_forces.argtypes = [P, C.c_int32, P, P, P, C.c_double, C.c_double, P, P]
         L.ifem_plan_status.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int32]
         L.ifem_plan_kernel_times.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.ifem_last_error.restype = C.c_char_p
@@ -217,3 +220,13 @@ class Plan:
         """Adams-Bashforth update x_out = x + dt (3/2 v - 1/2 v_prev) (forward Euler without v_prev)."""
         _check(lib().ifem_advance(self.handle, dtype, _ptr(x), _ptr(v), _ptr(v_prev), float(dt), _ptr(x_out),
                                   _stream(stream)))
+
+    def interp_cells(self, dtype, x, anchor, grid, out, stream=None):
+        """Cell-centred fields grid [ncomp][total_cells] to the nodes, out [ncomp][n_nodes]."""
+        _check(lib().ifem_interp_cells(self.handle, dtype, _ptr(x), _ptr(anchor), _ptr(grid), int(grid.shape[0]),
+                                       _ptr(out), _stream(stream)))
+
+    def fluid_forces(self, dtype, x, v, f_inout, C=None, eta=1.0, G=0.0, stream=None):
+        """Add the Newtonian and polymer fluid-stress forces of every solid to f_inout."""
+        _check(lib().ifem_fluid_forces(self.handle, dtype, _ptr(x), _ptr(v), _ptr(C), float(eta), float(G),
+                                       _ptr(f_inout), _stream(stream)))
