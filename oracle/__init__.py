@@ -63,6 +63,10 @@ def lib():
         L.orc_tet_fluid_element.argtypes = [_D, _D, _D, C.c_void_p, C.c_double, C.c_double, _D]
         L.orc_fluid_forces.argtypes = [C.c_int, _D, _D, _D, C.c_void_p, C.c_int, _I, _I, C.c_int, C.c_double,
                                        C.c_double, _D]
+        L.orc_point_triangle.argtypes = [_D, _D, _D, _D, _D]
+        L.orc_boundary_faces.argtypes = [C.c_int, _D, C.c_int, _I, _I, C.c_int, C.c_int, _I, _I]
+        L.orc_antistick.argtypes = [C.c_int, _D, _D, C.c_int, _I, _I, _I, C.c_int, _I, _I, C.c_int, _I, _D,
+                                    C.c_double, _D, _L]
         L.orc_advance.restype = None
         _lib = L
     return _lib
@@ -256,3 +260,34 @@ def fluid_forces(scene, u, C=None, eta=1.0, G=1.0, x=None):
                                  scene.n_particles, _c(scene.tet_start, np.int32), _c(scene.tet, np.int32),
                                  scene.n_tets, float(eta), float(G), f)
     return f, bad
+
+
+def point_triangle(p, a, b, c):
+    """(closest point on triangle abc to p, 1 if it is the plane projection)."""
+    out = np.zeros(3)
+    st = lib().orc_point_triangle(_c(p, np.float64), _c(a, np.float64), _c(b, np.float64), _c(c, np.float64), out)
+    return out, st
+
+
+def boundary_faces(scene):
+    """([3][n] outward boundary faces of the solids, [n] owning particle)."""
+    cap = 4 * scene.n_tets + 1
+    out = np.zeros((3, cap), dtype=np.int32)
+    part = np.zeros(cap, dtype=np.int32)
+    n = lib().orc_boundary_faces(scene.n_nodes, _c(scene.X_ref, np.float64), scene.n_particles,
+                                 _c(scene.tet_start, np.int32), _c(scene.tet, np.int32), scene.n_tets, cap, out, part)
+    return out[:, :n].copy(), part[:n].copy()
+
+
+def antistick(scene, d_min, x=None):
+    """Node-face anti-sticking: (x_out [3][n_nodes], winner face per node or -1, moved count)."""
+    x = scene.x64 if x is None else x
+    out = np.zeros((3, scene.n_nodes))
+    win = np.zeros(scene.n_nodes, dtype=np.int64)
+    L = np.array([b.length for b in scene.boxes], dtype=np.float64).reshape(-1, 3)
+    moved = lib().orc_antistick(scene.n_nodes, _c(scene.X_ref, np.float64), _c(x, np.float64), scene.n_particles,
+                                _c(scene.node_start, np.int32), _c(scene.tri_start, np.int32),
+                                _c(scene.tri, np.int32), scene.n_tris, _c(scene.tet_start, np.int32),
+                                _c(scene.tet, np.int32), scene.n_tets, _c(scene.box, np.int32), L, float(d_min), out,
+                                win)
+    return out, win, moved

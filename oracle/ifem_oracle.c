@@ -28,7 +28,8 @@
  *   - the second-order Adams-Bashforth update of the positions (Sec. III.A);
  *   - the interpolation of the conformation tensor to the nodes and the
  *     fluid-stress (Newtonian and polymer) forces on solids (Sec. II.B,
- *     Sec. III.A steps 1 and 4).
+ *     Sec. III.A steps 1 and 4);
+ *   - node-face anti-sticking (Sec. III.B).
  *
  * Readings of the paper where it is silent or garbled are marked READING.
  */
@@ -876,4 +877,253 @@ int orc_fluid_forces(int n_nodes, const double* X, const double* x, const double
         for (int i = 0; i < 3; ++i) f[i * (size_t)n_nodes + id[v]] += fe[v][i];
     }
   return bad;
+}
+
+/* ------------------------------------------------------------ node-face anti-sticking (Sec. III.B) */
+/* Closest point on the segment [a, b] to p. */
+static void seg_closest(const double p[3], const double a[3], const double b[3], double out[3]) {
+  double ab[3], ap[3];
+  sub3(b, a, ab);
+  sub3(p, a, ap);
+  const double L2 = dot3(ab, ab);
+  double t = L2 > 0.0 ? dot3(ap, ab) / L2 : 0.0;
+  t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  for (int i = 0; i < 3; ++i) out[i] = a[i] + t * ab[i];
+}
+
+/* Closest point on triangle (a, b, c) to p: the projection of p on the
+ * triangle's plane when it lies inside the triangle (on the inner side of all
+ * three edges), otherwise the nearest of the closest points of the three edges
+ * (first of ab, bc, ca on ties).  Returns 1 if the closest point is the plane
+ * projection. */
+int orc_point_triangle(const double p[3], const double a[3], const double b[3], const double c[3], double out[3]) {
+  double ab[3], ac[3], n[3], ap[3];
+  sub3(b, a, ab);
+  sub3(c, a, ac);
+  cross3(ab, ac, n);
+  sub3(p, a, ap);
+  const double n2 = dot3(n, n);
+  if (n2 > 0.0) {
+    const double s = dot3(ap, n) / n2;
+    double q[3];
+    for (int i = 0; i < 3; ++i) q[i] = p[i] - s * n[i];
+    const double* v[3] = {a, b, c};
+    int inside = 1;
+    for (int e = 0; e < 3; ++e) {
+      double ed[3], vq[3], cr[3];
+      sub3(v[(e + 1) % 3], v[e], ed);
+      sub3(q, v[e], vq);
+      cross3(ed, vq, cr);
+      if (dot3(cr, n) < 0.0) inside = 0;
+    }
+    if (inside) {
+      for (int i = 0; i < 3; ++i) out[i] = q[i];
+      return 1;
+    }
+  }
+  const double* v[3] = {a, b, c};
+  double best = INFINITY;
+  for (int e = 0; e < 3; ++e) {
+    double q[3], d[3];
+    seg_closest(p, v[e], v[(e + 1) % 3], q);
+    sub3(q, p, d);
+    const double dd = dot3(d, d);
+    if (dd < best) {
+      best = dd;
+      for (int i = 0; i < 3; ++i) out[i] = q[i];
+    }
+  }
+  return 0;
+}
+
+static int cmp_face_key(const void* pa, const void* pb) {
+  const int64_t* a = (const int64_t*)pa;
+  const int64_t* b = (const int64_t*)pb;
+  return a[0] < b[0] ? -1 : (a[0] > b[0] ? 1 : (a[1] < b[1] ? -1 : (a[1] > b[1])));
+}
+
+/* Boundary faces of the tetrahedral meshes of the solids: the faces that
+ * belong to one tetrahedron only, oriented outward (away from the
+ * tetrahedron's fourth node, in the reference configuration X), listed in the
+ * order of (tetrahedron, face opposite node j = 0..3).  READING: the paper's
+ * node-face check needs a surface for every particle; a solid's surface is its
+ * mesh boundary.  out [3][cap] node ids, part [cap] owning particle; returns
+ * the number of faces (at most cap) or -1 if cap is too small. */
+int orc_boundary_faces(int n_nodes, const double* X, int n_particles, const int* tet_start, const int* tet, int n_tet,
+                       int cap, int* out, int* part) {
+  int nf = 0;
+  for (int p = 0; p < n_particles; ++p) {
+    const int t0 = tet_start[p], nt = tet_start[p + 1] - t0;
+    if (nt == 0) continue;
+    int64_t* keys = malloc(sizeof(int64_t) * 2 * 4 * (size_t)nt); /* (sorted-triple key, 4 t + j) */
+    for (int t = 0; t < nt; ++t)
+      for (int j = 0; j < 4; ++j) {
+        int v[3], m = 0;
+        for (int q = 0; q < 4; ++q)
+          if (q != j) v[m++] = tet[q * n_tet + t0 + t];
+        for (int a = 0; a < 2; ++a) /* sort the triple */
+          for (int b = 0; b < 2 - a; ++b)
+            if (v[b] > v[b + 1]) {
+              const int s = v[b];
+              v[b] = v[b + 1];
+              v[b + 1] = s;
+            }
+        keys[2 * (4 * t + j)] = ((int64_t)v[0] << 42) | ((int64_t)v[1] << 21) | (int64_t)v[2];
+        keys[2 * (4 * t + j) + 1] = 4 * t + j;
+      }
+    qsort(keys, 4 * (size_t)nt, 2 * sizeof(int64_t), cmp_face_key);
+    char* boundary = calloc(4 * (size_t)nt, 1);
+    for (int i = 0; i < 4 * nt;) {
+      int e = i;
+      while (e < 4 * nt && keys[2 * e] == keys[2 * i]) ++e;
+      if (e - i == 1) boundary[keys[2 * i + 1]] = 1;
+      i = e;
+    }
+    for (int t = 0; t < nt; ++t)
+      for (int j = 0; j < 4; ++j) {
+        if (!boundary[4 * t + j]) continue;
+        if (nf >= cap) {
+          free(keys);
+          free(boundary);
+          return -1;
+        }
+        int v[3], m = 0;
+        for (int q = 0; q < 4; ++q)
+          if (q != j) v[m++] = tet[q * n_tet + t0 + t];
+        double a[3], b[3], c[3], o[3], ab[3], ac[3], n[3], ao[3];
+        pos(X, n_nodes, v[0], a);
+        pos(X, n_nodes, v[1], b);
+        pos(X, n_nodes, v[2], c);
+        pos(X, n_nodes, tet[j * n_tet + t0 + t], o);
+        sub3(b, a, ab);
+        sub3(c, a, ac);
+        cross3(ab, ac, n);
+        sub3(o, a, ao);
+        if (dot3(n, ao) > 0.0) { /* the normal points at the fourth node: flip */
+          const int s = v[1];
+          v[1] = v[2];
+          v[2] = s;
+        }
+        for (int i = 0; i < 3; ++i) out[i * cap + nf] = v[i];
+        part[nf++] = p;
+      }
+    free(keys);
+    free(boundary);
+  }
+  return nf;
+}
+
+/* Node-face anti-sticking (Sec. III.B, resolving numerical sticking): every
+ * node closer than d_min to a face of another particle of its box is moved
+ * away from the closest point of that face until it is d_min from it.
+ * Faces: the membrane triangles (ids 0 .. n_tri-1) and the boundary faces of
+ * the solids (ids n_tri + k, in the order orc_boundary_faces lists them).
+ * Distances use the periodic minimum image of the box.  READINGS: the closest
+ * face is the one of least distance, distances compared in float32 (the
+ * precision of the device's ordering key), ties to the lower face id; a node
+ * moves when that float32 distance is below (float)d_min; the move is along
+ * (x - c)/|x - c| from the closest point c (the face normal when x lies on the
+ * face), to c + d_min (x - c)/|x - c|; all nodes are tested against the
+ * positions before the pass (none sees another's move).  The paper's particle
+ * bounding-box check is a culling step: particles whose box, grown by 2 d_min
+ * and taken periodically, cannot reach the node are skipped, which changes no
+ * result.  x, x_out [3][n_nodes]; box_len [n_boxes][3] box lengths;
+ * winner [n_nodes]: the face that moved the node, or -1.  Returns the number
+ * of moved nodes. */
+int orc_antistick(int n_nodes, const double* X, const double* x, int n_particles, const int* node_start,
+                  const int* tri_start, const int* tri, int n_tri, const int* tet_start, const int* tet, int n_tet,
+                  const int* box_of_particle, const double* box_len, double d_min, double* x_out, int64_t* winner) {
+  memcpy(x_out, x, sizeof(double) * 3 * (size_t)n_nodes);
+  const int cap = 4 * n_tet + 1;
+  int* bf = malloc(sizeof(int) * 3 * (size_t)cap);
+  int* bp = malloc(sizeof(int) * (size_t)cap);
+  const int nb = orc_boundary_faces(n_nodes, X, n_particles, tet_start, tet, n_tet, cap, bf, bp);
+  double* lo = malloc(sizeof(double) * 3 * (size_t)n_particles);
+  double* hi = malloc(sizeof(double) * 3 * (size_t)n_particles);
+  for (int p = 0; p < n_particles; ++p)
+    for (int i = 0; i < 3; ++i) {
+      lo[3 * p + i] = INFINITY;
+      hi[3 * p + i] = -INFINITY;
+      for (int k = node_start[p]; k < node_start[p + 1]; ++k) {
+        const double v = x[(size_t)i * n_nodes + k];
+        lo[3 * p + i] = fmin(lo[3 * p + i], v);
+        hi[3 * p + i] = fmax(hi[3 * p + i], v);
+      }
+    }
+  int moved = 0;
+  for (int P = 0; P < n_particles; ++P) {
+    const int b = box_of_particle[P];
+    const double* Lb = box_len + 3 * b;
+    for (int k = node_start[P]; k < node_start[P + 1]; ++k) {
+      double xk[3];
+      pos(x, n_nodes, k, xk);
+      float best = INFINITY;
+      int64_t bestf = -1;
+      double bestc[3] = {0, 0, 0}, bestn[3] = {0, 0, 0};
+      for (int Q = 0; Q < n_particles; ++Q) {
+        if (Q == P || box_of_particle[Q] != b) continue;
+        int near = 1; /* periodic box test, grown by 2 d_min */
+        for (int i = 0; i < 3; ++i) {
+          const double c = 0.5 * (lo[3 * Q + i] + hi[3 * Q + i]), r = 0.5 * (hi[3 * Q + i] - lo[3 * Q + i]) + 2.0 * d_min;
+          double d = xk[i] - c;
+          d -= Lb[i] * nearbyint(d / Lb[i]);
+          if (fabs(d) > r) near = 0;
+        }
+        if (!near) continue;
+        const int nfq = tri_start[Q + 1] - tri_start[Q];
+        for (int s = 0; s < nfq + nb; ++s) {
+          int v[3];
+          int64_t fid;
+          if (s < nfq) {
+            const int t = tri_start[Q] + s;
+            for (int i = 0; i < 3; ++i) v[i] = tri[i * n_tri + t];
+            fid = t;
+          } else {
+            const int j = s - nfq;
+            if (bp[j] != Q) continue;
+            for (int i = 0; i < 3; ++i) v[i] = bf[i * cap + j];
+            fid = (int64_t)n_tri + j;
+          }
+          double r[3][3]; /* corners relative to the node, periodic minimum image */
+          for (int m = 0; m < 3; ++m)
+            for (int i = 0; i < 3; ++i) {
+              double d = x[(size_t)i * n_nodes + v[m]] - xk[i];
+              d -= Lb[i] * nearbyint(d / Lb[i]);
+              r[m][i] = d;
+            }
+          const double zero[3] = {0.0, 0.0, 0.0};
+          double c[3];
+          orc_point_triangle(zero, r[0], r[1], r[2], c);
+          const float dist = (float)norm3(c);
+          if (dist < best || (dist == best && fid < bestf)) {
+            best = dist;
+            bestf = fid;
+            double e1[3], e2[3];
+            sub3(r[1], r[0], e1);
+            sub3(r[2], r[0], e2);
+            cross3(e1, e2, bestn);
+            for (int i = 0; i < 3; ++i) bestc[i] = c[i];
+          }
+        }
+      }
+      if (winner) winner[k] = -1;
+      if (bestf < 0 || !(best < (float)d_min)) continue;
+      const double dc = norm3(bestc);
+      double dir[3];
+      if (dc > 0.0) {
+        for (int i = 0; i < 3; ++i) dir[i] = -bestc[i] / dc; /* from the closest point to the node */
+      } else {
+        const double nn = norm3(bestn);
+        for (int i = 0; i < 3; ++i) dir[i] = bestn[i] / nn;
+      }
+      for (int i = 0; i < 3; ++i) x_out[(size_t)i * n_nodes + k] = xk[i] + bestc[i] + d_min * dir[i];
+      if (winner) winner[k] = bestf;
+      moved++;
+    }
+  }
+  free(bf);
+  free(bp);
+  free(lo);
+  free(hi);
+  return moved;
 }
