@@ -1018,7 +1018,8 @@ int orc_boundary_faces(int n_nodes, const double* X, int n_particles, const int*
  * away from the closest point of that face until it is d_min from it.
  * Faces: the membrane triangles (ids 0 .. n_tri-1) and the boundary faces of
  * the solids (ids n_tri + k, in the order orc_boundary_faces lists them).
- * Distances use the periodic minimum image of the box.  READINGS: the closest
+ * Distances use the periodic image of each face nearest to the node (the
+ * image of its first corner, applied to the whole face).  READINGS: the closest
  * face is the one of least distance, distances compared in float32 (the
  * precision of the device's ordering key), ties to the lower face id; a node
  * moves when that float32 distance is below (float)d_min; the move is along
@@ -1084,13 +1085,14 @@ int orc_antistick(int n_nodes, const double* X, const double* x, int n_particles
             for (int i = 0; i < 3; ++i) v[i] = bf[i * cap + j];
             fid = (int64_t)n_tri + j;
           }
-          double r[3][3]; /* corners relative to the node, periodic minimum image */
-          for (int m = 0; m < 3; ++m)
-            for (int i = 0; i < 3; ++i) {
-              double d = x[(size_t)i * n_nodes + v[m]] - xk[i];
-              d -= Lb[i] * nearbyint(d / Lb[i]);
-              r[m][i] = d;
-            }
+          /* corners relative to the node in the periodic image of the face nearest to the node,
+           * chosen by its first corner and applied to all three (a face is one piece) */
+          double r[3][3];
+          for (int i = 0; i < 3; ++i) {
+            const double d0 = x[(size_t)i * n_nodes + v[0]] - xk[i];
+            const double shift = Lb[i] * nearbyint(d0 / Lb[i]);
+            for (int m = 0; m < 3; ++m) r[m][i] = x[(size_t)i * n_nodes + v[m]] - xk[i] - shift;
+          }
           const double zero[3] = {0.0, 0.0, 0.0};
           double c[3];
           orc_point_triangle(zero, r[0], r[1], r[2], c);

@@ -150,3 +150,13 @@ def test_membrane_near_a_solid_is_pushed_along_the_face_normal():
     assert inner.size > 0
     np.testing.assert_allclose(out[0, inner], 6.0 + d_min, rtol=0, atol=1e-12)
     np.testing.assert_allclose(out[1:, inner], sc.x64[1:, inner], rtol=0, atol=1e-12)
+
+
+def test_faces_half_a_box_away_are_not_torn_by_the_periodic_image():
+    # the second sphere's centre half a box length away in x: per-corner wrapping would split faces
+    # that straddle the half-box distance into two images and fake a near face; nothing is near
+    d_min = 0.5
+    sc = _two_spheres(3.0)  # centres 5.0 apart in x in a box 10 long
+    assert np.isclose(sc.x64[0, sc.node_start[1]:].mean() - sc.x64[0, :sc.node_start[1]].mean(), 5.0, atol=0.05)
+    out, win, moved = oracle.antistick(sc, d_min)
+    assert moved == 0 and np.array_equal(out, sc.x64)
