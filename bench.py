@@ -295,6 +295,28 @@ def bench_viscoelastic(plan, sc, steps, dev, x32, anchor):
     return res
 
 
+def bench_antistick(plan, sc, steps, dev, x32, anchor):
+    """Node-face anti-sticking (Sec. III.B) on the main workload with d_min = h, float32 offsets."""
+    import torch
+
+    from paper_1807_08219_amd import ifem
+
+    d_min = min(b.h for b in sc.boxes)
+    out = torch.empty_like(x32)
+    faces = torch.empty(sc.n_nodes, dtype=torch.int64, device=dev)
+    ms = _kernel_ms(plan, "k_contact", lambda: plan.antistick(ifem.IFEM_F32, x32, anchor, out, d_min, faces), steps)
+    moved = int((faces >= 0).sum())
+    nf = sc.n_tris + 4 * sc.n_tets  # upper bound on the solids' boundary faces
+    nbytes = sc.n_nodes * (12 + 12) + nf * 12
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log(f"anti-sticking: {ms:.4f} ms, {moved} nodes moved ({gbs:.0f} GB/s algorithmic)")
+    return {"workload": f"{sc.name}, d_min = h", "ms": round(ms, 4), "value": round(sc.n_nodes / (ms * 1e-3), 1),
+            "unit": "nodes/s", "moved_nodes": moved,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(nbytes)},
+            "device_status": plan.status()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +330,7 @@ def main():
     ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-visco", action="store_true")
+    ap.add_argument("--no-contact", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="spread tile, e.g. 32,16,8 (powers of two)")
     ap.add_argument("--block-forces", type=int, default=None, help="threads per particle workgroup")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -457,6 +480,8 @@ def main():
         out["lagrangian_loop"] = bench_loop(plan, sc, args.steps, dev, anchor, u32)
     if not args.no_visco:
         out["viscoelastic"] = bench_viscoelastic(plan, sc, args.steps, dev, x32, anchor)
+    if not args.no_contact:
+        out["antistick"] = bench_antistick(plan, sc, args.steps, dev, x32, anchor)
 
     if not args.no_fp64:
         x64 = torch.as_tensor(sc.x64, device=dev)

@@ -17,9 +17,10 @@
  * for viscoelastic suspensions, the interpolation of the conformation tensor
  * to the nodes (ifem_interp_cells, Sec. III.A step 4) and the fluid-stress
  * forces on solids (ifem_fluid_forces, Sec. II.B eq. FEM, Sec. III.A step 1);
- * and the end of a time step (Sec. III.A, last step): the second-order
+ * and the end of a time step (Sec. III.A, last step; Sec. III.B): the second-order
  * Adams-Bashforth update of the positions (ifem_advance) and the membrane
- * volume correction of Sec. II.E (ifem_volume_correct),
+ * volume correction of Sec. II.E (ifem_volume_correct) and the node-face
+ * anti-sticking of Sec. III.B (ifem_antistick),
  *
  * with phi the linear moving-least-squares weights of Sec. II.C (27-node
  * stencil around the nearest lattice node, cubic-spline weight, support
@@ -130,7 +131,8 @@ enum {
   IFEM_KERNEL_VOLUME = 9,        /* membrane volume correction                          */
   IFEM_KERNEL_ADVANCE = 10,      /* Adams-Bashforth position update                     */
   IFEM_KERNEL_INTERP_CELLS = 11, /* interpolation of cell-centred fields                */
-  IFEM_KERNEL_FLUID = 12         /* fluid-stress forces on solids                       */
+  IFEM_KERNEL_FLUID = 12,        /* fluid-stress forces on solids                       */
+  IFEM_KERNEL_CONTACT = 13       /* node-face anti-sticking (all of its kernels)        */
 };
 
 /* Mesh description, HOST memory, read once by ifem_plan_create. */
@@ -296,6 +298,32 @@ ifem_status ifem_fluid_forces(ifem_plan plan, int32_t dtype, const void* x, cons
 ifem_status ifem_advance(ifem_plan plan, int32_t dtype, const void* x, const void* v, const void* v_prev, double dt,
                          void* x_out, void* stream);
 
+/* Node-face anti-sticking (Sec. III.B, resolving numerical sticking): every
+ * node closer than d_min to a face of another particle of its periodic box is
+ * moved away from the closest point c of that face to c + d_min (x - c)/|x - c|
+ * (along the face normal when x lies on the face).  Faces are the membrane
+ * triangles (face id = triangle index) and the boundary faces of the solids'
+ * tetrahedral meshes (ids n_tris + k, listed by tetrahedron and local face
+ * opposite node j = 0..3, oriented outward in X_ref).  The closest face is the
+ * one of least distance rounded to float32, ties to the lower id; a node moves
+ * when that float32 distance is below (float)d_min.  Distances are float64 with
+ * the periodic minimum image; every node is tested against the positions
+ * before the call (no node sees another's move).  Exact search: a uniform grid
+ * of contact cells about four lattice cells wide per box replaces the paper's
+ * bounding-box broad phase.  A face that is not finite or spans more than half
+ * a box is skipped.  One pass; a node pushed out of one particle's range into
+ * another's is not checked again.
+ *   x, anchor  positions (see dtype), device.
+ *   d_min      separation, 0 < d_min <= the contact-cell width (box length /
+ *              max(1, floor(n / 4)) per axis) and <= a quarter box; the paper
+ *              uses one lattice spacing h.
+ *   x_out      [3][n_nodes] moved positions, same dtype (float32: offsets from
+ *              the same anchors); must not overlap x.
+ *   face_out   [n_nodes] int64, device, or NULL: the face that moved each node,
+ *              -1 for nodes that stay. */
+ifem_status ifem_antistick(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, double d_min,
+                           void* x_out, int64_t* face_out, void* stream);
+
 /* Synchronise `stream` and the timer's events; total_ms[i] and launches[i]
  * receive the summed duration and number of launches of kernel slot i
  * (IFEM_KERNEL_*) recorded since the last reset; launches[15] counts launches
@@ -310,7 +338,7 @@ ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[5], in
 /* Thread-local description of the last non-OK return ("" if none). */
 const char* ifem_last_error(void);
 
-/* Library version, e.g. 10300 for 1.3.0. */
+/* Library version, e.g. 10400 for 1.4.0. */
 int32_t ifem_version(void);
 
 #ifdef __cplusplus

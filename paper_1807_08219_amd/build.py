@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libifem.so")
 SOURCES = ["ifem_api.hip", "ifem_forces.hip", "ifem_transfer.hip", "ifem_volume.hip", "ifem_advance.hip",
-           "ifem_fluid.hip"]
+           "ifem_fluid.hip", "ifem_contact.hip"]
 HEADERS = ["ifem_device.hpp", "ifem_internal.hpp", os.path.join("..", "..", "include", "ifem.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

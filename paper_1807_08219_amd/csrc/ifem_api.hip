@@ -63,6 +63,8 @@ struct ifem_plan_s {
   int spread_mode = IFEM_SPREAD_TILED;
   int64_t workspace_bytes = 0;
   int32_t open_surface = -1;  // first membrane whose faces do not close, or -1
+  double contact_cell = 0.0;  // smallest contact-cell width over the boxes
+  double min_box_len = 0.0;   // smallest box length over the axes and boxes
 };
 
 // ------------------------------------------------------------------ host-side mesh preprocessing
@@ -277,6 +279,70 @@ hipError_t upload(DeviceBuffers& mem, T** dst, const T* src, size_t n, hipStream
 
 namespace {
 
+// Boundary faces of the solids' tetrahedral meshes: the faces of one
+// tetrahedron only, listed by (tetrahedron, face opposite local node j =
+// 0..3), corners in the tetrahedron's order without node j, turned (second and
+// third corner swapped) so that the normal points away from node j in the
+// reference configuration.  out [3][n] global node ids.
+void boundary_faces(const ifem_mesh_desc& m, std::vector<int32_t>& out) {
+  out.clear();
+  struct Key {
+    int32_t v[3];
+    int32_t slot;
+  };
+  std::vector<Key> keys;
+  std::vector<char> single;
+  std::vector<int32_t> f0, f1, f2;
+  for (int p = 0; p < m.n_particles; ++p) {
+    const int t0 = m.tet_start[p], nt = m.tet_start[p + 1] - t0;
+    if (nt == 0) continue;
+    keys.resize((size_t)4 * nt);
+    for (int t = 0; t < nt; ++t)
+      for (int j = 0; j < 4; ++j) {
+        Key& k = keys[(size_t)4 * t + j];
+        int c = 0;
+        for (int q = 0; q < 4; ++q)
+          if (q != j) k.v[c++] = m.tet[q * m.n_tets + t0 + t];
+        std::sort(k.v, k.v + 3);
+        k.slot = 4 * t + j;
+      }
+    std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
+      return std::lexicographical_compare(a.v, a.v + 3, b.v, b.v + 3);
+    });
+    single.assign((size_t)4 * nt, 0);
+    for (size_t i = 0; i < keys.size();) {
+      size_t e = i + 1;
+      while (e < keys.size() && std::equal(keys[e].v, keys[e].v + 3, keys[i].v)) ++e;
+      if (e - i == 1) single[keys[i].slot] = 1;
+      i = e;
+    }
+    for (int t = 0; t < nt; ++t)
+      for (int j = 0; j < 4; ++j) {
+        if (!single[(size_t)4 * t + j]) continue;
+        int v[3], c = 0;
+        for (int q = 0; q < 4; ++q)
+          if (q != j) v[c++] = m.tet[q * m.n_tets + t0 + t];
+        const int o = m.tet[j * m.n_tets + t0 + t];
+        double e1[3], e2[3], eo[3];
+        for (int a = 0; a < 3; ++a) {
+          const double x0 = m.X_ref[(size_t)a * m.n_nodes + v[0]];
+          e1[a] = m.X_ref[(size_t)a * m.n_nodes + v[1]] - x0;
+          e2[a] = m.X_ref[(size_t)a * m.n_nodes + v[2]] - x0;
+          eo[a] = m.X_ref[(size_t)a * m.n_nodes + o] - x0;
+        }
+        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                             e1[0] * e2[1] - e1[1] * e2[0]};
+        if (n[0] * eo[0] + n[1] * eo[1] + n[2] * eo[2] > 0.0) std::swap(v[1], v[2]);
+        f0.push_back(v[0]);
+        f1.push_back(v[1]);
+        f2.push_back(v[2]);
+      }
+  }
+  out.insert(out.end(), f0.begin(), f0.end());
+  out.insert(out.end(), f1.begin(), f1.end());
+  out.insert(out.end(), f2.begin(), f2.end());
+}
+
 // First particle whose triangles do not form a closed, consistently oriented
 // surface (every directed edge once and its reverse once), or -1.  The
 // enclosed volume, and so the volume correction, is defined only for those.
@@ -312,7 +378,7 @@ int first_open_surface(const ifem_mesh_desc& m) {
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
-int32_t ifem_version(void) { return 10300; }
+int32_t ifem_version(void) { return 10400; }
 
 const char* ifem_last_error(void) { return g_last_error.c_str(); }
 
@@ -385,6 +451,10 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   std::vector<int32_t> node_particle(m.n_nodes);
   for (int p = 0; p < m.n_particles; ++p)
     for (int k = m.node_start[p]; k < m.node_start[p + 1]; ++k) node_particle[k] = p;
+  std::vector<int32_t> bfaces;
+  boundary_faces(m, bfaces);
+  const int n_bfaces = (int)(bfaces.size() / 3);
+  if ((int64_t)m.n_tris + n_bfaces >= ((int64_t)1 << 31)) return fail(IFEM_ERR_UNSUPPORTED, "too many faces");
   std::vector<BoxDev> hb(n_boxes);
   std::vector<int32_t> tile_box;
   int64_t total_cells = 0;
@@ -407,8 +477,33 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     tile_box.insert(tile_box.end(), (size_t)nt, b);
   }
 
+  // contact cells: about 4 lattice cells wide, an exact tiling of every periodic box
+  std::vector<ContactBoxDev> cb(n_boxes);
+  int64_t n_ccells = 0;
+  double contact_cell = 1e308, min_box_len = 1e308;
+  for (int b = 0; b < n_boxes; ++b) {
+    ContactBoxDev& C = cb[b];
+    memset(&C, 0, sizeof C);
+    C.base = (int32_t)n_ccells;
+    int64_t nb = 1;
+    for (int a = 0; a < 3; ++a) {
+      C.nc[a] = std::max(1, boxes[b].n[a] / 4);
+      C.origin[a] = boxes[b].origin[a];
+      C.len[a] = boxes[b].n[a] * boxes[b].h;
+      C.inv_len[a] = 1.0 / C.len[a];
+      C.inv_cs[a] = C.nc[a] / C.len[a];
+      contact_cell = std::min(contact_cell, C.len[a] / C.nc[a]);
+      min_box_len = std::min(min_box_len, C.len[a]);
+      nb *= C.nc[a];
+    }
+    n_ccells += nb;
+    if (n_ccells >= ((int64_t)1 << 30)) return fail(IFEM_ERR_UNSUPPORTED, "too many contact cells");
+  }
+
   // --- device upload
   ifem_plan plan = new ifem_plan_s();
+  plan->contact_cell = contact_cell;
+  plan->min_box_len = min_box_len;
   plan->tune = tn;
   plan->open_surface = open_surface;
   PlanDev& P = plan->P;
@@ -478,6 +573,17 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   uint32_t* d_fmax;
   HIP_TRY(mem.alloc(&d_fmax, (size_t)3 * n_tiles));
   HIP_TRY(mem.alloc(&d_halo, (size_t)3 * n_tiles * region_cells));  // sized for float64
+  ContactBoxDev* d_cboxes;
+  int32_t *d_bface, *d_ccount, *d_coff, *d_ccur, *d_cown, *d_clist;
+  unsigned long long* d_ckeys;
+  HIP_TRY(upload(mem, &d_cboxes, cb.data(), cb.size(), st));
+  HIP_TRY(upload(mem, &d_bface, bfaces.data(), bfaces.size(), st));
+  HIP_TRY(mem.alloc(&d_ccount, (size_t)n_ccells));
+  HIP_TRY(mem.alloc(&d_coff, (size_t)n_ccells + 1));
+  HIP_TRY(mem.alloc(&d_ccur, (size_t)n_ccells));
+  HIP_TRY(mem.alloc(&d_cown, (size_t)n_ccells));
+  HIP_TRY(mem.alloc(&d_clist, (size_t)m.n_nodes));
+  HIP_TRY(mem.alloc(&d_ckeys, (size_t)m.n_nodes));
   plan->workspace_bytes = (int64_t)(12 * (int64_t)n_tiles + 1 + list_cap) * 4 + (int64_t)3 * n_tiles * region_cells * 8;
 
   P.tri_src = d_tri_src;
@@ -534,6 +640,22 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     ta.tile[a] = tn.tile[a];
     ta.tile_shift[a] = __builtin_ctz(tn.tile[a]);
   }
+  ContactArgs& ca = P.cargs;
+  ca.node_particle = d_np;
+  ca.particle_box = d_box;
+  ca.boxes = d_cboxes;
+  ca.tri = d_tri_glob;
+  ca.bface = d_bface;
+  ca.count = d_ccount;
+  ca.off = d_coff;
+  ca.cursor = d_ccur;
+  ca.owner = d_cown;
+  ca.list = d_clist;
+  ca.keys = d_ckeys;
+  ca.n_nodes = m.n_nodes;
+  ca.n_tris = m.n_tris;
+  ca.n_bfaces = n_bfaces;
+  ca.n_cells = (int32_t)n_ccells;
 
   // --- reference metrics on the device (float64), degeneracy check
   HIP_TRY(launch_fill_u64(d_status, 5, st));
@@ -743,6 +865,23 @@ ifem_status ifem_fluid_forces(ifem_plan plan, int32_t dtype, const void* x, cons
   if (overlaps(f_inout, nb, x, nb) || overlaps(f_inout, nb, v, nb) || overlaps(f_inout, nb, C, cb))
     return fail(IFEM_ERR_INVALID_ARG, "f_inout aliases an input");
   return launched(launch_fluid(P, dtype, x, v, C, eta, G, f_inout, (hipStream_t)stream));
+}
+
+ifem_status ifem_antistick(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, double d_min,
+                           void* x_out, int64_t* face_out, void* stream) {
+  ifem_status s = check_common(plan, dtype, x, anchor);
+  if (s != IFEM_OK) return s;
+  const PlanDev& P = plan->P;
+  if (P.n_nodes > 0 && !x_out) return fail(IFEM_ERR_INVALID_ARG, "x_out is NULL");
+  if (!(d_min > 0.0) || !(d_min <= plan->contact_cell) || !(d_min <= 0.25 * plan->min_box_len))
+    return fail(IFEM_ERR_INVALID_ARG, "d_min must be positive, at most the contact-cell width %g and a quarter box",
+                plan->contact_cell);
+  const size_t nb = (size_t)3 * P.n_nodes * (dtype == IFEM_F32 ? 4 : 8), fb = (size_t)P.n_nodes * 8;
+  const size_t ab = (size_t)3 * P.n_particles * 8;
+  if (overlaps(x_out, nb, x, nb) || overlaps(x_out, nb, anchor, ab) || overlaps(face_out, fb, x, nb) ||
+      overlaps(face_out, fb, x_out, nb) || overlaps(face_out, fb, anchor, ab))
+    return fail(IFEM_ERR_INVALID_ARG, "outputs alias inputs (every node reads the positions before the pass)");
+  return launched(launch_antistick(P, dtype, x, anchor, d_min, x_out, face_out, (hipStream_t)stream));
 }
 
 ifem_status ifem_plan_kernel_times(ifem_plan plan, void* stream, double total_ms[16], int64_t launches[16],

@@ -88,6 +88,30 @@ __device__ __forceinline__ void block_sum(double v[NV], double* lds /*[NV][16]*/
   __syncthreads();
 }
 
+// Groups the active lanes (key >= 0) of a wavefront by key: every lane gets
+// the lane of its group's leader and its rank in the group; the leader also
+// gets the group size (0 elsewhere).  Ballots and lane reads only, no memory
+// traffic, so the atomics that follow can all be in flight at once.  Every
+// lane of the wavefront must call it.
+__device__ __forceinline__ void wave_groups(int key, int& leader, int& rank, int& size) {
+  const int lane = threadIdx.x & (kWave - 1);
+  unsigned long long todo = __ballot(key >= 0);
+  leader = lane;
+  rank = 0;
+  size = 0;
+  while (todo) {
+    const int l = __ffsll((long long)todo) - 1;
+    const int kl = __builtin_amdgcn_readlane(key, l);
+    const unsigned long long m = __ballot(key == kl) & todo;
+    if (key == kl) {
+      leader = l;
+      rank = (int)__popcll(m & ((1ull << lane) - 1ull));
+    }
+    if (lane == l) size = (int)__popcll(m);
+    todo &= ~m;
+  }
+}
+
 // ------------------------------------------------------------------ fast elementary functions
 // float32: the hardware square root and reciprocal (about 1 ulp); float64:
 // the correctly rounded operations.

@@ -55,6 +55,32 @@ struct TransferArgs {
   int32_t region_cells;   // (tile_x + 1)(tile_y + 2)(tile_z + 2): rows of tile_x cells and one pad cell
 };
 
+// One periodic box's grid of contact cells (node-face anti-sticking).
+struct ContactBoxDev {
+  int32_t nc[3];      // cells per axis
+  int32_t base;       // first cell of this box
+  double origin[3];
+  double inv_cs[3];   // 1 / cell width per axis
+  double len[3];      // box length per axis (periodic minimum image)
+  double inv_len[3];
+};
+
+// Everything the anti-sticking kernels read.
+struct ContactArgs {
+  const int32_t* node_particle;  // [n_nodes]
+  const int32_t* particle_box;   // [n_p]
+  const ContactBoxDev* boxes;    // [n_boxes]
+  const int32_t* tri;            // [3][n_tris] membrane triangles, global node ids (input order)
+  const int32_t* bface;          // [3][n_bfaces] boundary faces of the solids, outward
+  int32_t* count;                // [n_cells] nodes per cell
+  int32_t* off;                  // [n_cells + 1]
+  int32_t* cursor;               // [n_cells]
+  int32_t* owner;                // [n_cells] particle of all the cell's nodes, -2 mixed, -1 empty
+  int32_t* list;                 // [n_nodes] node ids grouped by cell
+  unsigned long long* keys;      // [n_nodes] (float32 distance bits, face id) of the nearest close face
+  int32_t n_nodes, n_tris, n_bfaces, n_cells;
+};
+
 // Kernel slots of the per-kernel event timer.
 enum KernelSlot {
   K_FORCES = 0,
@@ -70,6 +96,7 @@ enum KernelSlot {
   K_ADVANCE = 10,
   K_INTERP_CELLS = 11,
   K_FLUID = 12,
+  K_CONTACT = 13,
   K_NSLOTS = 16
 };
 
@@ -113,6 +140,7 @@ struct PlanDev {
   double* vref;                // [n_p] enclosed volume of every membrane in the reference configuration
   ForceArgs fargs;
   TransferArgs targs;
+  ContactArgs cargs;
   KernelTimer* timer;  // host object owned by the plan
 };
 
@@ -150,6 +178,14 @@ hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const
 hipError_t launch_interp(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* grid,
                          void* v, int block, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_scan(int32_t n, const int32_t* cnt, int32_t* off, int32_t* cursor, int64_t cap,
+                       unsigned long long* status, hipStream_t st);
+
+// ---- launchers (ifem_contact.hip)
+hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const double* anchor, double d_min,
+                            void* x_out, int64_t* face_out, hipStream_t st);
 size_t spread_tile_lds_bytes(const PlanDev& P, int dtype);
 
 }  // namespace ifem

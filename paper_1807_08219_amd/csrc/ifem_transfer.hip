@@ -61,6 +61,10 @@ static hipError_t fill(T* p, int64_t n, T v, hipStream_t st) {
 }
 
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) { return fill(p, n, 0ull, st); }
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st) {
+  return fill(p, n, v, st);
+}
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) { return fill(p, n, v, st); }
 
 // ------------------------------------------------------------------ interpolation
 // Three consecutive lattice values of one x-row, in one 12- or 24-byte load
@@ -207,30 +211,6 @@ __device__ __forceinline__ void node_lists(const TransferArgs& a, const BoxDev& 
   keys[2] = right >= 0 ? row + right : -1;
 }
 
-// Groups the active lanes (key >= 0) of a wavefront by key: every lane gets
-// the lane of its group's leader and its rank in the group; the leader also
-// gets the group size (0 elsewhere).  Ballots and lane reads only, no memory
-// traffic, so the atomics that follow can all be in flight at once.  Every
-// lane of the wavefront must call it.
-__device__ __forceinline__ void wave_groups(int key, int& leader, int& rank, int& size) {
-  const int lane = threadIdx.x & (kWave - 1);
-  unsigned long long todo = __ballot(key >= 0);
-  leader = lane;
-  rank = 0;
-  size = 0;
-  while (todo) {
-    const int l = __ffsll((long long)todo) - 1;
-    const int kl = __builtin_amdgcn_readlane(key, l);
-    const unsigned long long m = __ballot(key == kl) & todo;
-    if (key == kl) {
-      leader = l;
-      rank = (int)__popcll(m & ((1ull << lane) - 1ull));
-    }
-    if (lane == l) size = (int)__popcll(m);
-    todo &= ~m;
-  }
-}
-
 // The lists of one node, all components: keys[d * kListsPerEntry + j].
 template <typename T>
 __device__ __forceinline__ void all_lists(const TransferArgs& a, const T* __restrict__ x,
@@ -337,6 +317,12 @@ __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restr
     off[n] = run;
     if ((int64_t)run > cap) atomicAdd(status + 3, 1ull);
   }
+}
+
+hipError_t launch_scan(int32_t n, const int32_t* cnt, int32_t* off, int32_t* cursor, int64_t cap,
+                       unsigned long long* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, n, cnt, off, cursor, cap, status);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ tiled spread: accumulation

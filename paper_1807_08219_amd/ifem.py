@@ -29,12 +29,12 @@ IFEM_OPT_SPREAD_MODE = 1
 IFEM_OPT_KERNEL_TIMING = 2
 KERNEL_SLOTS = {0: "k_forces", 1: "k_bin_count", 2: "k_scan", 3: "k_bin_fill", 4: "k_spread_home",
                 5: "k_spread_atomic", 6: "k_interp", 7: "k_fill", 8: "k_spread_merge", 9: "k_volume",
-                10: "k_advance", 11: "k_interp_cells", 12: "k_fluid"}
+                10: "k_advance", 11: "k_interp_cells", 12: "k_fluid", 13: "k_contact"}
 
 EXPORTED = [
     "ifem_plan_create", "ifem_plan_destroy", "ifem_plan_set", "ifem_plan_info", "ifem_element_forces",
     "ifem_spread", "ifem_interp", "ifem_volume_correct", "ifem_advance", "ifem_interp_cells", "ifem_fluid_forces",
-    "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
+    "ifem_antistick", "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
 ]
 
 
@@ -84,6 +84,7 @@ def lib():
         L.ifem_advance.argtypes = [P, C.c_int32, P, P, P, C.c_double, P, P]
         L.ifem_interp_cells.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P, P]
         L.ifem_fluid_forces.argtypes = [P, C.c_int32, P, P, P, C.c_double, C.c_double, P, P]
+        L.ifem_antistick.argtypes = [P, C.c_int32, P, P, C.c_double, P, P, P]
         L.ifem_plan_status.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int32]
         L.ifem_plan_kernel_times.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.ifem_last_error.restype = C.c_char_p
@@ -230,3 +231,8 @@ class Plan:
         """Add the Newtonian and polymer fluid-stress forces of every solid to f_inout."""
         _check(lib().ifem_fluid_forces(self.handle, dtype, _ptr(x), _ptr(v), _ptr(C), float(eta), float(G),
                                        _ptr(f_inout), _stream(stream)))
+
+    def antistick(self, dtype, x, anchor, x_out, d_min, face_out=None, stream=None):
+        """Node-face anti-sticking: nodes closer than d_min to another particle's face move to d_min."""
+        _check(lib().ifem_antistick(self.handle, dtype, _ptr(x), _ptr(anchor), float(d_min), _ptr(x_out),
+                                    _ptr(face_out), _stream(stream)))

@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     for name in decl:
         assert hasattr(L, name), name
     assert sorted(ifem.EXPORTED) == decl
-    assert L.ifem_version() == 10300
+    assert L.ifem_version() == 10400
 
 
 def _desc(sc):
@@ -76,6 +76,7 @@ def test_null_arguments_are_rejected():
     assert L.ifem_advance(None, 1, None, None, None, 1.0, None, None) == ifem.IFEM_ERR_INVALID_ARG
     assert L.ifem_interp_cells(None, 1, None, None, None, 6, None, None) == ifem.IFEM_ERR_INVALID_ARG
     assert L.ifem_fluid_forces(None, 1, None, None, None, 1.0, 0.0, None, None) == ifem.IFEM_ERR_INVALID_ARG
+    assert L.ifem_antistick(None, 1, None, None, 1.0, None, None, None) == ifem.IFEM_ERR_INVALID_ARG
     assert L.ifem_plan_set(None, 1, 0) == ifem.IFEM_ERR_INVALID_ARG
     out = (C.c_int64 * 5)()
     assert L.ifem_plan_status(None, None, out, 0) == ifem.IFEM_ERR_INVALID_ARG
