@@ -309,13 +309,13 @@ ifem_status ifem_advance(ifem_plan plan, int32_t dtype, const void* x, const voi
  * when that float32 distance is below (float)d_min.  Distances are float64 with
  * the periodic minimum image; every node is tested against the positions
  * before the call (no node sees another's move).  Exact search: a uniform grid
- * of contact cells about four lattice cells wide per box replaces the paper's
+ * of contact cells about two lattice cells wide per box replaces the paper's
  * bounding-box broad phase.  A face that is not finite or spans more than half
  * a box is skipped.  One pass; a node pushed out of one particle's range into
  * another's is not checked again.
  *   x, anchor  positions (see dtype), device.
  *   d_min      separation, 0 < d_min <= the contact-cell width (box length /
- *              max(1, floor(n / 4)) per axis) and <= a quarter box; the paper
+ *              max(1, floor(n / 2)) per axis) and <= a quarter box; the paper
  *              uses one lattice spacing h.
  *   x_out      [3][n_nodes] moved positions, same dtype (float32: offsets from
  *              the same anchors); must not overlap x.

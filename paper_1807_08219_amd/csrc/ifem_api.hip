@@ -477,7 +477,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     tile_box.insert(tile_box.end(), (size_t)nt, b);
   }
 
-  // contact cells: about 4 lattice cells wide, an exact tiling of every periodic box
+  // contact cells: about 2 lattice cells wide, an exact tiling of every periodic box
   std::vector<ContactBoxDev> cb(n_boxes);
   int64_t n_ccells = 0;
   double contact_cell = 1e308, min_box_len = 1e308;
@@ -487,7 +487,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     C.base = (int32_t)n_ccells;
     int64_t nb = 1;
     for (int a = 0; a < 3; ++a) {
-      C.nc[a] = std::max(1, boxes[b].n[a] / 4);
+      C.nc[a] = std::max(1, boxes[b].n[a] / 2);
       C.origin[a] = boxes[b].origin[a];
       C.len[a] = boxes[b].n[a] * boxes[b].h;
       C.inv_len[a] = 1.0 / C.len[a];
@@ -574,7 +574,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_fmax, (size_t)3 * n_tiles));
   HIP_TRY(mem.alloc(&d_halo, (size_t)3 * n_tiles * region_cells));  // sized for float64
   ContactBoxDev* d_cboxes;
-  int32_t *d_bface, *d_ccount, *d_coff, *d_ccur, *d_cown, *d_clist;
+  int32_t *d_bface, *d_ccount, *d_coff, *d_ccur, *d_cown;
+  ContactNode* d_crec;
   unsigned long long* d_ckeys;
   HIP_TRY(upload(mem, &d_cboxes, cb.data(), cb.size(), st));
   HIP_TRY(upload(mem, &d_bface, bfaces.data(), bfaces.size(), st));
@@ -582,8 +583,25 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_coff, (size_t)n_ccells + 1));
   HIP_TRY(mem.alloc(&d_ccur, (size_t)n_ccells));
   HIP_TRY(mem.alloc(&d_cown, (size_t)n_ccells));
-  HIP_TRY(mem.alloc(&d_clist, (size_t)m.n_nodes));
+  int32_t *d_nlo, *d_nhi, *d_nlo2, *d_nhi2;
+  HIP_TRY(mem.alloc(&d_nlo, (size_t)n_ccells));
+  HIP_TRY(mem.alloc(&d_nhi, (size_t)n_ccells));
+  HIP_TRY(mem.alloc(&d_nlo2, (size_t)n_ccells));
+  HIP_TRY(mem.alloc(&d_nhi2, (size_t)n_ccells));
+  HIP_TRY(mem.alloc(&d_crec, (size_t)m.n_nodes));
   HIP_TRY(mem.alloc(&d_ckeys, (size_t)m.n_nodes));
+  int32_t* d_cscan;
+  HIP_TRY(mem.alloc(&d_cscan, (size_t)contact_scan_blocks((int32_t)n_ccells) + 1));
+  // (face, cell) work of the contact search: one item per face on average fits; items beyond the
+  // capacity are searched by the face's own thread
+  const int32_t work_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(2 * ((int64_t)m.n_tris + n_bfaces), 1 << 16),
+                                                      (int64_t)1 << 30);
+  uint2* d_cwork;
+  int32_t* d_cwcount;
+  int32_t* d_cslow;
+  HIP_TRY(mem.alloc(&d_cwork, (size_t)work_cap));
+  HIP_TRY(mem.alloc(&d_cwcount, 256 + 1));
+  HIP_TRY(mem.alloc(&d_cslow, (size_t)m.n_tris + n_bfaces));
   plan->workspace_bytes = (int64_t)(12 * (int64_t)n_tiles + 1 + list_cap) * 4 + (int64_t)3 * n_tiles * region_cells * 8;
 
   P.tri_src = d_tri_src;
@@ -650,8 +668,19 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ca.off = d_coff;
   ca.cursor = d_ccur;
   ca.owner = d_cown;
-  ca.list = d_clist;
+  ca.near_lo = d_nlo;
+  ca.near_hi = d_nhi;
+  ca.near_lo2 = d_nlo2;
+  ca.near_hi2 = d_nhi2;
+  ca.n_boxes = n_boxes;
+  ca.rec = d_crec;
   ca.keys = d_ckeys;
+  ca.scan_tmp = d_cscan;
+  ca.work = d_cwork;
+  ca.work_count = d_cwcount;
+  ca.slow_count = d_cwcount + 256;
+  ca.slow = d_cslow;
+  ca.work_cap = work_cap;
   ca.n_nodes = m.n_nodes;
   ca.n_tris = m.n_tris;
   ca.n_bfaces = n_bfaces;

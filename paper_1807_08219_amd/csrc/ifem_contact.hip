@@ -2,20 +2,28 @@
 // of another particle of its box moves away from the closest point of that
 // face until it is d_min from it.  The paper finds candidate pairs with a
 // bounding-box check and searches them densely; here one uniform grid of
-// coarse cells per box (4 lattice cells wide) replaces both: nodes are binned
+// coarse cells per box (2 lattice cells wide) replaces both: nodes are binned
 // by cell, and every face visits the cells its bounding box, grown by d_min,
 // covers.  A face within d_min of a node always visits the node's cell, so the
 // search is exact; a cell whose nodes all belong to the face's own particle is
 // skipped whole.
 //
 //  k_ac_count<T>  per node: its cell; one atomic per distinct cell and wavefront;
-//  (k_scan)       cell offsets;
-//  k_ac_fill<T>   per node: writes the node id into its cell's list;
+//  k_cscan_*      cell offsets (a three-kernel scan over all cells);
+//  k_ac_fill<T>   per node: a record {position, node, particle} in its cell's list;
 //  k_ac_owner     per cell: the particle owning all its nodes, -2 if mixed, -1 empty;
-//  k_ac_faces<T>  per face: for the nodes of other particles in the cells it
-//                 reaches, the distance to the face (float64, the face's
-//                 periodic image nearest to the node); below d_min, an atomic minimum of the key
-//                 (float32 distance, face id) per node;
+//  k_ac_near_*    per cell: the least and greatest owner over the 5^3 cells around
+//                 it (separable, one pass per axis), so that a face whose whole
+//                 neighbourhood holds only its own particle is dropped at once;
+//  k_ac_faces<T>  per face: the cells it reaches that hold nodes of other
+//                 particles, appended as (face, cell) work items to one of
+//                 kWorkSegs segments (one counter per segment); a face reaching
+//                 more than 27 cells, or a full segment, goes to the slow list;
+//  k_ac_pairs<T>  per work item: the face against the cell's records, the distance
+//                 (float64, the face's periodic image nearest to the node);
+//                 below d_min, an atomic minimum of the key (float32 distance,
+//                 face id) per node;
+//  k_ac_slow<T>   per slow face: the same over every cell its grown box covers;
 //  k_ac_push<T>   per node: the move from its winning face, or a copy.
 //
 // The key orders faces by float32 distance, then face id, so the choice is
@@ -25,6 +33,11 @@
 namespace ifem {
 
 constexpr unsigned long long kNoFace = ~0ull;
+constexpr int kWorkSegs = 256;  // segments of the (face, cell) work list, one counter each
+
+struct alignas(4) Row3c {  // three consecutive cells' owners
+  int32_t v[3];
+};
 
 // Closest point to the origin on triangle (a, b, c): the Voronoi-region tests
 // of Ericson (Real-Time Collision Detection, 2005, Sec. 5.1.5), vertex regions,
@@ -159,10 +172,10 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_ac_fill(const ContactArgs a, const T* __restrict__ x,
                                                  const double* __restrict__ anchor) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  int key = -1;
+  int key = -1, p = 0;
+  double pos[3] = {0.0, 0.0, 0.0};
   if (k < a.n_nodes) {
-    const int p = a.node_particle[k];
-    double pos[3];
+    p = a.node_particle[k];
     abs_position(a, x, anchor, k, p, pos);
     key = cell_of(a.boxes[a.particle_box[p]], pos);
   }
@@ -170,7 +183,15 @@ __global__ void __launch_bounds__(256) k_ac_fill(const ContactArgs a, const T* _
   wave_groups(key, leader, rank, size);
   const int base = size > 0 ? atomicAdd(a.cursor + key, size) : 0;
   const int slot = __shfl(base, leader, kWave) + rank;
-  if (key >= 0 && slot < a.n_nodes) a.list[slot] = k;
+  if (key >= 0 && slot < a.n_nodes) {
+    ContactNode r;
+    r.x = pos[0];
+    r.y = pos[1];
+    r.z = pos[2];
+    r.k = k;
+    r.p = p;
+    a.rec[slot] = r;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_ac_owner(const ContactArgs a) {
@@ -179,12 +200,53 @@ __global__ void __launch_bounds__(256) k_ac_owner(const ContactArgs a) {
   const int n = a.count[c], o = a.off[c];
   int owner = -1;
   for (int i = 0; i < n; ++i) {
-    const int k = a.list[o + i];
-    if ((unsigned)k >= (unsigned)a.n_nodes) continue;
-    const int p = a.node_particle[k];
+    const int p = a.rec[o + i].p;
     owner = (owner == -1 || owner == p) ? p : -2;
   }
   a.owner[c] = owner;
+}
+
+// Neighbourhood test, separable: every cell gets the least and the greatest
+// owner over the cells within kNear cells along each axis in turn (periodic),
+// empty cells neutral and mixed cells forcing lo < hi.  After the three passes
+// lo < hi says that the (2 kNear + 1)^3 cells around hold nodes of more than
+// one particle; a face whose grown box stays inside that neighbourhood of its
+// first corner's cell, and finds lo == hi there, has no other particle's node
+// to test and is skipped.
+constexpr int kNear = 2;
+constexpr int kOwnerEmptyLo = 0x7fffffff, kOwnerEmptyHi = -0x7fffffff;
+
+__global__ void __launch_bounds__(256) k_ac_near_init(const ContactArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_cells) return;
+  const int o = a.owner[c];
+  a.near_lo[c] = o == -1 ? kOwnerEmptyLo : (o == -2 ? -1 : o);
+  a.near_hi[c] = o == -1 ? kOwnerEmptyHi : (o == -2 ? kOwnerEmptyLo : o);
+}
+
+// One axis of the filter: (lo, hi) -> (lo2, hi2), cells of every box.
+__global__ void __launch_bounds__(256) k_ac_near_axis(const ContactArgs a, int axis, const int32_t* __restrict__ lo,
+                                                      const int32_t* __restrict__ hi, int32_t* __restrict__ lo2,
+                                                      int32_t* __restrict__ hi2) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_cells) return;
+  // the box holding cell c: boxes are few and ordered by base
+  int b = 0;
+  while (b + 1 < a.n_boxes && a.boxes[b + 1].base <= c) ++b;
+  const ContactBoxDev& C = a.boxes[b];
+  const int r = c - C.base;
+  const int ix = r % C.nc[0], iy = (r / C.nc[0]) % C.nc[1], iz = r / (C.nc[0] * C.nc[1]);
+  const int stride = axis == 0 ? 1 : (axis == 1 ? C.nc[0] : C.nc[0] * C.nc[1]);
+  const int i0 = axis == 0 ? ix : (axis == 1 ? iy : iz), n = C.nc[axis];
+  int l = kOwnerEmptyLo, h = kOwnerEmptyHi;
+  for (int d = -kNear; d <= kNear; ++d) {  // on an axis shorter than the window a cell may come twice: harmless
+    const int j = ((i0 + d) % n + n) % n;
+    const int cc = c + (j - i0) * stride;
+    l = min(l, lo[cc]);
+    h = max(h, hi[cc]);
+  }
+  lo2[c] = l;
+  hi2[c] = h;
 }
 
 // The corners of contact face f (global node ids) and its particle.
@@ -199,61 +261,223 @@ __device__ __forceinline__ void face_nodes(const ContactArgs& a, int f, int v[3]
   }
 }
 
+// c wrapped into [0, n).
+__device__ __forceinline__ int wrap_cell(int c, int n) {
+  c %= n;
+  return c < 0 ? c + n : c;
+}
+
+// Cell index of the (periodically wrapped) cell coordinates (cx, cy, cz) of box C.
+__device__ __forceinline__ int contact_cell(const ContactBoxDev& C, int cx, int cy, int cz) {
+  int c[3] = {cx, cy, cz};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    c[i] %= C.nc[i];
+    c[i] = c[i] < 0 ? c[i] + C.nc[i] : c[i];
+  }
+  return C.base + (c[2] * C.nc[1] + c[1]) * C.nc[0] + c[0];
+}
+
+// Face f of particle q against the nodes of other particles in one cell, their
+// records loaded four at a time.
+__device__ __forceinline__ void face_cell_nodes(const ContactArgs& a, int f, int q, const ContactBoxDev& C,
+                                                const double pv[3][3], const double blo[3], const double bhi[3],
+                                                float dmin32, int cell, unsigned long long* __restrict__ keys) {
+  const int o = a.off[cell], n = a.count[cell];
+  for (int i0 = 0; i0 < n; i0 += 4) {
+    ContactNode r4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) r4[u] = a.rec[o + min(i0 + u, n - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + u >= n || r4[u].p == q || (unsigned)r4[u].k >= (unsigned)a.n_nodes) continue;
+      const double xk[3] = {r4[u].x, r4[u].y, r4[u].z};
+      // the node's image nearest to the face's first corner, tested against the grown box
+      bool inside = true;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double d = xk[j] - pv[0][j];
+        const double dn = d - C.len[j] * rint(d * C.inv_len[j]);
+        inside = inside && dn >= blo[j] && dn <= bhi[j];
+      }
+      if (!inside) continue;
+      double r[3][3];
+      face_image(pv, xk, C, r);
+      double cp[3];
+      closest_on_triangle0(r[0], r[1], r[2], cp);
+      const float dist = (float)norm_nc(cp);
+      if (dist < dmin32)
+        atomicMin(keys + r4[u].k, ((unsigned long long)__float_as_uint(dist) << 32) | (unsigned)f);
+    }
+  }
+}
+
+// Face f: its particle q, box C, corners pv, the cell range its box grown by d_min
+// covers (lo, cnt per axis) and that box relative to the first corner (blo, bhi,
+// grown a hair more, so that no pair whose float32 distance could still fall
+// below d_min is dropped).  False for a face that is not finite or spans half a
+// box: it belongs to a broken mesh and is skipped.
+template <typename T>
+__device__ __forceinline__ bool face_setup(const ContactArgs& a, const T* __restrict__ x,
+                                           const double* __restrict__ anchor, int f, double d_min, int& q,
+                                           ContactBoxDev& C, double pv[3][3], int lo[3], int cnt[3], double blo[3],
+                                           double bhi[3]) {
+  int v[3];
+  face_nodes(a, f, v);
+  q = a.node_particle[v[0]];
+  C = a.boxes[a.particle_box[q]];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) abs_position(a, x, anchor, v[m], q, pv[m]);
+  bool ok = true;
+  const double g = d_min * (1.0 + 1e-6);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double mn = fmin(pv[0][i], fmin(pv[1][i], pv[2][i]));
+    const double mx = fmax(pv[0][i], fmax(pv[1][i], pv[2][i]));
+    ok = ok && (mx - mn <= 0.5 * C.len[i]);
+    lo[i] = ok ? (int)floor((mn - d_min - C.origin[i]) * C.inv_cs[i]) : 0;
+    const int hi = ok ? (int)floor((mx + d_min - C.origin[i]) * C.inv_cs[i]) : -1;
+    cnt[i] = min(hi - lo[i] + 1, C.nc[i]);  // a range wider than the box visits each cell once
+    blo[i] = fmin(0.0, fmin(pv[1][i] - pv[0][i], pv[2][i] - pv[0][i])) - g;
+    bhi[i] = fmax(0.0, fmax(pv[1][i] - pv[0][i], pv[2][i] - pv[0][i])) + g;
+  }
+  return ok;
+}
+
+// Phase 1, one thread per face: the cells of its grown box that hold nodes of
+// other particles (at most 3 x 3 x 3 for a face no wider than a cell less
+// 2 d_min, their owners requested together) become (face, cell) work items,
+// appended with one atomic per wavefront.  A face whose box covers more cells,
+// or whose items do not all fit the list, goes to the list of faces searched
+// whole (which holds every face at most once, so it cannot overflow).
 template <typename T>
 __global__ void __launch_bounds__(256) k_ac_faces(const ContactArgs a, const T* __restrict__ x,
                                                   const double* __restrict__ anchor, double d_min,
                                                   unsigned long long* __restrict__ keys) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= a.n_tris + a.n_bfaces) return;
-  int v[3];
-  face_nodes(a, f, v);
-  const int q = a.node_particle[v[0]];
-  const int b = a.particle_box[q];
-  const ContactBoxDev C = a.boxes[b];
-  double pv[3][3];
+  const int lane = threadIdx.x & (kWave - 1);
+  int q = -1, lo[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
+  ContactBoxDev C;
+  double pv[3][3], blo[3], bhi[3];
+  bool ok = f < a.n_tris + a.n_bfaces;
+  if (ok) ok = face_setup(a, x, anchor, f, d_min, q, C, pv, lo, cnt, blo, bhi);
+  int ncell = ok ? cnt[0] * cnt[1] * cnt[2] : 0;
+  unsigned visit = 0;
+  int cx[3], cy[3], cz[3];  // wrapped cell coordinates of the first three cells per axis
+  if (ok) {  // one particle alone around the first corner, and the grown box inside that neighbourhood: nothing to test
+    const int c0[3] = {(int)floor((pv[0][0] - C.origin[0]) * C.inv_cs[0]),
+                       (int)floor((pv[0][1] - C.origin[1]) * C.inv_cs[1]),
+                       (int)floor((pv[0][2] - C.origin[2]) * C.inv_cs[2])};
+    bool inside = true;
 #pragma unroll
-  for (int m = 0; m < 3; ++m) abs_position(a, x, anchor, v[m], q, pv[m]);
-  int lo[3], cnt[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const double mn = fmin(pv[0][i], fmin(pv[1][i], pv[2][i]));
-    const double mx = fmax(pv[0][i], fmax(pv[1][i], pv[2][i]));
-    // a face that is not finite or spans half a box belongs to a broken mesh: skipped
-    if (!(mx - mn <= 0.5 * C.len[i])) return;
-    lo[i] = (int)floor((mn - d_min - C.origin[i]) * C.inv_cs[i]);
-    const int hi = (int)floor((mx + d_min - C.origin[i]) * C.inv_cs[i]);
-    cnt[i] = min(hi - lo[i] + 1, C.nc[i]);  // a range wider than the box visits each cell once
+    for (int i = 0; i < 3; ++i) inside = inside && lo[i] >= c0[i] - kNear && lo[i] + cnt[i] - 1 <= c0[i] + kNear;
+    if (inside) {
+      const int cell0 = contact_cell(C, c0[0], c0[1], c0[2]);
+      if (a.near_lo2[cell0] >= a.near_hi2[cell0]) ok = false;
+    }
   }
-  const float dmin32 = (float)d_min;
-  for (int iz = 0; iz < cnt[2]; ++iz)
-    for (int iy = 0; iy < cnt[1]; ++iy)
-      for (int ix = 0; ix < cnt[0]; ++ix) {
-        int c[3] = {lo[0] + ix, lo[1] + iy, lo[2] + iz};
+  if (!ok) ncell = 0;
+  if (ok && ncell <= 27) {
+    const int w0 = wrap_cell(lo[0], C.nc[0]), w1 = wrap_cell(lo[1], C.nc[1]), w2 = wrap_cell(lo[2], C.nc[2]);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          c[i] %= C.nc[i];
-          c[i] = c[i] < 0 ? c[i] + C.nc[i] : c[i];
-        }
-        const int cell = C.base + (c[2] * C.nc[1] + c[1]) * C.nc[0] + c[0];
-        const int owner = a.owner[cell];
-        if (owner == -1 || owner == q) continue;
-        const int o = a.off[cell], n = a.count[cell];
-        for (int i = 0; i < n; ++i) {
-          const int k = a.list[o + i];
-          if ((unsigned)k >= (unsigned)a.n_nodes) continue;
-          const int p = a.node_particle[k];
-          if (p == q) continue;
-          double xk[3];
-          abs_position(a, x, anchor, k, p, xk);
-          double r[3][3];
-          face_image(pv, xk, C, r);
-          double cp[3];
-          closest_on_triangle0(r[0], r[1], r[2], cp);
-          const float dist = (float)norm_nc(cp);
-          if (dist < dmin32)
-            atomicMin(keys + k, ((unsigned long long)__float_as_uint(dist) << 32) | (unsigned)f);
-        }
+    for (int i = 0; i < 3; ++i) {  // one step past the end wraps to the start: cnt <= nc per axis
+      cx[i] = w0 + i >= C.nc[0] ? w0 + i - C.nc[0] : w0 + i;
+      cy[i] = (w1 + i >= C.nc[1] ? w1 + i - C.nc[1] : w1 + i) * C.nc[0];
+      cz[i] = (w2 + i >= C.nc[2] ? w2 + i - C.nc[2] : w2 + i) * C.nc[0] * C.nc[1];
+    }
+    // owners by rows of three cells along x: one 12-byte load per row unless the row wraps
+    int own[27];
+    const bool row = w0 + 2 < C.nc[0];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const int iy = r % 3, iz = r / 3;
+      const bool use = iy < cnt[1] && iz < cnt[2];
+      const int rb = C.base + cz[iz] + cy[iy];
+      if (use && row) {
+        const Row3c i3 = *reinterpret_cast<const Row3c*>(a.owner + rb + w0);
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) own[3 * r + ix] = ix < cnt[0] ? i3.v[ix] : -1;
+      } else {
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) own[3 * r + ix] = use && ix < cnt[0] ? a.owner[rb + cx[ix]] : -1;
       }
+    }
+#pragma unroll
+    for (int j = 0; j < 27; ++j) visit |= (own[j] != -1 && own[j] != q ? 1u : 0u) << j;
+  }
+  // wavefront prefix of the items, one atomic for the wavefront's run
+  const int mine = __popc(visit);
+  int incl = mine;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += u;
+  }
+  const int total = __shfl(incl, kWave - 1, kWave);
+  // the list is cut into kWorkSegs segments with a counter each, so that the wavefronts' atomics
+  // spread over many addresses instead of queueing on one
+  const int seg = (int)((blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) % kWorkSegs);
+  int base = 0;
+  if (lane == 0 && total > 0) base = atomicAdd(a.work_count + seg, total);
+  base = __shfl(base, 0, kWave) + incl - mine;
+  const int seg_cap = a.work_cap / kWorkSegs;
+  if ((ok && ncell > 27) || (mine > 0 && base + mine > seg_cap)) {
+    for (int i = base; i < min(base + mine, seg_cap); ++i) a.work[seg * seg_cap + i] = make_uint2(~0u, 0u);  // reserved, unused
+    a.slow[atomicAdd(a.slow_count, 1)] = f;
+    return;
+  }
+  uint2* w = a.work + (size_t)seg * seg_cap;
+  while (visit) {
+    const int j = __builtin_ctz(visit);
+    visit &= visit - 1;
+    w[base++] = make_uint2((unsigned)f, (unsigned)(C.base + cz[j / 9] + cy[(j / 3) % 3] + cx[j % 3]));
+  }
+}
+
+// Faces searched whole: every cell of the grown box, one by one.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ac_slow(const ContactArgs a, const T* __restrict__ x,
+                                                 const double* __restrict__ anchor, double d_min,
+                                                 unsigned long long* __restrict__ keys) {
+  const int n = *a.slow_count;
+  const float dmin32 = (float)d_min;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int f = a.slow[i];
+    int q, lo[3], cnt[3];
+    ContactBoxDev C;
+    double pv[3][3], blo[3], bhi[3];
+    if (!face_setup(a, x, anchor, f, d_min, q, C, pv, lo, cnt, blo, bhi)) continue;
+    for (int iz = 0; iz < cnt[2]; ++iz)
+      for (int iy = 0; iy < cnt[1]; ++iy)
+        for (int ix = 0; ix < cnt[0]; ++ix) {
+          const int cell = contact_cell(C, lo[0] + ix, lo[1] + iy, lo[2] + iz);
+          const int owner = a.owner[cell];
+          if (owner != -1 && owner != q) face_cell_nodes(a, f, q, C, pv, blo, bhi, dmin32, cell, keys);
+        }
+  }
+}
+
+// Phase 2, one thread per (face, cell) work item (grid-stride over the items
+// phase 1 listed): the face against the cell's nodes of other particles.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ac_pairs(const ContactArgs a, const T* __restrict__ x,
+                                                  const double* __restrict__ anchor, double d_min,
+                                                  unsigned long long* __restrict__ keys) {
+  // blocks are dealt to the segments round robin (the grid is a multiple of kWorkSegs)
+  const int seg_cap = a.work_cap / kWorkSegs;
+  const int seg = (int)(blockIdx.x % kWorkSegs), per_seg = (int)(gridDim.x / kWorkSegs);
+  const int n = min(a.work_count[seg], seg_cap);
+  const uint2* __restrict__ list = a.work + (size_t)seg * seg_cap;
+  const float dmin32 = (float)d_min;
+  for (int i = (int)(blockIdx.x / kWorkSegs) * blockDim.x + threadIdx.x; i < n; i += per_seg * blockDim.x) {
+    const uint2 w = list[i];
+    if (w.x >= (unsigned)(a.n_tris + a.n_bfaces)) continue;
+    int q, lo[3], cnt[3];
+    ContactBoxDev C;
+    double pv[3][3], blo[3], bhi[3];
+    face_setup(a, x, anchor, (int)w.x, d_min, q, C, pv, lo, cnt, blo, bhi);
+    face_cell_nodes(a, (int)w.x, q, C, pv, blo, bhi, dmin32, (int)w.y, keys);
+  }
 }
 
 template <typename T>
@@ -306,6 +530,87 @@ __global__ void __launch_bounds__(256) k_ac_push(const ContactArgs a, const T* _
   if (face_out) face_out[k] = f;
 }
 
+// ------------------------------------------------------------------ cell offsets
+// Exclusive prefix sum of the cell counts in index order, in three passes:
+// block totals (kScanItems cells per workgroup), one workgroup scanning the
+// totals, then each block's cells.  off[n] receives the total.
+constexpr int kScanBlock = 256, kScanPer = 16, kScanItems = kScanBlock * kScanPer;
+
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* wsum, int32_t& total) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  int32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t u = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += u;
+  }
+  if (lane == kWave - 1) wsum[wave] = incl;
+  __syncthreads();
+  int32_t before = 0;
+  total = 0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+    if (w < wave) before += wsum[w];
+    total += wsum[w];
+  }
+  __syncthreads();
+  return before + incl - v;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_cscan_totals(int32_t n, const int32_t* __restrict__ cnt,
+                                                             int32_t* __restrict__ totals) {
+  __shared__ int32_t wsum[kScanBlock / kWave];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * kScanPer;
+  int32_t s = 0;
+  for (int j = 0; j < kScanPer; ++j)
+    if (b0 + j < n) s += cnt[b0 + j];
+  int32_t total;
+  block_exclusive_scan(s, wsum, total);
+  if (threadIdx.x == 0) totals[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(1024) k_cscan_top(int32_t nb, int32_t* __restrict__ totals) {
+  __shared__ int32_t wsum[1024 / kWave];
+  const int per = (nb + 1023) / 1024;
+  const int b0 = threadIdx.x * per;
+  int32_t s = 0;
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nb) s += totals[b0 + j];
+  int32_t total;
+  int32_t run = block_exclusive_scan(s, wsum, total);
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nb) {
+      const int32_t t = totals[b0 + j];
+      totals[b0 + j] = run;
+      run += t;
+    }
+  if (threadIdx.x == 0) totals[nb] = total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_cscan_cells(int32_t n, const int32_t* __restrict__ cnt,
+                                                            const int32_t* __restrict__ totals,
+                                                            int32_t* __restrict__ off, int32_t* __restrict__ cursor) {
+  __shared__ int32_t wsum[kScanBlock / kWave];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * kScanPer;
+  int32_t c[kScanPer], s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    c[j] = b0 + j < n ? cnt[b0 + j] : 0;
+    s += c[j];
+  }
+  int32_t total;
+  int32_t run = totals[blockIdx.x] + block_exclusive_scan(s, wsum, total);
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j)
+    if (b0 + j < n) {
+      off[b0 + j] = run;
+      cursor[b0 + j] = run;
+      run += c[j];
+    }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) off[n] = totals[gridDim.x];
+}
+
+int32_t contact_scan_blocks(int32_t n_cells) { return (n_cells + kScanItems - 1) / kScanItems; }
+
 // ------------------------------------------------------------------ host launcher
 hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const double* anchor, double d_min,
                             void* x_out, int64_t* face_out, hipStream_t st) {
@@ -317,6 +622,7 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
   hipError_t e;
   P.timer->begin(K_FILL, st);
   e = launch_fill_i32(a.count, a.n_cells, 0, st);
+  if (e == hipSuccess) e = launch_fill_i32(a.work_count, kWorkSegs + 1, 0, st);  // segment and slow-face counters
   if (e == hipSuccess) e = launch_fill_u64(a.keys, a.n_nodes, kNoFace, st);
   P.timer->end(st);
   if (e != hipSuccess) return e;
@@ -325,19 +631,36 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
     hipLaunchKernelGGL(k_ac_count<float>, gn, dim3(B), 0, st, a, (const float*)x, anchor);
   else
     hipLaunchKernelGGL(k_ac_count<double>, gn, dim3(B), 0, st, a, (const double*)x, anchor);
-  e = launch_scan(a.n_cells, a.count, a.off, a.cursor, (int64_t)a.n_nodes, P.status, st);
-  if (e != hipSuccess) return e;
+  const int nb = contact_scan_blocks(a.n_cells);
+  hipLaunchKernelGGL(k_cscan_totals, dim3(nb), dim3(kScanBlock), 0, st, a.n_cells, a.count, a.scan_tmp);
+  hipLaunchKernelGGL(k_cscan_top, dim3(1), dim3(1024), 0, st, nb, a.scan_tmp);
+  hipLaunchKernelGGL(k_cscan_cells, dim3(nb), dim3(kScanBlock), 0, st, a.n_cells, a.count, a.scan_tmp, a.off,
+                     a.cursor);
   if (dtype == 0)
     hipLaunchKernelGGL(k_ac_fill<float>, gn, dim3(B), 0, st, a, (const float*)x, anchor);
   else
     hipLaunchKernelGGL(k_ac_fill<double>, gn, dim3(B), 0, st, a, (const double*)x, anchor);
   hipLaunchKernelGGL(k_ac_owner, gc, dim3(B), 0, st, a);
+  hipLaunchKernelGGL(k_ac_near_init, gc, dim3(B), 0, st, a);
+  for (int axis = 0; axis < 3; ++axis) {  // ping-pong, three passes: the result lands in near_lo2, near_hi2
+    const bool even = axis % 2 == 0;
+    hipLaunchKernelGGL(k_ac_near_axis, gc, dim3(B), 0, st, a, axis, even ? a.near_lo : a.near_lo2,
+                       even ? a.near_hi : a.near_hi2, even ? a.near_lo2 : a.near_lo, even ? a.near_hi2 : a.near_hi);
+  }
   if (nf > 0) {
     const dim3 gf((unsigned)((nf + B - 1) / B));
     if (dtype == 0)
       hipLaunchKernelGGL(k_ac_faces<float>, gf, dim3(B), 0, st, a, (const float*)x, anchor, d_min, a.keys);
     else
       hipLaunchKernelGGL(k_ac_faces<double>, gf, dim3(B), 0, st, a, (const double*)x, anchor, d_min, a.keys);
+    const dim3 gp(16 * kWorkSegs);
+    if (dtype == 0) {
+      hipLaunchKernelGGL(k_ac_pairs<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, a.keys);
+      hipLaunchKernelGGL(k_ac_slow<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, a.keys);
+    } else {
+      hipLaunchKernelGGL(k_ac_pairs<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, a.keys);
+      hipLaunchKernelGGL(k_ac_slow<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, a.keys);
+    }
   }
   if (dtype == 0)
     hipLaunchKernelGGL(k_ac_push<float>, gn, dim3(B), 0, st, a, (const float*)x, anchor, d_min, a.keys,

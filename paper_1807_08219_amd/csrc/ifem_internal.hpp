@@ -65,6 +65,12 @@ struct ContactBoxDev {
   double inv_len[3];
 };
 
+// A node as binned for the anti-sticking search: its absolute position, id and particle.
+struct alignas(16) ContactNode {
+  double x, y, z;
+  int32_t k, p;
+};
+
 // Everything the anti-sticking kernels read.
 struct ContactArgs {
   const int32_t* node_particle;  // [n_nodes]
@@ -76,9 +82,17 @@ struct ContactArgs {
   int32_t* off;                  // [n_cells + 1]
   int32_t* cursor;               // [n_cells]
   int32_t* owner;                // [n_cells] particle of all the cell's nodes, -2 mixed, -1 empty
-  int32_t* list;                 // [n_nodes] node ids grouped by cell
+  int32_t *near_lo, *near_hi;    // [n_cells] least / greatest owner around each cell (filter passes)
+  int32_t *near_lo2, *near_hi2;  // [n_cells] the same, second buffers (the final result)
+  ContactNode* rec;              // [n_nodes] the nodes grouped by cell
   unsigned long long* keys;      // [n_nodes] (float32 distance bits, face id) of the nearest close face
-  int32_t n_nodes, n_tris, n_bfaces, n_cells;
+  int32_t* scan_tmp;             // [cell blocks + 1] block totals of the offset scan
+  uint2* work;                   // [work_cap] (face, cell) pairs to search
+  int32_t* work_count;           // [256 + 1]: items per work-list segment, then slow faces (slow_count)
+  int32_t* slow_count;
+  int32_t* slow;                 // [n_tris + n_bfaces] faces searched whole
+  int32_t work_cap;
+  int32_t n_nodes, n_tris, n_bfaces, n_cells, n_boxes;
 };
 
 // Kernel slots of the per-kernel event timer.
@@ -186,6 +200,7 @@ hipError_t launch_scan(int32_t n, const int32_t* cnt, int32_t* off, int32_t* cur
 // ---- launchers (ifem_contact.hip)
 hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const double* anchor, double d_min,
                             void* x_out, int64_t* face_out, hipStream_t st);
+int32_t contact_scan_blocks(int32_t n_cells);
 size_t spread_tile_lds_bytes(const PlanDev& P, int dtype);
 
 }  // namespace ifem
