@@ -83,11 +83,15 @@ def step_bytes(sc, fp64: bool):
     return a["k_forces"][0] + a["k_spread_home"][0] + a["k_interp"][0]
 
 
+# the sources the spread's accumulation kernel is built from: its counters go stale when one changes
+TRAFFIC_SOURCES = ("ifem_transfer.hip", "ifem_device.hpp", "ifem_internal.hpp")
+
+
 def source_digest():
     import hashlib
 
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1807_08219_amd", "csrc"))):
+    for f in TRAFFIC_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_1807_08219_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -592,8 +592,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_ckeys, (size_t)m.n_nodes));
   int32_t* d_cscan;
   HIP_TRY(mem.alloc(&d_cscan, (size_t)contact_scan_blocks((int32_t)n_ccells) + 1));
-  // (face, cell) work of the contact search: one item per face on average fits; items beyond the
-  // capacity are searched by the face's own thread
+  // (face, cell) work of the contact search, in 256 equal segments: two items per face on average
+  // fit; a face whose items do not fit its segment is searched whole from the slow list
   const int32_t work_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(2 * ((int64_t)m.n_tris + n_bfaces), 1 << 16),
                                                       (int64_t)1 << 30);
   uint2* d_cwork;

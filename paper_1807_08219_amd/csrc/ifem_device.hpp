@@ -247,9 +247,9 @@ __device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
 // Round a float64 value (|v| < 2^51) to the nearest integer (ties to even)
 // and return it as int64, with one add and one integer subtract: adding
 // 1.5 * 2^52 places the integer in the low mantissa bits.
+constexpr double kRoundMagic = 6755399441055744.0;  // 1.5 * 2^52
 __device__ __forceinline__ long long round_to_i64(double v) {
-  const double magic = 6755399441055744.0;  // 1.5 * 2^52
-  return __double_as_longlong(v + magic) - __double_as_longlong(magic);
+  return __double_as_longlong(v + kRoundMagic) - __double_as_longlong(kRoundMagic);
 }
 
 // ------------------------------------------------------------------ lattices

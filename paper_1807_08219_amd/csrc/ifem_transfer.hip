@@ -445,10 +445,11 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
           for (int mx = 0; mx < 3; ++mx) {
             const T phi = W[(mz * 3 + my) * 3 + mx] * (vyz + cf[1] * (T(mx - 1) - tau[0]));
             const double q = (double)phi * fsx[mx];
-            const long long qh = round_to_i64(q);
+            const double t = q + kRoundMagic;  // q rounded to an integer, held in the low mantissa bits
+            const long long qh = __double_as_longlong(t) - __double_as_longlong(kRoundMagic);
             atomicAdd(acc + row + cx[mx], (unsigned long long)qh);
-            if (NW == 2) {
-              const long long ql = round_to_i64((q - (double)qh) * 0x1p40);
+            if (NW == 2) {  // t - magic is that integer as a double, exactly (no integer conversion)
+              const long long ql = round_to_i64((q - (t - kRoundMagic)) * 0x1p40);
               atomicAdd(acc + nreg + row + cx[mx], (unsigned long long)ql);
             }
           }
