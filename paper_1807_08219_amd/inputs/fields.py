@@ -47,6 +47,14 @@ def _mode_vectors(box, ks, amps, dirs):
     return kap, a
 
 
+def _plane_wave(kap, phase, coords):
+    """cos(kx x + ky y + kz z + phase) on the (nz, ny, nx) lattice, separably:
+    cos(a + b) = cos a cos b - sin a sin b with a on x and b on the (z, y) plane."""
+    a = kap[0] * coords[0]
+    b = kap[2] * coords[2][:, None] + kap[1] * coords[1][None, :] + phase
+    return torch.cos(b)[:, :, None] * torch.cos(a)[None, None, :] - torch.sin(b)[:, :, None] * torch.sin(a)[None, None, :]
+
+
 def fourier_field(box, modes, comp: int, device="cpu", dtype=torch.float64, shear_rate: float = 0.0):
     """Sample component ``comp`` of the mode sum on its staggered lattice, shape (nz, ny, nx)."""
     ks, amps, phases, dirs = modes
@@ -58,11 +66,7 @@ def fourier_field(box, modes, comp: int, device="cpu", dtype=torch.float64, shea
     for m in range(kap.shape[0]):
         if a[m, comp] == 0.0:
             continue
-        # cos(kx x + ky y + kz z + theta) via separable complex exponentials
-        ex = torch.exp(1j * (kap[m, 0] * coords[0]).to(torch.complex128))
-        ey = torch.exp(1j * (kap[m, 1] * coords[1]).to(torch.complex128))
-        ez = torch.exp(1j * (kap[m, 2] * coords[2] + phases[m]).to(torch.complex128))
-        out += a[m, comp] * (ez[:, None, None] * ey[None, :, None] * ex[None, None, :]).real
+        out += a[m, comp] * _plane_wave(kap[m], phases[m], coords)
     if shear_rate and comp == 0:
         Ly = box.length[1]
         out += shear_rate * Ly / (2 * math.pi) * torch.sin(2 * math.pi * coords[1] / Ly)[None, :, None]
@@ -117,9 +121,6 @@ def conformation_field(scene, seed: int | None = None, amp: float = 0.2, n_modes
             kap = 2 * np.pi * ks / L[None, :]
             f = torch.full((nz, ny, nx), 1.0 if c < 3 else 0.0, dtype=torch.float64, device=device)
             for m in range(n_modes):
-                ex = torch.exp(1j * (kap[m, 0] * coords[0]).to(torch.complex128))
-                ey = torch.exp(1j * (kap[m, 1] * coords[1]).to(torch.complex128))
-                ez = torch.exp(1j * (kap[m, 2] * coords[2] + phases[m]).to(torch.complex128))
-                f += amps[m] * (ez[:, None, None] * ey[None, :, None] * ex[None, None, :]).real
+                f += amps[m] * _plane_wave(kap[m], phases[m], coords)
             out[c, off[b]:off[b + 1]] = f.reshape(-1).to(dtype)
     return out
