@@ -203,3 +203,45 @@ def test_fullsize_volume_correct_sampled(full):
     # solids keep their nodes bit for bit
     solid = np.isin(sc.node_particle(), np.where(sc.law == scenes.LAW_TET_NEOHOOKE)[0])
     assert np.array_equal(got[:, solid], dr.x32[:, solid].astype(np.float64))
+
+
+def test_fullsize_advance_sampled(full):
+    # the Adams-Bashforth update is per node: a node sample is checked against the oracle exactly (float64)
+    # and to one float32 rounding of the offset (float32), in the benchmark's launch configuration
+    cfg, sc, plan = full
+    rng = np.random.default_rng(300 + cfg)
+    v = rng.normal(size=(3, sc.n_nodes)).astype(np.float32)
+    vp = rng.normal(size=(3, sc.n_nodes)).astype(np.float32)
+    dt = 0.0071
+    say(f"[gpu] config {cfg}: advance fp32 and fp64")
+    x32 = cu(sc.x32, torch.float32)
+    o32 = torch.empty_like(x32)
+    plan.advance(ifem.IFEM_F32, x32, cu(v, torch.float32), o32, v_prev=cu(vp, torch.float32), dt=dt)
+    x64 = cu(sc.x64, torch.float64)
+    o64 = torch.empty_like(x64)
+    plan.advance(ifem.IFEM_F64, x64, cu(v, torch.float64), o64, v_prev=cu(vp, torch.float64), dt=dt)
+    torch.cuda.synchronize()
+    k = np.unique(rng.integers(0, sc.n_nodes, 200_000))
+    ref = oracle.advance(sc.x64[:, k], v[:, k].astype(np.float64), vp[:, k].astype(np.float64), dt)
+    assert np.array_equal(o64.cpu().numpy()[:, k], ref)
+    a = sc.anchor[sc.node_particle()[k]].T
+    got = o32.cpu().numpy()[:, k].astype(np.float64)
+    assert np.all(np.abs(got - (ref - a)) <= U32 * np.abs(ref - a) + 4 * 2.0 ** -53 * np.abs(ref))
+
+
+def test_fullsize_conformation_interpolation_sampled(full):
+    # the six cell-centred conformation components at a node sample, float32 grid and offsets
+    cfg, sc, plan = full
+    rng = np.random.default_rng(400 + cfg)
+    say(f"[gpu] config {cfg}: conformation field and cell interpolation fp32")
+    Cg = fields.conformation_field(sc, device="cuda", dtype=torch.float32)
+    out = torch.empty((6, sc.n_nodes), dtype=torch.float32, device="cuda")
+    plan.interp_cells(ifem.IFEM_F32, cu(sc.x32, torch.float32), cu(sc.anchor, torch.float64), Cg, out)
+    torch.cuda.synchronize()
+    k = np.unique(rng.integers(0, sc.n_nodes, 20_000))
+    ref = oracle.interp_cells(sc, Cg.cpu().numpy().astype(np.float64), x=sc.x64[:, k],
+                              box_of_point=sc.box[sc.node_particle()[k]])
+    err = rel(out.cpu().numpy()[:, k], ref)
+    say(f"    sampled rel err {err:.3e}")
+    assert err <= F32_TRANSFER_TOL
+    assert plan.status() == [0, 0, 0, 0, 0]
