@@ -134,7 +134,22 @@ def cpu_baseline(sc, u64, budget_s: float):
         n_part += len(ids)
     return {"value": done_nodes / t_total, "unit": "nodes/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_part} of {sc.n_particles} particles ({done_nodes} nodes): forces+bending+reductions, "
-                      f"spread onto the full grid, interpolation; {t_total:.1f} s single-threaded FP64"}
+                      f"spread onto the full grid, interpolation; {t_total:.1f} s single-threaded FP64",
+            "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
+
+
+def host_cpu():
+    """Model name of the host processor (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
 
 
 def bench_volume(plan, sc, steps, dev, stream):
