@@ -343,7 +343,8 @@ constexpr int kTileThreads = 512;  // threads of a spread-tile workgroup (8 wave
 // and accumulates every contribution that lands inside the tile's x range
 // into an LDS region covering the tile plus a one-cell halo along y and z
 // (64-bit fixed point: exact, order-independent sums).  The region interior
-// is written straight to the grid, the y/z halo rows to scratch for the merge.
+// is written straight to the grid, the y/z halo rows to scratch for the merge;
+// a tile with an empty list only writes zeros to its interior.
 template <typename T>
 __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs a, const T* __restrict__ x,
                                                               const double* __restrict__ anchor,
@@ -370,6 +371,18 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   T* halo = reinterpret_cast<T*>(a.halo) + (int64_t)L * a.region_cells;
   const int64_t NN = a.n_nodes;
   const T* Fd = F + d * NN;
+  if (cnt == 0) {  // nothing lands in this tile (uniform over the workgroup): zeros, no halo, no LDS
+    const int rows = ex[1] * ex[2];
+    const int lrow = lane >> a.tile_shift[0], ix = lane & (a.tile[0] - 1);
+    const int rpw = kWave >> a.tile_shift[0];
+    if (ix < ex[0])
+      for (int row = wave * rpw + lrow; row < rows; row += nwaves * rpw) {
+        const int iz = row / ex[1], iy = row - iz * ex[1];
+        g[(uint32_t)(((c0[2] + iz) * B.n[1] + (c0[1] + iy)) * B.n[0] + c0[0] + ix)] = T(0);
+      }
+    if (tid == 0) a.tile_flag[L] = 0;
+    return;  // no barrier follows
+  }
 
   // fixed-point scale from the bound on |F| of the list (raised by the count pass) and its length; a
   // non-finite force cannot be held in fixed point and poisons (NaN) the tile's whole region instead
