@@ -336,6 +336,67 @@ def bench_antistick(plan, sc, steps, dev, x32, anchor):
             "device_status": plan.status()}
 
 
+def bench_batched(steps, warmup, dev):
+    """The FP32 coupling step on the batched workload (64 independent boxes of uneven size and mixed
+    particles): eager launches and one captured graph, with its share of the HBM roofline."""
+    import torch
+
+    from paper_1807_08219_amd import ifem
+    from paper_1807_08219_amd.inputs import fields, scenes
+
+    sc = scenes.make_config(4)
+    plan = ifem.Plan(sc)
+    u32 = fields.scene_velocity(sc, device=dev, dtype=torch.float32)
+    x32 = torch.as_tensor(sc.x32, device=dev)
+    anchor = torch.as_tensor(sc.anchor, device=dev)
+    F = torch.empty((3, sc.n_nodes), dtype=torch.float32, device=dev)
+    red = torch.empty((sc.n_particles, 5), dtype=torch.float64, device=dev)
+    G = torch.empty((3, sc.total_cells), dtype=torch.float32, device=dev)
+    v = torch.empty((3, sc.n_nodes), dtype=torch.float32, device=dev)
+
+    def step():
+        plan.element_forces(ifem.IFEM_F32, x32, anchor, F, red)
+        plan.spread(ifem.IFEM_F32, x32, anchor, F, G)
+        plan.interp(ifem.IFEM_F32, x32, anchor, u32, v)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+    nbytes = step_bytes(sc, False)
+    log(f"batched workload ({sc.n_nodes} nodes, {sc.total_cells} cells in {len(sc.boxes)} boxes): {ms:.3f} ms/step, "
+        f"graph {ms_graph:.3f} ms/step, {nbytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS:.3f} of HBM roofline")
+    out = {"workload": sc.name, "nodes": sc.n_nodes, "cells": sc.total_cells, "boxes": len(sc.boxes),
+           "ms_per_step": round(ms, 4), "value": round(sc.n_nodes / (ms * 1e-3), 1), "unit": "nodes/s",
+           "graph_ms_per_step": round(ms_graph, 4), "graph_value": round(sc.n_nodes / (ms_graph * 1e-3), 1),
+           "algorithmic_bytes": int(nbytes),
+           "step_hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "graph_step_hbm_frac": round(nbytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "device_status": plan.status()}
+    del graph
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +411,7 @@ def main():
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-visco", action="store_true")
     ap.add_argument("--no-contact", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the FP32 step on the 64-box batched workload")
     ap.add_argument("--tile", type=str, default=None, help="spread tile, e.g. 32,16,8 (powers of two)")
     ap.add_argument("--block-forces", type=int, default=None, help="threads per particle workgroup")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -501,6 +563,8 @@ def main():
         out["viscoelastic"] = bench_viscoelastic(plan, sc, args.steps, dev, x32, anchor)
     if not args.no_contact:
         out["antistick"] = bench_antistick(plan, sc, args.steps, dev, x32, anchor)
+    if not args.no_batched and args.config != 4:
+        out["batched"] = bench_batched(args.steps, args.warmup, dev)
 
     if not args.no_fp64:
         x64 = torch.as_tensor(sc.x64, device=dev)
