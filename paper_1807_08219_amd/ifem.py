@@ -65,7 +65,7 @@ _lib = None
 
 
 def lib():
-    """Load libifem.so (built in-tree by ``__graft_entry__.build()``)."""
+    """Load libifem.so (built in-tree by ``python -m paper_1807_08219_amd.build``)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
