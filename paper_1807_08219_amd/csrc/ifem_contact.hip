@@ -12,7 +12,7 @@
 //  k_cscan_*      cell offsets (a three-kernel scan over all cells);
 //  k_ac_fill<T>   per node: a record {position, node, particle} in its cell's list;
 //  k_ac_owner     per cell: the particle owning all its nodes, -2 if mixed, -1 empty;
-//  k_ac_near_*    per cell: the least and greatest owner over the 5^3 cells around
+//  k_ac_near_*    per cell: the least and greatest owner over the 3^3 cells around
 //                 it (separable, one pass per axis), so that a face whose whole
 //                 neighbourhood holds only its own particle is dropped at once;
 //  k_ac_faces<T>  per face: the cells it reaches that hold nodes of other
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) k_ac_owner(const ContactArgs a) {
 // one particle; a face whose grown box stays inside that neighbourhood of its
 // first corner's cell, and finds lo == hi there, has no other particle's node
 // to test and is skipped.
-constexpr int kNear = 2;
+constexpr int kNear = 1;  // a face with d_min <= h reaches at most one contact cell past its first corner
 constexpr int kOwnerEmptyLo = 0x7fffffff, kOwnerEmptyHi = -0x7fffffff;
 
 __global__ void __launch_bounds__(256) k_ac_near_init(const ContactArgs a) {
