@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ifem.h"
@@ -103,25 +104,134 @@ int colour_elements(const int32_t* conn, int n_all, int e0, int e1, int node0, i
   return ncol;
 }
 
+// Colouring for workgroup rounds: every colour holds at most B elements, no
+// two of which share a node, so the force kernel runs one colour per round of
+// B threads.  Each colour is filled greedily from the uncoloured elements taken
+// by decreasing number of uncoloured elements they conflict with (ties by
+// element order): the hard-to-place elements go first and the last colours
+// still fill up (a 5120-triangle red cell takes 10 colours of 512, where the
+// plain greedy colouring needs 16 rounds).  Returns the colour count, or -1
+// beyond kMaxColours.
+template <int NV>
+int colour_rounds(const int32_t* conn, int n_all, int e0, int e1, int node0, int nn, int B, std::vector<int>& colour) {
+  const int n = e1 - e0;
+  std::vector<int> ioff(nn + 1, 0), inc((size_t)n * NV);
+  for (int e = 0; e < n; ++e)
+    for (int v = 0; v < NV; ++v) ioff[conn[v * n_all + e0 + e] - node0 + 1]++;
+  for (int i = 0; i < nn; ++i) ioff[i + 1] += ioff[i];
+  std::vector<int> cur(ioff.begin(), ioff.end() - 1);
+  for (int e = 0; e < n; ++e)
+    for (int v = 0; v < NV; ++v) inc[cur[conn[v * n_all + e0 + e] - node0]++] = e;
+  std::vector<int> noff(n + 1, 0), nbr, mark(n, -1);
+  nbr.reserve((size_t)n * 4 * NV);
+  for (int e = 0; e < n; ++e) {
+    for (int v = 0; v < NV; ++v) {
+      const int l = conn[v * n_all + e0 + e] - node0;
+      for (int i = ioff[l]; i < ioff[l + 1]; ++i) {
+        const int f = inc[i];
+        if (f != e && mark[f] != e) {
+          mark[f] = e;
+          nbr.push_back(f);
+        }
+      }
+    }
+    noff[e + 1] = (int)nbr.size();
+  }
+  std::vector<int> deg(n), order, stamp(nn, -1);
+  for (int e = 0; e < n; ++e) deg[e] = noff[e + 1] - noff[e];
+  std::vector<char> done(n, 0);
+  int ncol = 0, left = n;
+  while (left > 0) {
+    if (ncol >= kMaxColours) return -1;
+    order.clear();
+    for (int e = 0; e < n; ++e)
+      if (!done[e]) order.push_back(e);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return deg[a] != deg[b] ? deg[a] > deg[b] : a < b; });
+    int taken = 0;
+    for (int e : order) {
+      if (taken >= B) break;
+      bool free = true;
+      for (int v = 0; v < NV && free; ++v) free = stamp[conn[v * n_all + e0 + e] - node0] != ncol;
+      if (!free) continue;
+      for (int v = 0; v < NV; ++v) stamp[conn[v * n_all + e0 + e] - node0] = ncol;
+      colour[e] = ncol;
+      done[e] = 1;
+      ++taken;
+    }
+    for (int e : order)
+      if (done[e] && colour[e] == ncol)
+        for (int i = noff[e]; i < noff[e + 1]; ++i) --deg[nbr[i]];
+    left -= taken;
+    ++ncol;
+  }
+  return ncol;
+}
+
+// Rounds of B threads a colouring takes: sum over colours of ceil(size / B).
+int colouring_rounds(const std::vector<int>& colour, int nc, int B) {
+  std::vector<int> size(nc, 0);
+  for (int c : colour) size[c]++;
+  int r = 0;
+  for (int c = 0; c < nc; ++c) r += (size[c] + B - 1) / B;
+  return r;
+}
+
 // Sort the elements of every particle by colour.  Outputs the slot -> element
 // map, the particle-local connectivity in slot order, per-particle colour
-// offsets and per-colour slot offsets.
+// offsets and per-colour slot offsets.  Of the plain greedy colouring and the
+// round colouring for workgroups of B threads, the one with fewer rounds is
+// kept; particles with the same local connectivity (all red cells of a
+// suspension) share one computation.
 template <int NV>
 ifem_status build_coloured(const int32_t* conn, int n_all, int n_p, const int32_t* estart, const int32_t* nstart,
-                           std::vector<int32_t>& src, std::vector<int32_t>& local, std::vector<int32_t>& pcol,
+                           int B, std::vector<int32_t>& src, std::vector<int32_t>& local, std::vector<int32_t>& pcol,
                            std::vector<int32_t>& colb) {
   src.resize(n_all);
   local.resize((size_t)NV * n_all);
   pcol.assign(n_p + 1, 0);
   colb.clear();
-  std::vector<int> colour;
+  std::vector<int> colour, greedy;
+  // topology hash -> particles already coloured with it (their colourings kept below)
+  std::unordered_multimap<uint64_t, int> seen;
+  std::vector<std::vector<int>> kept(n_p);
+  std::vector<int> kept_nc(n_p, 0);
   for (int p = 0; p < n_p; ++p) {
     const int e0 = estart[p], e1 = estart[p + 1], node0 = nstart[p], nn = nstart[p + 1] - nstart[p];
     pcol[p] = (int32_t)colb.size();
     if (e1 == e0) continue;
-    colour.assign(e1 - e0, 0);
-    const int nc = colour_elements<NV>(conn, n_all, e0, e1, node0, nn, colour);
-    if (nc < 0) return fail(IFEM_ERR_UNSUPPORTED, "particle %d needs more than %d element colours", p, kMaxColours);
+    uint64_t hsh = 1469598103934665603ull ^ (uint64_t)nn;
+    for (int e = e0; e < e1; ++e)
+      for (int v = 0; v < NV; ++v) hsh = (hsh ^ (uint64_t)(conn[v * n_all + e] - node0 + 1)) * 1099511628211ull;
+    int nc = -1;
+    const auto range = seen.equal_range(hsh);
+    for (auto it = range.first; it != range.second && nc < 0; ++it) {
+      const int q = it->second, f0 = estart[q], m0 = nstart[q];
+      if (estart[q + 1] - f0 != e1 - e0 || nstart[q + 1] - m0 != nn) continue;
+      bool same = true;
+      for (int e = 0; e < e1 - e0 && same; ++e)
+        for (int v = 0; v < NV && same; ++v) same = conn[v * n_all + f0 + e] - m0 == conn[v * n_all + e0 + e] - node0;
+      if (same) {
+        colour = kept[q];
+        nc = kept_nc[q];
+      }
+    }
+    if (nc < 0) {
+      greedy.assign(e1 - e0, 0);
+      const int ng = colour_elements<NV>(conn, n_all, e0, e1, node0, nn, greedy);
+      colour.assign(e1 - e0, 0);
+      const int nr = colour_rounds<NV>(conn, n_all, e0, e1, node0, nn, B, colour);
+      if (ng < 0 && nr < 0)
+        return fail(IFEM_ERR_UNSUPPORTED, "particle %d needs more than %d element colours", p, kMaxColours);
+      if (nr < 0 || (ng >= 0 && colouring_rounds(greedy, ng, B) < colouring_rounds(colour, nr, B))) {
+        colour.swap(greedy);
+        nc = ng;
+      } else {
+        nc = nr;
+      }
+      seen.emplace(hsh, p);
+      kept[p] = colour;
+      kept_nc[p] = nc;
+    }
     std::vector<int> count(nc + 1, 0);
     for (int c : colour) count[c + 1]++;
     for (int c = 0; c < nc; ++c) count[c + 1] += count[c];
@@ -407,11 +517,11 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
 
   // --- host preprocessing
   std::vector<int32_t> tri_src, tri_local, tri_pcol, tri_colb, tet_src, tet_local, tet_pcol, tet_colb;
-  s = build_coloured<3>(m.tri, m.n_tris, m.n_particles, m.tri_start, m.node_start, tri_src, tri_local, tri_pcol,
-                        tri_colb);
+  s = build_coloured<3>(m.tri, m.n_tris, m.n_particles, m.tri_start, m.node_start, tn.block_forces, tri_src,
+                        tri_local, tri_pcol, tri_colb);
   if (s != IFEM_OK) return s;
-  s = build_coloured<4>(m.tet, m.n_tets, m.n_particles, m.tet_start, m.node_start, tet_src, tet_local, tet_pcol,
-                        tet_colb);
+  s = build_coloured<4>(m.tet, m.n_tets, m.n_particles, m.tet_start, m.node_start, tn.block_forces, tet_src,
+                        tet_local, tet_pcol, tet_colb);
   if (s != IFEM_OK) return s;
   std::vector<char> bend(m.n_particles, 0);
   bool any_bend = false;
