@@ -506,8 +506,12 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
 // neighbours in the y-z plane (periodic; possibly itself) accumulated for
 // them, in a fixed order.  Tiles that are neighbours in y or z share their x
 // range, so every row is a contiguous run of ex_x cells on both sides.
+// One wavefront per (tile, component): most workgroups of a sparse grid only read their neighbours'
+// flags, and small workgroups keep more of them in flight.
+constexpr int kMergeThreads = 64;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_spread_merge(const TransferArgs a, T* __restrict__ grid) {
+__global__ void __launch_bounds__(kMergeThreads) k_spread_merge(const TransferArgs a, T* __restrict__ grid) {
   __shared__ int nbL[9];
   __shared__ int nbflag[9];
   __shared__ int nbe[9][2];  // neighbour extents along y and z
@@ -545,7 +549,7 @@ __global__ void __launch_bounds__(256) k_spread_merge(const TransferArgs a, T* _
   const int nzr = zf * ey, nrows = nzr + yf * inz;
   // lanes cover rows of the power-of-two tile width; lanes past the tile's extent idle
   const int sh = a.tile_shift[0];
-  const int rpp = a.tile[0] >= 256 ? 1 : 256 / a.tile[0];  // rows per workgroup pass
+  const int rpp = a.tile[0] >= (int)blockDim.x ? 1 : (int)blockDim.x / a.tile[0];  // rows per workgroup pass
   const int ix = tid & (a.tile[0] - 1), lrow = tid >> sh;
   if (ix >= exx || lrow >= rpp) return;  // no barrier follows
   for (int row = lrow; row < nrows; row += rpp) {
@@ -669,9 +673,9 @@ hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const
   P.timer->end(st);
   P.timer->begin(K_SPREAD_MERGE, st);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_spread_merge<float>, g, dim3(256), 0, st, a, (float*)grid);
+    hipLaunchKernelGGL(k_spread_merge<float>, g, dim3(kMergeThreads), 0, st, a, (float*)grid);
   else
-    hipLaunchKernelGGL(k_spread_merge<double>, g, dim3(256), 0, st, a, (double*)grid);
+    hipLaunchKernelGGL(k_spread_merge<double>, g, dim3(kMergeThreads), 0, st, a, (double*)grid);
   P.timer->end(st);
   return hipGetLastError();
 }
