@@ -96,8 +96,9 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it is current."""
+def measured_traffic(kernel, workload, tile):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it is current
+    (same kernel sources, same spread tile)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -109,6 +110,8 @@ def measured_traffic(kernel, workload):
         return None
     if rec.get("source_digest") != source_digest():
         return None  # the kernel changed since the counters were taken
+    if rec.get("spread_tile") != [int(v) for v in tile]:
+        return None  # taken with another tile shape
     return rec.get("hbm_bytes_per_launch")
 
 
@@ -436,7 +439,7 @@ def main():
     t0 = time.time()
     tuning = None
     if args.tile is not None or args.block_forces is not None:
-        tuning = {"tile": [int(v) for v in args.tile.split(",")] if args.tile else [64, 8, 8],
+        tuning = {"tile": [int(v) for v in args.tile.split(",")] if args.tile else [32, 16, 8],
                   "block_forces": args.block_forces or 512}
     plan = ifem.Plan(sc, tuning=tuning)
     log(f"plan created ({time.time() - t0:.1f} s), info {plan.info()}")
@@ -515,7 +518,7 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(hbm_frac, 4)}
     roofline.update({
-        "traffic": measured_traffic(dom, sc.name), "kernel": dom, "kernel_ms": round(kavg[dom][0], 4),
+        "traffic": measured_traffic(dom, sc.name, plan.info()[3:6]), "kernel": dom, "kernel_ms": round(kavg[dom][0], 4),
         "algorithmic_bytes": int(bytes_dom) if bytes_dom else None,
         "algorithmic_flops": int(flops_dom) if flops_dom else None,
         "hbm_frac": round(hbm_frac, 4), "alu_frac": round(alu_frac, 4),

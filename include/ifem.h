@@ -161,8 +161,9 @@ typedef struct {
 } ifem_box;
 
 /* Launch shape.  Pass NULL to ifem_plan_create for the defaults
- * {tile 64 x 8 x 8, block_forces 512, block_points 256}, the fastest measured
- * on dense red-cell suspensions on a 512 x 256 x 256 grid.  The spread region
+ * {tile 32 x 16 x 8, block_forces 512, block_points 256}, the fastest measured
+ * on a dense red-cell suspension on a 512 x 256 x 256 grid and on 64 sparse
+ * boxes of mixed particles.  The spread region
  * of a tile, (tile_x + 1)(tile_y + 2)(tile_z + 2) cells, must not exceed 10176. */
 typedef struct {
   int32_t tile[3];      /* spread tile, cells per axis (powers of two, 4..64) */

@@ -501,7 +501,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   const ifem_mesh_desc& m = *mesh;
   hipStream_t st = (hipStream_t)stream;
 
-  ifem_tuning tn{{64, 8, 8}, 512, 256};  // the fastest measured on dense red-cell suspensions
+  ifem_tuning tn{{32, 16, 8}, 512, 256};  // the fastest measured on dense and on batched suspensions
   if (tuning) tn = *tuning;
   for (int a = 0; a < 3; ++a)
     if (tn.tile[a] < 4 || tn.tile[a] > 64 || (tn.tile[a] & (tn.tile[a] - 1)))

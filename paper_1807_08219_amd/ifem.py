@@ -154,7 +154,7 @@ class Plan:
         tp = None
         if tuning is not None:
             t = ifem_tuning()
-            t.tile[:] = list(tuning.get("tile", (64, 8, 8)))
+            t.tile[:] = list(tuning.get("tile", (32, 16, 8)))
             t.block_forces = int(tuning.get("block_forces", 512))
             t.block_points = int(tuning.get("block_points", 256))
             tp = C.byref(t)

@@ -197,7 +197,7 @@ def test_adjoint_identity_on_gpu(runs):
         assert np.dot(G[d], u[d]) == pytest.approx(np.dot(F[d], v[d]), rel=1e-12)
 
 
-TILES = [(4, 4, 4), (8, 4, 16), (16, 8, 4), (4, 16, 8), (64, 8, 8)]
+TILES = [(4, 4, 4), (8, 4, 16), (16, 8, 4), (4, 16, 8), (64, 8, 8), (32, 16, 8)]
 
 
 @pytest.mark.parametrize("tile", TILES, ids=lambda t: "x".join(map(str, t)))
