@@ -417,6 +417,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the FP32 step on the 64-box batched workload")
     ap.add_argument("--tile", type=str, default=None, help="spread tile, e.g. 32,16,8 (powers of two)")
     ap.add_argument("--block-forces", type=int, default=None, help="threads per particle workgroup")
+    ap.add_argument("--block-points", type=int, default=None, help="threads per workgroup of the point kernels")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="bytes of a plain device copy made before the steps (scale for HBM counters)")
     args = ap.parse_args()
@@ -438,9 +439,9 @@ def main():
         f"{sc.total_cells} cells ({time.time() - t0:.1f} s)")
     t0 = time.time()
     tuning = None
-    if args.tile is not None or args.block_forces is not None:
+    if args.tile is not None or args.block_forces is not None or args.block_points is not None:
         tuning = {"tile": [int(v) for v in args.tile.split(",")] if args.tile else [32, 16, 8],
-                  "block_forces": args.block_forces or 512}
+                  "block_forces": args.block_forces or 512, "block_points": args.block_points or 256}
     plan = ifem.Plan(sc, tuning=tuning)
     log(f"plan created ({time.time() - t0:.1f} s), info {plan.info()}")
     u64 = fields.scene_velocity(sc, device=dev, dtype=torch.float64, shear_rate=1.0 if args.config == 3 else 0.0)
