@@ -76,6 +76,9 @@ CASES = {
     "spheres_across_the_seam": (lambda: _spheres(0.15, shift=(-10.0, 8.0, 0.0)), 0.5),
     "sphere_and_solid_cube": (_sphere_and_cube, 0.75),
     "squeezed_mixed": (_squeezed_mixed, None),
+    # d_min equal to the contact-cell width (1.0 here): grown boxes reach four cells per axis, so
+    # faces take the slow list as well as the work list
+    "spheres_d_min_at_cell_width": (lambda: _spheres(0.3, noise=0.01, seed=5), 1.0),
 }
 
 
