@@ -245,3 +245,59 @@ def test_fullsize_conformation_interpolation_sampled(full):
     say(f"    sampled rel err {err:.3e}")
     assert err <= F32_TRANSFER_TOL
     assert plan.status() == [0, 0, 0, 0, 0]
+
+
+def _one_ulp_change(one, Fo, seeds=(0, 1)):
+    """Smallest change of the oracle's forces over a few seeded moves of every position coordinate by
+    at most one unit in its last place: how far the float64 forces of the particle are determined by
+    its float64 inputs at all."""
+    out = []
+    for seed in seeds:
+        rng = np.random.default_rng(seed)
+        x = one.x64 + np.spacing(np.abs(one.x64)) * rng.integers(-1, 2, one.x64.shape)
+        Fp, _ = oracle.forces(scenes.Scene(**{**one.__dict__, "x64": x}))
+        out.append(np.linalg.norm(Fp - Fo))
+    return min(out)
+
+
+def test_fullsize_fp64_forces_and_interp_sampled(full):
+    # the float64 path at full size: forces and reductions of whole sampled particles, velocities of
+    # a node sample.  Bar per particle: 1e-12 normwise, or half of what moving the positions by one
+    # unit in the last place changes (the forces' own conditioning) where that is larger: the
+    # near-incompressible platelets (lambda / mu = 50, flat reference tetrahedra) under small, nearly
+    # isochoric strain change by 3e-10 to 1e-9 relative under such a move, so two float64
+    # evaluations of them cannot agree to 1e-12
+    cfg, sc, plan = full
+    rng = np.random.default_rng(500 + cfg)
+    x64 = cu(sc.x64, torch.float64)
+    F = torch.empty((3, sc.n_nodes), dtype=torch.float64, device="cuda")
+    red = torch.empty((sc.n_particles, 5), dtype=torch.float64, device="cuda")
+    say(f"[gpu] config {cfg}: element forces fp64")
+    plan.element_forces(ifem.IFEM_F64, x64, None, F, red)
+    torch.cuda.synchronize()
+    assert plan.status()[:2] == [0, 0]
+    parts = np.unique(np.linspace(0, sc.n_particles - 1, 6).astype(int))
+    Fh = F.cpu().numpy()
+    for p in parts:
+        one = scenes.subset(sc, [p])
+        Fo, _ = oracle.forces(one)
+        nodes = np.arange(sc.node_start[p], sc.node_start[p + 1])
+        nF = np.linalg.norm(Fo)
+        err = np.linalg.norm(Fh[:, nodes] - Fo)
+        bar = max(1e-12 * nF, 0.5 * _one_ulp_change(one, Fo))
+        say(f"    particle {p} (law {int(sc.law[p])}): rel err {err / nF:.3e}, bar {bar / nF:.3e}")
+        assert err <= bar
+    sub = scenes.subset(sc, parts)
+    ro = oracle.reduce(sub)
+    assert rel(red.cpu().numpy()[parts], ro) <= 1e-12
+    u = fields.scene_velocity(sc, device="cuda", dtype=torch.float64)
+    v = torch.empty((3, sc.n_nodes), dtype=torch.float64, device="cuda")
+    say(f"[gpu] config {cfg}: interp fp64")
+    plan.interp(ifem.IFEM_F64, x64, None, u, v)
+    torch.cuda.synchronize()
+    samp = rng.choice(sc.n_nodes, size=min(2000, sc.n_nodes), replace=False)
+    vo = oracle.interp(sc, u.cpu().numpy(), x=sc.x64[:, samp], box_of_point=sc.box[sc.node_particle()[samp]])
+    e = rel(v.cpu().numpy()[:, samp], vo)
+    say(f"    sampled velocity rel err {e:.3e}")
+    assert e <= 1e-12
+    assert plan.status() == [0, 0, 0, 0, 0]
