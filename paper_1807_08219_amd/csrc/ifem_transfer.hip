@@ -352,7 +352,8 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   extern __shared__ __align__(16) unsigned char smem_raw[];
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);
   constexpr int NW = FixedAcc<T>::kWords;
-  const int w = xcd_remap(blockIdx.x, gridDim.x), tile = w / 3, d = w - 3 * tile;  // the 3 components of a tile adjacent
+  // the 3 components of a tile are adjacent workgroups
+  const int w = xcd_remap(blockIdx.x, gridDim.x), tile = w / 3, d = w - 3 * tile;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int nwaves = nt / kWave;
   const int L = d * a.n_tiles + tile;
@@ -373,13 +374,25 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   const T* Fd = F + d * NN;
   if (cnt == 0) {  // nothing lands in this tile (uniform over the workgroup): zeros, no halo, no LDS
     const int rows = ex[1] * ex[2];
-    const int lrow = lane >> a.tile_shift[0], ix = lane & (a.tile[0] - 1);
-    const int rpw = kWave >> a.tile_shift[0];
-    if (ix < ex[0])
-      for (int row = wave * rpw + lrow; row < rows; row += nwaves * rpw) {
-        const int iz = row / ex[1], iy = row - iz * ex[1];
-        g[(uint32_t)(((c0[2] + iz) * B.n[1] + (c0[1] + iy)) * B.n[0] + c0[0] + ix)] = T(0);
+    constexpr int VW = 16 / (int)sizeof(T);  // values per 16-byte store
+    if (ex[0] % VW == 0 && B.n[0] % VW == 0 && (reinterpret_cast<uintptr_t>(g) & 15) == 0) {
+      // 16-byte stores: every row of the tile starts on a 16-byte boundary
+      const int per_row = ex[0] / VW;
+      for (int v = tid; v < rows * per_row; v += nt) {
+        const int row = v / per_row, iz = row / ex[1], iy = row - iz * ex[1];
+        const int ix = (v - row * per_row) * VW;
+        T* cell = g + (uint32_t)(((c0[2] + iz) * B.n[1] + (c0[1] + iy)) * B.n[0] + c0[0] + ix);
+        *reinterpret_cast<uint4*>(cell) = make_uint4(0u, 0u, 0u, 0u);
       }
+    } else {
+      const int lrow = lane >> a.tile_shift[0], ix = lane & (a.tile[0] - 1);
+      const int rpw = kWave >> a.tile_shift[0];
+      if (ix < ex[0])
+        for (int row = wave * rpw + lrow; row < rows; row += nwaves * rpw) {
+          const int iz = row / ex[1], iy = row - iz * ex[1];
+          g[(uint32_t)(((c0[2] + iz) * B.n[1] + (c0[1] + iy)) * B.n[0] + c0[0] + ix)] = T(0);
+        }
+    }
     if (tid == 0) a.tile_flag[L] = 0;
     return;  // no barrier follows
   }
