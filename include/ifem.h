@@ -62,7 +62,11 @@
  *
  * Streams: `stream` is a hipStream_t passed as void*; NULL is the default
  * stream.  The step calls are asynchronous, allocate nothing and do not
- * synchronise, so a caller may capture them in a hipGraph.
+ * synchronise, so a caller may capture them in a hipGraph.  A plan owns the
+ * workspaces its calls use (spread lists and halos, contact cells and keys,
+ * status counters): calls on one plan must be ordered (one stream, or streams
+ * the caller synchronises); calls that overlap on one plan race on that
+ * workspace.  Different plans are independent.
  *
  * Errors: every call returns IFEM_OK or a negative code; argument errors are
  * reported before anything is launched and ifem_last_error() (thread local)
