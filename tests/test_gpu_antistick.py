@@ -167,6 +167,16 @@ def test_fullsize_sampled(cfg):
     w = faces.cpu().numpy()
     got = out.cpu().numpy().astype(np.float64)
     part = sc.node_particle()
+    # float64 positions are anchor + offset exactly, so the float64 pass picks the same faces and moves
+    # every node to the float32 result up to that result's rounding
+    faces64 = torch.empty_like(faces)
+    out64 = torch.empty((3, sc.n_nodes), dtype=torch.float64, device="cuda")
+    plan.antistick(ifem.IFEM_F64, cu(sc.x64, torch.float64), None, out64, d_min, faces64)
+    torch.cuda.synchronize()
+    assert np.array_equal(faces64.cpu().numpy(), w)
+    abs32 = got + sc.anchor[part].T
+    o64 = out64.cpu().numpy()
+    assert np.all(np.abs(o64 - abs32) <= U32 * np.abs(got) + 1e-12 * (1 + np.abs(o64)))
     moved_parts = np.unique(part[w >= 0])
     say(f"    moved nodes {(w >= 0).sum()} in {moved_parts.size} particles")
     rng = np.random.default_rng(cfg)

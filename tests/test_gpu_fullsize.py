@@ -203,6 +203,17 @@ def test_fullsize_volume_correct_sampled(full):
     # solids keep their nodes bit for bit
     solid = np.isin(sc.node_particle(), np.where(sc.law == scenes.LAW_TET_NEOHOOKE)[0])
     assert np.array_equal(got[:, solid], dr.x32[:, solid].astype(np.float64))
+    # float64 positions: the same multipliers and corrected nodes to the float64 bars
+    x64 = cu(dr.x64, torch.float64)
+    out64 = torch.empty_like(x64)
+    lam64 = torch.empty(sc.n_particles, dtype=torch.float64, device="cuda")
+    say(f"[gpu] config {cfg}: volume correction fp64")
+    plan.volume_correct(ifem.IFEM_F64, x64, out64, lambda_out=lam64)
+    torch.cuda.synchronize()
+    assert plan.status()[4] == 0
+    assert np.all(np.abs(lam64.cpu().numpy()[parts] - lo) <= bars)
+    assert np.all(np.abs(out64.cpu().numpy()[:, nodes] - xo) <= xbar)
+    assert np.array_equal(out64.cpu().numpy()[:, solid], dr.x64[:, solid])
 
 
 def test_fullsize_advance_sampled(full):
