@@ -255,6 +255,18 @@ def test_fullsize_conformation_interpolation_sampled(full):
     err = rel(out.cpu().numpy()[:, k], ref)
     say(f"    sampled rel err {err:.3e}")
     assert err <= F32_TRANSFER_TOL
+    # float64 field and positions: the perturbation C - I to 1e-12 (C itself is I plus at most 0.2)
+    del out
+    Cg64 = fields.conformation_field(sc, device="cuda", dtype=torch.float64)
+    out64 = torch.empty((6, sc.n_nodes), dtype=torch.float64, device="cuda")
+    say(f"[gpu] config {cfg}: cell interpolation fp64")
+    plan.interp_cells(ifem.IFEM_F64, cu(sc.x64, torch.float64), None, Cg64, out64)
+    torch.cuda.synchronize()
+    ref64 = oracle.interp_cells(sc, Cg64.cpu().numpy(), x=sc.x64[:, k], box_of_point=sc.box[sc.node_particle()[k]])
+    eye = 1.0 * (np.arange(6) < 3)[:, None]
+    err64 = rel(out64.cpu().numpy()[:, k] - eye, ref64 - eye)
+    say(f"    sampled rel err of C - I {err64:.3e}")
+    assert err64 <= 1e-12
     assert plan.status() == [0, 0, 0, 0, 0]
 
 
