@@ -166,8 +166,8 @@ typedef struct {
 
 /* Launch shape.  Pass NULL to ifem_plan_create for the defaults
  * {tile 32 x 16 x 8, block_forces 512, block_points 256}, the fastest measured
- * on a dense red-cell suspension on a 512 x 256 x 256 grid and on 64 sparse
- * boxes of mixed particles.  The spread region
+ * on dense red-cell suspensions; with fewer than one node per 20 grid cells
+ * (sparse boxes of mixed particles) the default tile is 16 x 16 x 16.  The spread region
  * of a tile, (tile_x + 1)(tile_y + 2)(tile_z + 2) cells, must not exceed 10176. */
 typedef struct {
   int32_t tile[3];      /* spread tile, cells per axis (powers of two, 4..64) */
