@@ -85,7 +85,8 @@ __global__ void __launch_bounds__(256) k_interp(const TransferArgs a, const T* _
   double pos[3];
   node_position(a, x, anchor, k, p, pos);
   unsigned int bad = 0;
-#pragma unroll 1
+  // unrolled: the three components' loads and arithmetic interleave
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     int32_t base[3];
     double tau64[3];
