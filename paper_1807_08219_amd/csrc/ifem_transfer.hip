@@ -402,10 +402,13 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   // non-finite force cannot be held in fixed point and poisons (NaN) the tile's whole region instead
   const double m = (double)__uint_as_float(a.tile_fmax[L]);
   const bool poison = cnt > 0 && !(m <= DBL_MAX);
-  for (int i = tid; i < NW * nreg; i += nt) acc[i] = 0ull;
+  // float64 keeps a 32-bit remainder word per cell after the 64-bit words (12 bytes per cell)
+  unsigned int* lo = reinterpret_cast<unsigned int*>(acc + nreg);
+  unsigned int* acc32 = reinterpret_cast<unsigned int*>(acc);
+  for (int i = tid; i < (NW == 2 ? 3 : 2) * nreg; i += nt) acc32[i] = 0u;
   __syncthreads();
   const bool active = cnt > 0 && m > 0.0 && !poison;
-  int sc = 0;
+  int sc = 0, sl = 0;
   if (active) {
     // one contribution is at most 4 max|F| (sum of |phi| <= 4), a cell sum at most cnt times that:
     // keep every contribution below 2^50 and every sum below 2^62
@@ -414,6 +417,10 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     frexp(4.0 * (double)cnt * m, &e2);
     sc = min(50 - e1, 62 - e2);
     const double scale = ldexp(1.0, sc);
+    // float64 remainder scale: |remainder| <= 1/2 unit, at most cnt of them per cell, so with
+    // 2^(lc - 1) <= cnt < 2^lc every cell's sum stays below 2^29 in its 32-bit word
+    sl = 30 - (32 - __builtin_clz((unsigned)cnt));
+    const double lscale = ldexp(1.0, sl);
     // entry order: qi -> (qi * stride) mod cnt with a prime stride that does not divide cnt (a
     // permutation), so that the lanes of a wavefront take nodes far apart in the list, i.e. far apart
     // on the surface, and rarely add to the same LDS cell in one instruction
@@ -476,8 +483,8 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
             const long long qh = __double_as_longlong(t) - __double_as_longlong(kRoundMagic);
             atomicAdd(acc + row + cx[mx], (unsigned long long)qh);
             if (NW == 2) {  // t - magic is that integer as a double, exactly (no integer conversion)
-              const long long ql = round_to_i64((q - (t - kRoundMagic)) * 0x1p40);
-              atomicAdd(acc + nreg + row + cx[mx], (unsigned long long)ql);
+              const long long ql = round_to_i64((q - (t - kRoundMagic)) * lscale);
+              atomicAdd(lo + row + cx[mx], (unsigned int)(int)ql);
             }
           }
         }
@@ -505,7 +512,7 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     T v = fillv;
     if (active) {
       double w = (double)(long long)acc[r];
-      if (NW == 2) w += (double)(long long)acc[nreg + r] * 0x1p-40;
+      if (NW == 2) w += (double)(int)lo[r] * ldexp(1.0, -sl);
       v = (T)(w * inv);
     }
     if ((unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2])
@@ -597,7 +604,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_spread_merge(const TransferAr
 
 // ------------------------------------------------------------------ host launchers
 size_t spread_tile_lds_bytes(const PlanDev& P, int dtype) {
-  return (size_t)P.targs.region_cells * 8 * (dtype == 0 ? 1 : 2);
+  return (size_t)P.targs.region_cells * (dtype == 0 ? 8 : 12);
 }
 
 hipError_t prepare_transfer_kernels(const PlanDev& P) {
