@@ -66,7 +66,9 @@ def lib():
         L.orc_point_triangle.argtypes = [_D, _D, _D, _D, _D]
         L.orc_boundary_faces.argtypes = [C.c_int, _D, C.c_int, _I, _I, C.c_int, C.c_int, _I, _I]
         L.orc_antistick.argtypes = [C.c_int, _D, _D, C.c_int, _I, _I, _I, C.c_int, _I, _I, C.c_int, _I, _D,
-                                    C.c_double, _D, _L]
+                                    C.c_double, _D, _L, _D]
+        L.orc_pair_distances.argtypes = [C.c_int, _D, _D, C.c_void_p, C.c_int, _I, _I, C.c_int, _I, _I, C.c_int, _I,
+                                         _D, C.c_int, _I, _L, _D]
         L.orc_advance.restype = None
         _lib = L
     return _lib
@@ -279,15 +281,38 @@ def boundary_faces(scene):
     return out[:, :n].copy(), part[:n].copy()
 
 
-def antistick(scene, d_min, x=None):
-    """Node-face anti-sticking: (x_out [3][n_nodes], winner face per node or -1, moved count)."""
+def _box_lengths(scene):
+    return np.array([b.length for b in scene.boxes], dtype=np.float64).reshape(-1, 3)
+
+
+def antistick(scene, d_min, x=None, with_distance=False):
+    """Node-face anti-sticking: (x_out [3][n_nodes], winner face per node or -1, moved count), plus the
+    least float64 node-face distance per node (inf where no face can reach) with with_distance."""
     x = scene.x64 if x is None else x
     out = np.zeros((3, scene.n_nodes))
     win = np.zeros(scene.n_nodes, dtype=np.int64)
-    L = np.array([b.length for b in scene.boxes], dtype=np.float64).reshape(-1, 3)
+    dist = np.zeros(scene.n_nodes)
     moved = lib().orc_antistick(scene.n_nodes, _c(scene.X_ref, np.float64), _c(x, np.float64), scene.n_particles,
                                 _c(scene.node_start, np.int32), _c(scene.tri_start, np.int32),
                                 _c(scene.tri, np.int32), scene.n_tris, _c(scene.tet_start, np.int32),
-                                _c(scene.tet, np.int32), scene.n_tets, _c(scene.box, np.int32), L, float(d_min), out,
-                                win)
-    return out, win, moved
+                                _c(scene.tet, np.int32), scene.n_tets, _c(scene.box, np.int32), _box_lengths(scene),
+                                float(d_min), out, win, dist)
+    return (out, win, moved, dist) if with_distance else (out, win, moved)
+
+
+def pair_distances(scene, nodes, faces, x=None, moved=None):
+    """Float64 distance from each node to the paired face (face ids as in antistick), the face taken at x
+    and the node at `moved` if given (else at x)."""
+    x = _c(scene.x64 if x is None else x, np.float64)
+    nodes = _c(nodes, np.int32)
+    faces = _c(faces, np.int64)
+    out = np.zeros(nodes.size)
+    mv = None if moved is None else _c(moved, np.float64)
+    bad = lib().orc_pair_distances(scene.n_nodes, _c(scene.X_ref, np.float64), x,
+                                   None if mv is None else mv.ctypes.data, scene.n_particles,
+                                   _c(scene.node_start, np.int32), _c(scene.tri, np.int32), scene.n_tris,
+                                   _c(scene.tet_start, np.int32), _c(scene.tet, np.int32), scene.n_tets,
+                                   _c(scene.box, np.int32), _box_lengths(scene), nodes.size, nodes, faces, out)
+    if bad:
+        raise ValueError(f"{bad} face ids out of range")
+    return out

@@ -1020,20 +1020,23 @@ int orc_boundary_faces(int n_nodes, const double* X, int n_particles, const int*
  * the solids (ids n_tri + k, in the order orc_boundary_faces lists them).
  * Distances use the periodic image of each face nearest to the node (the
  * image of its first corner, applied to the whole face).  READINGS: the closest
- * face is the one of least distance, distances compared in float32 (the
- * precision of the device's ordering key), ties to the lower face id; a node
- * moves when that float32 distance is below (float)d_min; the move is along
+ * face is the one of least float64 distance, ties to the lower face id (the
+ * paper's minimum distance; exact ties occur where faces share the closest
+ * edge or vertex); a node moves when that distance is below d_min; the move is along
  * (x - c)/|x - c| from the closest point c (the face normal when x lies on the
  * face), to c + d_min (x - c)/|x - c|; all nodes are tested against the
  * positions before the pass (none sees another's move).  The paper's particle
  * bounding-box check is a culling step: particles whose box, grown by 2 d_min
  * and taken periodically, cannot reach the node are skipped, which changes no
  * result.  x, x_out [3][n_nodes]; box_len [n_boxes][3] box lengths;
- * winner [n_nodes]: the face that moved the node, or -1.  Returns the number
- * of moved nodes. */
+ * winner [n_nodes]: the face that moved the node, or -1; dist [n_nodes] (or
+ * NULL): the least distance to a face of another particle whose bounding box
+ * can reach the node, INFINITY where none can.  Returns the number of moved
+ * nodes. */
 int orc_antistick(int n_nodes, const double* X, const double* x, int n_particles, const int* node_start,
                   const int* tri_start, const int* tri, int n_tri, const int* tet_start, const int* tet, int n_tet,
-                  const int* box_of_particle, const double* box_len, double d_min, double* x_out, int64_t* winner) {
+                  const int* box_of_particle, const double* box_len, double d_min, double* x_out, int64_t* winner,
+                  double* dist) {
   memcpy(x_out, x, sizeof(double) * 3 * (size_t)n_nodes);
   const int cap = 4 * n_tet + 1;
   int* bf = malloc(sizeof(int) * 3 * (size_t)cap);
@@ -1058,7 +1061,7 @@ int orc_antistick(int n_nodes, const double* X, const double* x, int n_particles
     for (int k = node_start[P]; k < node_start[P + 1]; ++k) {
       double xk[3];
       pos(x, n_nodes, k, xk);
-      float best = INFINITY;
+      double best = INFINITY;
       int64_t bestf = -1;
       double bestc[3] = {0, 0, 0}, bestn[3] = {0, 0, 0};
       for (int Q = 0; Q < n_particles; ++Q) {
@@ -1096,9 +1099,9 @@ int orc_antistick(int n_nodes, const double* X, const double* x, int n_particles
           const double zero[3] = {0.0, 0.0, 0.0};
           double c[3];
           orc_point_triangle(zero, r[0], r[1], r[2], c);
-          const float dist = (float)norm3(c);
-          if (dist < best || (dist == best && fid < bestf)) {
-            best = dist;
+          const double dc = norm3(c);
+          if (dc < best || (dc == best && fid < bestf)) {
+            best = dc;
             bestf = fid;
             double e1[3], e2[3];
             sub3(r[1], r[0], e1);
@@ -1109,7 +1112,8 @@ int orc_antistick(int n_nodes, const double* X, const double* x, int n_particles
         }
       }
       if (winner) winner[k] = -1;
-      if (bestf < 0 || !(best < (float)d_min)) continue;
+      if (dist) dist[k] = best;
+      if (bestf < 0 || !(best < d_min)) continue;
       const double dc = norm3(bestc);
       double dir[3];
       if (dc > 0.0) {
@@ -1128,4 +1132,52 @@ int orc_antistick(int n_nodes, const double* X, const double* x, int n_particles
   free(lo);
   free(hi);
   return moved;
+}
+
+/* Distance from node node[i] to face face[i] (ids as in orc_antistick), in the
+ * periodic image of the face nearest to the node (chosen by its first corner),
+ * for i < n_pairs; out[i] = the distance.  With moved != NULL the node's
+ * position is taken from moved [3][n_nodes] instead of x (to measure where a
+ * move put it; the face stays at x). */
+int orc_pair_distances(int n_nodes, const double* X, const double* x, const double* moved, int n_particles,
+                       const int* node_start, const int* tri, int n_tri, const int* tet_start, const int* tet,
+                       int n_tet, const int* box_of_particle, const double* box_len, int n_pairs, const int* node,
+                       const int64_t* face, double* out) {
+  const int cap = 4 * n_tet + 1;
+  int* bf = malloc(sizeof(int) * 3 * (size_t)cap);
+  int* bp = malloc(sizeof(int) * (size_t)cap);
+  const int nb = orc_boundary_faces(n_nodes, X, n_particles, tet_start, tet, n_tet, cap, bf, bp);
+  int bad = 0;
+  for (int i = 0; i < n_pairs; ++i) {
+    const int k = node[i];
+    const int64_t f = face[i];
+    int v[3];
+    if (f >= 0 && f < n_tri) {
+      for (int m = 0; m < 3; ++m) v[m] = tri[m * n_tri + f];
+    } else if (f >= n_tri && f < (int64_t)n_tri + nb) {
+      for (int m = 0; m < 3; ++m) v[m] = bf[m * cap + (f - n_tri)];
+    } else {
+      out[i] = NAN;
+      ++bad;
+      continue;
+    }
+    int P = 0;
+    while (P + 1 < n_particles && node_start[P + 1] <= k) ++P;
+    const double* Lb = box_len + 3 * box_of_particle[P];
+    double xk[3];
+    pos(moved ? moved : x, n_nodes, k, xk);
+    double r[3][3];
+    for (int j = 0; j < 3; ++j) {
+      const double d0 = x[(size_t)j * n_nodes + v[0]] - xk[j];
+      const double shift = Lb[j] * nearbyint(d0 / Lb[j]);
+      for (int m = 0; m < 3; ++m) r[m][j] = x[(size_t)j * n_nodes + v[m]] - xk[j] - shift;
+    }
+    const double zero[3] = {0.0, 0.0, 0.0};
+    double c[3];
+    orc_point_triangle(zero, r[0], r[1], r[2], c);
+    out[i] = norm3(c);
+  }
+  free(bf);
+  free(bp);
+  return bad;
 }
