@@ -21,18 +21,26 @@
 //                 more than 27 cells, or a full segment, goes to the slow list;
 //  k_ac_pairs<T>  per work item: the face against the cell's records, the distance
 //                 (float64, the face's periodic image nearest to the node);
-//                 below d_min, an atomic minimum of the key (float32 distance,
-//                 face id) per node;
+//                 below d_min, an atomic minimum of the distance's float64 bits
+//                 per node, and the item is marked;
 //  k_ac_slow<T>   per slow face: the same over every cell its grown box covers;
+//                 then both again (second pass) over the marked items only: a
+//                 pair whose distance equals its node's minimum bit for bit
+//                 takes an atomic minimum of the face id;
 //  k_ac_push<T>   per node: the move from its winning face, or a copy.
 //
-// The key orders faces by float32 distance, then face id, so the choice is
-// deterministic; positions are float64 throughout.
+// The closest face is the one of least float64 distance, ties (faces sharing
+// the closest edge or vertex) to the lower face id, so the choice is exact and
+// deterministic: the second pass recomputes each marked pair's distance with
+// the same code, without fused multiply-add, so it reproduces the first pass's
+// bits.  Positions are float64 throughout.
 #include "ifem_internal.hpp"
 
 namespace ifem {
 
 constexpr unsigned long long kNoFace = ~0ull;
+constexpr int32_t kNoFaceId = 0x7fffffff;
+constexpr unsigned kHitBit = 0x80000000u;  // marks a work item or slow face that found a pair below d_min
 constexpr int kWorkSegs = 256;  // segments of the (face, cell) work list, one counter each
 
 struct alignas(4) Row3c {  // three consecutive cells' owners
@@ -127,6 +135,7 @@ __device__ __forceinline__ void abs_position(const ContactArgs& a, const T* __re
 // half a box away).
 __device__ __forceinline__ void face_image(const double pv[3][3], const double xk[3], const ContactBoxDev& C,
                                            double r[3][3]) {
+#pragma clang fp contract(off)
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const double shift = C.len[j] * rint((pv[0][j] - xk[j]) * C.inv_len[j]);
@@ -279,10 +288,14 @@ __device__ __forceinline__ int contact_cell(const ContactBoxDev& C, int cx, int 
 }
 
 // Face f of particle q against the nodes of other particles in one cell, their
-// records loaded four at a time.
-__device__ __forceinline__ void face_cell_nodes(const ContactArgs& a, int f, int q, const ContactBoxDev& C,
+// records loaded four at a time.  First pass (second == false): every pair below
+// d_min lowers its node's least distance; returns whether there was one.
+// Second pass: a pair at exactly its node's least distance lowers the node's
+// face id.
+__device__ __forceinline__ bool face_cell_nodes(const ContactArgs& a, int f, int q, const ContactBoxDev& C,
                                                 const double pv[3][3], const double blo[3], const double bhi[3],
-                                                float dmin32, int cell, unsigned long long* __restrict__ keys) {
+                                                double d_min, bool second, int cell) {
+  bool hit = false;
   const int o = a.off[cell], n = a.count[cell];
   for (int i0 = 0; i0 < n; i0 += 4) {
     ContactNode r4[4];
@@ -305,16 +318,24 @@ __device__ __forceinline__ void face_cell_nodes(const ContactArgs& a, int f, int
       face_image(pv, xk, C, r);
       double cp[3];
       closest_on_triangle0(r[0], r[1], r[2], cp);
-      const float dist = (float)norm_nc(cp);
-      if (dist < dmin32)
-        atomicMin(keys + r4[u].k, ((unsigned long long)__float_as_uint(dist) << 32) | (unsigned)f);
+      const double dist = norm_nc(cp);
+      if (!(dist < d_min)) continue;
+      // non-negative doubles order like their bit patterns
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(dist);
+      if (!second) {
+        atomicMin(a.keys + r4[u].k, bits);
+        hit = true;
+      } else if (bits == a.keys[r4[u].k]) {
+        atomicMin(a.keyf + r4[u].k, f);
+      }
     }
   }
+  return hit;
 }
 
 // Face f: its particle q, box C, corners pv, the cell range its box grown by d_min
 // covers (lo, cnt per axis) and that box relative to the first corner (blo, bhi,
-// grown a hair more, so that no pair whose float32 distance could still fall
+// grown a hair more, so that no pair whose rounded distance could still fall
 // below d_min is dropped).  False for a face that is not finite or spans half a
 // box: it belongs to a broken mesh and is skipped.
 template <typename T>
@@ -437,23 +458,26 @@ __global__ void __launch_bounds__(256) k_ac_faces(const ContactArgs a, const T* 
 // Faces searched whole: every cell of the grown box, one by one.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ac_slow(const ContactArgs a, const T* __restrict__ x,
-                                                 const double* __restrict__ anchor, double d_min,
-                                                 unsigned long long* __restrict__ keys) {
-  const int n = *a.slow_count;
-  const float dmin32 = (float)d_min;
+                                                 const double* __restrict__ anchor, double d_min, int second) {
+  const int n = min(*a.slow_count, a.n_tris + a.n_bfaces);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int f = a.slow[i];
+    const unsigned s = (unsigned)a.slow[i];
+    if (second && !(s & kHitBit)) continue;
+    const int f = (int)(s & ~kHitBit);
+    if (f >= a.n_tris + a.n_bfaces) continue;
     int q, lo[3], cnt[3];
     ContactBoxDev C;
     double pv[3][3], blo[3], bhi[3];
     if (!face_setup(a, x, anchor, f, d_min, q, C, pv, lo, cnt, blo, bhi)) continue;
+    bool hit = false;
     for (int iz = 0; iz < cnt[2]; ++iz)
       for (int iy = 0; iy < cnt[1]; ++iy)
         for (int ix = 0; ix < cnt[0]; ++ix) {
           const int cell = contact_cell(C, lo[0] + ix, lo[1] + iy, lo[2] + iz);
           const int owner = a.owner[cell];
-          if (owner != -1 && owner != q) face_cell_nodes(a, f, q, C, pv, blo, bhi, dmin32, cell, keys);
+          if (owner != -1 && owner != q) hit |= face_cell_nodes(a, f, q, C, pv, blo, bhi, d_min, second != 0, cell);
         }
+    if (!second && hit) a.slow[i] = (int32_t)(s | kHitBit);
   }
 }
 
@@ -461,22 +485,23 @@ __global__ void __launch_bounds__(256) k_ac_slow(const ContactArgs a, const T* _
 // phase 1 listed): the face against the cell's nodes of other particles.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ac_pairs(const ContactArgs a, const T* __restrict__ x,
-                                                  const double* __restrict__ anchor, double d_min,
-                                                  unsigned long long* __restrict__ keys) {
+                                                  const double* __restrict__ anchor, double d_min, int second) {
   // blocks are dealt to the segments round robin (the grid is a multiple of kWorkSegs)
   const int seg_cap = a.work_cap / kWorkSegs;
   const int seg = (int)(blockIdx.x % kWorkSegs), per_seg = (int)(gridDim.x / kWorkSegs);
   const int n = min(a.work_count[seg], seg_cap);
-  const uint2* __restrict__ list = a.work + (size_t)seg * seg_cap;
-  const float dmin32 = (float)d_min;
+  uint2* __restrict__ list = a.work + (size_t)seg * seg_cap;
   for (int i = (int)(blockIdx.x / kWorkSegs) * blockDim.x + threadIdx.x; i < n; i += per_seg * blockDim.x) {
     const uint2 w = list[i];
-    if (w.x >= (unsigned)(a.n_tris + a.n_bfaces)) continue;
+    if (w.x == ~0u || (second && !(w.x & kHitBit))) continue;  // reserved slot, or no pair below d_min
+    const int f = (int)(w.x & ~kHitBit);
+    if (f >= a.n_tris + a.n_bfaces) continue;
     int q, lo[3], cnt[3];
     ContactBoxDev C;
     double pv[3][3], blo[3], bhi[3];
-    face_setup(a, x, anchor, (int)w.x, d_min, q, C, pv, lo, cnt, blo, bhi);
-    face_cell_nodes(a, (int)w.x, q, C, pv, blo, bhi, dmin32, (int)w.y, keys);
+    face_setup(a, x, anchor, f, d_min, q, C, pv, lo, cnt, blo, bhi);
+    const bool hit = face_cell_nodes(a, f, q, C, pv, blo, bhi, d_min, second != 0, (int)w.y);
+    if (!second && hit) list[i].x = w.x | kHitBit;
   }
 }
 
@@ -489,13 +514,15 @@ __global__ void __launch_bounds__(256) k_ac_push(const ContactArgs a, const T* _
   if (k >= a.n_nodes) return;
   const int64_t N = a.n_nodes;
   const unsigned long long key = keys[k];
-  if (key == kNoFace) {
+  const int f = a.keyf[k];
+  if (key == kNoFace || (unsigned)f >= (unsigned)(a.n_tris + a.n_bfaces)) {
+    // a distance without a face id: the second pass did not reproduce it (positions written during the call)
+    if (key != kNoFace) atomicAdd(a.status + 3, 1ull);
 #pragma unroll
     for (int i = 0; i < 3; ++i) x_out[i * N + k] = x[i * N + k];
     if (face_out) face_out[k] = -1;
     return;
   }
-  const int f = (int)(key & 0xffffffffull);
   const int p = a.node_particle[k];
   double xk[3];
   abs_position(a, x, anchor, k, p, xk);
@@ -624,6 +651,7 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
   e = launch_fill_i32(a.count, a.n_cells, 0, st);
   if (e == hipSuccess) e = launch_fill_i32(a.work_count, kWorkSegs + 1, 0, st);  // segment and slow-face counters
   if (e == hipSuccess) e = launch_fill_u64(a.keys, a.n_nodes, kNoFace, st);
+  if (e == hipSuccess) e = launch_fill_i32(a.keyf, a.n_nodes, kNoFaceId, st);
   P.timer->end(st);
   if (e != hipSuccess) return e;
   P.timer->begin(K_CONTACT, st);
@@ -654,12 +682,14 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
     else
       hipLaunchKernelGGL(k_ac_faces<double>, gf, dim3(B), 0, st, a, (const double*)x, anchor, d_min, a.keys);
     const dim3 gp(16 * kWorkSegs);
-    if (dtype == 0) {
-      hipLaunchKernelGGL(k_ac_pairs<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, a.keys);
-      hipLaunchKernelGGL(k_ac_slow<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, a.keys);
-    } else {
-      hipLaunchKernelGGL(k_ac_pairs<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, a.keys);
-      hipLaunchKernelGGL(k_ac_slow<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, a.keys);
+    for (int second = 0; second < 2; ++second) {  // least distance, then least face id at that distance
+      if (dtype == 0) {
+        hipLaunchKernelGGL(k_ac_pairs<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, second);
+        hipLaunchKernelGGL(k_ac_slow<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, second);
+      } else {
+        hipLaunchKernelGGL(k_ac_pairs<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, second);
+        hipLaunchKernelGGL(k_ac_slow<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, second);
+      }
     }
   }
   if (dtype == 0)

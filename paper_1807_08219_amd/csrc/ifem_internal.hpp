@@ -85,12 +85,14 @@ struct ContactArgs {
   int32_t *near_lo, *near_hi;    // [n_cells] least / greatest owner around each cell (filter passes)
   int32_t *near_lo2, *near_hi2;  // [n_cells] the same, second buffers (the final result)
   ContactNode* rec;              // [n_nodes] the nodes grouped by cell
-  unsigned long long* keys;      // [n_nodes] (float32 distance bits, face id) of the nearest close face
+  unsigned long long* keys;      // [n_nodes] float64 bits of the least distance below d_min (atomic min)
+  int32_t* keyf;                 // [n_nodes] least face id at exactly that distance (second pass)
   int32_t* scan_tmp;             // [cell blocks + 1] block totals of the offset scan
   uint2* work;                   // [work_cap] (face, cell) pairs to search
   int32_t* work_count;           // [256 + 1]: items per work-list segment, then slow faces (slow_count)
   int32_t* slow_count;
   int32_t* slow;                 // [n_tris + n_bfaces] faces searched whole
+  unsigned long long* status;    // the plan's status counters
   int32_t work_cap;
   int32_t n_nodes, n_tris, n_bfaces, n_cells, n_boxes;
 };

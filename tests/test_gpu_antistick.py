@@ -1,10 +1,20 @@
 """GPU node-face anti-sticking (Sec. III.B) against the oracle's brute-force search.
 
-Both sides decide in the same precision (the closest face by float32 distance, then face id; a move
-when that distance is below float32 d_min), from float64 distances; the winning face per node is
-compared exactly, moved positions to float64 rounding (1e-12 of the positions), float32 offsets to
-one rounding.  Full-size workloads are checked on sampled particles together with every particle
-whose box can reach them.
+Both sides take the closest face as the one of least float64 distance (ties to the lower face id) and
+move a node when that distance is below d_min.  They evaluate the closest point by different routines,
+so where two faces lie at the same distance up to rounding (faces sharing the closest edge or vertex)
+either may win, and a node within rounding of d_min may move on one side only.  The check is therefore
+one of validity, with the rounding bound EPS of a float64 distance between points of magnitude |x|:
+  * a node moved by one side only is within EPS of d_min (by the oracle's distance);
+  * the face the GPU chose is, by the oracle's own distance, within EPS of the least distance;
+  * the moved node is d_min from that face (the oracle measures it), to EPS in float64 and to the
+    offset's rounding in float32;
+  * where both sides chose the same face the moved positions agree to 1e-12 of the positions, float32
+    offsets to one rounding; unmoved nodes are copied exactly;
+  * where the oracle's closest face is unique (no other face of another particle within EPS of the
+    least distance) and the least distance is not within EPS of d_min, the GPU chose that face.
+Full-size workloads are checked on sampled particles together with every particle whose box can reach
+them.
 """
 import numpy as np
 import pytest
@@ -18,6 +28,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+def eps_of(x):
+    """Rounding bound of a float64 node-face distance among points of magnitude up to max|x|."""
+    return 256 * U64 * (1.0 + np.abs(x).max())
 
 
 def say(msg):
@@ -82,16 +98,67 @@ CASES = {
 }
 
 
-def _check(sc, d_min, plan, out, faces, ref_x, ref_w, dtype):
+def _validate(sc, d_min, got_w, got_abs, ref_x, ref_w, ref_d, nodes, off_scale, tag):
+    """Validity of the GPU's anti-sticking on `nodes` of scene sc (face ids of sc): see the module
+    docstring.  got_abs [3][n] absolute moved positions; off_scale [n] the magnitude of each node's
+    stored value (0 in float64, |offset| in float32) for the float32 rounding of the result."""
+    eps = eps_of(sc.x64)
+    gw, rw = got_w[nodes], ref_w[nodes]
+    mg, mo = gw >= 0, rw >= 0
+    one = mg != mo
+    assert np.all(np.abs(ref_d[nodes][one] - d_min) <= eps), f"{tag}: a node moved on one side only, far from d_min"
+    k = nodes[mg]
+    if k.size:
+        dg = oracle.pair_distances(sc, k, gw[mg])
+        assert np.all(dg <= ref_d[k] + eps), f"{tag}: the GPU's face is not the closest"
+        assert np.all(dg < d_min + eps), f"{tag}: moved although the face is not within d_min"
+        dm = oracle.pair_distances(sc, k, gw[mg], moved=got_abs)
+        tol = eps + 4 * U32 * off_scale[k]
+        assert np.all(np.abs(dm - d_min) <= tol), f"{tag}: moved node not at d_min from its face"
+    same = nodes[mg & mo & (gw == rw)]
+    assert np.all(np.abs(got_abs[:, same] - ref_x[:, same])
+                  <= 1e-12 * (1.0 + np.abs(ref_x[:, same])) + U32 * off_scale[same]), f"{tag}: moved positions"
+    stay = nodes[~mg]
+    assert np.all(np.abs(got_abs[:, stay] - sc.x64[:, stay]) <= U32 * off_scale[stay]), f"{tag}: unmoved nodes"
+    # unique winners must agree
+    cand = nodes[mo & (np.abs(ref_d[nodes] - d_min) > eps)]
+    uniq = cand[_n_near_faces(sc, cand, ref_d[cand] + eps) == 1]
+    assert np.array_equal(got_w[uniq], ref_w[uniq]), f"{tag}: a unique closest face was not chosen"
+    differ = int(np.count_nonzero(mg & mo & (gw != rw)) + np.count_nonzero(one))
+    return differ
+
+
+def _n_near_faces(sc, nodes, bound):
+    """Per node: how many faces of other particles lie within bound[i] of it (oracle distances)."""
+    if nodes.size == 0:
+        return np.zeros(0, dtype=np.int64)
+    part = sc.node_particle()
+    fpart = part[sc.tri[0]] if sc.n_tris else np.zeros(0, np.int32)
+    if sc.n_tets:
+        _, bp = oracle.boundary_faces(sc)
+        fpart = np.concatenate([fpart, bp])
+    nf = fpart.size
+    out = np.zeros(nodes.size, dtype=np.int64)
+    for i, k in enumerate(nodes):
+        faces = np.nonzero(fpart != part[k])[0].astype(np.int64)
+        d = oracle.pair_distances(sc, np.full(faces.size, k, dtype=np.int32), faces)
+        out[i] = np.count_nonzero(d <= bound[i])
+    return out
+
+
+def _check(sc, d_min, out, faces, ref, dtype):
+    ref_x, ref_w, _, ref_d = ref
     got_w = faces.cpu().numpy()
-    assert np.array_equal(got_w, ref_w)
+    part = sc.node_particle()
+    nodes = np.arange(sc.n_nodes)
     if dtype == ifem.IFEM_F64:
-        got = out.cpu().numpy()
-        assert np.all(np.abs(got - ref_x) <= 1e-12 * (1.0 + np.abs(ref_x)))
+        got_abs = out.cpu().numpy()
+        off_scale = np.zeros(sc.n_nodes)
     else:
-        off = ref_x - sc.anchor[sc.node_particle()].T
         got = out.cpu().numpy().astype(np.float64)
-        assert np.all(np.abs(got - off) <= U32 * np.abs(off) + 1e-12 * (1.0 + np.abs(ref_x)))
+        got_abs = got + sc.anchor[part].T
+        off_scale = np.abs(got).max(axis=0)
+    return _validate(sc, d_min, got_w, got_abs, ref_x, ref_w, ref_d, nodes, off_scale, "scene")
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -99,7 +166,8 @@ def test_antistick_matches_oracle(name):
     make, d_min = CASES[name]
     sc = make()
     d_min = d_min if d_min is not None else sc.boxes[0].h
-    ref_x, ref_w, moved = oracle.antistick(sc, d_min)
+    ref = oracle.antistick(sc, d_min, with_distance=True)
+    moved = ref[2]
     say(f"[gpu] anti-sticking {name}: {sc.n_nodes} nodes, d_min {d_min}, oracle moved {moved}")
     assert moved > 0
     plan = ifem.Plan(sc)
@@ -107,15 +175,19 @@ def test_antistick_matches_oracle(name):
     out = torch.empty((3, sc.n_nodes), dtype=torch.float64, device="cuda")
     plan.antistick(ifem.IFEM_F64, cu(sc.x64, torch.float64), None, out, d_min, faces)
     torch.cuda.synchronize()
-    _check(sc, d_min, plan, out, faces, ref_x, ref_w, ifem.IFEM_F64)
-    first = out.cpu().numpy()
+    differ = _check(sc, d_min, out, faces, ref, ifem.IFEM_F64)
+    say(f"    winners that differ from the oracle's (rounding ties): {differ}")
+    first, first_w = out.cpu().numpy(), faces.cpu().numpy()
     plan.antistick(ifem.IFEM_F64, cu(sc.x64, torch.float64), None, out, d_min, faces)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), first)  # run to run
+    assert np.array_equal(faces.cpu().numpy(), first_w)
     out32 = torch.empty((3, sc.n_nodes), dtype=torch.float32, device="cuda")
     plan.antistick(ifem.IFEM_F32, cu(sc.x32, torch.float32), cu(sc.anchor, torch.float64), out32, d_min, faces)
     torch.cuda.synchronize()
-    _check(sc, d_min, plan, out32, faces, ref_x, ref_w, ifem.IFEM_F32)
+    # float32 offsets from float64 anchors give the same float64 positions: the same decisions
+    assert np.array_equal(faces.cpu().numpy(), first_w)
+    _check(sc, d_min, out32, faces, ref, ifem.IFEM_F32)
     assert plan.status() == [0, 0, 0, 0, 0]
     plan.close()
 
@@ -183,18 +255,50 @@ def test_fullsize_sampled(cfg):
     picks = list(rng.choice(moved_parts, size=min(3, moved_parts.size), replace=False)) if moved_parts.size else []
     picks += list(rng.choice(sc.n_particles, size=2, replace=False))
     lohi = _boxes(sc)
+    bf_full = _bface_keys(sc) if sc.n_tets else {}
     for p in picks:
         group = _neighbours(sc, p, 3 * d_min, lohi)
         sub = scenes.subset(sc, group)
-        ref_x, ref_w, _ = oracle.antistick(sub, d_min)
+        ref_x, ref_w, _, ref_d = oracle.antistick(sub, d_min, with_distance=True)
         nodes = np.arange(sc.node_start[p], sc.node_start[p + 1])
         mine = np.arange(sub.node_start[0], sub.node_start[1])
-        # face ids of the subset map back through the triangle offsets of the chosen particles
-        fmap = np.concatenate([np.arange(sc.tri_start[q], sc.tri_start[q + 1]) for q in group]).astype(np.int64)
-        rw = ref_w[mine]
-        mapped = np.where(rw >= 0, fmap[np.clip(rw, 0, max(fmap.size - 1, 0))] if fmap.size else -1, -1)
-        if sc.n_tets == 0 or np.all(rw < sub.n_tris):
-            assert np.array_equal(w[nodes], mapped), f"particle {p}"
-        off = ref_x[:, mine] - sc.anchor[p][:, None]
-        assert np.all(np.abs(got[:, nodes] - off) <= U32 * np.abs(off) + 1e-12 * (1 + np.abs(ref_x[:, mine])))
+        # the GPU's face ids (full scene) in the subset's numbering
+        sub_w = np.full(sub.n_nodes, -1, dtype=np.int64)
+        sub_w[mine] = _to_subset_faces(sc, sub, group, w[nodes], bf_full)
+        got_abs = np.zeros((3, sub.n_nodes))
+        got_abs[:, mine] = got[:, nodes] + sc.anchor[p][:, None]
+        off_scale = np.zeros(sub.n_nodes)
+        off_scale[mine] = np.abs(got[:, nodes]).max(axis=0)
+        _validate(sub, d_min, sub_w, got_abs, ref_x, ref_w, ref_d, mine, off_scale, f"particle {p}")
     plan.close()
+
+
+def _bface_keys(sc):
+    """Boundary face id of the full scene by its sorted node triple."""
+    bf, _ = oracle.boundary_faces(sc)
+    return {tuple(sorted(bf[:, j])): sc.n_tris + j for j in range(bf.shape[1])}
+
+
+def _to_subset_faces(sc, sub, group, faces, bf_full):
+    """Face ids of the full scene -> ids of the subset made of particles `group` (in that order)."""
+    tri_map, node_map = {}, {}
+    t_off, n_off = 0, 0
+    for q in group:
+        for t in range(sc.tri_start[q], sc.tri_start[q + 1]):
+            tri_map[t] = t_off + t - sc.tri_start[q]
+        t_off += sc.tri_start[q + 1] - sc.tri_start[q]
+        for k in range(sc.node_start[q], sc.node_start[q + 1]):
+            node_map[k] = n_off + k - sc.node_start[q]
+        n_off += sc.node_start[q + 1] - sc.node_start[q]
+    inv_bf = {v: key for key, v in bf_full.items()}
+    sub_bf = _bface_keys(sub) if sub.n_tets else {}
+    out = np.full(faces.size, -1, dtype=np.int64)
+    for i, f in enumerate(faces):
+        if f < 0:
+            continue
+        if f < sc.n_tris:
+            out[i] = tri_map[int(f)]
+        else:
+            key = tuple(sorted(node_map[v] for v in inv_bf[int(f)]))
+            out[i] = sub_bf[key]
+    return out
