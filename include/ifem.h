@@ -77,7 +77,9 @@
  *   counts[1]  non-finite nodal force components written;
  *   counts[2]  points whose MLS moment matrix was singular (weights zero);
  *   counts[3]  nodes a tiled spread skipped because their nearest lattice
- *              node moved between binning and accumulation (positions
+ *              node moved between binning and accumulation, or nodes the
+ *              anti-sticking pass left unmoved because its second pass could
+ *              not reproduce their least distance (in both cases: positions
  *              written concurrently with the call); 0 in normal use;
  *   counts[4]  membranes whose volume-correction multiplier did not converge
  *              (ifem_volume_correct; their nodes are moved by the last iterate).
@@ -168,7 +170,8 @@ typedef struct {
  * {tile 32 x 16 x 8, block_forces 512, block_points 256}, the fastest measured
  * on dense red-cell suspensions; with fewer than one node per 20 grid cells
  * (sparse boxes of mixed particles) the default tile is 16 x 16 x 16.  The spread region
- * of a tile, (tile_x + 1)(tile_y + 2)(tile_z + 2) cells, must not exceed 10176. */
+ * of a tile, (tile_x + 1)(tile_y + 2)(tile_z + 2) cells, must not exceed 13568
+ * (12 bytes of LDS per cell in float64). */
 typedef struct {
   int32_t tile[3];      /* spread tile, cells per axis (powers of two, 4..64) */
   int32_t block_forces; /* threads per particle workgroup (power of two, 64..512) */
@@ -212,12 +215,15 @@ ifem_status ifem_element_forces(ifem_plan plan, int32_t dtype, const void* x, co
 /* Step 2 (Sec. III.A): spread nodal forces F [3][n_nodes] to grid [3][total_cells].
  * The grid holds forces (its sum equals the Lagrangian total), not densities.
  * IFEM_SPREAD_TILED (default) sums in 64-bit fixed point per lattice tile:
- * bitwise reproducible, no global float atomics.  A non-finite force
- * component, or a float64 one beyond the float32 range (3.4e38, the range of
- * the per-tile bound on |F|), cannot be held in fixed point: it turns the
- * tiles that take its stencil (its home tile and at most one x-neighbour),
- * plus their one-cell y/z halos, into NaN for that component (the plain
- * IFEM_SPREAD_ATOMIC mode spreads it to the 27 stencil cells only). */
+ * bitwise reproducible, no global float atomics; every finite force of
+ * either precision is held (the fixed-point scale of a tile's list follows a
+ * power-of-two bound on its largest |F|).  A non-finite force component, or a
+ * node whose position is not finite (its MLS system has no solution: counted
+ * in counts[2]), cannot be held in fixed point: it turns the tiles that take
+ * its stencil (its home tile and at most one x-neighbour; a non-finite
+ * position is binned at lattice index 0), plus their one-cell y/z halos, into
+ * NaN for that component (the plain IFEM_SPREAD_ATOMIC mode spreads it to the
+ * 27 stencil cells only). */
 ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F,
                         void* grid, void* stream);
 
@@ -310,9 +316,9 @@ ifem_status ifem_advance(ifem_plan plan, int32_t dtype, const void* x, const voi
  * triangles (face id = triangle index) and the boundary faces of the solids'
  * tetrahedral meshes (ids n_tris + k, listed by tetrahedron and local face
  * opposite node j = 0..3, oriented outward in X_ref).  The closest face is the
- * one of least distance rounded to float32, ties to the lower id; a node moves
- * when that float32 distance is below (float)d_min.  Distances are float64 with
- * the periodic minimum image; every node is tested against the positions
+ * one of least float64 distance, exact ties (faces sharing the closest edge or
+ * vertex) to the lower id; a node moves when that distance is below d_min.
+ * Distances use the periodic minimum image; every node is tested against the positions
  * before the call (no node sees another's move).  Exact search: a uniform grid
  * of contact cells about two lattice cells wide per box replaces the paper's
  * bounding-box broad phase.  A face that is not finite or spans more than half

@@ -513,10 +513,10 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   for (int a = 0; a < 3; ++a)
     if (tn.tile[a] < 4 || tn.tile[a] > 64 || (tn.tile[a] & (tn.tile[a] - 1)))
       return fail(IFEM_ERR_INVALID_ARG, "tile sizes must be powers of two in [4, 64]");
-  // spread region: the tile plus a one-cell halo along y and z and one pad cell per row, two 64-bit
-  // words per cell in float64
-  if ((int64_t)(tn.tile[0] + 1) * (tn.tile[1] + 2) * (tn.tile[2] + 2) * 16 + 1024 > (int64_t)kLdsLimit)
-    return fail(IFEM_ERR_INVALID_ARG, "tile too large for LDS: (tile_x + 1)(tile_y + 2)(tile_z + 2) must be <= 10176");
+  // spread region: the tile plus a one-cell halo along y and z and one pad cell per row, 12 bytes per
+  // cell in float64 (a 64-bit word and a 32-bit remainder word)
+  if ((int64_t)(tn.tile[0] + 1) * (tn.tile[1] + 2) * (tn.tile[2] + 2) * 12 + 1024 > (int64_t)kLdsLimit)
+    return fail(IFEM_ERR_INVALID_ARG, "tile too large for LDS: (tile_x + 1)(tile_y + 2)(tile_z + 2) must be <= 13568");
   if (tn.block_forces < 64 || tn.block_forces > 512 || (tn.block_forces & (tn.block_forces - 1)))
     return fail(IFEM_ERR_INVALID_ARG, "block_forces must be a power of two in [64, 512]");
   if (tn.block_points != 64 && tn.block_points != 128 && tn.block_points != 256)
@@ -707,6 +707,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_nhi2, (size_t)n_ccells));
   HIP_TRY(mem.alloc(&d_crec, (size_t)m.n_nodes));
   HIP_TRY(mem.alloc(&d_ckeys, (size_t)m.n_nodes));
+  int32_t* d_ckeyf;
+  HIP_TRY(mem.alloc(&d_ckeyf, (size_t)m.n_nodes));
   int32_t* d_cscan;
   HIP_TRY(mem.alloc(&d_cscan, (size_t)contact_scan_blocks((int32_t)n_ccells) + 1));
   // (face, cell) work of the contact search, in 256 equal segments: two items per face on average
@@ -792,11 +794,13 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ca.n_boxes = n_boxes;
   ca.rec = d_crec;
   ca.keys = d_ckeys;
+  ca.keyf = d_ckeyf;
   ca.scan_tmp = d_cscan;
   ca.work = d_cwork;
   ca.work_count = d_cwcount;
   ca.slow_count = d_cwcount + 256;
   ca.slow = d_cslow;
+  ca.status = d_status;
   ca.work_cap = work_cap;
   ca.n_nodes = m.n_nodes;
   ca.n_tris = m.n_tris;

@@ -228,11 +228,26 @@ __device__ __forceinline__ void all_lists(const TransferArgs& a, const T* __rest
   }
 }
 
+// Bound code of a force value for the fixed-point scale: 0 for 0, e + 1100 for
+// a finite |f| < 2^e (e from frexp: -1073..1024 in float64, so the code is
+// positive), all ones for a non-finite value.  Codes order like the bounds,
+// so a list's bound is the atomic maximum of its codes.
+constexpr int kBoundBias = 1100;
+constexpr uint32_t kBoundPoison = 0xffffffffu;
+template <typename T>
+__device__ __forceinline__ uint32_t bound_code(T f) {
+  const double v = fabs((double)f);
+  if (!(v <= DBL_MAX)) return kBoundPoison;
+  if (v == 0.0) return 0u;
+  int e;
+  frexp(v, &e);
+  return (uint32_t)(e + kBoundBias);
+}
+
 // Count pass: one thread per node; every (node, component) counts once in
 // each of its lists, one atomic per distinct list per wavefront.  The same
-// atomics raise each list's bound on |F| to the wavefront's largest |F| of
-// that component (float bits of non-negative values order like the values,
-// NaN above infinity); the bound sets the list's fixed-point scale.
+// atomics raise each list's bound code (bound_code) to the wavefront's largest
+// of that component; the bound sets the list's fixed-point scale.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_count(const TransferArgs a, const T* __restrict__ x,
                                                    const double* __restrict__ anchor, const T* __restrict__ F) {
@@ -243,7 +258,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const TransferArgs a, const T
   uint32_t fm[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    uint32_t v = k < a.n_nodes ? __float_as_uint(fabsf((float)F[d * (int64_t)a.n_nodes + k])) : 0u;
+    uint32_t v = k < a.n_nodes ? bound_code(F[d * (int64_t)a.n_nodes + k]) : 0u;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
       const uint32_t w = __shfl_xor(v, o, kWave);
@@ -398,28 +413,32 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     return;  // no barrier follows
   }
 
-  // fixed-point scale from the bound on |F| of the list (raised by the count pass) and its length; a
-  // non-finite force cannot be held in fixed point and poisons (NaN) the tile's whole region instead
-  const double m = (double)__uint_as_float(a.tile_fmax[L]);
-  const bool poison = cnt > 0 && !(m <= DBL_MAX);
+  // fixed-point scale from the bound code of the list (raised by the count pass) and its length; a
+  // non-finite force cannot be held in fixed point and poisons (NaN) the tile's whole region instead,
+  // as does an entry whose MLS system has no solution (a non-finite position)
+  __shared__ int bad_entry;
+  const uint32_t code = a.tile_fmax[L];
+  bool poison = code == kBoundPoison;
   // float64 keeps a 32-bit remainder word per cell after the 64-bit words (12 bytes per cell)
   unsigned int* lo = reinterpret_cast<unsigned int*>(acc + nreg);
   unsigned int* acc32 = reinterpret_cast<unsigned int*>(acc);
   for (int i = tid; i < (NW == 2 ? 3 : 2) * nreg; i += nt) acc32[i] = 0u;
+  if (tid == 0) bad_entry = 0;
   __syncthreads();
-  const bool active = cnt > 0 && m > 0.0 && !poison;
+  // every entry goes through the loop when the forces are finite, also when they are all zero, so
+  // that an entry with a non-finite position is found
+  const bool active = !poison;
+  const bool nonzero = code > 0u && !poison;
   int sc = 0, sl = 0;
   if (active) {
-    // one contribution is at most 4 max|F| (sum of |phi| <= 4), a cell sum at most cnt times that:
-    // keep every contribution below 2^50 and every sum below 2^62
-    int e1, e2;
-    frexp(4.0 * m, &e1);
-    frexp(4.0 * (double)cnt * m, &e2);
-    sc = min(50 - e1, 62 - e2);
-    const double scale = ldexp(1.0, sc);
-    // float64 remainder scale: |remainder| <= 1/2 unit, at most cnt of them per cell, so with
-    // 2^(lc - 1) <= cnt < 2^lc every cell's sum stays below 2^29 in its 32-bit word
-    sl = 30 - (32 - __builtin_clz((unsigned)cnt));
+    // |F| < 2^em; one contribution is at most 4 max|F| (sum of |phi| <= 4) < 2^(em + 2), a cell sum
+    // at most cnt < 2^lc times that: keep every contribution below 2^50 and every sum below 2^62
+    const int em = nonzero ? (int)code - kBoundBias : 0;
+    const int lc = 32 - __builtin_clz((unsigned)cnt);  // 2^(lc - 1) <= cnt < 2^lc
+    sc = min(48 - em, 60 - em - lc);
+    // float64 remainder scale: |remainder| <= 1/2 unit, at most cnt of them per cell, so every
+    // cell's sum stays below 2^29 in its 32-bit word
+    sl = 30 - lc;
     const double lscale = ldexp(1.0, sl);
     // entry order: qi -> (qi * stride) mod cnt with a prime stride that does not divide cnt (a
     // permutation), so that the lanes of a wavefront take nodes far apart in the list, i.e. far apart
@@ -455,8 +474,12 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
       }
       const T tau[3] = {(T)tau64[0], (T)tau64[1], (T)tau64[2]};
       T W[27], cf[4];
-      mls_weights<T>(tau, W, cf);
-      const double fs = (double)Fd[k] * scale;
+      if (!mls_weights<T>(tau, W, cf)) {  // no weights: the tile cannot hold this node's share
+        atomicAdd(a.status + 2, 1ull);
+        bad_entry = 1;
+        continue;
+      }
+      const double fs = ldexp((double)Fd[k], sc);  // exact: |F| 2^sc < 2^48
       // a column outside the tile adds zero to the row's pad cell (its contribution belongs to the
       // x-neighbour, which holds this node in its list too)
       double fsx[3];
@@ -492,16 +515,17 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     }
   }
   __syncthreads();
+  if (bad_entry) poison = true;  // uniform: read after the barrier
   // interior -> grid (final unless a neighbour's halo adds to it), y/z halo rows -> scratch.  A
   // wavefront takes 64 / tile_x region rows at a time (lane -> row of the group, x), so the row is
   // decoded once per row; (row + 1/2) / ry is at least 1/(2 ry) away from an integer, far above the
   // rounding of this small quotient, so the truncation is exact.
-  const double inv = ldexp(1.0, -sc);
   const int lrow = lane >> a.tile_shift[0], ix = lane & (a.tile[0] - 1);
   const int rpw = kWave >> a.tile_shift[0];  // tiles are at most 64 cells wide
   const int nrows = ry * rz;
   const float inv_ry = frcp((float)ry);
-  const bool halo_on = active || poison;
+  const bool halo_on = nonzero || poison;
+  const bool sums = nonzero && !poison;
   const T fillv = poison ? (T)__builtin_nan("") : T(0);
   for (int row0 = wave * rpw; row0 < nrows; row0 += nwaves * rpw) {
     const int row = row0 + lrow;
@@ -510,17 +534,17 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     const int iy = row - iz * ry;
     const int r = row * rx + ix;
     T v = fillv;
-    if (active) {
+    if (sums) {
       double w = (double)(long long)acc[r];
       if (NW == 2) w += (double)(int)lo[r] * ldexp(1.0, -sl);
-      v = (T)(w * inv);
+      v = (T)ldexp(w, -sc);
     }
     if ((unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2])
       g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix)] = v;
     else if (halo_on)
       halo[r] = v;
   }
-  if (tid == 0) a.tile_flag[L] = (active || poison) ? 1 : 0;
+  if (tid == 0) a.tile_flag[L] = halo_on ? 1 : 0;
 }
 
 // Merge: every tile adds, to its y/z border rows, the halo rows that its 8

@@ -114,6 +114,26 @@ def _ptr(t):
     return t.data_ptr()
 
 
+def _torch_dtype(dtype):
+    """The element type of positions, forces, grids and velocities for an IFEM_* precision flag, or None
+    for a flag the library does not know (the C ABI then rejects the call)."""
+    import torch
+
+    return {IFEM_F32: torch.float32, IFEM_F64: torch.float64}.get(int(dtype))
+
+
+def _check_arg(t, name, dt, numel):
+    """Check `t`'s element type and count against what the call reads or writes (the kernels trust
+    both: a mismatch would access memory outside the tensor).  dt None skips the type check (an unknown
+    precision flag, left to the C ABI)."""
+    if t is None:
+        return
+    if dt is not None and t.dtype != dt:
+        raise ValueError(f"{name}: expected {dt}, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+
+
 def _stream(stream):
     import torch
 
@@ -200,39 +220,69 @@ class Plan:
             out["dropped"] = (0.0, n[15])
         return out
 
+    # --- argument checks: element types and counts from the plan (the C ABI checks pointers, aliasing
+    # and values; it cannot see the size of a device allocation).  Every argument is checked before
+    # any pointer is taken.  Kinds: "node" [ncomp][n_nodes] and "cell" [ncomp][total_cells] in the
+    # call's precision, "particle" [n_particles][ncomp] float64, "face" [n_nodes] int64.
+    def _pointers(self, dtype, *args):
+        import torch
+
+        for t, name, kind, ncomp in args:
+            if kind == "node":
+                _check_arg(t, name, _torch_dtype(dtype), ncomp * self.n_nodes)
+            elif kind == "cell":
+                _check_arg(t, name, _torch_dtype(dtype), ncomp * self.total_cells)
+            elif kind == "particle":
+                _check_arg(t, name, torch.float64, ncomp * self.n_particles)
+            else:
+                _check_arg(t, name, torch.int64, self.n_nodes)
+        return [_ptr(a[0]) for a in args]
+
     # --- the three steps (device tensors in, device tensors out)
     def element_forces(self, dtype, x, anchor, f_out, red_out=None, stream=None):
-        _check(lib().ifem_element_forces(self.handle, dtype, _ptr(x), _ptr(anchor), _ptr(f_out), _ptr(red_out),
-                                         _stream(stream)))
+        p = self._pointers(dtype, (x, "x", "node", 3), (anchor, "anchor", "particle", 3), (f_out, "f_out", "node", 3),
+                           (red_out, "red_out", "particle", 5))
+        _check(lib().ifem_element_forces(self.handle, dtype, *p, _stream(stream)))
 
     def spread(self, dtype, x, anchor, F, grid, stream=None):
-        _check(lib().ifem_spread(self.handle, dtype, _ptr(x), _ptr(anchor), _ptr(F), _ptr(grid), _stream(stream)))
+        p = self._pointers(dtype, (x, "x", "node", 3), (anchor, "anchor", "particle", 3), (F, "F", "node", 3),
+                           (grid, "grid", "cell", 3))
+        _check(lib().ifem_spread(self.handle, dtype, *p, _stream(stream)))
 
     def interp(self, dtype, x, anchor, grid_u, v_out, stream=None):
-        _check(lib().ifem_interp(self.handle, dtype, _ptr(x), _ptr(anchor), _ptr(grid_u), _ptr(v_out),
-                                 _stream(stream)))
+        p = self._pointers(dtype, (x, "x", "node", 3), (anchor, "anchor", "particle", 3),
+                           (grid_u, "grid_u", "cell", 3), (v_out, "v_out", "node", 3))
+        _check(lib().ifem_interp(self.handle, dtype, *p, _stream(stream)))
 
     def volume_correct(self, dtype, x, x_out, V0=None, lambda_out=None, stream=None):
         """Membrane volume correction; x_out may be x itself (in place)."""
-        _check(lib().ifem_volume_correct(self.handle, dtype, _ptr(x), _ptr(V0), _ptr(x_out), _ptr(lambda_out),
-                                         _stream(stream)))
+        px, pv0, pxo, plam = self._pointers(dtype, (x, "x", "node", 3), (V0, "V0", "particle", 1),
+                                            (x_out, "x_out", "node", 3), (lambda_out, "lambda_out", "particle", 1))
+        _check(lib().ifem_volume_correct(self.handle, dtype, px, pv0, pxo, plam, _stream(stream)))
 
     def advance(self, dtype, x, v, x_out, v_prev=None, dt=1.0, stream=None):
         """Adams-Bashforth update x_out = x + dt (3/2 v - 1/2 v_prev) (forward Euler without v_prev)."""
-        _check(lib().ifem_advance(self.handle, dtype, _ptr(x), _ptr(v), _ptr(v_prev), float(dt), _ptr(x_out),
-                                  _stream(stream)))
+        px, pv, pvp, pxo = self._pointers(dtype, (x, "x", "node", 3), (v, "v", "node", 3),
+                                          (v_prev, "v_prev", "node", 3), (x_out, "x_out", "node", 3))
+        _check(lib().ifem_advance(self.handle, dtype, px, pv, pvp, float(dt), pxo, _stream(stream)))
 
     def interp_cells(self, dtype, x, anchor, grid, out, stream=None):
         """Cell-centred fields grid [ncomp][total_cells] to the nodes, out [ncomp][n_nodes]."""
-        _check(lib().ifem_interp_cells(self.handle, dtype, _ptr(x), _ptr(anchor), _ptr(grid), int(grid.shape[0]),
-                                       _ptr(out), _stream(stream)))
+        ncomp = int(grid.shape[0]) if grid.dim() == 2 else 0
+        if ncomp < 1:
+            raise ValueError("grid: expected [ncomp][total_cells]")
+        px, pa, pg, po = self._pointers(dtype, (x, "x", "node", 3), (anchor, "anchor", "particle", 3),
+                                        (grid, "grid", "cell", ncomp), (out, "out", "node", ncomp))
+        _check(lib().ifem_interp_cells(self.handle, dtype, px, pa, pg, ncomp, po, _stream(stream)))
 
     def fluid_forces(self, dtype, x, v, f_inout, C=None, eta=1.0, G=0.0, stream=None):
         """Add the Newtonian and polymer fluid-stress forces of every solid to f_inout."""
-        _check(lib().ifem_fluid_forces(self.handle, dtype, _ptr(x), _ptr(v), _ptr(C), float(eta), float(G),
-                                       _ptr(f_inout), _stream(stream)))
+        px, pv, pc, pf = self._pointers(dtype, (x, "x", "node", 3), (v, "v", "node", 3), (C, "C", "node", 6),
+                                        (f_inout, "f_inout", "node", 3))
+        _check(lib().ifem_fluid_forces(self.handle, dtype, px, pv, pc, float(eta), float(G), pf, _stream(stream)))
 
     def antistick(self, dtype, x, anchor, x_out, d_min, face_out=None, stream=None):
         """Node-face anti-sticking: nodes closer than d_min to another particle's face move to d_min."""
-        _check(lib().ifem_antistick(self.handle, dtype, _ptr(x), _ptr(anchor), float(d_min), _ptr(x_out),
-                                    _ptr(face_out), _stream(stream)))
+        px, pa, pxo, pf = self._pointers(dtype, (x, "x", "node", 3), (anchor, "anchor", "particle", 3),
+                                         (x_out, "x_out", "node", 3), (face_out, "face_out", "face", 1))
+        _check(lib().ifem_antistick(self.handle, dtype, px, pa, float(d_min), pxo, pf, _stream(stream)))

@@ -143,3 +143,37 @@ def test_bad_tuning_is_rejected(mixed):
     t.block_forces = 100
     code, msg = _create(d, boxes, tuning=C.byref(t))
     assert code == ifem.IFEM_ERR_INVALID_ARG and "block_forces" in msg
+
+
+def test_binding_checks_element_types_and_counts():
+    # the kernels trust the element type and size of every device array; the binding checks both
+    # against the plan before the call (a stand-in plan: the checks run before anything is launched)
+    torch = pytest.importorskip("torch")
+    plan = ifem.Plan.__new__(ifem.Plan)
+    plan.handle, plan.n_nodes, plan.n_particles, plan.total_cells = None, 10, 2, 64
+    f64, f32 = torch.float64, torch.float32
+    x64, x32 = torch.zeros((3, 10), dtype=f64), torch.zeros((3, 10), dtype=f32)
+    g64 = torch.zeros((3, 64), dtype=f64)
+    cases = [
+        (lambda: plan.spread(ifem.IFEM_F64, x32, None, x64, g64), "x: expected torch.float64"),
+        (lambda: plan.spread(ifem.IFEM_F32, x32, torch.zeros((2, 3), dtype=f64), x32, g64), "grid: expected torch.float32"),
+        (lambda: plan.spread(ifem.IFEM_F64, x64, None, x64, torch.zeros((3, 63), dtype=f64)), "grid: expected 192"),
+        (lambda: plan.interp(ifem.IFEM_F64, x64, None, g64, torch.zeros((3, 9), dtype=f64)), "v_out: expected 30"),
+        (lambda: plan.element_forces(ifem.IFEM_F32, x32, torch.zeros((2, 2), dtype=f64), x32), "anchor: expected 6"),
+        (lambda: plan.element_forces(ifem.IFEM_F64, x64, None, x64, torch.zeros((2, 5), dtype=f32)),
+         "red_out: expected torch.float64"),
+        (lambda: plan.volume_correct(ifem.IFEM_F64, x64, x64, lambda_out=torch.zeros(3, dtype=f64)),
+         "lambda_out: expected 2"),
+        (lambda: plan.advance(ifem.IFEM_F32, x32, x64, x32), "v: expected torch.float32"),
+        (lambda: plan.interp_cells(ifem.IFEM_F64, x64, None, torch.zeros((6, 64), dtype=f64),
+                                   torch.zeros((3, 10), dtype=f64)), "out: expected 60"),
+        (lambda: plan.fluid_forces(ifem.IFEM_F64, x64, x64, x64, C=torch.zeros((6, 9), dtype=f64)), "C: expected 60"),
+        (lambda: plan.antistick(ifem.IFEM_F64, x64, None, x64, 0.5, torch.zeros(10, dtype=torch.int32)),
+         "face_out: expected torch.int64"),
+    ]
+    for call, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            call()
+    # well-typed host tensors pass these checks and stop at the device check
+    with pytest.raises(ValueError, match="device tensor"):
+        plan.spread(ifem.IFEM_F64, x64, None, x64, g64)

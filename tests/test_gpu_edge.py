@@ -4,6 +4,7 @@ import sys
 import numpy as np
 import pytest
 
+import fixed_point
 import oracle
 from paper_1807_08219_amd import ifem
 from paper_1807_08219_amd.inputs import meshes, scenes
@@ -189,4 +190,158 @@ def test_nonfinite_force_poisons_its_home_tile_only(dtype):
     assert nan_g[1].sum() <= 2 * tx * (ty + 2) * (tz + 2)
     fin = ~nan_g
     assert rel(got[fin], Go[fin]) <= (1e-12 if dtype == ifem.IFEM_F64 else 1e-6)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [ifem.IFEM_F64, ifem.IFEM_F32])
+def test_nonfinite_position_in_transfers(dtype):
+    # A node whose position is not finite has no MLS weights (Sec. II.C): both transfers count it in
+    # counts[2]; the tiled spread turns the tiles that took its entry into NaN for every component (it
+    # is binned at lattice index 0 along the non-finite axis, so its home tile and the x-neighbour
+    # before it), the atomic spread its 27 stencil cells; interpolation gives it NaN.  Every other
+    # node's contribution and velocity is unchanged.
+    say(f"[gpu] non-finite position in spread and interpolation dtype {dtype}")
+    sc = scenes.small_mixed()
+    rng = np.random.default_rng(11)
+    Fin = rng.normal(size=(3, sc.n_nodes))
+    u = rng.normal(size=(3, sc.total_cells))
+    k = sc.n_nodes // 2
+    tdt = torch.float64 if dtype == ifem.IFEM_F64 else torch.float32
+    if dtype == ifem.IFEM_F32:
+        Fin = Fin.astype(np.float32).astype(np.float64)
+        u = u.astype(np.float32).astype(np.float64)
+        xb = sc.x32.copy()
+        xb[0, k] = np.nan
+        x, a = cu(xb, torch.float32), cu(sc.anchor, torch.float64)
+    else:
+        xb = sc.x64.copy()
+        xb[0, k] = np.nan
+        x, a = cu(xb, torch.float64), None
+    Fm = Fin.copy()
+    Fm[:, k] = 0.0
+    Go = oracle.spread(sc, Fm)  # every node but k, at the positions the library sees (x64 = anchor + x32)
+    vo = oracle.interp(sc, u)
+    plan = ifem.Plan(sc)
+    tx, ty, tz = plan.info()[3:6]
+    tol = 1e-12 if dtype == ifem.IFEM_F64 else 1e-6
+    for mode, most in ((ifem.IFEM_SPREAD_TILED, 2 * tx * (ty + 2) * (tz + 2)), (ifem.IFEM_SPREAD_ATOMIC, 27)):
+        plan.set(ifem.IFEM_OPT_SPREAD_MODE, mode)
+        G = torch.empty((3, sc.total_cells), dtype=tdt, device="cuda")
+        plan.spread(dtype, x, a, cu(Fin, tdt), G)
+        st = plan.status()
+        got = G.cpu().numpy().astype(np.float64)
+        nan_g = np.isnan(got)
+        say(f"    mode {mode}: status {st}, NaN cells per component {nan_g.sum(axis=1).tolist()}")
+        assert 3 <= st[2] <= 6 and st[0] == st[1] == st[3] == 0
+        assert all(0 < nan_g[d].sum() <= most for d in range(3))
+        fin = ~nan_g
+        assert rel(got[fin], Go[fin]) <= tol
+    plan.set(ifem.IFEM_OPT_SPREAD_MODE, ifem.IFEM_SPREAD_TILED)
+    v = torch.empty((3, sc.n_nodes), dtype=tdt, device="cuda")
+    plan.interp(dtype, x, a, cu(u, tdt), v)
+    st = plan.status()
+    got = v.cpu().numpy().astype(np.float64)
+    assert st[2] == 3
+    assert np.all(np.isnan(got[:, k]))
+    others = np.arange(sc.n_nodes) != k
+    assert np.all(np.isfinite(got[:, others]))
+    assert rel(got[:, others], vo[:, others]) <= tol
+    plan.close()
+
+
+@pytest.mark.parametrize("scale", [1e39, 1e-46, 1e300, 1e-300])
+def test_fp64_spread_of_forces_beyond_the_float32_range(scale):
+    # the tiled spread's fixed-point scale follows a power-of-two bound of each list's largest |F|, so
+    # float64 forces far outside float32's range are held like any others
+    say(f"[gpu] float64 spread of forces of magnitude {scale:g}")
+    sc = scenes.small_mixed()
+    rng = np.random.default_rng(12)
+    Fin = rng.normal(size=(3, sc.n_nodes)) * scale
+    Go = oracle.spread(sc, Fin)
+    plan = ifem.Plan(sc)
+    x = cu(sc.x64, torch.float64)
+    out = {}
+    for mode in (ifem.IFEM_SPREAD_TILED, ifem.IFEM_SPREAD_ATOMIC):
+        plan.set(ifem.IFEM_OPT_SPREAD_MODE, mode)
+        G = torch.empty((3, sc.total_cells), dtype=torch.float64, device="cuda")
+        plan.spread(ifem.IFEM_F64, x, None, cu(Fin, torch.float64), G)
+        out[mode] = G.cpu().numpy()
+        assert np.all(np.isfinite(out[mode]))
+        e = rel(out[mode] / scale, Go / scale)  # scaled: the norm of values near 1e300 would overflow
+        say(f"    mode {mode}: rel err {e:.3e}")
+        assert e <= 1e-12
+    assert plan.status() == [0, 0, 0, 0, 0]
+    plan.close()
+
+
+@pytest.mark.parametrize("what", ["collapsed_triangle", "flat_tetrahedron", "inverted_tetrahedron"])
+def test_degenerate_reference_is_rejected_at_plan_creation(what):
+    # a reference element with no area or volume has no shape-function gradients (Sec. II.B): the plan
+    # refuses the mesh, with IFEM_ERR_DEGENERATE, before any step runs
+    say(f"[gpu] degenerate reference element: {what}")
+    box = Box((12, 12, 12), 0.5, (0.0, 0.0, 0.0))
+    if what == "collapsed_triangle":
+        X, tris = meshes.icosphere(3)
+        X = X + 3.0
+        X[tris[7, 2]] = X[tris[7, 0]]  # two corners of triangle 7 coincide
+        parts = [Particle(X=X, x=X.copy(), tri=tris)]
+    else:
+        Xs, tets = meshes.ellipsoid_tets(2, 2, 2, (1.0, 0.9, 0.8))
+        Xs = Xs + 3.0
+        tets = tets.copy()
+        if what == "flat_tetrahedron":
+            a, b, c, d = tets[3]
+            Xs[d] = Xs[a]  # two corners coincide: exactly zero volume (a corner moved onto the plane of the
+            # other three would leave a rounding-sized volume of either sign)
+        else:
+            tets[3, [0, 1]] = tets[3, [1, 0]]  # negative reference volume
+        parts = [Particle(X=Xs, x=Xs.copy(), tet=tets, law=scenes.LAW_TET_NEOHOOKE, mu=1.0, mu2=50.0)]
+    sc = assemble(what, [box], parts)
+    with pytest.raises(ifem.IfemError) as e:
+        ifem.Plan(sc)
+    assert e.value.code == ifem.IFEM_ERR_DEGENERATE, str(e.value)
+    say(f"    {e.value}")
+
+
+def test_fp64_spread_of_one_long_tile_list():
+    # 40,000 points in one spread tile: the list's length sets the float64 remainder word's scale
+    # (2^(30 - 16) here), which must keep every cell's remainder sum in range; grid values against the
+    # oracle cell by cell, to 1e-12 of the magnitude that produces them plus the stated fixed-point
+    # quantum (tests/fixed_point.py), and normwise to 1e-12
+    say("[gpu] float64 spread of one 40,000-entry tile list")
+    rng = np.random.default_rng(13)
+    box = Box((32, 32, 32), 1.0, (0.0, 0.0, 0.0))
+    pts = rng.uniform([1.5, 1.5, 1.5], [30.5, 14.5, 6.5], size=(40000, 3))
+    # ten point particles of 4000 nodes (one particle's nodes must fit a force workgroup)
+    sc = assemble("dense_tile", [box], [Particle(X=pts[i:i + 4000].copy(), x=pts[i:i + 4000].copy())
+                                        for i in range(0, len(pts), 4000)])
+    sc.x64 = pts.T.copy()
+    plan = ifem.Plan(sc, tuning={"tile": (32, 16, 8), "block_forces": 512, "block_points": 256})
+    Fin = rng.normal(size=(3, sc.n_nodes))
+    Go = oracle.spread(sc, Fin)
+    G = torch.empty((3, sc.total_cells), dtype=torch.float64, device="cuda")
+    plan.spread(ifem.IFEM_F64, cu(sc.x64, torch.float64), None, cu(Fin, torch.float64), G)
+    got = G.cpu().numpy()
+    assert plan.status() == [0, 0, 0, 0, 0]
+    # sum_k |phi||F_k| per cell from the oracle's weights
+    mag = np.zeros((3, sc.total_cells))
+    nJ = np.zeros((3, sc.total_cells))
+    n = np.array(box.n)
+    m = np.arange(27)
+    for k in range(sc.n_nodes):
+        for d in range(3):
+            base, phi = oracle.mls(sc.x64[:, k], box, d)
+            ix = (base[0] + m % 3 - 1) % n[0]
+            iy = (base[1] + (m // 3) % 3 - 1) % n[1]
+            iz = (base[2] + m // 9 - 1) % n[2]
+            cells = (iz * n[1] + iy) * n[0] + ix
+            np.add.at(mag[d], cells, np.abs(phi) * abs(Fin[d, k]))
+            np.add.at(nJ[d], cells, 1.0)
+    err = np.abs(got - Go)
+    # the list holds every node: 2^15 <= cnt < 2^16 leaves the float64 remainder 14 bits
+    U = fixed_point.unit(np.abs(Fin).max(), sc.n_nodes, fp64=True)
+    say(f"    max |err| / sum|phi||F| = {(err / (mag + 1e-300)).max():.2e}, max |err| / (n_J U) = "
+        f"{(err / (nJ * U + 1e-300)).max():.2f}, normwise {rel(got, Go):.2e}")
+    assert rel(got, Go) <= 1e-12
+    assert np.all(err <= 1e-12 * mag + nJ * U)
     plan.close()

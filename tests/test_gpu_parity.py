@@ -132,7 +132,8 @@ def test_forces_and_reductions_fp32(runs, name):
     ro = oracle.reduce(r.sc)
     assert rel(red[:, 0], ro[:, 0]) <= 1e-12
     assert rel(red[:, 2:], ro[:, 2:]) <= 1e-12
-    r.plan.status()
+    st = r.plan.status()
+    assert st[0] == cnt[0] and st[1] == cnt[1] == 0
 
 
 @pytest.mark.parametrize("name", list(SCENES))
