@@ -689,7 +689,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_flag, (size_t)3 * n_tiles));
   uint32_t* d_fmax;
   HIP_TRY(mem.alloc(&d_fmax, (size_t)3 * n_tiles));
-  HIP_TRY(mem.alloc(&d_halo, (size_t)3 * n_tiles * region_cells));  // sized for float64
+  const int halo_cells = (tn.tile[0] + 1) * (2 * (tn.tile[1] + tn.tile[2]) + 4);
+  HIP_TRY(mem.alloc(&d_halo, (size_t)3 * n_tiles * halo_cells));  // sized for float64
   ContactBoxDev* d_cboxes;
   int32_t *d_bface, *d_ccount, *d_coff, *d_ccur, *d_cown;
   ContactNode* d_crec;
@@ -721,7 +722,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_cwork, (size_t)work_cap));
   HIP_TRY(mem.alloc(&d_cwcount, 256 + 1));
   HIP_TRY(mem.alloc(&d_cslow, (size_t)m.n_tris + n_bfaces));
-  plan->workspace_bytes = (int64_t)(12 * (int64_t)n_tiles + 1 + list_cap) * 4 + (int64_t)3 * n_tiles * region_cells * 8;
+  plan->workspace_bytes = (int64_t)(15 * (int64_t)n_tiles + 1 + list_cap) * 4 + (int64_t)3 * n_tiles * halo_cells * 8;
 
   P.tri_src = d_tri_src;
   P.tri_global = d_tri_glob;
@@ -767,6 +768,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ta.tile_fmax = d_fmax;
   ta.halo = d_halo;
   ta.region_cells = region_cells;
+  ta.halo_cells = halo_cells;
   ta.status = d_status;
   ta.list_cap = list_cap;
   ta.total_cells = total_cells;
@@ -943,7 +945,7 @@ ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const doub
   hipStream_t st = (hipStream_t)stream;
   if (plan->spread_mode == IFEM_SPREAD_ATOMIC)
     return launched(launch_spread_atomic(P, dtype, x, anchor, F, grid, plan->tune.block_points, st));
-  return launched(launch_spread_tiled(P, dtype, x, anchor, F, grid, plan->tune.block_points, st));
+  return launched(launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st));
 }
 
 ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* grid_u,

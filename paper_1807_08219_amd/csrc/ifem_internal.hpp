@@ -45,7 +45,7 @@ struct TransferArgs {
   int32_t* bin_list;              // [list_cap] node ids, grouped by (component, tile)
   int32_t* tile_flag;             // [3 n_tiles] 1 if the tile wrote a halo shell this call
   uint32_t* tile_fmax;            // [3 n_tiles] bound on |F| of each list, float32 bits (atomic max)
-  void* halo;                     // [3 n_tiles][region_cells] y/z halo rows (float or double)
+  void* halo;                     // [3 n_tiles][halo_cells] y/z halo shell rows (float or double)
   unsigned long long* status;
   int64_t list_cap;
   int64_t total_cells;
@@ -53,7 +53,16 @@ struct TransferArgs {
   int32_t tile[3];        // cells per tile and axis (powers of two)
   int32_t tile_shift[3];  // log2 of tile
   int32_t region_cells;   // (tile_x + 1)(tile_y + 2)(tile_z + 2): rows of tile_x cells and one pad cell
+  int32_t halo_cells;     // (tile_x + 1)(2 (tile_y + tile_z) + 4): the region's y/z shell rows
 };
+
+// Index of region row (iy, iz) among the y/z shell rows of a region with ry x rz rows: the two z
+// faces (every y), then the two y faces without the z-face rows.  (iy, iz) must be a shell row.
+__device__ __forceinline__ int halo_row(int iy, int iz, int ry, int rz) {
+  if (iz == 0) return iy;
+  if (iz == rz - 1) return ry + iy;
+  return 2 * ry + (iy == 0 ? 0 : rz - 2) + (iz - 1);
+}
 
 // One periodic box's grid of contact cells (node-face anti-sticking).
 struct ContactBoxDev {
@@ -189,8 +198,9 @@ hipError_t launch_fluid(const PlanDev& P, int dtype, const void* x, const void* 
 hipError_t prepare_transfer_kernels(const PlanDev& P);
 hipError_t launch_spread_atomic(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* F,
                                 void* grid, int block, hipStream_t st);
-hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* F,
-                               void* grid, int block, hipStream_t st);
+// `a` is P.targs, or a copy whose workspace pointers lead elsewhere (the allocation-free entry point)
+hipError_t launch_spread_tiled(const PlanDev& P, const TransferArgs& a, int dtype, const void* x, const double* anchor,
+                               const void* F, void* grid, hipStream_t st);
 hipError_t launch_interp(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* grid,
                          void* v, int block, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);

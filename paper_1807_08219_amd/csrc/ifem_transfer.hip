@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   const int32_t* list = a.bin_list + a.tile_off[L];
   const int cnt = a.tile_count[L];
   T* g = grid + d * a.total_cells + B.cell_off;
-  T* halo = reinterpret_cast<T*>(a.halo) + (int64_t)L * a.region_cells;
+  T* halo = reinterpret_cast<T*>(a.halo) + (int64_t)L * a.halo_cells;
   const int64_t NN = a.n_nodes;
   const T* Fd = F + d * NN;
   if (cnt == 0) {  // nothing lands in this tile (uniform over the workgroup): zeros, no halo, no LDS
@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     if ((unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2])
       g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix)] = v;
     else if (halo_on)
-      halo[r] = v;
+      halo[halo_row(iy, iz, ry, rz) * rx + ix] = v;
   }
   if (tid == 0) a.tile_flag[L] = halo_on ? 1 : 0;
 }
@@ -616,10 +616,12 @@ __global__ void __launch_bounds__(kMergeThreads) k_spread_merge(const TransferAr
         if ((oy == -1 && iy != 0) || (oy == 1 && iy != ey - 1)) continue;
         const int nbi = (oz + 1) * 3 + (oy + 1);
         if (!nbflag[nbi]) continue;
-        // region coordinates of this cell in the neighbour: -1 -> its last+1, +1 -> 0, 0 -> i + 1
+        // region coordinates of this cell in the neighbour: -1 -> its last+1, +1 -> 0, 0 -> i + 1; a
+        // shell row of the neighbour's region
         const int ry = oy == -1 ? nbe[nbi][0] + 1 : (oy == 1 ? 0 : iy + 1);
         const int rz = oz == -1 ? nbe[nbi][1] + 1 : (oz == 1 ? 0 : iz + 1);
-        v += halo[(int64_t)nbL[nbi] * a.region_cells + (rz * (nbe[nbi][0] + 2) + ry) * (exx + 1) + ix];
+        const int hr = halo_row(ry, rz, nbe[nbi][0] + 2, nbe[nbi][1] + 2);
+        v += halo[(int64_t)nbL[nbi] * a.halo_cells + hr * (exx + 1) + ix];
       }
     }
     g[cell] = v;
@@ -676,10 +678,8 @@ hipError_t launch_spread_atomic(const PlanDev& P, int dtype, const void* x, cons
   return hipGetLastError();
 }
 
-hipError_t launch_spread_tiled(const PlanDev& P, int dtype, const void* x, const double* anchor, const void* F,
-                               void* grid, int block, hipStream_t st) {
-  (void)block;
-  const TransferArgs& a = P.targs;
+hipError_t launch_spread_tiled(const PlanDev& P, const TransferArgs& a, int dtype, const void* x, const double* anchor,
+                               const void* F, void* grid, hipStream_t st) {
   const int nl = 3 * a.n_tiles;
   P.timer->begin(K_FILL, st);
   hipError_t e = fill(a.tile_count, (int64_t)nl, 0, st);
