@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -893,7 +894,36 @@ ifem_status ifem_plan_info(ifem_plan plan, int64_t info[10]) {
 
 }  // extern "C"
 
+// Workspace of the allocation-free spread (ifem_spread_noalloc): a file-scope device array, one copy
+// per GPU the library runs on, held until the process ends.  Host code never passes `scratch` itself
+// (on the host it is a stand-in, not a device address): static_scratch() looks up each device's
+// address once, with that device current, and the kernels receive that pointer.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr size_t kStaticAlign = 256;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the first call per device).
+ifem_status static_scratch(unsigned char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(IFEM_ERR_DEVICE, "no current device for the static scratch");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(IFEM_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return IFEM_OK;
+}
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   if (!a || !b || na == 0 || nb == 0) return false;
@@ -946,6 +976,45 @@ ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const doub
   if (plan->spread_mode == IFEM_SPREAD_ATOMIC)
     return launched(launch_spread_atomic(P, dtype, x, anchor, F, grid, plan->tune.block_points, st));
   return launched(launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st));
+}
+
+ifem_status ifem_spread_noalloc(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F,
+                                void* grid, void* stream) {
+  ifem_status s = check_common(plan, dtype, x, anchor);
+  if (s != IFEM_OK) return s;
+  const PlanDev& P = plan->P;
+  const size_t es = dtype == IFEM_F32 ? 4 : 8, nb = (size_t)3 * P.n_nodes * es, gb = (size_t)3 * P.total_cells * es;
+  if (!grid || (P.n_nodes > 0 && !F)) return fail(IFEM_ERR_INVALID_ARG, "F or grid is NULL");
+  if (overlaps(grid, gb, x, nb) || overlaps(grid, gb, F, nb) || overlaps(grid, gb, anchor, (size_t)3 * P.n_particles * 8))
+    return fail(IFEM_ERR_INVALID_ARG, "grid aliases an input");
+  // the plan's spread workspace, laid out in the device's static array instead
+  const TransferArgs& t = P.targs;
+  const int64_t nl = 3 * (int64_t)t.n_tiles;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + kStaticAlign - 1) / kStaticAlign * kStaticAlign;
+    return at;
+  };
+  const size_t o_cnt = take((size_t)nl * 4), o_off = take((size_t)(nl + 1) * 4), o_cur = take((size_t)nl * 4),
+               o_flag = take((size_t)nl * 4), o_fmax = take((size_t)nl * 4),
+               o_list = take((size_t)std::max<int64_t>(t.list_cap, 1) * 4),
+               o_halo = take((size_t)nl * t.halo_cells * es);
+  if (off > kStaticScratchBytes)
+    return fail(IFEM_ERR_UNSUPPORTED, "the spread workspace of this plan (%zu bytes in this precision) exceeds the "
+                                      "static scratch of %zu bytes", off, kStaticScratchBytes);
+  unsigned char* base = nullptr;
+  s = static_scratch(&base);
+  if (s != IFEM_OK) return s;
+  TransferArgs a = t;
+  a.tile_count = reinterpret_cast<int32_t*>(base + o_cnt);
+  a.tile_off = reinterpret_cast<int32_t*>(base + o_off);
+  a.tile_cursor = reinterpret_cast<int32_t*>(base + o_cur);
+  a.tile_flag = reinterpret_cast<int32_t*>(base + o_flag);
+  a.tile_fmax = reinterpret_cast<uint32_t*>(base + o_fmax);
+  a.bin_list = reinterpret_cast<int32_t*>(base + o_list);
+  a.halo = base + o_halo;
+  return launched(launch_spread_tiled(P, a, dtype, x, anchor, F, grid, (hipStream_t)stream));
 }
 
 ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* grid_u,
