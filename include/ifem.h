@@ -170,7 +170,7 @@ typedef struct {
  * {tile 32 x 16 x 8, block_forces 512, block_points 256}, the fastest measured
  * on dense red-cell suspensions; with fewer than one node per 20 grid cells
  * (sparse boxes of mixed particles) the default tile is 16 x 16 x 16.  The spread region
- * of a tile, (tile_x + 1)(tile_y + 2)(tile_z + 2) cells, must not exceed 13568
+ * of a tile, (tile_x + 5)(tile_y + 2)(tile_z + 2) cells, must not exceed 13568
  * (12 bytes of LDS per cell in float64). */
 typedef struct {
   int32_t tile[3];      /* spread tile, cells per axis (powers of two, 4..64) */

@@ -514,10 +514,10 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   for (int a = 0; a < 3; ++a)
     if (tn.tile[a] < 4 || tn.tile[a] > 64 || (tn.tile[a] & (tn.tile[a] - 1)))
       return fail(IFEM_ERR_INVALID_ARG, "tile sizes must be powers of two in [4, 64]");
-  // spread region: the tile plus a one-cell halo along y and z and one pad cell per row, 12 bytes per
-  // cell in float64 (a 64-bit word and a 32-bit remainder word)
-  if ((int64_t)(tn.tile[0] + 1) * (tn.tile[1] + 2) * (tn.tile[2] + 2) * 12 + 1024 > (int64_t)kLdsLimit)
-    return fail(IFEM_ERR_INVALID_ARG, "tile too large for LDS: (tile_x + 1)(tile_y + 2)(tile_z + 2) must be <= 13568");
+  // spread region: the tile plus a one-cell halo along y and z and rows padded by two cells on each
+  // side (odd pitch), 12 bytes per cell in float64 (a 64-bit word and a 32-bit remainder word)
+  if ((int64_t)(tn.tile[0] + 5) * (tn.tile[1] + 2) * (tn.tile[2] + 2) * 12 + 1024 > (int64_t)kLdsLimit)
+    return fail(IFEM_ERR_INVALID_ARG, "tile too large for LDS: (tile_x + 5)(tile_y + 2)(tile_z + 2) must be <= 13568");
   if (tn.block_forces < 64 || tn.block_forces > 512 || (tn.block_forces & (tn.block_forces - 1)))
     return fail(IFEM_ERR_INVALID_ARG, "block_forces must be a power of two in [64, 512]");
   if (tn.block_points != 64 && tn.block_points != 128 && tn.block_points != 256)
@@ -686,7 +686,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_off, (size_t)3 * n_tiles + 1));
   HIP_TRY(mem.alloc(&d_cur, (size_t)3 * n_tiles));
   HIP_TRY(mem.alloc(&d_list, (size_t)std::max<int64_t>(list_cap, 1)));
-  const int region_cells = (tn.tile[0] + 1) * (tn.tile[1] + 2) * (tn.tile[2] + 2);
+  const int region_cells = (tn.tile[0] + 5) * (tn.tile[1] + 2) * (tn.tile[2] + 2);
   HIP_TRY(mem.alloc(&d_flag, (size_t)3 * n_tiles));
   uint32_t* d_fmax;
   HIP_TRY(mem.alloc(&d_fmax, (size_t)3 * n_tiles));

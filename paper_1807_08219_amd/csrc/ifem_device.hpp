@@ -153,76 +153,72 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
 // (each component in [-1/2, 1/2]); stencil node m in {-1,0,1}^3 sits at
 // xi_m = m - tau from the point.  W_m = W(|xi_m| / sqrt 3) with the cubic
 // spline W(r) = 2/3 - 4 r^2 + 4 r^3 (r <= 1/2), 4/3 (1 - r)^3 (1/2 < r <= 1).
-// The weighted normal equations A c = e_1, A = sum_m W_m p_m p_m^T,
-// p_m = (1, xi_m), give phi_m = W_m (c0 + c1 xi_mx + c2 xi_my + c3 xi_mz).
+//
+// The weighted least-squares fit uses the linear basis p = (1, m) in the
+// stencil's integer offsets: an affine change of the linear basis leaves phi
+// unchanged, and in this basis every moment of the weights is a sum or a
+// difference of weights (m_i, m_i m_j in {-1, 0, 1}), no products.  With
+// A = sum_m W_m p_m p_m^T and the point at p = (1, tau), A c = (1, tau) gives
+// phi_m = W_m (c0 + c1 m_x + c2 m_y + c3 m_z).
 // phi does not change when every W_m is scaled by one factor (c scales by its
 // inverse), so the weights are taken as 3/4 W: with R = |xi| and
-// s0 = 1 - R / sqrt 3, that is 1/2 - R^2 s0 (R^2 <= 3/4) and max(s0, 0)^3.
-// Output: the scaled W[27] (m_x fastest), c[4]; returns false if A is singular.
+// s0 = 1 - R / sqrt 3 the inner piece is 1/2 - R^2 s0 and the outer one s0^3,
+// clamped at 0 past the support.  The two pieces agree to second order at
+// R^2 = 3/4 (their difference is a positive multiple of (R - sqrt(3)/2)^3),
+// so the right piece is always the smaller one.
+// Output: the scaled W[27] (m_x fastest), c[4]; returns false if A is singular
+// (or tau not finite).
 template <typename T>
 __device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
   const T kInvSqrt3 = T(0.57735026918962576451);
-  T ax[3], ay[3], az[3], qx[3], qy[3], qz[3];
+  T qx[3], qy[3], qz[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    ax[i] = T(i - 1) - tau[0];
-    ay[i] = T(i - 1) - tau[1];
-    az[i] = T(i - 1) - tau[2];
-    qx[i] = ax[i] * ax[i];
-    qy[i] = ay[i] * ay[i];
-    qz[i] = az[i] * az[i];
+    const T ax = T(i - 1) - tau[0], ay = T(i - 1) - tau[1], az = T(i - 1) - tau[2];
+    qx[i] = ax * ax;
+    qy[i] = ay * ay;
+    qz[i] = az * az;
   }
-  // moments of the weights: along x within a row, rows into a plane, planes into the total
-  T S0 = 0, Sx = 0, Sy = 0, Sz = 0, Sxx = 0, Syy = 0, Szz = 0, Sxy = 0, Sxz = 0, Syz = 0;
+  // plane sums (per m_z): sum w, sum w m_x, sum w m_x^2, sum w m_y, sum w m_y^2, sum w m_x m_y
+  T PS[3], PD[3], PE[3], PY[3], PYY[3], PXY[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    T P0 = 0, Px = 0, Py = 0, Pxx = 0, Pyy = 0, Pxy = 0;
+    T RS[3], RD[3], RE[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const T qyz = qy[j] + qz[k];
-      T w0 = 0, w1 = 0, w2 = 0;
+      T w[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         // |tau| <= 1/2 bounds q by the number of off-centre offsets: the centre node always takes the
         // inner piece (q <= 3/4), a corner the outer one (q >= 3/4), and only nodes with two or three
-        // off-centre offsets can leave the support (q > 3); these are compile-time facts after unrolling
+        // off-centre offsets can leave the support (q > 3); compile-time facts after unrolling
         const int noff = (i != 1) + (j != 1) + (k != 1);
         const T q = qx[i] + qyz;
         const T s0 = T(1) - fsqrt(q) * kInvSqrt3;
         const T inner = T(0.5) - q * s0;
-        T w;
-        if (noff == 0) {
-          w = inner;
-        } else {
-          const T sc = noff >= 2 ? fmax(s0, T(0)) : s0;
-          const T outer = (sc * sc) * sc;
-          w = noff == 3 ? outer : (q <= T(0.75) ? inner : outer);
-        }
-        W[(k * 3 + j) * 3 + i] = w;
-        w0 += w;
-        w1 += w * ax[i];
-        w2 += w * qx[i];
+        const T sc = noff >= 2 ? fmax(s0, T(0)) : s0;
+        const T outer = (sc * sc) * sc;
+        w[i] = noff == 0 ? inner : (noff == 3 ? outer : fmin(inner, outer));
+        W[(k * 3 + j) * 3 + i] = w[i];
       }
-      P0 += w0;
-      Px += w1;
-      Pxx += w2;
-      Py += w0 * ay[j];
-      Pyy += w0 * qy[j];
-      Pxy += w1 * ay[j];
+      RE[j] = w[0] + w[2];
+      RS[j] = RE[j] + w[1];
+      RD[j] = w[2] - w[0];
     }
-    S0 += P0;
-    Sx += Px;
-    Sxx += Pxx;
-    Sy += Py;
-    Syy += Pyy;
-    Sxy += Pxy;
-    Sz += P0 * az[k];
-    Szz += P0 * qz[k];
-    Sxz += Px * az[k];
-    Syz += Py * az[k];
+    PS[k] = RS[0] + RS[1] + RS[2];
+    PD[k] = RD[0] + RD[1] + RD[2];
+    PE[k] = RE[0] + RE[1] + RE[2];
+    PY[k] = RS[2] - RS[0];
+    PYY[k] = RS[0] + RS[2];
+    PXY[k] = RD[2] - RD[0];
   }
-  // Schur complement on the 3x3 second-moment block Q: y = Q^-1 s,
-  // c0 = 1 / (S0 - s.y), (c1, c2, c3) = -c0 y.
+  const T S0 = PS[0] + PS[1] + PS[2];
+  const T Sx = PD[0] + PD[1] + PD[2], Sy = PY[0] + PY[1] + PY[2], Sz = PS[2] - PS[0];
+  const T Sxx = PE[0] + PE[1] + PE[2], Syy = PYY[0] + PYY[1] + PYY[2], Szz = PS[0] + PS[2];
+  const T Sxy = PXY[0] + PXY[1] + PXY[2], Sxz = PD[2] - PD[0], Syz = PY[2] - PY[0];
+  // Schur complement on the 3x3 second-moment block Q with s = (Sx, Sy, Sz):
+  // y = Q^-1 s, z = Q^-1 tau, c0 = (1 - s.z) / (S0 - s.y), (c1, c2, c3) = z - c0 y.
   const T a00 = Syy * Szz - Syz * Syz;
   const T a01 = Sxz * Syz - Sxy * Szz;
   const T a02 = Sxy * Syz - Sxz * Syy;
@@ -234,14 +230,33 @@ __device__ __forceinline__ bool mls_weights(const T tau[3], T W[27], T c[4]) {
   const T y0 = (a00 * Sx + a01 * Sy + a02 * Sz) * inv;
   const T y1 = (a01 * Sx + a11 * Sy + a12 * Sz) * inv;
   const T y2 = (a02 * Sx + a12 * Sy + a22 * Sz) * inv;
+  const T z0 = (a00 * tau[0] + a01 * tau[1] + a02 * tau[2]) * inv;
+  const T z1 = (a01 * tau[0] + a11 * tau[1] + a12 * tau[2]) * inv;
+  const T z2 = (a02 * tau[0] + a12 * tau[1] + a22 * tau[2]) * inv;
   const T schur = S0 - (Sx * y0 + Sy * y1 + Sz * y2);
   const bool ok = detQ > T(0) && schur > T(0);
-  const T c0 = ok ? frcp(schur) : T(0);
+  const T c0 = ok ? (T(1) - (Sx * z0 + Sy * z1 + Sz * z2)) * frcp(schur) : T(0);
   c[0] = c0;
-  c[1] = ok ? -c0 * y0 : T(0);
-  c[2] = ok ? -c0 * y1 : T(0);
-  c[3] = ok ? -c0 * y2 : T(0);
+  c[1] = ok ? z0 - c0 * y0 : T(0);
+  c[2] = ok ? z1 - c0 * y1 : T(0);
+  c[3] = ok ? z2 - c0 * y2 : T(0);
   return ok;
+}
+
+// phi_m = W_m (c0 + c1 m_x + c2 m_y + c3 m_z) for the 27 stencil nodes (m_x fastest).
+template <typename T>
+__device__ __forceinline__ void mls_phi(const T W[27], const T c[4], T phi[27]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T vz = k == 0 ? c[0] - c[3] : (k == 1 ? c[0] : c[0] + c[3]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T vyz = j == 0 ? vz - c[2] : (j == 1 ? vz : vz + c[2]);
+      phi[(k * 3 + j) * 3 + 0] = W[(k * 3 + j) * 3 + 0] * (vyz - c[1]);
+      phi[(k * 3 + j) * 3 + 1] = W[(k * 3 + j) * 3 + 1] * vyz;
+      phi[(k * 3 + j) * 3 + 2] = W[(k * 3 + j) * 3 + 2] * (vyz + c[1]);
+    }
+  }
 }
 
 // Round a float64 value (|v| < 2^51) to the nearest integer (ties to even)

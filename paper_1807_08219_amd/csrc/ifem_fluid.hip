@@ -53,17 +53,7 @@ __global__ void __launch_bounds__(256) k_interp_cells(const TransferArgs a, cons
   T W[27], c[4];
   const bool ok = mls_weights<T>(tau, W, c);
   T phi[27];
-#pragma unroll
-  for (int mz = 0; mz < 3; ++mz) {
-    const T cz = c[0] + c[3] * (T(mz - 1) - tau[2]);
-#pragma unroll
-    for (int my = 0; my < 3; ++my) {
-      const T cyz = cz + c[2] * (T(my - 1) - tau[1]);
-#pragma unroll
-      for (int mx = 0; mx < 3; ++mx)
-        phi[(mz * 3 + my) * 3 + mx] = W[(mz * 3 + my) * 3 + mx] * (cyz + c[1] * (T(mx - 1) - tau[0]));
-    }
-  }
+  mls_phi<T>(W, c, phi);
   const bool seam = base[0] == 0 || base[0] == B.n[0] - 1;
   const int32_t x0 = seam ? 0 : base[0] - 1;
   int32_t ix[3], rows[9];

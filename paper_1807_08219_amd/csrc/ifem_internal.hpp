@@ -52,7 +52,8 @@ struct TransferArgs {
   int32_t n_nodes, n_boxes, n_tiles;
   int32_t tile[3];        // cells per tile and axis (powers of two)
   int32_t tile_shift[3];  // log2 of tile
-  int32_t region_cells;   // (tile_x + 1)(tile_y + 2)(tile_z + 2): rows of tile_x cells and one pad cell
+  int32_t region_cells;   // (tile_x + 5)(tile_y + 2)(tile_z + 2): rows of tile_x cells, two pad cells on each
+                          // side, one more for an odd pitch
   int32_t halo_cells;     // (tile_x + 1)(2 (tile_y + tile_z) + 4): the region's y/z shell rows
 };
 

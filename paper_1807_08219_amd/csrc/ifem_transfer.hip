@@ -95,37 +95,43 @@ __global__ void __launch_bounds__(256) k_interp(const TransferArgs a, const T* _
     T W[27], c[4];
     if (!mls_weights<T>(tau, W, c)) ++bad;
     const T* g = grid + d * a.total_cells + B.cell_off;  // cells of one box fit 32-bit offsets
-    const bool seam = base[0] == 0 || base[0] == B.n[0] - 1;
-    const int32_t x0 = seam ? 0 : base[0] - 1;
-    int32_t ix[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) ix[m] = wrap1(base[0] + m - 1, B.n[0]);
     const int32_t nxy = B.n[0] * B.n[1];
+    int32_t ro[9];  // in-box offsets of the stencil's rows, first column
+#pragma unroll
+    for (int mz = 0; mz < 3; ++mz)
+#pragma unroll
+      for (int my = 0; my < 3; ++my)
+        ro[mz * 3 + my] = wrap1(base[2] + mz - 1, B.n[2]) * nxy + wrap1(base[1] + my - 1, B.n[1]) * B.n[0];
+    T u[27];
+    if (__builtin_expect(base[0] != 0 && base[0] != B.n[0] - 1, 1)) {  // one 12- or 24-byte load per row
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        const Row3<T> r3 = *reinterpret_cast<const Row3<T>*>(g + (uint32_t)(ro[r] + base[0] - 1));
+        u[3 * r] = r3.v[0];
+        u[3 * r + 1] = r3.v[1];
+        u[3 * r + 2] = r3.v[2];
+      }
+    } else {  // the stencil crosses the periodic seam along x
+      const int32_t ix0 = wrap1(base[0] - 1, B.n[0]), ix2 = wrap1(base[0] + 1, B.n[0]);
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        u[3 * r] = g[(uint32_t)(ro[r] + ix0)];
+        u[3 * r + 1] = g[(uint32_t)(ro[r] + base[0])];
+        u[3 * r + 2] = g[(uint32_t)(ro[r] + ix2)];
+      }
+    }
     T s = 0;
 #pragma unroll
     for (int mz = 0; mz < 3; ++mz) {
-      const int32_t zo = wrap1(base[2] + mz - 1, B.n[2]) * nxy;
-      const T cz = c[0] + c[3] * (T(mz - 1) - tau[2]);
+      const T vz = mz == 0 ? c[0] - c[3] : (mz == 1 ? c[0] : c[0] + c[3]);
 #pragma unroll
       for (int my = 0; my < 3; ++my) {
-        const T* row = g + (uint32_t)(zo + wrap1(base[1] + my - 1, B.n[1]) * B.n[0]);
-        T u[3];
-        if (!seam) {
-          const Row3<T> r3 = *reinterpret_cast<const Row3<T>*>(row + x0);
-          u[0] = r3.v[0];
-          u[1] = r3.v[1];
-          u[2] = r3.v[2];
-        } else {
-          u[0] = row[ix[0]];
-          u[1] = row[ix[1]];
-          u[2] = row[ix[2]];
-        }
-        const T cyz = cz + c[2] * (T(my - 1) - tau[1]);
-#pragma unroll
-        for (int mx = 0; mx < 3; ++mx) {
-          const T phi = W[(mz * 3 + my) * 3 + mx] * (cyz + c[1] * (T(mx - 1) - tau[0]));
-          s += phi * u[mx];
-        }
+        const T* uu = u + (mz * 3 + my) * 3;
+        const T vyz = my == 0 ? vz - c[2] : (my == 1 ? vz : vz + c[2]);
+        const T* w = W + (mz * 3 + my) * 3;
+        s += w[0] * (vyz - c[1]) * uu[0];
+        s += w[1] * vyz * uu[1];
+        s += w[2] * (vyz + c[1]) * uu[2];
       }
     }
     v[d * (int64_t)a.n_nodes + k] = s;
@@ -155,19 +161,17 @@ __global__ void __launch_bounds__(256) k_spread_atomic(const TransferArgs a, con
     if (!mls_weights<T>(tau, W, c)) ++bad;
     const T f = F[d * (int64_t)a.n_nodes + k];
     T* g = grid + d * a.total_cells + B.cell_off;
+    T phi[27];
+    mls_phi<T>(W, c, phi);
 #pragma unroll
     for (int mz = 0; mz < 3; ++mz) {
       const int64_t zo = (int64_t)wrap1(base[2] + mz - 1, B.n[2]) * B.n[1] * B.n[0];
-      const T cz = c[0] + c[3] * (T(mz - 1) - tau[2]);
 #pragma unroll
       for (int my = 0; my < 3; ++my) {
         const int64_t yo = zo + (int64_t)wrap1(base[1] + my - 1, B.n[1]) * B.n[0];
-        const T cyz = cz + c[2] * (T(my - 1) - tau[1]);
 #pragma unroll
-        for (int mx = 0; mx < 3; ++mx) {
-          const T phi = W[(mz * 3 + my) * 3 + mx] * (cyz + c[1] * (T(mx - 1) - tau[0]));
-          atomicAdd(g + yo + wrap1(base[0] + mx - 1, B.n[0]), phi * f);
-        }
+        for (int mx = 0; mx < 3; ++mx)
+          atomicAdd(g + yo + wrap1(base[0] + mx - 1, B.n[0]), phi[(mz * 3 + my) * 3 + mx] * f);
       }
     }
   }
@@ -379,9 +383,14 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   const int c0[3] = {tx * a.tile[0], ty * a.tile[1], tz * a.tile[2]};
   int ex[3];
   for (int i = 0; i < 3; ++i) ex[i] = min(a.tile[i], B.n[i] - c0[i]);
-  // region rows hold ex_x cells plus one pad cell: an odd pitch of 64-bit words spreads the rows and
-  // planes of the stencil over the LDS banks, and the pad takes the zero adds of masked columns
-  const int rx = ex[0] + 1, ry = ex[1] + 2, rz = ex[2] + 2, nreg = rx * ry * rz;
+  // region rows hold two pad cells, the ex_x cells of the tile and two more pad cells, so that the
+  // three stencil columns of every entry (home or x-neighbour) are consecutive cells of a row; the
+  // pads take the shares of columns outside the tile (an x-neighbour holds the node in its list too)
+  // and are never written out, except where one tile spans the box along x: there columns -1 and
+  // ex_x are the tile's own last and first columns, and the write-out adds them in (integer sums, so
+  // the result does not depend on where a share was held).  An odd pitch of 64-bit words spreads the rows and planes of the
+  // stencil over the LDS banks.
+  const int rx = (ex[0] + 4) | 1, ry = ex[1] + 2, rz = ex[2] + 2, nreg = rx * ry * rz;
   const int32_t* list = a.bin_list + a.tile_off[L];
   const int cnt = a.tile_count[L];
   T* g = grid + d * a.total_cells + B.cell_off;
@@ -457,18 +466,12 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
       int32_t base[3];
       node_position(a, x, anchor, k, a.node_particle[k], pos);
       nearest_node(B, d, pos, base, tau64);
-      // stencil columns wrapped onto the box, relative to the tile: kept when inside [0, ex_x)
-      int lx[3];
-      bool xin[3];
-#pragma unroll
-      for (int mx = 0; mx < 3; ++mx) {
-        int gx = base[0] + mx - 1;
-        gx = gx < 0 ? gx + B.n[0] : (gx >= B.n[0] ? gx - B.n[0] : gx);
-        lx[mx] = gx - c0[0];
-        xin[mx] = (unsigned)lx[mx] < (unsigned)ex[0];
-      }
+      // the nearest node's x relative to the tile, taken periodically: -1 (left neighbour's last
+      // layer) .. ex_x (right neighbour's first layer)
+      int dx = base[0] - c0[0];
+      dx = dx < -1 ? dx + B.n[0] : (dx > ex[0] ? dx - B.n[0] : dx);
       if ((unsigned)(base[1] - c0[1]) >= (unsigned)ex[1] || (unsigned)(base[2] - c0[2]) >= (unsigned)ex[2] ||
-          !(xin[0] || xin[1] || xin[2])) {
+          dx < -1 || dx > ex[0]) {
         atomicAdd(a.status + 3, 1ull);  // positions changed since binning: the node is skipped, not misplaced
         continue;
       }
@@ -480,34 +483,25 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
         continue;
       }
       const double fs = ldexp((double)Fd[k], sc);  // exact: |F| 2^sc < 2^48
-      // a column outside the tile adds zero to the row's pad cell (its contribution belongs to the
-      // x-neighbour, which holds this node in its list too)
-      double fsx[3];
-      int cx[3];
-#pragma unroll
-      for (int mx = 0; mx < 3; ++mx) {
-        fsx[mx] = xin[mx] ? fs : 0.0;
-        cx[mx] = xin[mx] ? lx[mx] : ex[0];
-      }
-      // region row of stencil rows (my, mz): the region starts one cell before the tile in y and z
-      const int r0 = ((base[2] - c0[2]) * ry + (base[1] - c0[1])) * rx;
+      T phi[27];
+      mls_phi<T>(W, cf, phi);
+      // first cell of stencil row (my, mz) = 0: the region starts one cell before the tile in y and z
+      // and two pad cells before it in x, so column x - 1 of the stencil sits at dx + 1
+      const int r0 = ((base[2] - c0[2]) * ry + (base[1] - c0[1])) * rx + dx + 1;
 #pragma unroll
       for (int mz = 0; mz < 3; ++mz) {
-        const T vz = cf[0] + cf[3] * (T(mz - 1) - tau[2]);
 #pragma unroll
         for (int my = 0; my < 3; ++my) {
-          const T vyz = vz + cf[2] * (T(my - 1) - tau[1]);
-          const int row = r0 + (mz * ry + my) * rx;
+          unsigned long long* cell = acc + r0 + (mz * ry + my) * rx;
 #pragma unroll
           for (int mx = 0; mx < 3; ++mx) {
-            const T phi = W[(mz * 3 + my) * 3 + mx] * (vyz + cf[1] * (T(mx - 1) - tau[0]));
-            const double q = (double)phi * fsx[mx];
+            const double q = (double)phi[(mz * 3 + my) * 3 + mx] * fs;
             const double t = q + kRoundMagic;  // q rounded to an integer, held in the low mantissa bits
             const long long qh = __double_as_longlong(t) - __double_as_longlong(kRoundMagic);
-            atomicAdd(acc + row + cx[mx], (unsigned long long)qh);
+            atomicAdd(cell + mx, (unsigned long long)qh);
             if (NW == 2) {  // t - magic is that integer as a double, exactly (no integer conversion)
               const long long ql = round_to_i64((q - (t - kRoundMagic)) * lscale);
-              atomicAdd(lo + row + cx[mx], (unsigned int)(int)ql);
+              atomicAdd(lo + (cell - acc) + mx, (unsigned int)(int)ql);
             }
           }
         }
@@ -525,6 +519,7 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   const int nrows = ry * rz;
   const float inv_ry = frcp((float)ry);
   const bool halo_on = nonzero || poison;
+  const bool wrap_x = B.ntile[0] == 1;
   const bool sums = nonzero && !poison;
   const T fillv = poison ? (T)__builtin_nan("") : T(0);
   for (int row0 = wave * rpw; row0 < nrows; row0 += nwaves * rpw) {
@@ -532,17 +527,29 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
     if (row >= nrows || ix >= ex[0]) continue;
     const int iz = (int)(((float)row + 0.5f) * inv_ry);
     const int iy = row - iz * ry;
-    const int r = row * rx + ix;
+    const int r = row * rx + ix + 2;
     T v = fillv;
     if (sums) {
-      double w = (double)(long long)acc[r];
-      if (NW == 2) w += (double)(int)lo[r] * ldexp(1.0, -sl);
+      long long wi = (long long)acc[r];
+      int li = NW == 2 ? (int)lo[r] : 0;
+      if (wrap_x) {  // one tile spans the box along x: the pad columns -1 and ex_x wrap onto its own columns
+        if (ix == 0) {
+          wi += (long long)acc[r + ex[0]];
+          if (NW == 2) li += (int)lo[r + ex[0]];
+        }
+        if (ix == ex[0] - 1) {
+          wi += (long long)acc[r - ex[0]];
+          if (NW == 2) li += (int)lo[r - ex[0]];
+        }
+      }
+      double w = (double)wi;
+      if (NW == 2) w += (double)li * ldexp(1.0, -sl);
       v = (T)ldexp(w, -sc);
     }
     if ((unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2])
       g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix)] = v;
     else if (halo_on)
-      halo[halo_row(iy, iz, ry, rz) * rx + ix] = v;
+      halo[halo_row(iy, iz, ry, rz) * (ex[0] + 1) + ix] = v;
   }
   if (tid == 0) a.tile_flag[L] = halo_on ? 1 : 0;
 }
