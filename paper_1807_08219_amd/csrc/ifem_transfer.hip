@@ -313,8 +313,17 @@ __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restr
                                                unsigned long long* status) {
   __shared__ int32_t wsum[1024 / kWave];
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  constexpr int kU = 8;  // loads in flight per thread
   int32_t s = 0;
-  for (int i = tid; i < n; i += nt) s += cnt[i];
+  int i = tid;
+  for (; i + (kU - 1) * nt < n; i += kU * nt) {
+    int32_t c[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) c[u] = cnt[i + u * nt];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) s += c[u];
+  }
+  for (; i < n; i += nt) s += cnt[i];
   // inclusive scan of the thread totals: within each wavefront, then across the wavefront totals
   int32_t incl = s;
 #pragma unroll
@@ -327,7 +336,19 @@ __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restr
   int32_t before = 0;
   for (int w = 0; w < wave; ++w) before += wsum[w];
   int32_t run = before + incl - s;
-  for (int i = tid; i < n; i += nt) {
+  i = tid;
+  for (; i + (kU - 1) * nt < n; i += kU * nt) {
+    int32_t c[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) c[u] = cnt[i + u * nt];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      off[i + u * nt] = run;
+      cursor[i + u * nt] = run;
+      run += c[u];
+    }
+  }
+  for (; i < n; i += nt) {
     const int32_t c = cnt[i];
     off[i] = run;
     cursor[i] = run;
