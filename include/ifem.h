@@ -166,10 +166,12 @@ typedef struct {
   double origin[3];
 } ifem_box;
 
-/* Launch shape.  Pass NULL to ifem_plan_create for the defaults
- * {tile 32 x 16 x 8, block_forces 512, block_points 256}, the fastest measured
- * on dense red-cell suspensions; with fewer than one node per 20 grid cells
- * (sparse boxes of mixed particles) the default tile is 16 x 16 x 16.  The spread region
+/* Launch shape.  Pass NULL to ifem_plan_create for the shape that
+ * ifem_plan_autotune last chose for plans of the same sizes on the same kind of
+ * device, else the defaults {tile 32 x 16 x 8, block_forces 512, block_points
+ * 256}, the fastest measured on dense red-cell suspensions; with fewer than one
+ * node per 20 grid cells (sparse boxes of mixed particles) the default tile is
+ * 16 x 16 x 16.  The spread region
  * of a tile, (tile_x + 5)(tile_y + 2)(tile_z + 2) cells, must not exceed 13568
  * (12 bytes of LDS per cell in float64). */
 typedef struct {
@@ -179,6 +181,32 @@ typedef struct {
 } ifem_tuning;
 
 typedef struct ifem_plan_s* ifem_plan;
+
+/* Launch-shape autotuning.  Times the tiled spread on the caller's inputs for
+ * each candidate tile shape that fits LDS (32x16x8, 16x16x16, 64x8x8,
+ * 32x32x4, 16x32x8, 32x8x8, 16x16x8, 64x16x4, 32x16x16; the plan's spread
+ * workspace is rebuilt for each, so the call allocates and frees device memory),
+ * then the interpolation for block_points 64, 128 and 256 (median of five
+ * calls after two untimed ones, HIP events on `stream`), and leaves the plan
+ * with the fastest: every later call of the plan uses it, and gives the same
+ * results bit for bit as a plan created with that tuning.  The choice is
+ * recorded for (current device, the plan's sizes: particle, node and element
+ * counts, bending membranes, box lattices): a later ifem_plan_create with
+ * tuning == NULL for the same sizes on the same kind of device takes it.  The
+ * record lasts for the process; when the environment variable IFEM_TUNE_CACHE
+ * names a file, it is also appended there and read back by later processes.
+ * block_forces is not tuned (it shapes the element colouring made at plan
+ * creation).
+ *   x, anchor, F  positions and forces as for ifem_spread (dtype as there: the
+ *                 tuning is for that precision), device
+ *   grid          [3][total_cells] scratch output of the timed spreads
+ *   grid_u        [3][total_cells] velocity for the timed interpolations
+ *   v_out         [3][n_nodes] scratch output of the timed interpolations
+ *   chosen        the tuning now in force, or NULL.
+ * Synchronises the device; not for graph capture.  Outputs may not alias
+ * inputs or each other. */
+ifem_status ifem_plan_autotune(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F,
+                               void* grid, const void* grid_u, void* v_out, void* stream, ifem_tuning* chosen);
 
 /* Build a plan for one set of meshes and boxes (Sec. II.B reference
  * configuration): copies connectivity and materials to the device, computes

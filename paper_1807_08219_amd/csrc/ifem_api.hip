@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -61,6 +62,9 @@ struct ifem_plan_s {
   PlanDev P{};
   KernelTimer timer;
   DeviceBuffers mem;
+  DeviceBuffers spread_mem;          // the tile-dependent spread workspace (rebuilt by ifem_plan_autotune)
+  std::vector<ifem::BoxDev> boxes;   // box geometry on the host (tile fields set by build_spread)
+  uint64_t shape_hash = 0;           // hash of the plan's sizes: the key of the tuning cache
   ifem_tuning tune{};
   int spread_mode = IFEM_SPREAD_TILED;
   int64_t workspace_bytes = 0;
@@ -380,6 +384,7 @@ hipError_t upload(DeviceBuffers& mem, T** dst, const T* src, size_t n, hipStream
     hipError_t _e = (call);                                                                         \
     if (_e != hipSuccess) {                                                                         \
       plan->mem.release();                                                                          \
+      plan->spread_mem.release();                                                                   \
       delete plan;                                                                                  \
       return fail(_e == hipErrorOutOfMemory ? IFEM_ERR_NOMEM : IFEM_ERR_DEVICE, "%s: %s", #call,    \
                   hipGetErrorString(_e));                                                           \
@@ -486,6 +491,190 @@ int first_open_surface(const ifem_mesh_desc& m) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ launch-shape tuning
+namespace {
+
+// FNV-1a hash of the sizes that decide which launch shape is fastest: the counts of particles, nodes,
+// elements and bending membranes and every box's lattice.  The key of the tuning cache.
+uint64_t shape_hash(const ifem_mesh_desc& m, const ifem_box* boxes, int32_t n_boxes) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)m.n_particles);
+  mix((uint64_t)m.n_nodes);
+  mix((uint64_t)m.n_tris);
+  mix((uint64_t)m.n_tets);
+  mix((uint64_t)n_boxes);
+  uint64_t bending = 0;
+  for (int p = 0; p < m.n_particles; ++p) bending += (m.kb && m.kb[p] != 0.0) ? 1 : 0;
+  mix(bending);
+  for (int b = 0; b < n_boxes; ++b)
+    for (int a = 0; a < 3; ++a) mix((uint64_t)boxes[b].n[a]);
+  return h;
+}
+
+// The current device as "<arch>_<compute units>_<name>" (spaces replaced), or "unknown".
+std::string device_key() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string k = std::string(prop.gcnArchName) + "_" + std::to_string(prop.multiProcessorCount) + "_" + prop.name;
+  for (char& c : k)
+    if (c == ' ' || c == '\t' || c == '\n') c = '_';
+  return k;
+}
+
+// Tuning cache: (device, shape hash) -> launch shape, filled by ifem_plan_autotune and read by
+// ifem_plan_create when it is given no tuning.  Kept for the process; with IFEM_TUNE_CACHE naming a
+// file, also read from it on first use and appended to on every store, one line per entry:
+// "ifem-tuning-v1 <device> <hash hex> <tile x y z> <block_forces> <block_points>" (later lines win).
+struct TuneEntry {
+  std::string dev;
+  uint64_t hash;
+  ifem_tuning t;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+const char* tune_file() {
+  const char* f = getenv("IFEM_TUNE_CACHE");
+  return f && *f ? f : nullptr;
+}
+
+void tune_upsert_locked(const std::string& dev, uint64_t hash, const ifem_tuning& t) {
+  for (TuneEntry& e : g_tune)
+    if (e.dev == dev && e.hash == hash) {
+      e.t = t;
+      return;
+    }
+  g_tune.push_back({dev, hash, t});
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* f = tune_file();
+  if (!f) return;
+  std::ifstream in(f);
+  std::string tag, dev;
+  unsigned long long hash;
+  ifem_tuning t;
+  while (in >> tag >> dev >> std::hex >> hash >> std::dec >> t.tile[0] >> t.tile[1] >> t.tile[2] >> t.block_forces >>
+         t.block_points)
+    if (tag == "ifem-tuning-v1") tune_upsert_locked(dev, (uint64_t)hash, t);
+}
+
+bool tuning_cache_find(const std::string& dev, uint64_t hash, ifem_tuning* out) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_load_locked();
+  for (const TuneEntry& e : g_tune)
+    if (e.dev == dev && e.hash == hash) {
+      *out = e.t;
+      return true;
+    }
+  return false;
+}
+
+void tuning_cache_store(const std::string& dev, uint64_t hash, const ifem_tuning& t) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_load_locked();
+  tune_upsert_locked(dev, hash, t);
+  if (const char* f = tune_file()) {
+    std::ofstream out(f, std::ios::app);
+    out << "ifem-tuning-v1 " << dev << " " << std::hex << (unsigned long long)hash << std::dec << " " << t.tile[0]
+        << " " << t.tile[1] << " " << t.tile[2] << " " << t.block_forces << " " << t.block_points << "\n";
+  }
+}
+
+bool tile_fits_lds(const int32_t tile[3]) {
+  for (int a = 0; a < 3; ++a)
+    if (tile[a] < 4 || tile[a] > 64 || (tile[a] & (tile[a] - 1))) return false;
+  return (int64_t)(tile[0] + 5) * (tile[1] + 2) * (tile[2] + 2) * 12 + 1024 <= (int64_t)kLdsLimit;
+}
+
+// The tile-dependent part of a plan: tiles per box, the tile -> box map, the spread lists, counts,
+// offsets, cursors, flags, force bounds and halo rows, in a buffer set of their own, so that
+// ifem_plan_autotune can rebuild them for another tile shape.  On failure the old workspace stays.
+ifem_status build_spread(ifem_plan plan, const int32_t tile[3], hipStream_t st) {
+  PlanDev& P = plan->P;
+  std::vector<BoxDev> hb = plan->boxes;
+  std::vector<int32_t> tile_box;
+  int lists_per_entry = 2;
+  for (size_t b = 0; b < hb.size(); ++b) {
+    BoxDev& B = hb[b];
+    int64_t nt = 1;
+    for (int a = 0; a < 3; ++a) {
+      B.ntile[a] = (B.n[a] + tile[a] - 1) / tile[a];
+      nt *= B.ntile[a];
+    }
+    B.tile_base = (int32_t)tile_box.size();
+    if ((int64_t)tile_box.size() + nt > (1 << 28)) return fail(IFEM_ERR_UNSUPPORTED, "too many tiles");
+    tile_box.insert(tile_box.end(), (size_t)nt, (int32_t)b);
+    // a (node, component) sits in its home list and at most one x-neighbour's, or both neighbours'
+    // when a box ends in a one-cell-wide tile between two others
+    if (B.n[0] % tile[0] == 1 && B.ntile[0] >= 3) lists_per_entry = 3;
+  }
+  const int n_tiles = (int)tile_box.size();
+  const int64_t list_cap = (int64_t)3 * lists_per_entry * P.n_nodes;
+  if (list_cap >= ((int64_t)1 << 31)) return fail(IFEM_ERR_UNSUPPORTED, "too many nodes for the spread lists");
+  const int region_cells = (tile[0] + 5) * (tile[1] + 2) * (tile[2] + 2);
+  const int halo_cells = (tile[0] + 1) * (2 * (tile[1] + tile[2]) + 4);
+  DeviceBuffers mem;
+  BoxDev* d_boxes = nullptr;
+  int32_t *d_tile_box = nullptr, *d_cnt = nullptr, *d_off = nullptr, *d_cur = nullptr, *d_list = nullptr,
+          *d_flag = nullptr;
+  uint32_t* d_fmax = nullptr;
+  double* d_halo = nullptr;  // sized for float64
+  hipError_t e = upload(mem, &d_boxes, hb.data(), hb.size(), st);
+  if (e == hipSuccess) e = upload(mem, &d_tile_box, tile_box.data(), tile_box.size(), st);
+  if (e == hipSuccess) e = mem.alloc(&d_cnt, (size_t)3 * n_tiles);
+  if (e == hipSuccess) e = mem.alloc(&d_off, (size_t)3 * n_tiles + 1);
+  if (e == hipSuccess) e = mem.alloc(&d_cur, (size_t)3 * n_tiles);
+  if (e == hipSuccess) e = mem.alloc(&d_list, (size_t)std::max<int64_t>(list_cap, 1));
+  if (e == hipSuccess) e = mem.alloc(&d_flag, (size_t)3 * n_tiles);
+  if (e == hipSuccess) e = mem.alloc(&d_fmax, (size_t)3 * n_tiles);
+  if (e == hipSuccess) e = mem.alloc(&d_halo, (size_t)3 * n_tiles * halo_cells);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the uploads read host vectors of this frame
+  if (e != hipSuccess) {
+    mem.release();
+    return fail(e == hipErrorOutOfMemory ? IFEM_ERR_NOMEM : IFEM_ERR_DEVICE, "spread workspace: %s",
+                hipGetErrorString(e));
+  }
+  (void)hipDeviceSynchronize();  // no queued call may still use the old workspace
+  plan->spread_mem.release();
+  plan->spread_mem = std::move(mem);
+  TransferArgs& ta = P.targs;
+  ta.boxes = d_boxes;
+  ta.tile_box = d_tile_box;
+  ta.tile_count = d_cnt;
+  ta.tile_off = d_off;
+  ta.tile_cursor = d_cur;
+  ta.bin_list = d_list;
+  ta.tile_flag = d_flag;
+  ta.tile_fmax = d_fmax;
+  ta.halo = d_halo;
+  ta.region_cells = region_cells;
+  ta.halo_cells = halo_cells;
+  ta.list_cap = list_cap;
+  ta.n_tiles = n_tiles;
+  for (int a = 0; a < 3; ++a) {
+    ta.tile[a] = tile[a];
+    ta.tile_shift[a] = __builtin_ctz(tile[a]);
+    plan->tune.tile[a] = tile[a];
+  }
+  plan->workspace_bytes = (int64_t)(15 * (int64_t)n_tiles + 1 + list_cap) * 4 + (int64_t)3 * n_tiles * halo_cells * 8;
+  e = prepare_transfer_kernels(P);
+  if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "spread kernel attributes: %s", hipGetErrorString(e));
+  return IFEM_OK;
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -510,7 +699,12 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     for (int b = 0; b < n_boxes; ++b) cells += (double)boxes[b].n[0] * boxes[b].n[1] * boxes[b].n[2];
     if (cells > 0.0 && (double)m.n_nodes < 0.05 * cells) tn.tile[0] = tn.tile[1] = tn.tile[2] = 16;
   }
-  if (tuning) tn = *tuning;
+  if (tuning) {
+    tn = *tuning;
+  } else {
+    ifem_tuning cached;
+    if (tuning_cache_find(device_key(), shape_hash(m, boxes, n_boxes), &cached)) tn = cached;
+  }
   for (int a = 0; a < 3; ++a)
     if (tn.tile[a] < 4 || tn.tile[a] > 64 || (tn.tile[a] & (tn.tile[a] - 1)))
       return fail(IFEM_ERR_INVALID_ARG, "tile sizes must be powers of two in [4, 64]");
@@ -574,25 +768,28 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   const int n_bfaces = (int)(bfaces.size() / 3);
   if ((int64_t)m.n_tris + n_bfaces >= ((int64_t)1 << 31)) return fail(IFEM_ERR_UNSUPPORTED, "too many faces");
   std::vector<BoxDev> hb(n_boxes);
-  std::vector<int32_t> tile_box;
   int64_t total_cells = 0;
   for (int b = 0; b < n_boxes; ++b) {
     BoxDev& B = hb[b];
     memset(&B, 0, sizeof B);
     for (int a = 0; a < 3; ++a) {
       B.n[a] = boxes[b].n[a];
-      B.ntile[a] = (B.n[a] + tn.tile[a] - 1) / tn.tile[a];
       B.origin[a] = boxes[b].origin[a];
     }
     for (int a = 0; a < 3; ++a) B.inv_n[a] = 1.0 / (double)B.n[a];
     B.h = boxes[b].h;
     B.inv_h = 1.0 / boxes[b].h;
     B.cell_off = total_cells;
-    B.tile_base = (int32_t)tile_box.size();
     total_cells += (int64_t)B.n[0] * B.n[1] * B.n[2];
-    const int64_t nt = (int64_t)B.ntile[0] * B.ntile[1] * B.ntile[2];
-    if ((int64_t)tile_box.size() + nt > (1 << 28)) return fail(IFEM_ERR_UNSUPPORTED, "too many tiles");
-    tile_box.insert(tile_box.end(), (size_t)nt, b);
+  }
+  {
+    int64_t tiles = 0;
+    for (int b = 0; b < n_boxes; ++b) {
+      int64_t nt = 1;
+      for (int a = 0; a < 3; ++a) nt *= (boxes[b].n[a] + tn.tile[a] - 1) / tn.tile[a];
+      tiles += nt;
+    }
+    if (tiles > (1 << 28)) return fail(IFEM_ERR_UNSUPPORTED, "too many tiles");
   }
 
   // contact cells: about 2 lattice cells wide, an exact tiling of every periodic box
@@ -624,6 +821,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   plan->min_box_len = min_box_len;
   plan->tune = tn;
   plan->open_surface = open_surface;
+  plan->boxes = hb;
+  plan->shape_hash = shape_hash(m, boxes, n_boxes);
   PlanDev& P = plan->P;
   P.timer = &plan->timer;
   P.n_particles = m.n_particles;
@@ -637,10 +836,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   DeviceBuffers& mem = plan->mem;
   int32_t *d_ns, *d_law, *d_box, *d_tri_src, *d_tri_glob, *d_tri_local, *d_tri_pcol, *d_tri_colb;
   int32_t *d_tet_src, *d_tet_glob, *d_tet_local, *d_tet_pcol, *d_tet_colb, *d_rstart = nullptr, *d_ring = nullptr;
-  int32_t *d_np, *d_tile_box, *d_cnt, *d_off, *d_cur, *d_list, *d_flag;
-  double* d_halo;
+  int32_t* d_np;
   double *d_mu, *d_mu2, *d_kb, *d_c0, *d_tri_ref, *d_tet_ref, *d_X, *d_vref;
-  BoxDev* d_boxes;
   unsigned long long* d_status;
   const int np = m.n_particles;
   HIP_TRY(upload(mem, &d_ns, m.node_start, np + 1, st));
@@ -667,31 +864,11 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     HIP_TRY(upload(mem, &d_ring, ring.data(), ring.size(), st));
   }
   HIP_TRY(upload(mem, &d_np, node_particle.data(), node_particle.size(), st));
-  HIP_TRY(upload(mem, &d_boxes, hb.data(), hb.size(), st));
-  HIP_TRY(upload(mem, &d_tile_box, tile_box.data(), tile_box.size(), st));
   HIP_TRY(upload(mem, &d_X, m.X_ref, (size_t)3 * m.n_nodes, st));
   HIP_TRY(mem.alloc(&d_tri_ref, (size_t)4 * m.n_tris));
   HIP_TRY(mem.alloc(&d_tet_ref, (size_t)7 * m.n_tets));
   HIP_TRY(mem.alloc(&d_status, 5));
   HIP_TRY(mem.alloc(&d_vref, (size_t)np));
-  const int n_tiles = (int)tile_box.size();
-  // a (node, component) sits in its home list and at most one x-neighbour's, or both neighbours' when
-  // a box ends in a one-cell-wide tile between two others
-  int lists_per_entry = 2;
-  for (int b = 0; b < n_boxes; ++b)
-    if (boxes[b].n[0] % tn.tile[0] == 1 && hb[b].ntile[0] >= 3) lists_per_entry = 3;
-  const int64_t list_cap = (int64_t)3 * lists_per_entry * m.n_nodes;
-  if (list_cap >= ((int64_t)1 << 31)) return fail(IFEM_ERR_UNSUPPORTED, "too many nodes for the spread lists");
-  HIP_TRY(mem.alloc(&d_cnt, (size_t)3 * n_tiles));
-  HIP_TRY(mem.alloc(&d_off, (size_t)3 * n_tiles + 1));
-  HIP_TRY(mem.alloc(&d_cur, (size_t)3 * n_tiles));
-  HIP_TRY(mem.alloc(&d_list, (size_t)std::max<int64_t>(list_cap, 1)));
-  const int region_cells = (tn.tile[0] + 5) * (tn.tile[1] + 2) * (tn.tile[2] + 2);
-  HIP_TRY(mem.alloc(&d_flag, (size_t)3 * n_tiles));
-  uint32_t* d_fmax;
-  HIP_TRY(mem.alloc(&d_fmax, (size_t)3 * n_tiles));
-  const int halo_cells = (tn.tile[0] + 1) * (2 * (tn.tile[1] + tn.tile[2]) + 4);
-  HIP_TRY(mem.alloc(&d_halo, (size_t)3 * n_tiles * halo_cells));  // sized for float64
   ContactBoxDev* d_cboxes;
   int32_t *d_bface, *d_ccount, *d_coff, *d_ccur, *d_cown;
   ContactNode* d_crec;
@@ -723,7 +900,6 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_cwork, (size_t)work_cap));
   HIP_TRY(mem.alloc(&d_cwcount, 256 + 1));
   HIP_TRY(mem.alloc(&d_cslow, (size_t)m.n_tris + n_bfaces));
-  plan->workspace_bytes = (int64_t)(15 * (int64_t)n_tiles + 1 + list_cap) * 4 + (int64_t)3 * n_tiles * halo_cells * 8;
 
   P.tri_src = d_tri_src;
   P.tri_global = d_tri_glob;
@@ -759,26 +935,18 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   TransferArgs& ta = P.targs;
   ta.node_particle = d_np;
   ta.particle_box = d_box;
-  ta.boxes = d_boxes;
-  ta.tile_box = d_tile_box;
-  ta.tile_count = d_cnt;
-  ta.tile_off = d_off;
-  ta.tile_cursor = d_cur;
-  ta.bin_list = d_list;
-  ta.tile_flag = d_flag;
-  ta.tile_fmax = d_fmax;
-  ta.halo = d_halo;
-  ta.region_cells = region_cells;
-  ta.halo_cells = halo_cells;
   ta.status = d_status;
-  ta.list_cap = list_cap;
   ta.total_cells = total_cells;
   ta.n_nodes = m.n_nodes;
   ta.n_boxes = n_boxes;
-  ta.n_tiles = n_tiles;
-  for (int a = 0; a < 3; ++a) {
-    ta.tile[a] = tn.tile[a];
-    ta.tile_shift[a] = __builtin_ctz(tn.tile[a]);
+  {
+    const ifem_status bs = build_spread(plan, tn.tile, st);
+    if (bs != IFEM_OK) {
+      plan->mem.release();
+      plan->spread_mem.release();
+      delete plan;
+      return bs;
+    }
   }
   ContactArgs& ca = P.cargs;
   ca.node_particle = d_np;
@@ -819,12 +987,12 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(hipStreamSynchronize(st));
   if (hs[3] != 0) {
     plan->mem.release();
+    plan->spread_mem.release();
     delete plan;
     return fail(IFEM_ERR_DEGENERATE, "%llu reference elements have non-positive area or volume", hs[3]);
   }
   HIP_TRY(launch_fill_u64(d_status, 5, st));
   HIP_TRY(prepare_force_kernels(P));
-  HIP_TRY(prepare_transfer_kernels(P));
   HIP_TRY(prepare_volume_kernels(P));
   HIP_TRY(prepare_fluid_kernels(P));
   HIP_TRY(hipStreamSynchronize(st));
@@ -845,6 +1013,7 @@ ifem_status ifem_plan_destroy(ifem_plan plan) {
   (void)hipDeviceSynchronize();
   release_timer(plan->timer);
   plan->mem.release();
+  plan->spread_mem.release();
   delete plan;
   return ok();
 }
@@ -1141,6 +1310,86 @@ ifem_status ifem_plan_status(ifem_plan plan, void* stream, int64_t counts[5], in
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "status reset failed: %s", hipGetErrorString(e));
   }
+  return ok();
+}
+
+}  // extern "C"
+
+extern "C" {
+
+ifem_status ifem_plan_autotune(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F,
+                               void* grid, const void* grid_u, void* v_out, void* stream, ifem_tuning* chosen) {
+  ifem_status s = check_common(plan, dtype, x, anchor);
+  if (s != IFEM_OK) return s;
+  PlanDev& P = plan->P;
+  const size_t es = dtype == IFEM_F32 ? 4 : 8, nb = (size_t)3 * P.n_nodes * es, gb = (size_t)3 * P.total_cells * es;
+  if (!grid || !grid_u || (P.n_nodes > 0 && (!F || !v_out)))
+    return fail(IFEM_ERR_INVALID_ARG, "F, grid, grid_u or v_out is NULL");
+  if (overlaps(grid, gb, x, nb) || overlaps(grid, gb, F, nb) || overlaps(grid, gb, grid_u, gb) ||
+      overlaps(v_out, nb, x, nb) || overlaps(v_out, nb, grid_u, gb) || overlaps(v_out, nb, F, nb) ||
+      overlaps(v_out, nb, grid, gb))
+    return fail(IFEM_ERR_INVALID_ARG, "outputs alias inputs or each other");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return fail(IFEM_ERR_DEVICE, "hipEventCreate failed");
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(IFEM_ERR_DEVICE, "hipEventCreate failed");
+  }
+  // median of kReps timed calls after two untimed ones; +inf if a launch fails
+  constexpr int kReps = 5;
+  auto timed = [&](auto&& call) -> float {
+    for (int i = 0; i < 2; ++i)
+      if (call() != hipSuccess) return INFINITY;
+    float t[kReps];
+    for (int i = 0; i < kReps; ++i) {
+      (void)hipEventRecord(ev[0], st);
+      if (call() != hipSuccess) return INFINITY;
+      (void)hipEventRecord(ev[1], st);
+      if (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&t[i], ev[0], ev[1]) != hipSuccess)
+        return INFINITY;
+    }
+    std::sort(t, t + kReps);
+    return t[kReps / 2];
+  };
+  // spread tiles: the shapes measured competitive on dense and on sparse workloads
+  static const int32_t kTiles[][3] = {{32, 16, 8}, {16, 16, 16}, {64, 8, 8}, {32, 32, 4}, {16, 32, 8},
+                                      {32, 8, 8},  {16, 16, 8},  {64, 16, 4}, {32, 16, 16}};
+  const ifem_tuning before = plan->tune;
+  int32_t best[3] = {before.tile[0], before.tile[1], before.tile[2]};
+  float best_ms = INFINITY;
+  for (const auto& t : kTiles) {
+    if (!tile_fits_lds(t)) continue;
+    if (build_spread(plan, t, st) != IFEM_OK) continue;  // e.g. no memory for this shape's workspace
+    const float ms = timed([&] { return launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st); });
+    if (ms < best_ms) {
+      best_ms = ms;
+      for (int a = 0; a < 3; ++a) best[a] = t[a];
+    }
+  }
+  if (best[0] != P.targs.tile[0] || best[1] != P.targs.tile[1] || best[2] != P.targs.tile[2]) {
+    s = build_spread(plan, best, st);
+    if (s != IFEM_OK) {
+      (void)hipEventDestroy(ev[0]);
+      (void)hipEventDestroy(ev[1]);
+      return s;
+    }
+  }
+  // threads per workgroup of the point kernels, timed on the interpolation
+  int best_bp = before.block_points;
+  float best_bp_ms = INFINITY;
+  for (int bp : {64, 128, 256}) {
+    const float ms = timed([&] { return launch_interp(P, dtype, x, anchor, grid_u, v_out, bp, st); });
+    if (ms < best_bp_ms) {
+      best_bp_ms = ms;
+      best_bp = bp;
+    }
+  }
+  plan->tune.block_points = best_bp;
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  tuning_cache_store(device_key(), plan->shape_hash, plan->tune);
+  if (chosen) *chosen = plan->tune;
   return ok();
 }
 

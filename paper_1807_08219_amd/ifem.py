@@ -33,7 +33,7 @@ KERNEL_SLOTS = {0: "k_forces", 1: "k_bin_count", 2: "k_scan", 3: "k_bin_fill", 4
 
 EXPORTED = [
     "ifem_plan_create", "ifem_plan_destroy", "ifem_plan_set", "ifem_plan_info", "ifem_element_forces",
-    "ifem_spread", "ifem_spread_noalloc", "ifem_interp", "ifem_volume_correct", "ifem_advance", "ifem_interp_cells", "ifem_fluid_forces",
+    "ifem_plan_autotune", "ifem_spread", "ifem_spread_noalloc", "ifem_interp", "ifem_volume_correct", "ifem_advance", "ifem_interp_cells", "ifem_fluid_forces",
     "ifem_antistick", "ifem_plan_status", "ifem_plan_kernel_times", "ifem_last_error", "ifem_version",
 ]
 
@@ -80,6 +80,7 @@ def lib():
         L.ifem_element_forces.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_spread.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_spread_noalloc.argtypes = [P, C.c_int32, P, P, P, P, P]
+        L.ifem_plan_autotune.argtypes = [P, C.c_int32, P, P, P, P, P, P, P, C.POINTER(ifem_tuning)]
         L.ifem_interp.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_volume_correct.argtypes = [P, C.c_int32, P, P, P, P, P]
         L.ifem_advance.argtypes = [P, C.c_int32, P, P, P, C.c_double, P, P]
@@ -249,6 +250,15 @@ class Plan:
         p = self._pointers(dtype, (x, "x", "node", 3), (anchor, "anchor", "particle", 3), (F, "F", "node", 3),
                            (grid, "grid", "cell", 3))
         _check(lib().ifem_spread(self.handle, dtype, *p, _stream(stream)))
+
+    def autotune(self, dtype, x, anchor, F, grid, grid_u, v_out, stream=None):
+        """Time the candidate launch shapes on these inputs, keep the fastest (ifem_plan_autotune) and
+        return it as {"tile", "block_forces", "block_points"}."""
+        p = self._pointers(dtype, (x, "x", "node", 3), (anchor, "anchor", "particle", 3), (F, "F", "node", 3),
+                           (grid, "grid", "cell", 3), (grid_u, "grid_u", "cell", 3), (v_out, "v_out", "node", 3))
+        t = ifem_tuning()
+        _check(lib().ifem_plan_autotune(self.handle, dtype, *p, _stream(stream), C.byref(t)))
+        return {"tile": [int(v) for v in t.tile], "block_forces": int(t.block_forces), "block_points": int(t.block_points)}
 
     def spread_noalloc(self, dtype, x, anchor, F, grid, stream=None):
         """ifem_spread (tiled) with its workspace in the library's static device array (allocates nothing)."""
