@@ -187,7 +187,8 @@ typedef struct ifem_plan_s* ifem_plan;
  * 32x32x4, 16x32x8, 32x8x8, 16x16x8, 64x16x4, 32x16x16; the plan's spread
  * workspace is rebuilt for each, so the call allocates and frees device memory),
  * then the interpolation for block_points 64, 128 and 256 (median of five
- * calls after two untimed ones, HIP events on `stream`), and leaves the plan
+ * calls after two untimed ones, each timed call after an untimed call of the
+ * other transfer, as in a coupling step; HIP events on `stream`), and leaves the plan
  * with the fastest: every later call of the plan uses it, and gives the same
  * results bit for bit as a plan created with that tuning.  The choice is
  * recorded for (current device, the plan's sizes: particle, node and element

@@ -1336,13 +1336,16 @@ ifem_status ifem_plan_autotune(ifem_plan plan, int32_t dtype, const void* x, con
     (void)hipEventDestroy(ev[0]);
     return fail(IFEM_ERR_DEVICE, "hipEventCreate failed");
   }
-  // median of kReps timed calls after two untimed ones; +inf if a launch fails
+  // median of kReps timed calls after two untimed ones, each call after an untimed `between` (the
+  // other transfer, which streams its own grid through the caches as a coupling step does, so that no
+  // candidate is timed on data still cached from its previous call); +inf if a launch fails
   constexpr int kReps = 5;
-  auto timed = [&](auto&& call) -> float {
+  auto timed = [&](auto&& call, auto&& between) -> float {
     for (int i = 0; i < 2; ++i)
       if (call() != hipSuccess) return INFINITY;
     float t[kReps];
     for (int i = 0; i < kReps; ++i) {
+      if (between() != hipSuccess) return INFINITY;
       (void)hipEventRecord(ev[0], st);
       if (call() != hipSuccess) return INFINITY;
       (void)hipEventRecord(ev[1], st);
@@ -1361,7 +1364,8 @@ ifem_status ifem_plan_autotune(ifem_plan plan, int32_t dtype, const void* x, con
   for (const auto& t : kTiles) {
     if (!tile_fits_lds(t)) continue;
     if (build_spread(plan, t, st) != IFEM_OK) continue;  // e.g. no memory for this shape's workspace
-    const float ms = timed([&] { return launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st); });
+    const float ms = timed([&] { return launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st); },
+                           [&] { return launch_interp(P, dtype, x, anchor, grid_u, v_out, before.block_points, st); });
     if (ms < best_ms) {
       best_ms = ms;
       for (int a = 0; a < 3; ++a) best[a] = t[a];
@@ -1379,7 +1383,8 @@ ifem_status ifem_plan_autotune(ifem_plan plan, int32_t dtype, const void* x, con
   int best_bp = before.block_points;
   float best_bp_ms = INFINITY;
   for (int bp : {64, 128, 256}) {
-    const float ms = timed([&] { return launch_interp(P, dtype, x, anchor, grid_u, v_out, bp, st); });
+    const float ms = timed([&] { return launch_interp(P, dtype, x, anchor, grid_u, v_out, bp, st); },
+                           [&] { return launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st); });
     if (ms < best_bp_ms) {
       best_bp_ms = ms;
       best_bp = bp;
