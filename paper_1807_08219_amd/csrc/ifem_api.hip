@@ -898,7 +898,9 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   int32_t* d_cwcount;
   int32_t* d_cslow;
   HIP_TRY(mem.alloc(&d_cwork, (size_t)work_cap));
-  HIP_TRY(mem.alloc(&d_cwcount, 256 + 1));
+  HIP_TRY(mem.alloc(&d_cwcount, 256 + 2));
+  int32_t* d_chits;
+  HIP_TRY(mem.alloc(&d_chits, (size_t)work_cap));
   HIP_TRY(mem.alloc(&d_cslow, (size_t)m.n_tris + n_bfaces));
 
   P.tri_src = d_tri_src;
@@ -970,6 +972,8 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ca.work = d_cwork;
   ca.work_count = d_cwcount;
   ca.slow_count = d_cwcount + 256;
+  ca.hit_count = d_cwcount + 257;
+  ca.hits = d_chits;
   ca.slow = d_cslow;
   ca.status = d_status;
   ca.work_cap = work_cap;

@@ -22,11 +22,12 @@
 //  k_ac_pairs<T>  per work item: the face against the cell's records, the distance
 //                 (float64, the face's periodic image nearest to the node);
 //                 below d_min, an atomic minimum of the distance's float64 bits
-//                 per node, and the item is marked;
-//  k_ac_slow<T>   per slow face: the same over every cell its grown box covers;
-//                 then both again (second pass) over the marked items only: a
-//                 pair whose distance equals its node's minimum bit for bit
-//                 takes an atomic minimum of the face id;
+//                 per node, and the item joins the hit list;
+//  k_ac_slow<T>   per slow face: the same over every cell its grown box covers
+//                 (a hit marks the slow-list entry);
+//  k_ac_hits<T>   second pass over the hit list (and k_ac_slow over the marked
+//                 slow faces): a pair whose distance equals its node's minimum
+//                 bit for bit takes an atomic minimum of the face id;
 //  k_ac_push<T>   per node: the move from its winning face, or a copy.
 //
 // The closest face is the one of least float64 distance, ties (faces sharing
@@ -483,25 +484,53 @@ __global__ void __launch_bounds__(256) k_ac_slow(const ContactArgs a, const T* _
 
 // Phase 2, one thread per (face, cell) work item (grid-stride over the items
 // phase 1 listed): the face against the cell's nodes of other particles.
+// First pass: every work item; an item that found a pair below d_min is appended to the hit list
+// (one atomic per wavefront), which the second pass walks.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ac_pairs(const ContactArgs a, const T* __restrict__ x,
-                                                  const double* __restrict__ anchor, double d_min, int second) {
+                                                  const double* __restrict__ anchor, double d_min) {
   // blocks are dealt to the segments round robin (the grid is a multiple of kWorkSegs)
   const int seg_cap = a.work_cap / kWorkSegs;
   const int seg = (int)(blockIdx.x % kWorkSegs), per_seg = (int)(gridDim.x / kWorkSegs);
   const int n = min(a.work_count[seg], seg_cap);
-  uint2* __restrict__ list = a.work + (size_t)seg * seg_cap;
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint2* __restrict__ list = a.work + (size_t)seg * seg_cap;
   for (int i = (int)(blockIdx.x / kWorkSegs) * blockDim.x + threadIdx.x; i < n; i += per_seg * blockDim.x) {
     const uint2 w = list[i];
-    if (w.x == ~0u || (second && !(w.x & kHitBit))) continue;  // reserved slot, or no pair below d_min
-    const int f = (int)(w.x & ~kHitBit);
-    if (f >= a.n_tris + a.n_bfaces) continue;
+    bool hit = false;
+    if (w.x < (unsigned)(a.n_tris + a.n_bfaces)) {  // not a reserved slot
+      int q, lo[3], cnt[3];
+      ContactBoxDev C;
+      double pv[3][3], blo[3], bhi[3];
+      face_setup(a, x, anchor, (int)w.x, d_min, q, C, pv, lo, cnt, blo, bhi);
+      hit = face_cell_nodes(a, (int)w.x, q, C, pv, blo, bhi, d_min, false, (int)w.y);
+    }
+    // the lanes still in the loop append their hits together
+    const unsigned long long m = __ballot(hit);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(a.hit_count, (int)__popcll(m));
+      base = __shfl(base, leader, kWave);
+      if (hit) a.hits[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = seg * seg_cap + i;
+    }
+  }
+}
+
+// Second pass: the listed items again, each pair at exactly its node's least distance lowering the
+// node's face id.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ac_hits(const ContactArgs a, const T* __restrict__ x,
+                                                 const double* __restrict__ anchor, double d_min) {
+  const int n = min(*a.hit_count, a.work_cap);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint2 w = a.work[a.hits[i]];
+    if (w.x >= (unsigned)(a.n_tris + a.n_bfaces)) continue;
     int q, lo[3], cnt[3];
     ContactBoxDev C;
     double pv[3][3], blo[3], bhi[3];
-    face_setup(a, x, anchor, f, d_min, q, C, pv, lo, cnt, blo, bhi);
-    const bool hit = face_cell_nodes(a, f, q, C, pv, blo, bhi, d_min, second != 0, (int)w.y);
-    if (!second && hit) list[i].x = w.x | kHitBit;
+    face_setup(a, x, anchor, (int)w.x, d_min, q, C, pv, lo, cnt, blo, bhi);
+    face_cell_nodes(a, (int)w.x, q, C, pv, blo, bhi, d_min, true, (int)w.y);
   }
 }
 
@@ -649,7 +678,7 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
   hipError_t e;
   P.timer->begin(K_FILL, st);
   e = launch_fill_i32(a.count, a.n_cells, 0, st);
-  if (e == hipSuccess) e = launch_fill_i32(a.work_count, kWorkSegs + 1, 0, st);  // segment and slow-face counters
+  if (e == hipSuccess) e = launch_fill_i32(a.work_count, kWorkSegs + 2, 0, st);  // segment, slow-face, hit counters
   if (e == hipSuccess) e = launch_fill_u64(a.keys, a.n_nodes, kNoFace, st);
   if (e == hipSuccess) e = launch_fill_i32(a.keyf, a.n_nodes, kNoFaceId, st);
   P.timer->end(st);
@@ -682,14 +711,17 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
     else
       hipLaunchKernelGGL(k_ac_faces<double>, gf, dim3(B), 0, st, a, (const double*)x, anchor, d_min, a.keys);
     const dim3 gp(16 * kWorkSegs);
-    for (int second = 0; second < 2; ++second) {  // least distance, then least face id at that distance
-      if (dtype == 0) {
-        hipLaunchKernelGGL(k_ac_pairs<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, second);
-        hipLaunchKernelGGL(k_ac_slow<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, second);
-      } else {
-        hipLaunchKernelGGL(k_ac_pairs<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, second);
-        hipLaunchKernelGGL(k_ac_slow<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, second);
-      }
+    // least distance, then least face id at that distance
+    if (dtype == 0) {
+      hipLaunchKernelGGL(k_ac_pairs<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min);
+      hipLaunchKernelGGL(k_ac_slow<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, 0);
+      hipLaunchKernelGGL(k_ac_hits<float>, dim3(1024), dim3(B), 0, st, a, (const float*)x, anchor, d_min);
+      hipLaunchKernelGGL(k_ac_slow<float>, gp, dim3(B), 0, st, a, (const float*)x, anchor, d_min, 1);
+    } else {
+      hipLaunchKernelGGL(k_ac_pairs<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min);
+      hipLaunchKernelGGL(k_ac_slow<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, 0);
+      hipLaunchKernelGGL(k_ac_hits<double>, dim3(1024), dim3(B), 0, st, a, (const double*)x, anchor, d_min);
+      hipLaunchKernelGGL(k_ac_slow<double>, gp, dim3(B), 0, st, a, (const double*)x, anchor, d_min, 1);
     }
   }
   if (dtype == 0)

@@ -99,8 +99,10 @@ struct ContactArgs {
   int32_t* keyf;                 // [n_nodes] least face id at exactly that distance (second pass)
   int32_t* scan_tmp;             // [cell blocks + 1] block totals of the offset scan
   uint2* work;                   // [work_cap] (face, cell) pairs to search
-  int32_t* work_count;           // [256 + 1]: items per work-list segment, then slow faces (slow_count)
-  int32_t* slow_count;
+  int32_t* work_count;           // [256 + 2]: items per work-list segment, slow faces, hits
+  int32_t* slow_count;           // work_count + 256
+  int32_t* hit_count;            // work_count + 257
+  int32_t* hits;                 // [work_cap] work-list slots of items that found a pair below d_min
   int32_t* slow;                 // [n_tris + n_bfaces] faces searched whole
   unsigned long long* status;    // the plan's status counters
   int32_t work_cap;
