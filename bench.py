@@ -351,7 +351,7 @@ def bench_viscoelastic(plan, sc, steps, dev, x32, anchor):
     from paper_1807_08219_amd.inputs import fields, scenes
 
     res = {}
-    Cg = fields.conformation_field(sc, device=dev, dtype=torch.float32)
+    Cg = fields.conformation_field(sc, dtype=torch.float32).to(dev)
     Cn = torch.empty((6, sc.n_nodes), dtype=torch.float32, device=dev)
     ms = _kernel_ms(plan, "k_interp_cells", lambda: plan.interp_cells(ifem.IFEM_F32, x32, anchor, Cg, Cn), steps)
     nbytes = sc.n_nodes * (12 + 24) + sc.total_cells * 24
@@ -369,7 +369,7 @@ def bench_viscoelastic(plan, sc, steps, dev, x32, anchor):
     p4 = ifem.Plan(s4)
     x4, a4 = torch.as_tensor(s4.x32, device=dev), torch.as_tensor(s4.anchor, device=dev)
     C4 = torch.empty((6, s4.n_nodes), dtype=torch.float32, device=dev)
-    p4.interp_cells(ifem.IFEM_F32, x4, a4, fields.conformation_field(s4, device=dev, dtype=torch.float32), C4)
+    p4.interp_cells(ifem.IFEM_F32, x4, a4, fields.conformation_field(s4, dtype=torch.float32).to(dev), C4)
     v4 = torch.randn((3, s4.n_nodes), dtype=torch.float32, device=dev)
     f4 = torch.zeros((3, s4.n_nodes), dtype=torch.float32, device=dev)
     ms = _kernel_ms(p4, "k_fluid", lambda: p4.fluid_forces(ifem.IFEM_F32, x4, v4, f4, C=C4, eta=1.0, G=0.5), steps)
@@ -502,7 +502,7 @@ def bench_workload(config, steps, warmup, dev):
 
     sc = scenes.make_config(config)
     plan = ifem.Plan(sc)
-    u64 = fields.scene_velocity(sc, device=dev, dtype=torch.float64, shear_rate=1.0 if config == 3 else 0.0)
+    u64 = fields.scene_velocity(sc, dtype=torch.float64, shear_rate=1.0 if config == 3 else 0.0).to(dev)
     u32 = u64.to(torch.float32)
     x32, anchor = torch.as_tensor(sc.x32, device=dev), torch.as_tensor(sc.anchor, device=dev)
     tuning = autotune(plan, sc, dev, x32, anchor, u32)
@@ -572,7 +572,7 @@ def bench_batched(steps, warmup, dev):
 
     sc = scenes.make_config(4)
     plan = ifem.Plan(sc)
-    u32 = fields.scene_velocity(sc, device=dev, dtype=torch.float32)
+    u32 = fields.scene_velocity(sc, dtype=torch.float32).to(dev)
     x32 = torch.as_tensor(sc.x32, device=dev)
     anchor = torch.as_tensor(sc.anchor, device=dev)
     tuning = autotune(plan, sc, dev, x32, anchor, u32)
@@ -678,7 +678,7 @@ def main():
                   "block_forces": args.block_forces or 512, "block_points": args.block_points or 256}
     plan = ifem.Plan(sc, tuning=tuning)
     log(f"plan created ({time.time() - t0:.1f} s), info {plan.info()}")
-    u64 = fields.scene_velocity(sc, device=dev, dtype=torch.float64, shear_rate=1.0 if args.config == 3 else 0.0)
+    u64 = fields.scene_velocity(sc, dtype=torch.float64, shear_rate=1.0 if args.config == 3 else 0.0).to(dev)
     u32 = u64.to(torch.float32)
     x32 = torch.as_tensor(sc.x32, device=dev)
     anchor = torch.as_tensor(sc.anchor, device=dev)
