@@ -213,10 +213,15 @@ ifem_status ifem_plan_autotune(ifem_plan plan, int32_t dtype, const void* x, con
  * configuration): copies connectivity and materials to the device, computes
  * the float64 reference metrics of every element on the device, colours the
  * elements of each particle for conflict-free accumulation, builds the
- * one-ring of every bending node and sizes the spreading workspace.
- * Returns IFEM_ERR_DEGENERATE if a reference element has non-positive area
- * or volume, IFEM_ERR_UNSUPPORTED for a particle too large for one
- * workgroup's LDS or a non-manifold bending surface.  Synchronises `stream`.
+ * one-ring of every bending node and sizes the spreading workspace.  A
+ * particle whose float64 nodal accumulators fit one workgroup's LDS (up to
+ * 6741 nodes, 5056 when any particle bends) is handled by one workgroup; a
+ * larger one by the global-memory path (element forces into a scratch slot
+ * per corner, then a fixed-order gather per node), with the same results to
+ * rounding and the same run-to-run bits; there is no size limit beyond the
+ * 32-bit counts.  Returns IFEM_ERR_DEGENERATE if a reference element has
+ * non-positive area or volume, IFEM_ERR_UNSUPPORTED for a non-manifold
+ * bending surface.  Synchronises `stream`.
  * tuning == NULL selects the default launch shape (see ifem_tuning). */
 ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, int32_t n_boxes,
                              const ifem_tuning* tuning, void* stream, ifem_plan* out);
@@ -304,9 +309,9 @@ ifem_status ifem_interp(ifem_plan plan, int32_t dtype, const void* x, const doub
  *               corrects in place; any other overlap with an input is rejected.
  *   lambda_out  [n_particles] float64 multipliers L (0 for solids), or NULL.
  * Returns IFEM_ERR_UNSUPPORTED if a membrane's triangles do not form a closed,
- * consistently oriented surface (its enclosed volume is then undefined), or if
- * the largest particle exceeds 6784 nodes (its float64 alpha sums must fit one
- * workgroup's LDS). */
+ * consistently oriented surface (its enclosed volume is then undefined).
+ * Membranes above the one-workgroup size take a global-memory path of four
+ * launches (alpha, beta, the multiplier, the move). */
 ifem_status ifem_volume_correct(ifem_plan plan, int32_t dtype, const void* x, const double* V0, void* x_out,
                                 double* lambda_out, void* stream);
 

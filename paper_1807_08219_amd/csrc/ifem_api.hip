@@ -727,11 +727,24 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   if (s != IFEM_OK) return s;
   std::vector<char> bend(m.n_particles, 0);
   bool any_bend = false;
-  int cap = 1;
   for (int p = 0; p < m.n_particles; ++p) {
     bend[p] = (m.kb[p] != 0.0 && m.law[p] != IFEM_LAW_TET_NEOHOOKE && m.tri_start[p + 1] > m.tri_start[p]) ? 1 : 0;
     any_bend = any_bend || bend[p];
-    cap = std::max(cap, m.node_start[p + 1] - m.node_start[p]);
+  }
+  // A particle whose nodal forces (and curvature) fit one workgroup's LDS takes the per-particle
+  // force kernel; a larger one the global-memory path.  cap: the largest of the former.
+  int cap = 1, cap_mem = 0, cap_solid = 0;
+  std::vector<int32_t> lds_part, large_part;
+  for (int p = 0; p < m.n_particles; ++p) {
+    const int nn = m.node_start[p + 1] - m.node_start[p];
+    if ((size_t)nn * force_lds_per_node(any_bend) + 2048 <= kLdsLimit) {
+      lds_part.push_back(p);
+      cap = std::max(cap, nn);
+      if (m.tri_start[p + 1] > m.tri_start[p]) cap_mem = std::max(cap_mem, nn);
+      if (m.tet_start[p + 1] > m.tet_start[p]) cap_solid = std::max(cap_solid, nn);
+    } else {
+      large_part.push_back(p);
+    }
   }
   // one-rings for bending, and for every membrane when all are closed (the volume correction)
   int open_surface = first_open_surface(m);
@@ -758,8 +771,45 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
       }
     }
   }
-  if ((size_t)(3 + (any_bend ? 1 : 0)) * cap * sizeof(double) > kLdsLimit)
-    return fail(IFEM_ERR_UNSUPPORTED, "a particle with %d nodes does not fit one workgroup's LDS", cap);
+  // the global-memory path's lists: its elements (slot order, particle by particle), and per node
+  // the element corners it gathers, in element order
+  std::vector<int32_t> lg_tri_begin(1, 0), lg_tet_begin(1, 0), lg_tri_slot, lg_tri_part, lg_tet_slot, lg_tet_part;
+  std::vector<int32_t> lg_node_part, lg_node_base, lg_node_lp, lg_part_base(1, 0), lg_gstart, lg_gather;
+  int lg_bend = 0;
+  if (!large_part.empty()) {
+    for (int p : large_part) {
+      for (int s2 = m.tri_start[p]; s2 < m.tri_start[p + 1]; ++s2) lg_tri_slot.push_back(s2), lg_tri_part.push_back(p);
+      for (int s2 = m.tet_start[p]; s2 < m.tet_start[p + 1]; ++s2) lg_tet_slot.push_back(s2), lg_tet_part.push_back(p);
+      lg_tri_begin.push_back((int32_t)lg_tri_slot.size());
+      lg_tet_begin.push_back((int32_t)lg_tet_slot.size());
+      const int base = (int)lg_node_part.size(), lp = (int)lg_part_base.size() - 1;
+      for (int k = m.node_start[p]; k < m.node_start[p + 1]; ++k)
+        lg_node_part.push_back(p), lg_node_base.push_back(base), lg_node_lp.push_back(lp);
+      lg_part_base.push_back((int32_t)lg_node_part.size());
+      lg_bend |= bend[p];
+    }
+    const int64_t n_el = (int64_t)lg_tri_slot.size() + (int64_t)lg_tet_slot.size();
+    if (n_el * 4 >= ((int64_t)1 << 31) || lg_node_part.size() >= ((size_t)1 << 31))
+      return fail(IFEM_ERR_UNSUPPORTED, "too many elements in particles larger than a workgroup's LDS");
+    const int n_ln = (int)lg_node_part.size(), n_lt = (int)lg_tri_slot.size();
+    // compact index of particle p's node k: node_base + (k - node_start[p]); per element its corners
+    std::vector<int32_t> first_of(m.n_particles, -1);
+    for (int i = 0; i < n_ln; ++i)
+      if (first_of[lg_node_part[i]] < 0) first_of[lg_node_part[i]] = i;
+    auto corner = [&](int e, int v) -> int {
+      if (e < n_lt) return first_of[lg_tri_part[e]] + tri_local[(size_t)v * m.n_tris + lg_tri_slot[e]];
+      const int t = e - n_lt;
+      return first_of[lg_tet_part[t]] + tet_local[(size_t)v * m.n_tets + lg_tet_slot[t]];
+    };
+    lg_gstart.assign(n_ln + 1, 0);
+    for (int e = 0; e < (int)n_el; ++e)
+      for (int v = 0; v < (e < n_lt ? 3 : 4); ++v) lg_gstart[corner(e, v) + 1]++;
+    for (int i = 0; i < n_ln; ++i) lg_gstart[i + 1] += lg_gstart[i];
+    lg_gather.resize(lg_gstart[n_ln]);
+    std::vector<int32_t> cur(lg_gstart.begin(), lg_gstart.end() - 1);
+    for (int e = 0; e < (int)n_el; ++e)
+      for (int v = 0; v < (e < n_lt ? 3 : 4); ++v) lg_gather[cur[corner(e, v)]++] = e * 4 + v;
+  }
   std::vector<int32_t> node_particle(m.n_nodes);
   for (int p = 0; p < m.n_particles; ++p)
     for (int k = m.node_start[p]; k < m.node_start[p + 1]; ++k) node_particle[k] = p;
@@ -833,6 +883,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   P.total_cells = total_cells;
   P.cap = cap;
   P.has_bending = any_bend ? 1 : 0;
+  P.n_lds_part = (int32_t)lds_part.size();
   DeviceBuffers& mem = plan->mem;
   int32_t *d_ns, *d_law, *d_box, *d_tri_src, *d_tri_glob, *d_tri_local, *d_tri_pcol, *d_tri_colb;
   int32_t *d_tet_src, *d_tet_glob, *d_tet_local, *d_tet_pcol, *d_tet_colb, *d_rstart = nullptr, *d_ring = nullptr;
@@ -859,6 +910,61 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(upload(mem, &d_tet_local, tet_local.data(), tet_local.size(), st));
   HIP_TRY(upload(mem, &d_tet_pcol, tet_pcol.data(), tet_pcol.size(), st));
   HIP_TRY(upload(mem, &d_tet_colb, tet_colb.data(), tet_colb.size(), st));
+  int32_t* d_lds_part = nullptr;
+  if (!large_part.empty() && !lds_part.empty()) HIP_TRY(upload(mem, &d_lds_part, lds_part.data(), lds_part.size(), st));
+  if (!large_part.empty()) {
+    LargeArgs& L = P.large;
+    L.n_part = (int32_t)large_part.size();
+    L.n_tri = (int32_t)lg_tri_slot.size();
+    L.n_tet = (int32_t)lg_tet_slot.size();
+    L.n_node = (int32_t)lg_node_part.size();
+    L.any_bending = lg_bend;
+    int32_t *d1, *d2, *d3, *d4, *d5, *d6, *d7, *d8, *d9, *d10 = nullptr, *d11 = nullptr, *d12, *d13;
+    HIP_TRY(upload(mem, &d12, lg_node_lp.data(), lg_node_lp.size(), st));
+    HIP_TRY(upload(mem, &d13, lg_part_base.data(), lg_part_base.size(), st));
+    L.node_lp = d12;
+    L.part_base = d13;
+    HIP_TRY(upload(mem, &d1, large_part.data(), large_part.size(), st));
+    HIP_TRY(upload(mem, &d2, lg_tri_begin.data(), lg_tri_begin.size(), st));
+    HIP_TRY(upload(mem, &d3, lg_tet_begin.data(), lg_tet_begin.size(), st));
+    HIP_TRY(upload(mem, &d8, lg_node_part.data(), lg_node_part.size(), st));
+    HIP_TRY(upload(mem, &d9, lg_node_base.data(), lg_node_base.size(), st));
+    HIP_TRY(upload(mem, &d10, lg_gstart.data(), lg_gstart.size(), st));
+    if (!lg_gather.empty()) HIP_TRY(upload(mem, &d11, lg_gather.data(), lg_gather.size(), st));
+    d4 = d5 = d6 = d7 = nullptr;
+    if (L.n_tri) {
+      HIP_TRY(upload(mem, &d4, lg_tri_slot.data(), lg_tri_slot.size(), st));
+      HIP_TRY(upload(mem, &d5, lg_tri_part.data(), lg_tri_part.size(), st));
+    }
+    if (L.n_tet) {
+      HIP_TRY(upload(mem, &d6, lg_tet_slot.data(), lg_tet_slot.size(), st));
+      HIP_TRY(upload(mem, &d7, lg_tet_part.data(), lg_tet_part.size(), st));
+    }
+    L.part = d1;
+    L.tri_begin = d2;
+    L.tet_begin = d3;
+    L.tri_slot = d4;
+    L.tri_part = d5;
+    L.tet_slot = d6;
+    L.tet_part = d7;
+    L.node_part = d8;
+    L.node_base = d9;
+    L.gather_start = d10;
+    L.gather = d11;
+    double *ef_tri, *ef_tet, *kh, *fb, *rt;
+    HIP_TRY(mem.alloc(&ef_tri, (size_t)9 * std::max(L.n_tri, 1)));
+    HIP_TRY(mem.alloc(&ef_tet, (size_t)12 * std::max(L.n_tet, 1)));
+    HIP_TRY(mem.alloc(&kh, (size_t)std::max(L.n_node, 1)));
+    HIP_TRY(mem.alloc(&fb, (size_t)3 * std::max(L.n_node, 1)));
+    HIP_TRY(mem.alloc(&rt, (size_t)5 * std::max(L.n_tri + L.n_tet, 1)));
+    HIP_TRY(mem.alloc(&L.vol_terms, (size_t)4 * std::max(L.n_node, 1)));
+    HIP_TRY(mem.alloc(&L.lam, (size_t)L.n_part));
+    L.ef_tri = ef_tri;
+    L.ef_tet = ef_tet;
+    L.kh = kh;
+    L.fb = fb;
+    L.red_terms = rt;
+  }
   if (any_ring) {
     HIP_TRY(upload(mem, &d_rstart, rstart.data(), rstart.size(), st));
     HIP_TRY(upload(mem, &d_ring, ring.data(), ring.size(), st));
@@ -933,6 +1039,9 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   fa.n_tris = m.n_tris;
   fa.n_tets = m.n_tets;
   fa.cap = cap;
+  fa.cap_mem = cap_mem;
+  fa.cap_solid = cap_solid;
+  fa.lds_part = d_lds_part;
   fa.has_bending = any_bend ? 1 : 0;
   TransferArgs& ta = P.targs;
   ta.node_particle = d_np;
@@ -1212,8 +1321,6 @@ ifem_status ifem_volume_correct(ifem_plan plan, int32_t dtype, const void* x, co
   if (plan->open_surface >= 0)
     return fail(IFEM_ERR_UNSUPPORTED, "particle %d: the volume correction needs a closed, consistently oriented surface",
                 plan->open_surface);
-  if (!volume_fits(P))
-    return fail(IFEM_ERR_UNSUPPORTED, "a particle with %d nodes is too large for the volume correction's LDS", P.cap);
   const size_t nb = (size_t)3 * P.n_nodes * (dtype == IFEM_F32 ? 4 : 8), pb = (size_t)P.n_particles * 8;
   if ((x_out != x && overlaps(x_out, nb, x, nb)) || overlaps(x_out, nb, V0, pb) || overlaps(lambda_out, pb, x, nb) ||
       overlaps(lambda_out, pb, x_out, nb) || overlaps(lambda_out, pb, V0, pb))

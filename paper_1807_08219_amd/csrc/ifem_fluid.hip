@@ -18,6 +18,8 @@
 // V grad_x N_1 = (d_2 x d_3) / 6 (cyclically) and grad_x N_0 = -sum, so the
 // forces need no division, and L one reciprocal of det[d_1 d_2 d_3] = 6 V.
 // All of it is float64 (float32 offsets and velocities are widened exactly).
+#include <algorithm>
+
 #include "ifem_internal.hpp"
 
 namespace ifem {
@@ -91,14 +93,77 @@ __global__ void __launch_bounds__(256) k_interp_cells(const TransferArgs a, cons
   if (!ok) atomicAdd(a.status + 2, 1ull);
 }
 
-// One workgroup per particle; particles without tetrahedra return at once.
+// Forces of one tetrahedron's viscous and polymeric stress on its four corners
+// (q: corner positions in a local frame, u: corner velocities, C: the
+// conformation [6][N] of the particle's nodes or null, ids: the corners' indices
+// into it).  False for an inverted or flat element, which gets no force.
+template <typename T>
+__device__ __forceinline__ bool fluid_tet(const double q[4][3], const double u[4][3], const T* __restrict__ Cp,
+                                          int64_t N, const int ids[4], double eta, double G, double fk[4][3]) {
+  double d[3][3], du[3][3];  // current edges and velocity differences from node 0
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      d[k][c] = q[k + 1][c] - q[0][c];
+      du[k][c] = u[k + 1][c] - u[0][c];
+    }
+  double g[3][3];  // V grad_x N_k for k = 1..3: (d_k+1 x d_k+2) / 6
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double* b = d[(k + 1) % 3];
+    const double* e = d[(k + 2) % 3];
+    g[k][0] = (b[1] * e[2] - b[2] * e[1]) * (1.0 / 6.0);
+    g[k][1] = (b[2] * e[0] - b[0] * e[2]) * (1.0 / 6.0);
+    g[k][2] = (b[0] * e[1] - b[1] * e[0]) * (1.0 / 6.0);
+  }
+  const double V = d[0][0] * g[0][0] + d[0][1] * g[0][1] + d[0][2] * g[0][2];  // det / 6
+  if (!(V > 0.0)) return false;
+  const double iv = 1.0 / V;
+  double L[3][3];  // sum_k du_k (x) grad_x N_k
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) L[i][j] = (du[0][i] * g[0][j] + du[1][i] * g[1][j] + du[2][i] * g[2][j]) * iv;
+  double sg[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sg[i][j] = eta * (L[i][j] + L[j][i]);
+  if (Cp) {
+    constexpr int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        double cs = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cs += (double)Cp[sym[i][j] * N + ids[k]];
+        const double pj = G * (cs * 0.25 - (i == j ? 1.0 : 0.0));
+        sg[i][j] += pj;
+        if (j != i) sg[j][i] += pj;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    fk[0][i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      fk[k + 1][i] = sg[i][0] * g[k][0] + sg[i][1] * g[k][1] + sg[i][2] * g[k][2];
+      fk[0][i] -= fk[k + 1][i];
+    }
+  }
+  return true;
+}
+
+// One workgroup per particle that fits its LDS (larger ones: the global path below); particles without tetrahedra return at once.
 // Element forces are accumulated in LDS (float64) colour by colour, then
 // added to f once per node.
 template <typename T>
 __global__ void __launch_bounds__(512) k_fluid(const ForceArgs a, const T* __restrict__ x, const T* __restrict__ v,
                                                const T* __restrict__ C, double eta, double G, T* __restrict__ f) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int p = blockIdx.x;
+  const int p = a.lds_part ? a.lds_part[blockIdx.x] : (int)blockIdx.x;
   if (a.pcol_tet[p] == a.pcol_tet[p + 1]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n0 = a.node_start[p];
@@ -107,8 +172,8 @@ __global__ void __launch_bounds__(512) k_fluid(const ForceArgs a, const T* __res
   double* acc = reinterpret_cast<double*>(smem_raw);  // [3][cap]
   for (int i = tid; i < nn; i += nt) {
     acc[i] = 0.0;
-    acc[a.cap + i] = 0.0;
-    acc[2 * a.cap + i] = 0.0;
+    acc[a.cap_solid + i] = 0.0;
+    acc[2 * a.cap_solid + i] = 0.0;
   }
   __syncthreads();
   const T* xx = x + n0;
@@ -134,75 +199,76 @@ __global__ void __launch_bounds__(512) k_fluid(const ForceArgs a, const T* __res
           u[k][c] = (double)vx[c * N + ids[k]];
         }
       }
-      double d[3][3], du[3][3];  // current edges and velocity differences from node 0
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          d[k][c] = q[k + 1][c] - q[0][c];
-          du[k][c] = u[k + 1][c] - u[0][c];
-        }
-      double g[3][3];  // V grad_x N_k for k = 1..3: (d_k+1 x d_k+2) / 6
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double* b = d[(k + 1) % 3];
-        const double* e = d[(k + 2) % 3];
-        g[k][0] = (b[1] * e[2] - b[2] * e[1]) * (1.0 / 6.0);
-        g[k][1] = (b[2] * e[0] - b[0] * e[2]) * (1.0 / 6.0);
-        g[k][2] = (b[0] * e[1] - b[1] * e[0]) * (1.0 / 6.0);
-      }
-      const double V = d[0][0] * g[0][0] + d[0][1] * g[0][1] + d[0][2] * g[0][2];  // det / 6
-      if (!(V > 0.0)) continue;  // inverted or flat: no force (counted by the elastic pass)
-      const double iv = 1.0 / V;
-      double L[3][3];  // sum_k du_k (x) grad_x N_k
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) L[i][j] = (du[0][i] * g[0][j] + du[1][i] * g[1][j] + du[2][i] * g[2][j]) * iv;
-      double sg[3][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) sg[i][j] = eta * (L[i][j] + L[j][i]);
-      if (Cp) {
-        constexpr int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = i; j < 3; ++j) {
-            double cs = 0.0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) cs += (double)Cp[sym[i][j] * N + ids[k]];
-            const double pj = G * (cs * 0.25 - (i == j ? 1.0 : 0.0));
-            sg[i][j] += pj;
-            if (j != i) sg[j][i] += pj;
-          }
-      }
       double fk[4][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        fk[0][i] = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          fk[k + 1][i] = sg[i][0] * g[k][0] + sg[i][1] * g[k][1] + sg[i][2] * g[k][2];
-          fk[0][i] -= fk[k + 1][i];
-        }
-      }
+      if (!fluid_tet(q, u, Cp, N, ids, eta, G, fk)) continue;  // inverted or flat: no force (counted by the elastic pass)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c * a.cap + ids[k]] += fk[k][c];
+        for (int c = 0; c < 3; ++c) acc[c * a.cap_solid + ids[k]] += fk[k][c];
     }
     __syncthreads();
   }
   for (int i = tid; i < nn; i += nt)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) f[c * N + n0 + i] = (T)((double)f[c * N + n0 + i] + acc[c * a.cap + i]);
+    for (int c = 0; c < 3; ++c) f[c * N + n0 + i] = (T)((double)f[c * N + n0 + i] + acc[c * a.cap_solid + i]);
+}
+
+// Solids too large for one workgroup's LDS: each tetrahedron's corner forces
+// into the element scratch (float64), then one thread per node adds its
+// tetrahedra's shares in element order (deterministic) to f.
+template <typename T>
+__global__ void __launch_bounds__(256) k_large_fluid_elems(const ForceArgs a, const LargeArgs L,
+                                                            const T* __restrict__ x, const T* __restrict__ v,
+                                                            const T* __restrict__ C, double eta, double G) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.n_tet) return;
+  const int s = L.tet_slot[t], p = L.tet_part[t];
+  const int n0 = a.node_start[p];
+  const int64_t N = a.n_nodes;
+  double o[3] = {0.0, 0.0, 0.0};
+  if (sizeof(T) == 8)
+    for (int c = 0; c < 3; ++c) o[c] = (double)x[c * N + n0];
+  int ids[4];
+  double q[4][3], u[4][3];
+  for (int k = 0; k < 4; ++k) {
+    ids[k] = a.tet_local[k * a.n_tets + s];
+    for (int c = 0; c < 3; ++c) {
+      q[k][c] = (double)x[c * N + n0 + ids[k]] - o[c];
+      u[k][c] = (double)v[c * N + n0 + ids[k]];
+    }
+  }
+  double fk[4][3];
+  if (!fluid_tet(q, u, C ? C + n0 : (const T*)nullptr, N, ids, eta, G, fk))
+    for (int k = 0; k < 4; ++k) fk[k][0] = fk[k][1] = fk[k][2] = 0.0;
+  double* ef = reinterpret_cast<double*>(L.ef_tet);
+  for (int k = 0; k < 4; ++k)
+    for (int c = 0; c < 3; ++c) ef[(k * 3 + c) * (int64_t)L.n_tet + t] = fk[k][c];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_large_fluid_gather(const ForceArgs a, const LargeArgs L, T* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n_node) return;
+  const int p = L.node_part[i];
+  if (a.pcol_tet[p] == a.pcol_tet[p + 1]) return;
+  const int k = a.node_start[p] + (i - L.node_base[i]);
+  const double* ef = reinterpret_cast<const double*>(L.ef_tet);
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int j = L.gather_start[i]; j < L.gather_start[i + 1]; ++j) {
+    const int g = L.gather[j];  // element e and corner v: e * 4 + v, tetrahedra after the triangles
+    const int e = (g >> 2) - L.n_tri, v = g & 3;
+    if (e < 0) continue;
+    for (int c = 0; c < 3; ++c) s[c] += ef[(v * 3 + c) * (int64_t)L.n_tet + e];
+  }
+  const int64_t N = a.n_nodes;
+  for (int c = 0; c < 3; ++c) f[c * N + k] = (T)((double)f[c * N + k] + s[c]);
 }
 
 // ------------------------------------------------------------------ host launchers
+static size_t fluid_lds(const PlanDev& P) { return (size_t)3 * std::max(P.fargs.cap_solid, 1) * sizeof(double); }
+
 hipError_t prepare_fluid_kernels(const PlanDev& P) {
-  const int lds = (int)((size_t)3 * P.cap * sizeof(double));
+  const int lds = (int)fluid_lds(P);
   hipError_t e = hipFuncSetAttribute((const void*)k_fluid<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_fluid<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -229,13 +295,29 @@ hipError_t launch_fluid(const PlanDev& P, int dtype, const void* x, const void* 
                         void* f, hipStream_t st) {
   if (P.n_tets == 0) return hipSuccess;
   P.timer->begin(K_FLUID, st);
-  const size_t lds = (size_t)3 * P.cap * sizeof(double);
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_fluid<float>, dim3(P.n_particles), dim3(256), lds, st, P.fargs, (const float*)x,
-                       (const float*)v, (const float*)C, eta, G, (float*)f);
-  else
-    hipLaunchKernelGGL(k_fluid<double>, dim3(P.n_particles), dim3(256), lds, st, P.fargs, (const double*)x,
-                       (const double*)v, (const double*)C, eta, G, (double*)f);
+  const size_t lds = fluid_lds(P);
+  if (P.n_lds_part > 0) {
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_fluid<float>, dim3(P.n_lds_part), dim3(256), lds, st, P.fargs, (const float*)x,
+                         (const float*)v, (const float*)C, eta, G, (float*)f);
+    else
+      hipLaunchKernelGGL(k_fluid<double>, dim3(P.n_lds_part), dim3(256), lds, st, P.fargs, (const double*)x,
+                         (const double*)v, (const double*)C, eta, G, (double*)f);
+  }
+  const LargeArgs& L = P.large;
+  if (L.n_tet > 0) {
+    const int B = 256;
+    const dim3 ge((L.n_tet + B - 1) / B), gn((L.n_node + B - 1) / B);
+    if (dtype == 0) {
+      hipLaunchKernelGGL(k_large_fluid_elems<float>, ge, dim3(B), 0, st, P.fargs, L, (const float*)x,
+                         (const float*)v, (const float*)C, eta, G);
+      hipLaunchKernelGGL(k_large_fluid_gather<float>, gn, dim3(B), 0, st, P.fargs, L, (float*)f);
+    } else {
+      hipLaunchKernelGGL(k_large_fluid_elems<double>, ge, dim3(B), 0, st, P.fargs, L, (const double*)x,
+                         (const double*)v, (const double*)C, eta, G);
+      hipLaunchKernelGGL(k_large_fluid_gather<double>, gn, dim3(B), 0, st, P.fargs, L, (double*)f);
+    }
+  }
   P.timer->end(st);
   return hipGetLastError();
 }

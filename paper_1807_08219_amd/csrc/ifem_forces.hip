@@ -7,6 +7,10 @@
 //  k_forces<T>            one workgroup per particle: elastic element forces,
 //                         Helfrich bending, float64 volume/area/centroid, and a
 //                         single coalesced write of the nodal forces.
+//  k_large_*<T>           the same for particles larger than a workgroup's
+//                         LDS: element forces into a scratch slot per corner,
+//                         curvature and Laplacian passes per node, a fixed-order
+//                         gather per node (see the section below).
 //
 // Element forces use the covariant form of the paper's constitutive laws.
 // With current edges D = [d1 d2 (d3)], g = D^T D, Delta = g - G and
@@ -408,7 +412,7 @@ __global__ void __launch_bounds__(512) k_forces(const ForceArgs a, const T* __re
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red_lds[5 * 16];
   __shared__ unsigned int bad_elems, bad_out;
-  const int p = blockIdx.x;
+  const int p = a.lds_part ? a.lds_part[blockIdx.x] : (int)blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n0 = a.node_start[p];
   const int nn = a.node_start[p + 1] - n0;
@@ -604,6 +608,242 @@ __global__ void __launch_bounds__(512) k_forces(const ForceArgs a, const T* __re
   }
 }
 
+// ------------------------------------------------------------------ particles larger than a workgroup's LDS
+// A particle whose forces (and curvature) do not fit one workgroup's LDS takes
+// this path instead of k_forces: the same element and one-ring routines, with
+// every intermediate in global memory and no element colouring:
+//  k_large_elems<T>  one thread per element: its nodal forces into a scratch
+//                    slot (no accumulation), its volume/area/centroid terms;
+//  k_large_curv<T>   one thread per node of a bending membrane: curvature, the
+//                    curvature term of the Helfrich force, kH - kH0;
+//  k_large_lap<T>    one thread per such node: the Laplacian term (needs every
+//                    node's kH - kH0: a launch of its own);
+//  k_large_gather<T> one thread per node: its element shares in a fixed order
+//                    (a node -> element-slot list built at plan creation) plus
+//                    the bending terms, written once;
+//  k_large_reduce    one workgroup per particle: the element terms of the
+//                    float64 reductions summed in a fixed order.
+// Sums run in fixed orders, so the forces are reproducible run to run.
+
+template <typename T>
+__device__ __forceinline__ void large_pos(const T* __restrict__ x, int64_t N, int k, T out[3]) {
+  out[0] = x[k];
+  out[1] = x[N + k];
+  out[2] = x[2 * N + k];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_large_elems(const ForceArgs a, const LargeArgs L, const T* __restrict__ x,
+                                                      double* __restrict__ red_terms) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t N = a.n_nodes;
+  bool bad = false;
+  if (e < L.n_tri + L.n_tet) {
+    const bool tri = e < L.n_tri;
+    const int s = tri ? L.tri_slot[e] : L.tet_slot[e - L.n_tri];
+    const int p = tri ? L.tri_part[e] : L.tet_part[e - L.n_tri];
+    const int n0 = a.node_start[p];
+    const T mu = (T)a.mu[p], mu2 = (T)a.mu2[p];
+    // float64 positions are taken relative to the particle's node 0 for the reductions, as in k_forces
+    double o[3] = {0.0, 0.0, 0.0};
+    if (sizeof(T) == 8) {
+      o[0] = (double)x[n0];
+      o[1] = (double)x[N + n0];
+      o[2] = (double)x[2 * N + n0];
+    }
+    double r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (tri) {
+      int ids[3];
+      T xs[3][3];
+      for (int v = 0; v < 3; ++v) {
+        ids[v] = a.tri_local[v * a.n_tris + s];
+        large_pos(x, N, n0 + ids[v], xs[v]);
+      }
+      const double G[3] = {a.tri_ref[s], a.tri_ref[a.n_tris + s], a.tri_ref[2 * a.n_tris + s]};
+      T f[3][3];
+      bad = !tri_element<T>(xs, G, a.tri_ref[3 * a.n_tris + s], a.law[p], mu, mu2, f);
+      for (int v = 0; v < 3; ++v)
+        for (int c = 0; c < 3; ++c) reinterpret_cast<T*>(L.ef_tri)[(v * 3 + c) * (int64_t)L.n_tri + e] = f[v][c];
+      double q[3][3];
+      for (int v = 0; v < 3; ++v)
+        for (int c = 0; c < 3; ++c) q[v][c] = (double)xs[v][c] - o[c];
+      double u[3], w[3];
+      for (int c = 0; c < 3; ++c) {
+        u[c] = q[1][c] - q[0][c];
+        w[c] = q[2][c] - q[0][c];
+      }
+      const double nx = u[1] * w[2] - u[2] * w[1], ny = u[2] * w[0] - u[0] * w[2], nz = u[0] * w[1] - u[1] * w[0];
+      const double cone = (q[0][0] * nx + q[0][1] * ny + q[0][2] * nz) * (1.0 / 6.0);
+      r[0] = cone;
+      r[1] = 0.5 * fsqrt(nx * nx + ny * ny + nz * nz);
+      for (int c = 0; c < 3; ++c) r[2 + c] = cone * (q[0][c] + q[1][c] + q[2][c]) * 0.25;
+    } else {
+      const int et = e - L.n_tri;
+      T xs[4][3];
+      for (int v = 0; v < 4; ++v) large_pos(x, N, n0 + a.tet_local[v * a.n_tets + s], xs[v]);
+      double G[6];
+      for (int k = 0; k < 6; ++k) G[k] = a.tet_ref[k * a.n_tets + s];
+      T f[4][3];
+      bad = !tet_element<T>(xs, G, a.tet_ref[6 * a.n_tets + s], mu, mu2, f);
+      for (int v = 0; v < 4; ++v)
+        for (int c = 0; c < 3; ++c) reinterpret_cast<T*>(L.ef_tet)[(v * 3 + c) * (int64_t)L.n_tet + et] = f[v][c];
+      double q[4][3];
+      for (int v = 0; v < 4; ++v)
+        for (int c = 0; c < 3; ++c) q[v][c] = (double)xs[v][c] - o[c];
+      double d[3][3];
+      for (int v = 0; v < 3; ++v)
+        for (int c = 0; c < 3; ++c) d[v][c] = q[v + 1][c] - q[0][c];
+      const double vol = (d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                          d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                          d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0])) / 6.0;
+      r[0] = vol;
+      for (int c = 0; c < 3; ++c) r[2 + c] = vol * (q[0][c] + q[1][c] + q[2][c] + q[3][c]) * 0.25;
+    }
+    if (red_terms)
+      for (int k = 0; k < 5; ++k) red_terms[k * (int64_t)(L.n_tri + L.n_tet) + e] = r[k];
+  }
+  const unsigned long long m = __ballot(bad);
+  if (m && lane == __ffsll((long long)m) - 1) atomicAdd(a.status + 0, (unsigned long long)__popcll(m));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_large_curv(const ForceArgs a, const LargeArgs L, const T* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n_node) return;
+  const int p = L.node_part[i];
+  if (a.kb[p] == 0.0 || a.ring_start == nullptr) return;
+  const int n0 = a.node_start[p], lb = L.node_base[i];  // lb: the compact index of the particle's node 0
+  const int k = i - lb;
+  const int64_t N = a.n_nodes;
+  T* kh = reinterpret_cast<T*>(L.kh);
+  T* fb = reinterpret_cast<T*>(L.fb);
+  const int* rs = a.ring_start + n0;
+  if (rs[k + 1] - rs[k] < 3) {  // node without a closed fan: no curvature, no bending force
+    kh[i] = 0;
+    for (int c = 0; c < 3; ++c) fb[c * (int64_t)L.n_node + i] = 0;
+    return;
+  }
+  const T kH0 = (T)(-0.5 * a.c0[p]);
+  const T kb = (T)a.kb[p];
+  RingGeom<T> R;
+  ring_geometry<T>(k, a.ring, rs[k], rs[k + 1], x + n0, x + N + n0, x + 2 * N + n0, R);
+  T kH, kG, nv[3];
+  ring_curvature(R, true, kH, kG, nv);
+  const T gk = kH - kH0;
+  kh[i] = gk;
+  const T s2 = T(4) * kb * gk * (kH * kH - kG + kH0 * kH) * R.A;
+  for (int c = 0; c < 3; ++c) fb[c * (int64_t)L.n_node + i] = s2 * nv[c];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_large_lap(const ForceArgs a, const LargeArgs L, const T* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n_node) return;
+  const int p = L.node_part[i];
+  if (a.kb[p] == 0.0 || a.ring_start == nullptr) return;
+  const int n0 = a.node_start[p], lb = L.node_base[i];
+  const int k = i - lb;
+  const int64_t N = a.n_nodes;
+  const int* rs = a.ring_start + n0;
+  if (rs[k + 1] - rs[k] < 3) return;
+  T* fb = reinterpret_cast<T*>(L.fb);
+  T Nv[3], lap;
+  ring_laplacian<T>(k, a.ring, rs[k], rs[k + 1], x + n0, x + N + n0, x + 2 * N + n0,
+                    reinterpret_cast<const T*>(L.kh) + lb, Nv, lap);
+  const T s1 = (T)a.kb[p] * lap * frcp(fsqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]));
+  for (int c = 0; c < 3; ++c) fb[c * (int64_t)L.n_node + i] += s1 * Nv[c];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_large_gather(const ForceArgs a, const LargeArgs L, T* __restrict__ fout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  unsigned int nonfinite = 0;
+  if (i < L.n_node) {
+    const int p = L.node_part[i];
+    const int k = a.node_start[p] + (i - L.node_base[i]);
+    const T* ef_tri = reinterpret_cast<const T*>(L.ef_tri);
+    const T* ef_tet = reinterpret_cast<const T*>(L.ef_tet);
+    T f[3] = {T(0), T(0), T(0)};
+    for (int j = L.gather_start[i]; j < L.gather_start[i + 1]; ++j) {
+      const int g = L.gather[j];  // element e and corner v: e * 4 + v, tetrahedra after the triangles
+      const int e = g >> 2, v = g & 3;
+      for (int c = 0; c < 3; ++c)
+        f[c] += e < L.n_tri ? ef_tri[(v * 3 + c) * (int64_t)L.n_tri + e]
+                            : ef_tet[(v * 3 + c) * (int64_t)L.n_tet + (e - L.n_tri)];
+    }
+    if (a.kb[p] != 0.0 && a.ring_start != nullptr) {
+      const T* fb = reinterpret_cast<const T*>(L.fb);
+      for (int c = 0; c < 3; ++c) f[c] += fb[c * (int64_t)L.n_node + i];
+    }
+    for (int c = 0; c < 3; ++c) {
+      if (!isfinite(f[c])) ++nonfinite;
+      fout[c * (int64_t)a.n_nodes + k] = f[c];
+    }
+  }
+  const unsigned long long m = __ballot(nonfinite != 0);
+  // every lane's count, summed over the wavefront
+  unsigned int total = nonfinite;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) total += __shfl_xor(total, off, kWave);
+  if (m && lane == 0) atomicAdd(a.status + 1, (unsigned long long)total);
+}
+
+// One workgroup per large particle: its elements' reduction terms in element order, strided over the
+// threads, then the deterministic block sum.
+__global__ void __launch_bounds__(256) k_large_reduce(const ForceArgs a, const LargeArgs L,
+                                                       const double* __restrict__ red_terms,
+                                                       const double* __restrict__ origin_x, int64_t N,
+                                                       int fp64, const double* __restrict__ anchor,
+                                                       double* __restrict__ red) {
+  __shared__ double red_lds[5 * 16];
+  const int lp = blockIdx.x;
+  const int p = L.part[lp];
+  const int ne = L.n_tri + L.n_tet;
+  double r[5] = {0, 0, 0, 0, 0};
+  for (int t = L.tri_begin[lp] + threadIdx.x; t < L.tri_begin[lp + 1]; t += blockDim.x)
+    for (int k = 0; k < 5; ++k) r[k] += red_terms[k * (int64_t)ne + t];
+  for (int t = L.tet_begin[lp] + threadIdx.x; t < L.tet_begin[lp + 1]; t += blockDim.x)
+    for (int k = 0; k < 5; ++k) r[k] += red_terms[k * (int64_t)ne + L.n_tri + t];
+  block_sum<5>(r, red_lds);
+  if (threadIdx.x == 0) {
+    const int n0 = a.node_start[p];
+    double base[3] = {0.0, 0.0, 0.0};
+    if (fp64)
+      for (int c = 0; c < 3; ++c) base[c] = origin_x[c * N + n0];
+    if (anchor)
+      for (int c = 0; c < 3; ++c) base[c] += anchor[3 * p + c];
+    const double V = r[0];
+    red[5 * p + 0] = V;
+    red[5 * p + 1] = r[1];
+    for (int c = 0; c < 3; ++c) red[5 * p + 2 + c] = base[c] + r[2 + c] / V;
+  }
+}
+
+template <typename T>
+static hipError_t launch_large_t(const PlanDev& P, const T* x, const double* anchor, T* f, double* red,
+                                 hipStream_t st) {
+  const LargeArgs& L = P.large;
+  const int B = 256;
+  const int ne = L.n_tri + L.n_tet;
+  if (ne > 0)
+    hipLaunchKernelGGL(k_large_elems<T>, dim3((ne + B - 1) / B), dim3(B), 0, st, P.fargs, L, x,
+                       red ? L.red_terms : (double*)nullptr);
+  if (L.n_node > 0) {
+    if (L.any_bending) {
+      hipLaunchKernelGGL(k_large_curv<T>, dim3((L.n_node + B - 1) / B), dim3(B), 0, st, P.fargs, L, x);
+      hipLaunchKernelGGL(k_large_lap<T>, dim3((L.n_node + B - 1) / B), dim3(B), 0, st, P.fargs, L, x);
+    }
+    hipLaunchKernelGGL(k_large_gather<T>, dim3((L.n_node + B - 1) / B), dim3(B), 0, st, P.fargs, L, f);
+  }
+  if (red)
+    hipLaunchKernelGGL(k_large_reduce, dim3(L.n_part), dim3(B), 0, st, P.fargs, L, L.red_terms,
+                       sizeof(T) == 8 ? (const double*)x : (const double*)nullptr, (int64_t)P.n_nodes,
+                       sizeof(T) == 8 ? 1 : 0, anchor, red);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ host launchers
 hipError_t launch_ref_setup(const PlanDev& P, const double* X, hipStream_t st) {
   const int B = 256;
@@ -647,11 +887,21 @@ size_t force_lds_bytes(const PlanDev& P, int dtype) {
   return dtype == 0 ? force_lds<float>(P, use_pos_lds<float>(P)) : force_lds<double>(P, use_pos_lds<double>(P));
 }
 
+size_t force_lds_per_node(bool has_bending) { return (size_t)(3 + (has_bending ? 1 : 0)) * sizeof(double); }
+
 hipError_t launch_forces(const PlanDev& P, int dtype, const void* x, const double* anchor, void* f, double* red,
                          int block, hipStream_t st) {
   if (P.n_particles == 0) return hipSuccess;
   P.timer->begin(K_FORCES, st);
-  const dim3 g(P.n_particles), b(block);
+  if (P.large.n_part > 0) {
+    const hipError_t e = dtype == 0 ? launch_large_t<float>(P, (const float*)x, anchor, (float*)f, red, st)
+                                    : launch_large_t<double>(P, (const double*)x, anchor, (double*)f, red, st);
+    if (e != hipSuccess || P.n_lds_part == 0) {
+      P.timer->end(st);
+      return e;
+    }
+  }
+  const dim3 g(P.n_lds_part), b(block);
   if (dtype == 0) {
     if (use_pos_lds<float>(P))
       hipLaunchKernelGGL((k_forces<float, true>), g, b, force_lds<float>(P, true), st, P.fargs, (const float*)x,

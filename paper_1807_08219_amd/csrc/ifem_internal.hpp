@@ -28,9 +28,38 @@ struct ForceArgs {
   const double* tet_ref;     // [7][n_tets] G11 G12 G13 G22 G23 G33 V0
   const int32_t* ring_start; // [n_nodes + 1]: one-rings of bending and (when all close) membrane nodes, or null
   const int32_t* ring;       // one-ring neighbours, particle-local ids
+  const int32_t* lds_part;   // [grid of k_forces] the particles it takes, or null for all of them
   unsigned long long* status;
-  int32_t n_nodes, n_tris, n_tets, cap;
+  int32_t n_nodes, n_tris, n_tets;
+  int32_t cap;               // largest particle k_forces takes (nodes): the stride of its LDS arrays
+  int32_t cap_mem;           // largest membrane (the volume correction's LDS)
+  int32_t cap_solid;         // largest solid (the fluid-stress kernel's LDS)
   int32_t has_bending;       // the force kernel's LDS holds a curvature array
+};
+
+// Particles too large for one workgroup's LDS (their forces by the global-memory kernels).
+struct LargeArgs {
+  int32_t n_part, n_tri, n_tet, n_node, any_bending;
+  const int32_t* part;          // [n_part] particle ids
+  const int32_t* tri_begin;     // [n_part + 1] first large triangle of each large particle
+  const int32_t* tet_begin;     // [n_part + 1]
+  const int32_t* tri_slot;      // [n_tri] element slot of each large triangle
+  const int32_t* tri_part;      // [n_tri] its particle
+  const int32_t* tet_slot;      // [n_tet]
+  const int32_t* tet_part;      // [n_tet]
+  const int32_t* node_part;     // [n_node] particle of each large node (compact numbering)
+  const int32_t* node_base;     // [n_node] compact index of that particle's first node
+  const int32_t* node_lp;       // [n_node] index of that particle in part
+  const int32_t* part_base;     // [n_part + 1] compact index of each large particle's first node
+  const int32_t* gather_start;  // [n_node + 1]
+  const int32_t* gather;        // element shares of each node: e * 4 + corner, tetrahedra after triangles
+  void* ef_tri;                 // [9][n_tri] element nodal forces (sized for float64)
+  void* ef_tet;                 // [12][n_tet]
+  void* kh;                     // [n_node] kH - kH0
+  void* fb;                     // [3][n_node] bending force
+  double* red_terms;            // [5][n_tri + n_tet] element terms of the reductions
+  double* vol_terms;            // [4][n_node] node terms of the volume correction's sums
+  double* lam;                  // [n_part] its multipliers
 };
 
 // Everything the transfer kernels read.
@@ -167,6 +196,8 @@ struct PlanDev {
   unsigned long long* status;  // [5]
   double* vref;                // [n_p] enclosed volume of every membrane in the reference configuration
   ForceArgs fargs;
+  int32_t n_lds_part;  // particles k_forces takes
+  LargeArgs large;     // the others
   TransferArgs targs;
   ContactArgs cargs;
   KernelTimer* timer;  // host object owned by the plan
@@ -178,10 +209,11 @@ hipError_t prepare_force_kernels(const PlanDev& P);
 size_t force_lds_bytes(const PlanDev& P, int dtype);
 hipError_t launch_forces(const PlanDev& P, int dtype, const void* x, const double* anchor, void* f, double* red,
                          int block, hipStream_t st);
+// LDS of k_forces for a particle of nn nodes (float64 sizing): a particle above the limit is large
+size_t force_lds_per_node(bool has_bending);
 
 // ---- launchers (ifem_volume.hip)
 hipError_t prepare_volume_kernels(const PlanDev& P);
-bool volume_fits(const PlanDev& P);  // the largest particle's alpha sums fit one workgroup's LDS
 hipError_t launch_ref_volume(const PlanDev& P, const double* X, double* vref, hipStream_t st);
 hipError_t launch_volume(const PlanDev& P, int dtype, const void* x, const double* V0, void* x_out, double* lam,
                          hipStream_t st);

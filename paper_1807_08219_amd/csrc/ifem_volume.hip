@@ -50,6 +50,25 @@ __device__ __forceinline__ void cross_acc(const double u[3], const double w[3], 
   sz += u[0] * w[1] - u[1] * w[0];
 }
 
+// The multiplier L from the four node sums r (alpha.beta, x.beta, |alpha|^2,
+// x.alpha): the cubic's coefficients, then Newton's iteration from 0.  A run
+// that does not converge to a finite root is counted in status[4].
+__device__ inline double volume_multiplier(const double r[4], double target, unsigned long long* status) {
+  const double A = r[0] * (1.0 / 18.0), B = r[1] * (1.0 / 6.0), C = -2.0 * r[2];
+  const double D = r[3] * (-2.0 / 3.0) - target;
+  double L = 0.0;
+  bool done = false;
+  for (int it = 0; it < 100 && !done; ++it) {
+    const double f = ((A * L + B) * L + C) * L + D;
+    const double df = (3.0 * A * L + 2.0 * B) * L + C;
+    const double step = f / df;
+    L -= step;
+    done = fabs(step) <= 1e-15 * fabs(L) || f == 0.0;
+  }
+  if (!done || !isfinite(L)) atomicAdd(status + 4, 1ull);
+  return L;
+}
+
 // One workgroup per particle: alpha of every node in LDS (float64), two node
 // passes, a block reduction, the cubic solved by one thread, the write-out.
 // Positions and one-rings are gathered from global memory (the caches): the
@@ -66,7 +85,7 @@ __global__ void __launch_bounds__(512) k_volume(const ForceArgs a, const T* x, c
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red_lds[4 * 16];
   __shared__ double lam_s;
-  const int p = blockIdx.x;
+  const int p = a.lds_part ? a.lds_part[blockIdx.x] : (int)blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n0 = a.node_start[p];
   const int nn = a.node_start[p + 1] - n0;
@@ -144,8 +163,8 @@ __global__ void __launch_bounds__(512) k_volume(const ForceArgs a, const T* x, c
     }
     const double ax = sx * (-1.0 / 12.0), ay = sy * (-1.0 / 12.0), az = sz * (-1.0 / 12.0);
     al[k] = ax;
-    al[a.cap + k] = ay;
-    al[2 * a.cap + k] = az;
+    al[a.cap_mem + k] = ay;
+    al[2 * a.cap_mem + k] = az;
     r[2] += ax * ax + ay * ay + az * az;
     r[3] += (xk[0] - o[0]) * ax + (xk[1] - o[1]) * ay + (xk[2] - o[2]) * az;
   }
@@ -171,7 +190,7 @@ __global__ void __launch_bounds__(512) k_volume(const ForceArgs a, const T* x, c
     if (re == rb) continue;
     double bx = 0.0, by = 0.0, bz = 0.0;
     int j = ring[re - 1];
-    double u[3] = {al[j], al[a.cap + j], al[2 * a.cap + j]};
+    double u[3] = {al[j], al[a.cap_mem + j], al[2 * a.cap_mem + j]};
     for (int m0 = rb; m0 < re; m0 += kRingChunk) {
       int js[kRingChunk];
 #pragma unroll
@@ -180,8 +199,8 @@ __global__ void __launch_bounds__(512) k_volume(const ForceArgs a, const T* x, c
 #pragma unroll
       for (int q = 0; q < kRingChunk; ++q) {
         w[q][0] = al[js[q]];
-        w[q][1] = al[a.cap + js[q]];
-        w[q][2] = al[2 * a.cap + js[q]];
+        w[q][1] = al[a.cap_mem + js[q]];
+        w[q][2] = al[2 * a.cap_mem + js[q]];
       }
 #pragma unroll
       for (int q = 0; q < kRingChunk; ++q) {
@@ -191,23 +210,12 @@ __global__ void __launch_bounds__(512) k_volume(const ForceArgs a, const T* x, c
         u[2] = w[q][2];
       }
     }
-    r[0] += al[k] * bx + al[a.cap + k] * by + al[2 * a.cap + k] * bz;
+    r[0] += al[k] * bx + al[a.cap_mem + k] * by + al[2 * a.cap_mem + k] * bz;
     r[1] += xk[0] * bx + xk[1] * by + xk[2] * bz;
   }
   block_sum<4>(r, red_lds);
   if (tid == 0) {
-    const double A = r[0] * (1.0 / 18.0), B = r[1] * (1.0 / 6.0), C = -2.0 * r[2];
-    const double D = r[3] * (-2.0 / 3.0) - (V0 ? V0[p] : vref[p]);
-    double L = 0.0;
-    bool done = false;
-    for (int it = 0; it < 100 && !done; ++it) {
-      const double f = ((A * L + B) * L + C) * L + D;
-      const double df = (3.0 * A * L + 2.0 * B) * L + C;
-      const double step = f / df;
-      L -= step;
-      done = fabs(step) <= 1e-15 * fabs(L) || f == 0.0;
-    }
-    if (!done || !isfinite(L)) atomicAdd(a.status + 4, 1ull);
+    const double L = volume_multiplier(r, V0 ? V0[p] : vref[p], a.status);
     lam_s = L;
     if (lam_out) lam_out[p] = L;
   }
@@ -219,11 +227,140 @@ __global__ void __launch_bounds__(512) k_volume(const ForceArgs a, const T* x, c
     const T p1[3] = {xx[i], xy[i], xz[i]};
     const T p2[3] = {xx[i2], xy[i2], xz[i2]};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) x_out[c * N + n0 + i] = (T)((double)p1[c] + L * al[c * a.cap + i]);
+    for (int c = 0; c < 3; ++c) x_out[c * N + n0 + i] = (T)((double)p1[c] + L * al[c * a.cap_mem + i]);
     if (i + nt < nn)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) x_out[c * N + n0 + i2] = (T)((double)p2[c] + L * al[c * a.cap + i2]);
+      for (int c = 0; c < 3; ++c) x_out[c * N + n0 + i2] = (T)((double)p2[c] + L * al[c * a.cap_mem + i2]);
   }
+}
+
+// ------------------------------------------------------------------ membranes larger than a workgroup's LDS
+// The same sums with alpha in global memory (float64), one thread per node and
+// a launch per dependency: alpha (needs positions), beta (needs every
+// neighbour's alpha), the multiplier (one workgroup per particle sums the node
+// terms in a fixed order), the move.  Solids among the large particles keep
+// their nodes.  x and x_out may be the same array: the move reads only the
+// node it writes, after every other read has finished.
+template <typename T>
+__global__ void __launch_bounds__(256) k_large_vol_alpha(const ForceArgs a, const LargeArgs L, const T* x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n_node) return;
+  const int p = L.node_part[i];
+  if (a.pcol_tri[p] == a.pcol_tri[p + 1]) return;
+  const int n0 = a.node_start[p], k = i - L.node_base[i];
+  const int64_t N = a.n_nodes;
+  const T* xx = x + n0;
+  const T* xy = x + N + n0;
+  const T* xz = x + 2 * N + n0;
+  double o[3] = {0.0, 0.0, 0.0};
+  if (sizeof(T) == 8) {
+    o[0] = (double)xx[0];
+    o[1] = (double)xy[0];
+    o[2] = (double)xz[0];
+  }
+  const int32_t* rs = a.ring_start + n0;
+  const int rb = rs[k], re = rs[k + 1];
+  const double xk[3] = {(double)xx[k], (double)xy[k], (double)xz[k]};
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  if (re > rb) {
+    int j = a.ring[re - 1];
+    double u[3] = {(double)xx[j] - xk[0], (double)xy[j] - xk[1], (double)xz[j] - xk[2]};
+    for (int m = rb; m < re; ++m) {
+      j = a.ring[m];
+      const double w[3] = {(double)xx[j] - xk[0], (double)xy[j] - xk[1], (double)xz[j] - xk[2]};
+      cross_acc(u, w, sx, sy, sz);
+      u[0] = w[0];
+      u[1] = w[1];
+      u[2] = w[2];
+    }
+  }
+  const double ax = sx * (-1.0 / 12.0), ay = sy * (-1.0 / 12.0), az = sz * (-1.0 / 12.0);
+  double* al = reinterpret_cast<double*>(L.fb);
+  const int64_t M = L.n_node;
+  al[i] = ax;
+  al[M + i] = ay;
+  al[2 * M + i] = az;
+  L.vol_terms[2 * M + i] = ax * ax + ay * ay + az * az;
+  L.vol_terms[3 * M + i] = (xk[0] - o[0]) * ax + (xk[1] - o[1]) * ay + (xk[2] - o[2]) * az;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_large_vol_beta(const ForceArgs a, const LargeArgs L, const T* x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n_node) return;
+  const int p = L.node_part[i];
+  if (a.pcol_tri[p] == a.pcol_tri[p + 1]) return;
+  const int n0 = a.node_start[p], lb = L.node_base[i], k = i - lb;
+  const int64_t N = a.n_nodes, M = L.n_node;
+  double o[3] = {0.0, 0.0, 0.0};
+  if (sizeof(T) == 8)
+    for (int c = 0; c < 3; ++c) o[c] = (double)x[c * N + n0];
+  const double xk[3] = {(double)x[n0 + k] - o[0], (double)x[N + n0 + k] - o[1], (double)x[2 * N + n0 + k] - o[2]};
+  const double* al = reinterpret_cast<const double*>(L.fb) + lb;  // the particle's alpha
+  const int32_t* rs = a.ring_start + n0;
+  const int rb = rs[k], re = rs[k + 1];
+  double bx = 0.0, by = 0.0, bz = 0.0;
+  if (re > rb) {
+    int j = a.ring[re - 1];
+    double u[3] = {al[j], al[M + j], al[2 * M + j]};
+    for (int m = rb; m < re; ++m) {
+      j = a.ring[m];
+      const double w[3] = {al[j], al[M + j], al[2 * M + j]};
+      cross_acc(u, w, bx, by, bz);
+      u[0] = w[0];
+      u[1] = w[1];
+      u[2] = w[2];
+    }
+  }
+  L.vol_terms[i] = al[k] * bx + al[M + k] * by + al[2 * M + k] * bz;
+  L.vol_terms[M + i] = xk[0] * bx + xk[1] * by + xk[2] * bz;
+}
+
+// One workgroup per large particle: the node terms summed (thread-strided in
+// node order, then the fixed block sum), the multiplier into lam[lp].
+__global__ void __launch_bounds__(256) k_large_vol_solve(const ForceArgs a, const LargeArgs L,
+                                                          const double* __restrict__ V0,
+                                                          const double* __restrict__ vref, double* __restrict__ lam,
+                                                          double* __restrict__ lam_out) {
+  __shared__ double red_lds[4 * 16];
+  const int lp = blockIdx.x, p = L.part[lp];
+  const int n0 = a.node_start[p], nn = a.node_start[p + 1] - n0;
+  if (a.pcol_tri[p] == a.pcol_tri[p + 1]) {
+    if (threadIdx.x == 0) {
+      lam[lp] = 0.0;
+      if (lam_out) lam_out[p] = 0.0;
+    }
+    return;
+  }
+  const int lb = L.part_base[lp];  // the particle's nodes are contiguous in the compact numbering
+  const int64_t M = L.n_node;
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < nn; k += blockDim.x)
+    for (int c = 0; c < 4; ++c) r[c] += L.vol_terms[c * M + lb + k];
+  block_sum<4>(r, red_lds);
+  if (threadIdx.x == 0) {
+    const double Lm = volume_multiplier(r, V0 ? V0[p] : vref[p], a.status);
+    lam[lp] = Lm;
+    if (lam_out) lam_out[p] = Lm;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_large_vol_apply(const ForceArgs a, const LargeArgs L, const T* x,
+                                                          const double* __restrict__ lam, T* x_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n_node) return;
+  const int p = L.node_part[i];
+  const int k = a.node_start[p] + (i - L.node_base[i]);
+  const int64_t N = a.n_nodes, M = L.n_node;
+  if (a.pcol_tri[p] == a.pcol_tri[p + 1]) {
+    if (x_out != x)
+      for (int c = 0; c < 3; ++c) x_out[c * N + k] = x[c * N + k];
+    return;
+  }
+  const double Lm = lam[L.node_lp[i]];
+  const double* al = reinterpret_cast<const double*>(L.fb);
+  for (int c = 0; c < 3; ++c) x_out[c * N + k] = (T)((double)x[c * N + k] + Lm * al[c * M + i]);
 }
 
 // Reference volume of every membrane (float64 reference positions X [3][n_nodes]).
@@ -250,17 +387,14 @@ __global__ void __launch_bounds__(256) k_ref_volume(const ForceArgs a, const dou
 }
 
 // ------------------------------------------------------------------ host launchers
-static size_t volume_lds(const PlanDev& P) { return (size_t)3 * P.cap * sizeof(double); }
-
-bool volume_fits(const PlanDev& P) { return volume_lds(P) + 1024 <= 160 * 1024; }
+static size_t volume_lds(const PlanDev& P) { return (size_t)3 * std::max(P.fargs.cap_mem, 1) * sizeof(double); }
 
 // Threads per workgroup: 512, or fewer for small particles.  Two 512-thread
 // workgroups (16 waves) share a compute unit; 576 threads, which would save
 // the sixth pass of a 2562-node red cell, measured slower.
-static int volume_block(const PlanDev& P) { return std::min(512, (P.cap + 63) / 64 * 64); }
+static int volume_block(const PlanDev& P) { return std::max(64, std::min(512, (P.fargs.cap_mem + 63) / 64 * 64)); }
 
 hipError_t prepare_volume_kernels(const PlanDev& P) {
-  if (!volume_fits(P)) return hipSuccess;  // ifem_volume_correct refuses such plans
   hipError_t e = hipFuncSetAttribute((const void*)k_volume<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)volume_lds(P));
   if (e == hipSuccess)
@@ -279,13 +413,35 @@ hipError_t launch_volume(const PlanDev& P, int dtype, const void* x, const doubl
                          hipStream_t st) {
   if (P.n_particles == 0) return hipSuccess;
   P.timer->begin(K_VOLUME, st);
-  const dim3 g(P.n_particles), b(volume_block(P));
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_volume<float>, g, b, volume_lds(P), st, P.fargs, (const float*)x, V0, P.vref,
-                       (float*)x_out, lam);
-  else
-    hipLaunchKernelGGL(k_volume<double>, g, b, volume_lds(P), st, P.fargs, (const double*)x, V0, P.vref,
-                       (double*)x_out, lam);
+  const LargeArgs& L = P.large;
+  const int B = 256;
+  const dim3 gn((L.n_node + B - 1) / B);
+  // the large membranes read x before the per-particle kernel may rewrite it in place (x_out == x)
+  if (L.n_part > 0) {
+    if (dtype == 0) {
+      hipLaunchKernelGGL(k_large_vol_alpha<float>, gn, dim3(B), 0, st, P.fargs, L, (const float*)x);
+      hipLaunchKernelGGL(k_large_vol_beta<float>, gn, dim3(B), 0, st, P.fargs, L, (const float*)x);
+    } else {
+      hipLaunchKernelGGL(k_large_vol_alpha<double>, gn, dim3(B), 0, st, P.fargs, L, (const double*)x);
+      hipLaunchKernelGGL(k_large_vol_beta<double>, gn, dim3(B), 0, st, P.fargs, L, (const double*)x);
+    }
+    hipLaunchKernelGGL(k_large_vol_solve, dim3(L.n_part), dim3(B), 0, st, P.fargs, L, V0, P.vref, L.lam, lam);
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_large_vol_apply<float>, gn, dim3(B), 0, st, P.fargs, L, (const float*)x, L.lam,
+                         (float*)x_out);
+    else
+      hipLaunchKernelGGL(k_large_vol_apply<double>, gn, dim3(B), 0, st, P.fargs, L, (const double*)x, L.lam,
+                         (double*)x_out);
+  }
+  if (P.n_lds_part > 0) {
+    const dim3 g(P.n_lds_part), b(volume_block(P));
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_volume<float>, g, b, volume_lds(P), st, P.fargs, (const float*)x, V0, P.vref,
+                         (float*)x_out, lam);
+    else
+      hipLaunchKernelGGL(k_volume<double>, g, b, volume_lds(P), st, P.fargs, (const double*)x, V0, P.vref,
+                         (double*)x_out, lam);
+  }
   P.timer->end(st);
   return hipGetLastError();
 }
