@@ -169,9 +169,8 @@ typedef struct {
 /* Launch shape.  Pass NULL to ifem_plan_create for the shape that
  * ifem_plan_autotune last chose for plans of the same sizes on the same kind of
  * device, else the defaults {tile 32 x 16 x 8, block_forces 512, block_points
- * 256}, the fastest measured on dense red-cell suspensions; with fewer than one
- * node per 20 grid cells (sparse boxes of mixed particles) the default tile is
- * 16 x 16 x 16.  The spread region
+ * 256}, the fastest measured on dense red-cell suspensions and on sparse
+ * boxes of mixed particles.  The spread region
  * of a tile, (tile_x + 5)(tile_y + 2)(tile_z + 2) cells, must not exceed 13568
  * (12 bytes of LDS per cell in float64). */
 typedef struct {

@@ -623,7 +623,7 @@ ifem_status build_spread(ifem_plan plan, const int32_t tile[3], hipStream_t st) 
   const int64_t list_cap = (int64_t)3 * lists_per_entry * P.n_nodes;
   if (list_cap >= ((int64_t)1 << 31)) return fail(IFEM_ERR_UNSUPPORTED, "too many nodes for the spread lists");
   const int region_cells = (tile[0] + 5) * (tile[1] + 2) * (tile[2] + 2);
-  const int halo_cells = (tile[0] + 1) * (2 * (tile[1] + tile[2]) + 4);
+  const int halo_cells = tile[0] * (2 * (tile[1] + tile[2]) + 4);
   DeviceBuffers mem;
   BoxDev* d_boxes = nullptr;
   int32_t *d_tile_box = nullptr, *d_cnt = nullptr, *d_off = nullptr, *d_cur = nullptr, *d_list = nullptr,
@@ -691,14 +691,9 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   const ifem_mesh_desc& m = *mesh;
   hipStream_t st = (hipStream_t)stream;
 
-  // default launch shape, the fastest measured: 32 x 16 x 8 tiles on dense suspensions; cubic 16^3
-  // tiles where nodes are sparse (fewer than one per 20 cells), since most tiles then hold none
+  // default launch shape, the fastest measured on dense suspensions and on sparse boxes of mixed
+  // particles alike: 32 x 16 x 8 tiles
   ifem_tuning tn{{32, 16, 8}, 512, 256};
-  {
-    double cells = 0.0;
-    for (int b = 0; b < n_boxes; ++b) cells += (double)boxes[b].n[0] * boxes[b].n[1] * boxes[b].n[2];
-    if (cells > 0.0 && (double)m.n_nodes < 0.05 * cells) tn.tile[0] = tn.tile[1] = tn.tile[2] = 16;
-  }
   if (tuning) {
     tn = *tuning;
   } else {
@@ -1470,18 +1465,33 @@ ifem_status ifem_plan_autotune(ifem_plan plan, int32_t dtype, const void* x, con
   static const int32_t kTiles[][3] = {{32, 16, 8}, {16, 16, 16}, {64, 8, 8}, {32, 32, 4}, {16, 32, 8},
                                       {32, 8, 8},  {16, 16, 8},  {64, 16, 4}, {32, 16, 16}};
   const ifem_tuning before = plan->tune;
+  // bring the clocks up first (a freshly started device times its first candidates slow), then time the
+  // candidates in order and again in reverse order and keep each one's better median, so that a drift
+  // during the tuning favours no candidate
+  for (int i = 0; i < 30; ++i)
+    if (launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st) != hipSuccess ||
+        launch_interp(P, dtype, x, anchor, grid_u, v_out, before.block_points, st) != hipSuccess)
+      break;
+  constexpr int kNTiles = (int)(sizeof kTiles / sizeof kTiles[0]);
+  float tile_ms[kNTiles];
+  for (int i = 0; i < kNTiles; ++i) tile_ms[i] = INFINITY;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int j = 0; j < kNTiles; ++j) {
+      const int i = pass == 0 ? j : kNTiles - 1 - j;
+      if (!tile_fits_lds(kTiles[i])) continue;
+      if (build_spread(plan, kTiles[i], st) != IFEM_OK) continue;  // e.g. no memory for this shape's workspace
+      const float ms = timed([&] { return launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st); }, [&] {
+        return launch_interp(P, dtype, x, anchor, grid_u, v_out, before.block_points, st);
+      });
+      tile_ms[i] = std::min(tile_ms[i], ms);
+    }
   int32_t best[3] = {before.tile[0], before.tile[1], before.tile[2]};
   float best_ms = INFINITY;
-  for (const auto& t : kTiles) {
-    if (!tile_fits_lds(t)) continue;
-    if (build_spread(plan, t, st) != IFEM_OK) continue;  // e.g. no memory for this shape's workspace
-    const float ms = timed([&] { return launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st); },
-                           [&] { return launch_interp(P, dtype, x, anchor, grid_u, v_out, before.block_points, st); });
-    if (ms < best_ms) {
-      best_ms = ms;
-      for (int a = 0; a < 3; ++a) best[a] = t[a];
+  for (int i = 0; i < kNTiles; ++i)
+    if (tile_ms[i] < best_ms) {
+      best_ms = tile_ms[i];
+      for (int a = 0; a < 3; ++a) best[a] = kTiles[i][a];
     }
-  }
   if (best[0] != P.targs.tile[0] || best[1] != P.targs.tile[1] || best[2] != P.targs.tile[2]) {
     s = build_spread(plan, best, st);
     if (s != IFEM_OK) {
@@ -1491,16 +1501,22 @@ ifem_status ifem_plan_autotune(ifem_plan plan, int32_t dtype, const void* x, con
     }
   }
   // threads per workgroup of the point kernels, timed on the interpolation
+  static const int kBlocks[] = {64, 128, 256};
+  float bp_ms[3] = {INFINITY, INFINITY, INFINITY};
+  for (int pass = 0; pass < 2; ++pass)
+    for (int j = 0; j < 3; ++j) {
+      const int i = pass == 0 ? j : 2 - j;
+      const float ms = timed([&] { return launch_interp(P, dtype, x, anchor, grid_u, v_out, kBlocks[i], st); },
+                             [&] { return launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st); });
+      bp_ms[i] = std::min(bp_ms[i], ms);
+    }
   int best_bp = before.block_points;
   float best_bp_ms = INFINITY;
-  for (int bp : {64, 128, 256}) {
-    const float ms = timed([&] { return launch_interp(P, dtype, x, anchor, grid_u, v_out, bp, st); },
-                           [&] { return launch_spread_tiled(P, P.targs, dtype, x, anchor, F, grid, st); });
-    if (ms < best_bp_ms) {
-      best_bp_ms = ms;
-      best_bp = bp;
+  for (int i = 0; i < 3; ++i)
+    if (bp_ms[i] < best_bp_ms) {
+      best_bp_ms = bp_ms[i];
+      best_bp = kBlocks[i];
     }
-  }
   plan->tune.block_points = best_bp;
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);

@@ -314,6 +314,19 @@ __device__ __forceinline__ void nearest_node(const BoxDev& B, int comp, const do
   }
 }
 
+// The wrapped nearest nodes of one position for all three staggered components at once: per axis
+// the lattice coordinates with stagger 0 (the component along that axis) and 1/2 (the other two),
+// each by the rule of lattice_coord, so the bases equal those of nearest_node bit for bit.
+// Component d's base along axis a is (a == d ? b0[a] : bh[a]).
+__device__ __forceinline__ void nearest_bases(const BoxDev& B, const double p[3], int32_t b0[3], int32_t bh[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double dp = p[a] - B.origin[a];
+    b0[a] = wrap_index(B, a, floor(__builtin_fma(dp, B.inv_h, -0.0) + 0.5));
+    bh[a] = wrap_index(B, a, floor(__builtin_fma(dp, B.inv_h, -0.5) + 0.5));
+  }
+}
+
 __device__ __forceinline__ int32_t wrap1(int32_t i, int32_t n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 }  // namespace ifem

@@ -83,7 +83,7 @@ struct TransferArgs {
   int32_t tile_shift[3];  // log2 of tile
   int32_t region_cells;   // (tile_x + 5)(tile_y + 2)(tile_z + 2): rows of tile_x cells, two pad cells on each
                           // side, one more for an odd pitch
-  int32_t halo_cells;     // (tile_x + 1)(2 (tile_y + tile_z) + 4): the region's y/z shell rows
+  int32_t halo_cells;     // tile_x (2 (tile_y + tile_z) + 4): the region's y/z shell rows
 };
 
 // Index of region row (iy, iz) among the y/z shell rows of a region with ry x rz rows: the two z
@@ -241,8 +241,6 @@ hipError_t launch_interp(const PlanDev& P, int dtype, const void* x, const doubl
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
-hipError_t launch_scan(int32_t n, const int32_t* cnt, int32_t* off, int32_t* cursor, int64_t cap,
-                       unsigned long long* status, hipStream_t st);
 
 // ---- launchers (ifem_contact.hip)
 hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const double* anchor, double d_min,

@@ -21,6 +21,7 @@
 //    k_spread_merge<T>  adds the neighbours' halo values to each tile's
 //                       border cells in a fixed order.
 #include <cfloat>
+#include <algorithm>
 #include <climits>
 
 #include "ifem_device.hpp"
@@ -193,11 +194,8 @@ constexpr int kListsPerEntry = 3;
 // keys[2] the left and right x-neighbours when reached (else -1; a tile that
 // equals an earlier key is not repeated).  The count and fill passes both call
 // this on the same inputs, so they agree bit for bit.
-__device__ __forceinline__ void node_lists(const TransferArgs& a, const BoxDev& B, int d, const double pos[3],
+__device__ __forceinline__ void node_lists(const TransferArgs& a, const BoxDev& B, int d, const int32_t base[3],
                                            int keys[kListsPerEntry]) {
-  int32_t base[3];
-  double tau[3];
-  nearest_node(B, d, pos, base, tau);
   const int tx = base[0] >> a.tile_shift[0], ty = base[1] >> a.tile_shift[1], tz = base[2] >> a.tile_shift[2];
   const int row = d * a.n_tiles + B.tile_base + (tz * B.ntile[1] + ty) * B.ntile[0];
   const int c0x = tx << a.tile_shift[0];
@@ -227,8 +225,13 @@ __device__ __forceinline__ void all_lists(const TransferArgs& a, const T* __rest
     const BoxDev& B = a.boxes[a.particle_box[p]];
     double pos[3];
     node_position(a, x, anchor, k, p, pos);
+    int32_t b0[3], bh[3];
+    nearest_bases(B, pos, b0, bh);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) node_lists(a, B, d, pos, keys + d * kListsPerEntry);
+    for (int d = 0; d < 3; ++d) {
+      const int32_t base[3] = {d == 0 ? b0[0] : bh[0], d == 1 ? b0[1] : bh[1], d == 2 ? b0[2] : bh[2]};
+      node_lists(a, B, d, base, keys + d * kListsPerEntry);
+    }
   }
 }
 
@@ -360,10 +363,13 @@ __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restr
   }
 }
 
-hipError_t launch_scan(int32_t n, const int32_t* cnt, int32_t* off, int32_t* cursor, int64_t cap,
-                       unsigned long long* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, n, cnt, off, cursor, cap, status);
-  return hipGetLastError();
+// Four consecutive values to a 16-byte aligned address.
+__device__ __forceinline__ void store4(float* p, const float v[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store4(double* p, const double v[4]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
 }
 
 // ------------------------------------------------------------------ tiled spread: accumulation
@@ -387,14 +393,12 @@ constexpr int kTileThreads = 512;  // threads of a spread-tile workgroup (8 wave
 // is written straight to the grid, the y/z halo rows to scratch for the merge;
 // a tile with an empty list only writes zeros to its interior.
 template <typename T>
-__global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs a, const T* __restrict__ x,
-                                                              const double* __restrict__ anchor,
-                                                              const T* __restrict__ F, T* __restrict__ grid) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void spread_item(const TransferArgs& a, const T* __restrict__ x,
+                                            const double* __restrict__ anchor, const T* __restrict__ F,
+                                            T* __restrict__ grid, int w, unsigned char* smem_raw, int& bad_entry) {
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);
   constexpr int NW = FixedAcc<T>::kWords;
-  // the 3 components of a tile are adjacent workgroups
-  const int w = xcd_remap(blockIdx.x, gridDim.x), tile = w / 3, d = w - 3 * tile;
+  const int tile = w / 3, d = w - 3 * tile;  // the 3 components of a tile are adjacent items
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int nwaves = nt / kWave;
   const int L = d * a.n_tiles + tile;
@@ -446,13 +450,17 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   // fixed-point scale from the bound code of the list (raised by the count pass) and its length; a
   // non-finite force cannot be held in fixed point and poisons (NaN) the tile's whole region instead,
   // as does an entry whose MLS system has no solution (a non-finite position)
-  __shared__ int bad_entry;
   const uint32_t code = a.tile_fmax[L];
   bool poison = code == kBoundPoison;
   // float64 keeps a 32-bit remainder word per cell after the 64-bit words (12 bytes per cell)
   unsigned int* lo = reinterpret_cast<unsigned int*>(acc + nreg);
   unsigned int* acc32 = reinterpret_cast<unsigned int*>(acc);
-  for (int i = tid; i < (NW == 2 ? 3 : 2) * nreg; i += nt) acc32[i] = 0u;
+  {
+    const int nw32 = (NW == 2 ? 3 : 2) * nreg;  // 32-bit words of the region, cleared 16 bytes at a time
+    uint4* acc128 = reinterpret_cast<uint4*>(smem_raw);
+    for (int i = tid; i < (nw32 >> 2); i += nt) acc128[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = (nw32 & ~3) + tid; i < nw32; i += nt) acc32[i] = 0u;
+  }
   if (tid == 0) bad_entry = 0;
   __syncthreads();
   // every entry goes through the loop when the forces are finite, also when they are all zero, so
@@ -531,48 +539,90 @@ __global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs
   }
   __syncthreads();
   if (bad_entry) poison = true;  // uniform: read after the barrier
-  // interior -> grid (final unless a neighbour's halo adds to it), y/z halo rows -> scratch.  A
-  // wavefront takes 64 / tile_x region rows at a time (lane -> row of the group, x), so the row is
-  // decoded once per row; (row + 1/2) / ry is at least 1/(2 ry) away from an integer, far above the
-  // rounding of this small quotient, so the truncation is exact.
-  const int lrow = lane >> a.tile_shift[0], ix = lane & (a.tile[0] - 1);
-  const int rpw = kWave >> a.tile_shift[0];  // tiles are at most 64 cells wide
+  // interior -> grid (final unless a neighbour's halo adds to it), y/z halo rows -> scratch (rows of
+  // tile_x values).  Region row -> (iy, iz): (row + 1/2) / ry is at least 1/(2 ry) away from an
+  // integer, far above the rounding of this small quotient, so the truncation is exact.
   const int nrows = ry * rz;
   const float inv_ry = frcp((float)ry);
   const bool halo_on = nonzero || poison;
   const bool wrap_x = B.ntile[0] == 1;
   const bool sums = nonzero && !poison;
   const T fillv = poison ? (T)__builtin_nan("") : T(0);
-  for (int row0 = wave * rpw; row0 < nrows; row0 += nwaves * rpw) {
-    const int row = row0 + lrow;
-    if (row >= nrows || ix >= ex[0]) continue;
-    const int iz = (int)(((float)row + 0.5f) * inv_ry);
-    const int iy = row - iz * ry;
-    const int r = row * rx + ix + 2;
-    T v = fillv;
-    if (sums) {
-      long long wi = (long long)acc[r];
-      int li = NW == 2 ? (int)lo[r] : 0;
-      if (wrap_x) {  // one tile spans the box along x: the pad columns -1 and ex_x wrap onto its own columns
-        if (ix == 0) {
-          wi += (long long)acc[r + ex[0]];
-          if (NW == 2) li += (int)lo[r + ex[0]];
-        }
-        if (ix == ex[0] - 1) {
-          wi += (long long)acc[r - ex[0]];
-          if (NW == 2) li += (int)lo[r - ex[0]];
-        }
+  const int pitch = a.tile[0];
+  // the value of region cell r, column ixc of the tile (the pad columns wrap onto a tile that spans the
+  // box along x; integer sums, so the result does not depend on where a share was held)
+  auto cell_value = [&](int r, int ixc) -> T {
+    if (!sums) return fillv;
+    long long wi = (long long)acc[r];
+    int li = NW == 2 ? (int)lo[r] : 0;
+    if (wrap_x) {
+      if (ixc == 0) {
+        wi += (long long)acc[r + ex[0]];
+        if (NW == 2) li += (int)lo[r + ex[0]];
       }
-      double w = (double)wi;
-      if (NW == 2) w += (double)li * ldexp(1.0, -sl);
-      v = (T)ldexp(w, -sc);
+      if (ixc == ex[0] - 1) {
+        wi += (long long)acc[r - ex[0]];
+        if (NW == 2) li += (int)lo[r - ex[0]];
+      }
     }
-    if ((unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2])
-      g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix)] = v;
-    else if (halo_on)
-      halo[halo_row(iy, iz, ry, rz) * (ex[0] + 1) + ix] = v;
+    double w = (double)wi;
+    if (NW == 2) w += (double)li * ldexp(1.0, -sl);
+    return (T)ldexp(w, -sc);
+  };
+  if ((ex[0] & 3) == 0 && a.tile_shift[0] >= 2) {
+    // four consecutive cells per lane: one row decode per four values, 16-byte stores where aligned
+    // (halo rows always are: their pitch and every halo block are multiples of four values)
+    const int sh = a.tile_shift[0] - 2;
+    const int lrow = lane >> sh, ix = (lane & ((1 << sh) - 1)) * 4;
+    const int rpw = kWave >> sh;  // region rows per wavefront pass
+    const bool g_vec = (reinterpret_cast<uintptr_t>(g) & 15) == 0 && (B.n[0] & 3) == 0;
+    for (int row0 = wave * rpw; row0 < nrows; row0 += nwaves * rpw) {
+      const int row = row0 + lrow;
+      if (row >= nrows || ix >= ex[0]) continue;
+      const int iz = (int)(((float)row + 0.5f) * inv_ry);
+      const int iy = row - iz * ry;
+      const int r = row * rx + ix + 2;
+      T v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = cell_value(r + j, ix + j);
+      if ((unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2]) {
+        T* dst = g + (uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix);
+        if (g_vec)
+          store4(dst, v);
+        else
+#pragma unroll
+          for (int j = 0; j < 4; ++j) dst[j] = v[j];
+      } else if (halo_on) {
+        store4(halo + halo_row(iy, iz, ry, rz) * pitch + ix, v);
+      }
+    }
+  } else {
+    // one cell per lane: a wavefront takes 64 / tile_x region rows at a time
+    const int lrow = lane >> a.tile_shift[0], ix = lane & (a.tile[0] - 1);
+    const int rpw = kWave >> a.tile_shift[0];  // tiles are at most 64 cells wide
+    for (int row0 = wave * rpw; row0 < nrows; row0 += nwaves * rpw) {
+      const int row = row0 + lrow;
+      if (row >= nrows || ix >= ex[0]) continue;
+      const int iz = (int)(((float)row + 0.5f) * inv_ry);
+      const int iy = row - iz * ry;
+      const T v = cell_value(row * rx + ix + 2, ix);
+      if ((unsigned)(iy - 1) < (unsigned)ex[1] && (unsigned)(iz - 1) < (unsigned)ex[2])
+        g[(uint32_t)(((c0[2] + iz - 1) * B.n[1] + (c0[1] + iy - 1)) * B.n[0] + c0[0] + ix)] = v;
+      else if (halo_on)
+        halo[halo_row(iy, iz, ry, rz) * pitch + ix] = v;
+    }
   }
   if (tid == 0) a.tile_flag[L] = halo_on ? 1 : 0;
+}
+
+// One workgroup per item (tile, component), the items of neighbouring tiles on one XCD.
+template <typename T>
+__global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs a, const T* __restrict__ x,
+                                                              const double* __restrict__ anchor,
+                                                              const T* __restrict__ F, T* __restrict__ grid) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int bad_entry;
+  spread_item<T>(a, x, anchor, F, grid, xcd_remap(blockIdx.x, gridDim.x), smem_raw, bad_entry);
 }
 
 // Merge: every tile adds, to its y/z border rows, the halo rows that its 8
@@ -649,7 +699,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_spread_merge(const TransferAr
         const int ry = oy == -1 ? nbe[nbi][0] + 1 : (oy == 1 ? 0 : iy + 1);
         const int rz = oz == -1 ? nbe[nbi][1] + 1 : (oz == 1 ? 0 : iz + 1);
         const int hr = halo_row(ry, rz, nbe[nbi][0] + 2, nbe[nbi][1] + 2);
-        v += halo[(int64_t)nbL[nbi] * a.halo_cells + hr * (exx + 1) + ix];
+        v += halo[(int64_t)nbL[nbi] * a.halo_cells + hr * a.tile[0] + ix];
       }
     }
     g[cell] = v;
