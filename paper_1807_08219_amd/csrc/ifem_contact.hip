@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256) k_ac_count(const ContactArgs a, const T* 
     const int p = a.node_particle[k];
     double pos[3];
     abs_position(a, x, anchor, k, p, pos);
-    key = cell_of(a.boxes[a.particle_box[p]], pos);
+    key = cell_of(cbox_of(a, p), pos);
   }
   int leader, rank, size;
   wave_groups(key, leader, rank, size);
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256) k_ac_fill(const ContactArgs a, const T* _
   if (k < a.n_nodes) {
     p = a.node_particle[k];
     abs_position(a, x, anchor, k, p, pos);
-    key = cell_of(a.boxes[a.particle_box[p]], pos);
+    key = cell_of(cbox_of(a, p), pos);
   }
   int leader, rank, size;
   wave_groups(key, leader, rank, size);
@@ -347,7 +347,7 @@ __device__ __forceinline__ bool face_setup(const ContactArgs& a, const T* __rest
   int v[3];
   face_nodes(a, f, v);
   q = a.node_particle[v[0]];
-  C = a.boxes[a.particle_box[q]];
+  C = cbox_of(a, q);
 #pragma unroll
   for (int m = 0; m < 3; ++m) abs_position(a, x, anchor, v[m], q, pv[m]);
   bool ok = true;
@@ -558,7 +558,7 @@ __global__ void __launch_bounds__(256) k_ac_push(const ContactArgs a, const T* _
   int v[3];
   face_nodes(a, f, v);
   const int q = a.node_particle[v[0]];
-  const ContactBoxDev C = a.boxes[a.particle_box[q]];
+  const ContactBoxDev C = cbox_of(a, q);
   double pv[3][3], r[3][3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) abs_position(a, x, anchor, v[m], q, pv[m]);

@@ -112,6 +112,23 @@ __device__ __forceinline__ void wave_groups(int key, int& leader, int& rank, int
   }
 }
 
+// Largest of a value over the 64 lanes of a wavefront, returned to every lane:
+// data-parallel-primitive moves instead of LDS permutes.  Within each row of
+// 16 lanes: the quad swaps, then shifts by 4 and 8 (lanes shifted in from
+// outside the row read 0, the identity of the maximum), which leave lane 15 of
+// the row with the row's largest; then row 1 and 3 take lane 15 of the row
+// before them and rows 2 and 3 take lane 31, which leaves lane 63 with the
+// wavefront's largest, read back as a uniform value.  All lanes must be active.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false));  // row_shr 4
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false));  // row_shr 8
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast 15
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast 31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // ------------------------------------------------------------------ fast elementary functions
 // float32: the hardware square root and reciprocal (about 1 ulp); float64:
 // the correctly rounded operations.

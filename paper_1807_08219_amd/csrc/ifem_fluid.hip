@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(256) k_interp_cells(const TransferArgs a, cons
   const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= a.n_nodes) return;
   const int p = a.node_particle[k];
-  const BoxDev B = a.boxes[a.particle_box[p]];
+  const BoxDev B = box_of(a, p);
   double pos[3];
   const int64_t N = a.n_nodes;
   if (sizeof(T) == 4) {

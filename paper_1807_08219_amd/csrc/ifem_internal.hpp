@@ -86,6 +86,13 @@ struct TransferArgs {
   int32_t halo_cells;     // tile_x (2 (tile_y + tile_z) + 4): the region's y/z shell rows
 };
 
+// The box of particle p.  With one box (a kernel argument, uniform over the grid) its fields come from
+// scalar loads and the per-node gather of the particle's box index is skipped.
+__device__ __forceinline__ BoxDev box_of(const TransferArgs& a, int p) {
+  if (a.n_boxes == 1) return a.boxes[0];
+  return a.boxes[a.particle_box[p]];
+}
+
 // Index of region row (iy, iz) among the y/z shell rows of a region with ry x rz rows: the two z
 // faces (every y), then the two y faces without the z-face rows.  (iy, iz) must be a shell row.
 __device__ __forceinline__ int halo_row(int iy, int iz, int ry, int rz) {
@@ -137,6 +144,12 @@ struct ContactArgs {
   int32_t work_cap;
   int32_t n_nodes, n_tris, n_bfaces, n_cells, n_boxes;
 };
+
+// The contact box of particle p (scalar loads when there is one box).
+__device__ __forceinline__ ContactBoxDev cbox_of(const ContactArgs& a, int p) {
+  if (a.n_boxes == 1) return a.boxes[0];
+  return a.boxes[a.particle_box[p]];
+}
 
 // Kernel slots of the per-kernel event timer.
 enum KernelSlot {

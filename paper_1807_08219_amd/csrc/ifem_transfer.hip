@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) k_interp(const TransferArgs a, const T* _
   const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= a.n_nodes) return;
   const int p = a.node_particle[k];
-  const BoxDev B = a.boxes[a.particle_box[p]];
+  const BoxDev B = box_of(a, p);
   double pos[3];
   node_position(a, x, anchor, k, p, pos);
   unsigned int bad = 0;
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(256) k_spread_atomic(const TransferArgs a, con
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= a.n_nodes) return;
   const int p = a.node_particle[k];
-  const BoxDev B = a.boxes[a.particle_box[p]];
+  const BoxDev B = box_of(a, p);
   double pos[3];
   node_position(a, x, anchor, k, p, pos);
   unsigned int bad = 0;
@@ -222,7 +222,7 @@ __device__ __forceinline__ void all_lists(const TransferArgs& a, const T* __rest
   for (int i = 0; i < 3 * kListsPerEntry; ++i) keys[i] = -1;
   if (k < a.n_nodes) {
     const int p = a.node_particle[k];
-    const BoxDev& B = a.boxes[a.particle_box[p]];
+    const BoxDev B = box_of(a, p);
     double pos[3];
     node_position(a, x, anchor, k, p, pos);
     int32_t b0[3], bh[3];
@@ -265,13 +265,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const TransferArgs a, const T
   uint32_t fm[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    uint32_t v = k < a.n_nodes ? bound_code(F[d * (int64_t)a.n_nodes + k]) : 0u;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-      const uint32_t w = __shfl_xor(v, o, kWave);
-      v = w > v ? w : v;
-    }
-    fm[d] = v;
+    fm[d] = wave_max_u32(k < a.n_nodes ? bound_code(F[d * (int64_t)a.n_nodes + k]) : 0u);
   }
 #pragma unroll
   for (int i = 0; i < NK; ++i) {

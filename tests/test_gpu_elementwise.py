@@ -122,3 +122,31 @@ def test_elastic_forces_elementwise(name):
     print(f"    forces: max |err| / (u32 sum|f_e|) = {ratio.max():.2f}", flush=True)
     assert ratio.max() <= C_FORCES
     plan.close()
+
+
+@pytest.mark.parametrize("shift", [0, 32])
+def test_spread_scale_sees_every_lane(shift):
+    # The fixed-point scale of a list comes from the largest force of each wavefront of 64 consecutive
+    # nodes that feeds it.  One node per wavefront carries a force 10^6 times the others, at a lane
+    # that moves from wavefront to wavefront (7 w + shift mod 64); a scale that missed that lane would
+    # overflow the 64-bit sums of its cells and miss the bound below by orders of magnitude.
+    sc = scenes.config2()
+    print(f"[gpu] spread scale, one large force per wavefront (lane shift {shift})", flush=True)
+    rng = np.random.default_rng(5 + shift)
+    F = 1e-3 * rng.normal(size=(3, sc.n_nodes))
+    waves = np.arange((sc.n_nodes + 63) // 64)
+    big = np.minimum(waves * 64 + (7 * waves + shift) % 64, sc.n_nodes - 1)
+    F[:, big] = 1e3 * rng.choice([-1.0, 1.0], size=(3, big.size))
+    F = F.astype(np.float32).astype(np.float64)
+    plan = ifem.Plan(sc)
+    x, a = cu(sc.x32, torch.float32), cu(sc.anchor, torch.float64)
+    G = torch.empty((3, sc.total_cells), dtype=torch.float32, device="cuda")
+    plan.spread(ifem.IFEM_F32, x, a, cu(F, torch.float32), G)
+    got = G.cpu().numpy().astype(np.float64)
+    ref = oracle.spread(sc, F)
+    mag = abs_stencil_sums(sc, F=F)
+    ratio = np.abs(got - ref) / (U32 * mag + 1e-12 * np.abs(F).max())
+    print(f"    max |err| / (u32 sum|phi||F|) = {ratio.max():.2f}", flush=True)
+    assert ratio.max() <= C_TRANSFER
+    assert plan.status() == [0, 0, 0, 0, 0]
+    plan.close()
