@@ -271,7 +271,7 @@ ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const doub
  * array's address on each device is looked up once, on the first call there.
  * Returns IFEM_ERR_UNSUPPORTED, before launching anything, when the plan's
  * workspace does not fit: 4 (3 n_tiles) int32 + (3 n_tiles + 1) int32 + the
- * node lists (3 or 9 int32 per node) + 3 n_tiles (tile_x + 1)(2 (tile_y +
+ * node lists (3 or 9 int32 per node) + 3 n_tiles tile_x (2 (tile_y +
  * tile_z) + 4) values of the call's precision, each part rounded up to 256
  * bytes (a 128^3 grid with 32 x 16 x 8 tiles takes 21 MB in float64).  Every
  * call on one GPU uses that GPU's one array, whatever the plan: calls that

@@ -27,6 +27,36 @@ def test_library_exports_every_declared_symbol():
     assert L.ifem_version() == 10400
 
 
+def _declarations():
+    """name -> list of parameter declarations, from include/ifem.h."""
+    text = open(os.path.join(ROOT, "include", "ifem.h")).read()
+    out = {}
+    for m in re.finditer(r"^\s*(?:ifem_status|const char\*|int32_t)\s+(ifem_[a-z_]+)\s*\(([^)]*)\)", text, re.M):
+        params = [q.strip() for q in m.group(2).replace("\n", " ").split(",") if q.strip()]
+        out[m.group(1)] = [] if params == ["void"] else params
+    return out
+
+
+def test_binding_declares_every_argument_type():
+    # ctypes passes an undeclared Python int as a 32-bit C int: a device pointer would be cut to its
+    # low half, so every entry point with parameters must declare them, pointers as pointers
+    L = ifem.lib()
+    for name, params in _declarations().items():
+        if not params:
+            continue
+        at = getattr(L, name).argtypes
+        assert at is not None, name
+        assert len(at) == len(params), name
+        for decl, t in zip(params, at):
+            # ifem_plan is a pointer to an opaque struct; an array parameter is a pointer
+            if "*" in decl or "[" in decl or decl.startswith("ifem_plan "):
+                assert t is C.c_void_p or issubclass(t, C._Pointer), (name, decl)
+            elif decl.startswith("double"):
+                assert t is C.c_double, (name, decl)
+            else:
+                assert t in (C.c_int32, C.c_int64), (name, decl)
+
+
 def _desc(sc):
     keep = []
 
