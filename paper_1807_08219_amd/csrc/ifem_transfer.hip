@@ -357,13 +357,27 @@ __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restr
   }
 }
 
-// Four consecutive values to a 16-byte aligned address.
+// Four consecutive values to / from a 16-byte aligned address.
 __device__ __forceinline__ void store4(float* p, const float v[4]) {
   *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
 }
 __device__ __forceinline__ void store4(double* p, const double v[4]) {
   reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
   reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+}
+__device__ __forceinline__ void load4(const float* p, float v[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+__device__ __forceinline__ void load4(const double* p, double v[4]) {
+  const double2 q0 = reinterpret_cast<const double2*>(p)[0], q1 = reinterpret_cast<const double2*>(p)[1];
+  v[0] = q0.x;
+  v[1] = q0.y;
+  v[2] = q1.x;
+  v[3] = q1.y;
 }
 
 // ------------------------------------------------------------------ tiled spread: accumulation
@@ -664,10 +678,15 @@ __global__ void __launch_bounds__(kMergeThreads) k_spread_merge(const TransferAr
   // border rows: the z faces (all y), then the y faces without the z-face rows
   const int zf = ez > 1 ? 2 : 1, yf = ey > 1 ? 2 : 1, inz = max(ez - 2, 0);
   const int nzr = zf * ey, nrows = nzr + yf * inz;
-  // lanes cover rows of the power-of-two tile width; lanes past the tile's extent idle
-  const int sh = a.tile_shift[0];
-  const int rpp = a.tile[0] >= (int)blockDim.x ? 1 : (int)blockDim.x / a.tile[0];  // rows per workgroup pass
-  const int ix = tid & (a.tile[0] - 1), lrow = tid >> sh;
+  // lanes cover rows of the power-of-two tile width, VW consecutive cells each (four, with 16-byte
+  // accesses, where the tile's extent and the grid rows allow; halo rows always do); lanes past the
+  // tile's extent idle
+  const bool vec = (exx & 3) == 0 && a.tile_shift[0] >= 2 && (B.n[0] & 3) == 0 &&
+                   (reinterpret_cast<uintptr_t>(g) & 15) == 0;
+  const int vsh = vec ? 2 : 0;
+  const int sh = a.tile_shift[0] - vsh;  // lanes per row: tile_x >> vsh
+  const int rpp = (1 << sh) >= (int)blockDim.x ? 1 : (int)blockDim.x >> sh;  // rows per workgroup pass
+  const int ix = (tid & ((1 << sh) - 1)) << vsh, lrow = tid >> sh;
   if (ix >= exx || lrow >= rpp) return;  // no barrier follows
   for (int row = lrow; row < nrows; row += rpp) {
     int iy, iz;
@@ -681,7 +700,11 @@ __global__ void __launch_bounds__(kMergeThreads) k_spread_merge(const TransferAr
       iy = f ? ey - 1 : 0;
     }
     const uint32_t cell = (uint32_t)(((c0[2] + iz) * B.n[1] + (c0[1] + iy)) * B.n[0] + c0[0] + ix);
-    T v = g[cell];
+    T v[4];
+    if (vec)
+      load4(g + cell, v);
+    else
+      v[0] = g[cell];
     for (int oz = -1; oz <= 1; ++oz) {
       if ((oz == -1 && iz != 0) || (oz == 1 && iz != ez - 1)) continue;
       for (int oy = -1; oy <= 1; ++oy) {
@@ -693,10 +716,21 @@ __global__ void __launch_bounds__(kMergeThreads) k_spread_merge(const TransferAr
         const int ry = oy == -1 ? nbe[nbi][0] + 1 : (oy == 1 ? 0 : iy + 1);
         const int rz = oz == -1 ? nbe[nbi][1] + 1 : (oz == 1 ? 0 : iz + 1);
         const int hr = halo_row(ry, rz, nbe[nbi][0] + 2, nbe[nbi][1] + 2);
-        v += halo[(int64_t)nbL[nbi] * a.halo_cells + hr * a.tile[0] + ix];
+        const T* hp = halo + (int64_t)nbL[nbi] * a.halo_cells + hr * a.tile[0] + ix;
+        if (vec) {
+          T h4[4];
+          load4(hp, h4);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] += h4[j];
+        } else {
+          v[0] += hp[0];
+        }
       }
     }
-    g[cell] = v;
+    if (vec)
+      store4(g + cell, v);
+    else
+      g[cell] = v[0];
   }
 }
 
