@@ -500,7 +500,7 @@ def bench_workload(config, steps, warmup, dev):
     from paper_1807_08219_amd import ifem
     from paper_1807_08219_amd.inputs import fields, scenes
 
-    sc = scenes.make_config(config)
+    sc = scenes.refined_suspension() if config == "refined" else scenes.make_config(config)
     plan = ifem.Plan(sc)
     u64 = fields.scene_velocity(sc, dtype=torch.float64, shear_rate=1.0 if config == 3 else 0.0).to(dev)
     u32 = u64.to(torch.float32)
@@ -648,6 +648,8 @@ def main():
                     help="bytes of a plain device copy made before the steps (scale for HBM counters)")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape (or --tile)")
     ap.add_argument("--no-config3", action="store_true", help="skip the line of the blood suspension (config 3)")
+    ap.add_argument("--no-refined", action="store_true",
+                    help="skip the line of the suspension of nu = 32 red cells (the global-memory force path)")
     ap.add_argument("--no-errors", action="store_true", help="skip the sampled errors against the oracle")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)  # the child running the oracle
     ap.add_argument("--cpu-workers", type=int, default=16, help=argparse.SUPPRESS)
@@ -829,7 +831,11 @@ def main():
     if not args.no_batched and args.config != 4:
         out["batched"] = bench_batched(args.steps, args.warmup, dev)
     if not args.no_config3 and args.config != 3:
-        out["workloads"] = {"blood_500rbc_50plt": bench_workload(3, args.steps, args.warmup, dev)}
+        out.setdefault("workloads", {})["blood_500rbc_50plt"] = bench_workload(3, args.steps, args.warmup, dev)
+    if not args.no_refined:
+        # red cells meshed at nu = 32: every particle takes the global-memory force path
+        out.setdefault("workloads", {})["refined_130rbc_nu32"] = bench_workload("refined", args.steps, args.warmup,
+                                                                                 dev)
 
     if not args.no_fp64:
         x64 = torch.as_tensor(sc.x64, device=dev)

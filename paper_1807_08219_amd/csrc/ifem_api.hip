@@ -947,13 +947,14 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
     L.gather_start = d10;
     L.gather = d11;
     double *ef_tri, *ef_tet, *kh, *fb, *rt;
-    HIP_TRY(mem.alloc(&ef_tri, (size_t)9 * std::max(L.n_tri, 1)));
-    HIP_TRY(mem.alloc(&ef_tet, (size_t)12 * std::max(L.n_tet, 1)));
+    HIP_TRY(mem.alloc(&ef_tri, (size_t)12 * std::max(L.n_tri, 1)));
+    HIP_TRY(mem.alloc(&ef_tet, (size_t)16 * std::max(L.n_tet, 1)));
     HIP_TRY(mem.alloc(&kh, (size_t)std::max(L.n_node, 1)));
     HIP_TRY(mem.alloc(&fb, (size_t)3 * std::max(L.n_node, 1)));
     HIP_TRY(mem.alloc(&rt, (size_t)5 * std::max(L.n_tri + L.n_tet, 1)));
     HIP_TRY(mem.alloc(&L.vol_terms, (size_t)4 * std::max(L.n_node, 1)));
     HIP_TRY(mem.alloc(&L.lam, (size_t)L.n_part));
+    HIP_TRY(mem.alloc(&L.red_part, (size_t)L.n_part * 16 * 5));
     L.ef_tri = ef_tri;
     L.ef_tet = ef_tet;
     L.kh = kh;

@@ -240,9 +240,9 @@ __global__ void __launch_bounds__(256) k_large_fluid_elems(const ForceArgs a, co
   double fk[4][3];
   if (!fluid_tet(q, u, C ? C + n0 : (const T*)nullptr, N, ids, eta, G, fk))
     for (int k = 0; k < 4; ++k) fk[k][0] = fk[k][1] = fk[k][2] = 0.0;
-  double* ef = reinterpret_cast<double*>(L.ef_tet);
+  double* ef = reinterpret_cast<double*>(L.ef_tet);  // [4 corners][n_tet][4]
   for (int k = 0; k < 4; ++k)
-    for (int c = 0; c < 3; ++c) ef[(k * 3 + c) * (int64_t)L.n_tet + t] = fk[k][c];
+    for (int c = 0; c < 3; ++c) ef[((int64_t)k * L.n_tet + t) * 4 + c] = fk[k][c];
 }
 
 template <typename T>
@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256) k_large_fluid_gather(const ForceArgs a, c
     const int g = L.gather[j];  // element e and corner v: e * 4 + v, tetrahedra after the triangles
     const int e = (g >> 2) - L.n_tri, v = g & 3;
     if (e < 0) continue;
-    for (int c = 0; c < 3; ++c) s[c] += ef[(v * 3 + c) * (int64_t)L.n_tet + e];
+    for (int c = 0; c < 3; ++c) s[c] += ef[((int64_t)v * L.n_tet + e) * 4 + c];
   }
   const int64_t N = a.n_nodes;
   for (int c = 0; c < 3; ++c) f[c * N + k] = (T)((double)f[c * N + k] + s[c]);

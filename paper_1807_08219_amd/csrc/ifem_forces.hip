@@ -621,9 +621,31 @@ __global__ void __launch_bounds__(512) k_forces(const ForceArgs a, const T* __re
 //  k_large_gather<T> one thread per node: its element shares in a fixed order
 //                    (a node -> element-slot list built at plan creation) plus
 //                    the bending terms, written once;
-//  k_large_reduce    one workgroup per particle: the element terms of the
-//                    float64 reductions summed in a fixed order.
+//  k_large_partial,  the element terms of the float64 reductions summed in a
+//  k_large_reduce    fixed order: 16 shares per particle, then the shares.
 // Sums run in fixed orders, so the forces are reproducible run to run.
+
+// One corner's force in the element scratch: x, y, z and a pad, 16-byte aligned (one float4 or two
+// double2 accesses).
+__device__ __forceinline__ void store_corner(float* p, const float f[3]) {
+  *reinterpret_cast<float4*>(p) = make_float4(f[0], f[1], f[2], 0.0f);
+}
+__device__ __forceinline__ void store_corner(double* p, const double f[3]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(f[0], f[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(f[2], 0.0);
+}
+__device__ __forceinline__ void load_corner(const float* p, float f[3]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  f[0] = q.x;
+  f[1] = q.y;
+  f[2] = q.z;
+}
+__device__ __forceinline__ void load_corner(const double* p, double f[3]) {
+  const double2 q0 = reinterpret_cast<const double2*>(p)[0], q1 = reinterpret_cast<const double2*>(p)[1];
+  f[0] = q0.x;
+  f[1] = q0.y;
+  f[2] = q1.x;
+}
 
 template <typename T>
 __device__ __forceinline__ void large_pos(const T* __restrict__ x, int64_t N, int k, T out[3]) {
@@ -663,8 +685,7 @@ __global__ void __launch_bounds__(256) k_large_elems(const ForceArgs a, const La
       const double G[3] = {a.tri_ref[s], a.tri_ref[a.n_tris + s], a.tri_ref[2 * a.n_tris + s]};
       T f[3][3];
       bad = !tri_element<T>(xs, G, a.tri_ref[3 * a.n_tris + s], a.law[p], mu, mu2, f);
-      for (int v = 0; v < 3; ++v)
-        for (int c = 0; c < 3; ++c) reinterpret_cast<T*>(L.ef_tri)[(v * 3 + c) * (int64_t)L.n_tri + e] = f[v][c];
+      for (int v = 0; v < 3; ++v) store_corner(reinterpret_cast<T*>(L.ef_tri) + ((int64_t)v * L.n_tri + e) * 4, f[v]);
       double q[3][3];
       for (int v = 0; v < 3; ++v)
         for (int c = 0; c < 3; ++c) q[v][c] = (double)xs[v][c] - o[c];
@@ -686,8 +707,7 @@ __global__ void __launch_bounds__(256) k_large_elems(const ForceArgs a, const La
       for (int k = 0; k < 6; ++k) G[k] = a.tet_ref[k * a.n_tets + s];
       T f[4][3];
       bad = !tet_element<T>(xs, G, a.tet_ref[6 * a.n_tets + s], mu, mu2, f);
-      for (int v = 0; v < 4; ++v)
-        for (int c = 0; c < 3; ++c) reinterpret_cast<T*>(L.ef_tet)[(v * 3 + c) * (int64_t)L.n_tet + et] = f[v][c];
+      for (int v = 0; v < 4; ++v) store_corner(reinterpret_cast<T*>(L.ef_tet) + ((int64_t)v * L.n_tet + et) * 4, f[v]);
       double q[4][3];
       for (int v = 0; v < 4; ++v)
         for (int c = 0; c < 3; ++c) q[v][c] = (double)xs[v][c] - o[c];
@@ -769,9 +789,10 @@ __global__ void __launch_bounds__(256) k_large_gather(const ForceArgs a, const L
     for (int j = L.gather_start[i]; j < L.gather_start[i + 1]; ++j) {
       const int g = L.gather[j];  // element e and corner v: e * 4 + v, tetrahedra after the triangles
       const int e = g >> 2, v = g & 3;
-      for (int c = 0; c < 3; ++c)
-        f[c] += e < L.n_tri ? ef_tri[(v * 3 + c) * (int64_t)L.n_tri + e]
-                            : ef_tet[(v * 3 + c) * (int64_t)L.n_tet + (e - L.n_tri)];
+      T fc[3];
+      load_corner(e < L.n_tri ? ef_tri + ((int64_t)v * L.n_tri + e) * 4 : ef_tet + ((int64_t)v * L.n_tet + (e - L.n_tri)) * 4,
+                  fc);
+      for (int c = 0; c < 3; ++c) f[c] += fc[c];
     }
     if (a.kb[p] != 0.0 && a.ring_start != nullptr) {
       const T* fb = reinterpret_cast<const T*>(L.fb);
@@ -790,35 +811,49 @@ __global__ void __launch_bounds__(256) k_large_gather(const ForceArgs a, const L
   if (m && lane == 0) atomicAdd(a.status + 1, (unsigned long long)total);
 }
 
-// One workgroup per large particle: its elements' reduction terms in element order, strided over the
-// threads, then the deterministic block sum.
-__global__ void __launch_bounds__(256) k_large_reduce(const ForceArgs a, const LargeArgs L,
-                                                       const double* __restrict__ red_terms,
-                                                       const double* __restrict__ origin_x, int64_t N,
-                                                       int fp64, const double* __restrict__ anchor,
-                                                       double* __restrict__ red) {
+// The reductions of the large particles in two fixed-order stages: kRedParts workgroups per particle
+// each sum one contiguous share of its elements' terms (strided over the threads, then the block sum),
+// then one thread per particle adds the shares in order and writes volume, area and centroid.
+constexpr int kRedParts = 16;
+
+__global__ void __launch_bounds__(256) k_large_partial(const LargeArgs L, const double* __restrict__ red_terms) {
   __shared__ double red_lds[5 * 16];
-  const int lp = blockIdx.x;
-  const int p = L.part[lp];
+  const int lp = blockIdx.x / kRedParts, j = blockIdx.x % kRedParts;
   const int ne = L.n_tri + L.n_tet;
   double r[5] = {0, 0, 0, 0, 0};
-  for (int t = L.tri_begin[lp] + threadIdx.x; t < L.tri_begin[lp + 1]; t += blockDim.x)
-    for (int k = 0; k < 5; ++k) r[k] += red_terms[k * (int64_t)ne + t];
-  for (int t = L.tet_begin[lp] + threadIdx.x; t < L.tet_begin[lp + 1]; t += blockDim.x)
-    for (int k = 0; k < 5; ++k) r[k] += red_terms[k * (int64_t)ne + L.n_tri + t];
-  block_sum<5>(r, red_lds);
-  if (threadIdx.x == 0) {
-    const int n0 = a.node_start[p];
-    double base[3] = {0.0, 0.0, 0.0};
-    if (fp64)
-      for (int c = 0; c < 3; ++c) base[c] = origin_x[c * N + n0];
-    if (anchor)
-      for (int c = 0; c < 3; ++c) base[c] += anchor[3 * p + c];
-    const double V = r[0];
-    red[5 * p + 0] = V;
-    red[5 * p + 1] = r[1];
-    for (int c = 0; c < 3; ++c) red[5 * p + 2 + c] = base[c] + r[2 + c] / V;
+  // the particle's triangles, then its tetrahedra, as one index range split into kRedParts shares
+  const int t0 = L.tri_begin[lp], nt = L.tri_begin[lp + 1] - t0;
+  const int q0 = L.tet_begin[lp], nq = L.tet_begin[lp + 1] - q0;
+  const int n = nt + nq;
+  const int lo = (int)((int64_t)n * j / kRedParts), hi = (int)((int64_t)n * (j + 1) / kRedParts);
+  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int64_t col = i < nt ? t0 + i : L.n_tri + q0 + (i - nt);
+    for (int k = 0; k < 5; ++k) r[k] += red_terms[k * (int64_t)ne + col];
   }
+  block_sum<5>(r, red_lds);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) L.red_part[(lp * kRedParts + j) * 5 + k] = r[k];
+}
+
+__global__ void __launch_bounds__(64) k_large_reduce(const ForceArgs a, const LargeArgs L,
+                                                     const double* __restrict__ origin_x, int64_t N, int fp64,
+                                                     const double* __restrict__ anchor, double* __restrict__ red) {
+  const int lp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lp >= L.n_part) return;
+  const int p = L.part[lp];
+  double r[5] = {0, 0, 0, 0, 0};
+  for (int j = 0; j < kRedParts; ++j)
+    for (int k = 0; k < 5; ++k) r[k] += L.red_part[(lp * kRedParts + j) * 5 + k];
+  const int n0 = a.node_start[p];
+  double base[3] = {0.0, 0.0, 0.0};
+  if (fp64)
+    for (int c = 0; c < 3; ++c) base[c] = origin_x[c * N + n0];
+  if (anchor)
+    for (int c = 0; c < 3; ++c) base[c] += anchor[3 * p + c];
+  const double V = r[0];
+  red[5 * p + 0] = V;
+  red[5 * p + 1] = r[1];
+  for (int c = 0; c < 3; ++c) red[5 * p + 2 + c] = base[c] + r[2 + c] / V;
 }
 
 template <typename T>
@@ -837,10 +872,12 @@ static hipError_t launch_large_t(const PlanDev& P, const T* x, const double* anc
     }
     hipLaunchKernelGGL(k_large_gather<T>, dim3((L.n_node + B - 1) / B), dim3(B), 0, st, P.fargs, L, f);
   }
-  if (red)
-    hipLaunchKernelGGL(k_large_reduce, dim3(L.n_part), dim3(B), 0, st, P.fargs, L, L.red_terms,
+  if (red) {
+    hipLaunchKernelGGL(k_large_partial, dim3(L.n_part * kRedParts), dim3(B), 0, st, L, L.red_terms);
+    hipLaunchKernelGGL(k_large_reduce, dim3((L.n_part + 63) / 64), dim3(64), 0, st, P.fargs, L,
                        sizeof(T) == 8 ? (const double*)x : (const double*)nullptr, (int64_t)P.n_nodes,
                        sizeof(T) == 8 ? 1 : 0, anchor, red);
+  }
   return hipGetLastError();
 }
 

@@ -53,11 +53,12 @@ struct LargeArgs {
   const int32_t* part_base;     // [n_part + 1] compact index of each large particle's first node
   const int32_t* gather_start;  // [n_node + 1]
   const int32_t* gather;        // element shares of each node: e * 4 + corner, tetrahedra after triangles
-  void* ef_tri;                 // [9][n_tri] element nodal forces (sized for float64)
-  void* ef_tet;                 // [12][n_tet]
+  void* ef_tri;                 // [3 corners][n_tri][4] element nodal forces, x y z and a pad (sized for float64)
+  void* ef_tet;                 // [4 corners][n_tet][4]
   void* kh;                     // [n_node] kH - kH0
   void* fb;                     // [3][n_node] bending force
   double* red_terms;            // [5][n_tri + n_tet] element terms of the reductions
+  double* red_part;             // [n_part][16][5] their sums over 16 shares of each particle's elements
   double* vol_terms;            // [4][n_node] node terms of the volume correction's sums
   double* lam;                  // [n_part] its multipliers
 };

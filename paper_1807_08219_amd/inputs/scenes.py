@@ -301,7 +301,7 @@ def _fit_in_slot(rng, x, slot_centre, slot_size):
 
 
 def _dense_suspension(name, seed, n_rbc, n_plt, grid, hct, slot_counts, gamma_rbc, gamma_plt,
-                      max_tilt, plt_dims=(5, 5, 5)):
+                      max_tilt, plt_dims=(5, 5, 5), rbc_nu=16):
     rng = np.random.default_rng(seed)
     h = (n_rbc * RBC_VOLUME / (hct * grid[0] * grid[1] * grid[2])) ** (1.0 / 3.0)
     box = Box(tuple(grid), h, (0.0, 0.0, 0.0))
@@ -317,7 +317,7 @@ def _dense_suspension(name, seed, n_rbc, n_plt, grid, hct, slot_counts, gamma_rb
         for attempt in range(50):
             s = next(slot_iter, None) if attempt == 0 else s
             if kind == "rbc":
-                X, tris = rbc_template(16)
+                X, tris = rbc_template(rbc_nu)
                 gamma = rng.uniform(*gamma_rbc)
             else:
                 X, tets = ellipsoid_template(plt_dims)
@@ -343,6 +343,13 @@ def _dense_suspension(name, seed, n_rbc, n_plt, grid, hct, slot_counts, gamma_rb
     vol = n_rbc * RBC_VOLUME
     info = {"hct_target": hct, "hct": vol / (np.prod(box.length)), "h": h, "slots": list(slot_counts)}
     return assemble(name, [box], particles, seed, info)
+
+
+def refined_suspension(seed: int = 1006, n_rbc: int = 130, grid=(256, 128, 128)) -> Scene:
+    """Red cells meshed at nu = 32 (10,242 nodes each, above one workgroup's LDS: the global force path)
+    at 20% Ht; h = 0.244 = R0 / 16, the mesh spacing of such a cell."""
+    return _dense_suspension(f"refined_{n_rbc}rbc_nu32_grid{grid[0]}x{grid[1]}x{grid[2]}", seed, n_rbc, 0, grid,
+                             0.20, (7, 3, 9), (0.0, 0.2), (0.0, 0.1), np.deg2rad(4.0), rbc_nu=32)
 
 
 def config3(seed: int = 1003) -> Scene:

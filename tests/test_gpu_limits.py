@@ -234,3 +234,29 @@ def test_large_particles_fluid_forces(large):
     say(f"    f32 |err| / bar max {(np.abs(got32 - want) / bar).max():.3f}")
     assert np.all(np.abs(got32 - want) <= bar)
     assert plan.status() == [0, 0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("dtype", [ifem.IFEM_F64, ifem.IFEM_F32])
+def test_large_particles_transfers(large, dtype):
+    # the nodes of particles on the global force path are spread and interpolated like any others
+    sc, plan = large
+    say(f"[gpu] large particles: spread and interpolation, dtype {dtype}")
+    from paper_1807_08219_amd.inputs import fields
+    rng = np.random.default_rng(12)
+    F = rng.normal(size=(3, sc.n_nodes))
+    u = fields.scene_velocity(sc).numpy()
+    xd, a, dt = _pos(sc, dtype)
+    if dtype == ifem.IFEM_F32:
+        F = F.astype(np.float32).astype(np.float64)
+        u = u.astype(np.float32).astype(np.float64)
+    G = torch.empty((3, sc.total_cells), dtype=dt, device="cuda")
+    plan.spread(dtype, xd, a, cu(F, dt), G)
+    v = torch.empty((3, sc.n_nodes), dtype=dt, device="cuda")
+    plan.interp(dtype, xd, a, cu(u, dt), v)
+    torch.cuda.synchronize()
+    eg = rel(G.cpu().numpy(), oracle.spread(sc, F))
+    ev = rel(v.cpu().numpy(), oracle.interp(sc, u))
+    say(f"    spread rel err {eg:.3e}, interp rel err {ev:.3e}")
+    bar = F64_TOL if dtype == ifem.IFEM_F64 else 1e-6
+    assert eg <= bar and ev <= bar
+    assert plan.status() == [0, 0, 0, 0, 0]
