@@ -51,6 +51,15 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
     p[i] = v;
 }
 
+// The list counts and bound codes of the spread, cleared together (graph-safe: no memset node).
+__global__ void k_zero_counters(int32_t* __restrict__ count, uint32_t* __restrict__ code, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    count[i] = 0;
+    code[i] = 0u;
+  }
+}
+
 template <typename T>
 static hipError_t fill(T* p, int64_t n, T v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -788,9 +797,11 @@ hipError_t launch_spread_tiled(const PlanDev& P, const TransferArgs& a, int dtyp
                                const void* F, void* grid, hipStream_t st) {
   const int nl = 3 * a.n_tiles;
   P.timer->begin(K_FILL, st);
-  hipError_t e = fill(a.tile_count, (int64_t)nl, 0, st);
-  if (e == hipSuccess) e = fill(a.tile_fmax, (int64_t)nl, 0u, st);
+  if (nl > 0)
+    hipLaunchKernelGGL(k_zero_counters, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, a.tile_count,
+                       a.tile_fmax, nl);
   P.timer->end(st);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 ng = node_grid(a.n_nodes, 256), nb(256);
   if (a.n_nodes) {
