@@ -187,7 +187,10 @@ typedef struct ifem_plan_s* ifem_plan;
  * workspace is rebuilt for each, so the call allocates and frees device memory),
  * then the interpolation for block_points 64, 128 and 256 (median of five
  * calls after two untimed ones, each timed call after an untimed call of the
- * other transfer, as in a coupling step; HIP events on `stream`), and leaves the plan
+ * other transfer, as in a coupling step; HIP events on `stream`; 30 untimed
+ * spread + interpolation pairs first bring the device's clocks up, and the
+ * candidates are timed in order and again in reverse order, each keeping its
+ * better median, so that a drift favours none), and leaves the plan
  * with the fastest: every later call of the plan uses it, and gives the same
  * results bit for bit as a plan created with that tuning.  The choice is
  * recorded for (current device, the plan's sizes: particle, node and element

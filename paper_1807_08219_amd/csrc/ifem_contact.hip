@@ -288,20 +288,20 @@ __device__ __forceinline__ int contact_cell(const ContactBoxDev& C, int cx, int 
   return C.base + (c[2] * C.nc[1] + c[1]) * C.nc[0] + c[0];
 }
 
-// Face f of particle q against the nodes of other particles in one cell, their
-// records loaded four at a time.  First pass (second == false): every pair below
+// Face f of particle q against the nodes of other particles among the n records
+// of one cell starting at recs, loaded four at a time.  First pass (second == false): every pair below
 // d_min lowers its node's least distance; returns whether there was one.
 // Second pass: a pair at exactly its node's least distance lowers the node's
 // face id.
-__device__ __forceinline__ bool face_cell_nodes(const ContactArgs& a, int f, int q, const ContactBoxDev& C,
-                                                const double pv[3][3], const double blo[3], const double bhi[3],
-                                                double d_min, bool second, int cell) {
+__device__ __forceinline__ bool face_records(const ContactArgs& a, int f, int q, const ContactBoxDev& C,
+                                             const double pv[3][3], const double blo[3], const double bhi[3],
+                                             double d_min, bool second, const ContactNode* __restrict__ recs,
+                                             int n) {
   bool hit = false;
-  const int o = a.off[cell], n = a.count[cell];
   for (int i0 = 0; i0 < n; i0 += 4) {
     ContactNode r4[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r4[u] = a.rec[o + min(i0 + u, n - 1)];
+    for (int u = 0; u < 4; ++u) r4[u] = recs[min(i0 + u, n - 1)];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (i0 + u >= n || r4[u].p == q || (unsigned)r4[u].k >= (unsigned)a.n_nodes) continue;
@@ -332,6 +332,13 @@ __device__ __forceinline__ bool face_cell_nodes(const ContactArgs& a, int f, int
     }
   }
   return hit;
+}
+
+// The same against all records of one cell.
+__device__ __forceinline__ bool face_cell_nodes(const ContactArgs& a, int f, int q, const ContactBoxDev& C,
+                                                const double pv[3][3], const double blo[3], const double bhi[3],
+                                                double d_min, bool second, int cell) {
+  return face_records(a, f, q, C, pv, blo, bhi, d_min, second, a.rec + a.off[cell], a.count[cell]);
 }
 
 // Face f: its particle q, box C, corners pv, the cell range its box grown by d_min
@@ -495,15 +502,22 @@ __global__ void __launch_bounds__(256) k_ac_pairs(const ContactArgs a, const T* 
   const int n = min(a.work_count[seg], seg_cap);
   const int lane = threadIdx.x & (kWave - 1);
   const uint2* __restrict__ list = a.work + (size_t)seg * seg_cap;
-  for (int i = (int)(blockIdx.x / kWorkSegs) * blockDim.x + threadIdx.x; i < n; i += per_seg * blockDim.x) {
-    const uint2 w = list[i];
+  const int stride = per_seg * (int)blockDim.x;
+  int i = (int)(blockIdx.x / kWorkSegs) * blockDim.x + threadIdx.x;
+  // each thread's next work item is requested one item ahead, and an item's record range before its
+  // face set-up, so that these loads overlap the work of the chain in front of them
+  uint2 w_next = i < n ? list[i] : make_uint2(~0u, 0u);
+  for (; i < n; i += stride) {
+    const uint2 w = w_next;
+    if (i + stride < n) w_next = list[i + stride];
     bool hit = false;
     if (w.x < (unsigned)(a.n_tris + a.n_bfaces)) {  // not a reserved slot
+      const int o = a.off[w.y], nrec = a.count[w.y];
       int q, lo[3], cnt[3];
       ContactBoxDev C;
       double pv[3][3], blo[3], bhi[3];
       face_setup(a, x, anchor, (int)w.x, d_min, q, C, pv, lo, cnt, blo, bhi);
-      hit = face_cell_nodes(a, (int)w.x, q, C, pv, blo, bhi, d_min, false, (int)w.y);
+      hit = face_records(a, (int)w.x, q, C, pv, blo, bhi, d_min, false, a.rec + o, nrec);
     }
     // the lanes still in the loop append their hits together
     const unsigned long long m = __ballot(hit);
@@ -523,14 +537,19 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_ac_hits(const ContactArgs a, const T* __restrict__ x,
                                                  const double* __restrict__ anchor, double d_min) {
   const int n = min(*a.hit_count, a.work_cap);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint2 w = a.work[a.hits[i]];
+  const int stride = gridDim.x * blockDim.x;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int slot_next = i < n ? a.hits[i] : -1;  // the next listed item, requested one item ahead
+  for (; i < n; i += stride) {
+    const uint2 w = a.work[slot_next];
+    slot_next = i + stride < n ? a.hits[i + stride] : -1;
     if (w.x >= (unsigned)(a.n_tris + a.n_bfaces)) continue;
+    const int o = a.off[w.y], nrec = a.count[w.y];
     int q, lo[3], cnt[3];
     ContactBoxDev C;
     double pv[3][3], blo[3], bhi[3];
     face_setup(a, x, anchor, (int)w.x, d_min, q, C, pv, lo, cnt, blo, bhi);
-    face_cell_nodes(a, (int)w.x, q, C, pv, blo, bhi, d_min, true, (int)w.y);
+    face_records(a, (int)w.x, q, C, pv, blo, bhi, d_min, true, a.rec + o, nrec);
   }
 }
 
