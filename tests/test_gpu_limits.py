@@ -260,3 +260,33 @@ def test_large_particles_transfers(large, dtype):
     bar = F64_TOL if dtype == ifem.IFEM_F64 else 1e-6
     assert eg <= bar and ev <= bar
     assert plan.status() == [0, 0, 0, 0, 0]
+
+
+def test_large_membrane_without_bending():
+    # a plan whose only large particle is a neo-Hookean capsule without bending (the global path
+    # without its curvature passes), beside a small solid on the per-workgroup kernel
+    # sheared and roughened by 0.003 (1/40 of an edge): moving every position by one unit in its last
+    # place changes these forces by 5e-13 relative, inside the float64 bar (larger noise, or none,
+    # leaves forces that the float64 positions determine less well than 1e-12)
+    rng = np.random.default_rng(31)
+    X, tris = meshes.icosphere(32)  # 10,242 nodes
+    x = scenes.shear_about_centroid(X * 2.0, meshes.random_rotation(rng), 0.1) + 0.003 * rng.normal(size=X.shape)
+    x = x + [8.0, 8.0, 8.0]
+    Xs, tets = meshes.kuhn_box(4, 4, 4)
+    xs = Xs * 1.1 + [15.0, 8.0, 8.0]
+    sc = assemble("large_capsule", [Box((40, 32, 32), 0.5, (0.0, 0.0, 0.0))],
+                  [Particle(X=X * 2.0, x=x, tri=tris, law=scenes.LAW_TRI_NEOHOOKE, mu=1.0),
+                   Particle(X=Xs, x=xs, tet=tets, law=scenes.LAW_TET_NEOHOOKE, mu=1.0, mu2=10.0)], 31)
+    say(f"[gpu] large capsule without bending ({sc.node_start[1]} nodes) and a small solid")
+    Fo, cnt = oracle.forces(sc)
+    ro = oracle.reduce(sc)
+    assert cnt[0] == 0
+    plan = ifem.Plan(sc)
+    for dtype in (ifem.IFEM_F64, ifem.IFEM_F32):
+        F, red = _forces(plan, sc, dtype)
+        e = rel(F, Fo)
+        say(f"    dtype {dtype}: forces rel err {e:.3e}")
+        assert e <= (F64_TOL if dtype == ifem.IFEM_F64 else F32_ELASTIC_TOL)
+        assert rel(red[:, 0], ro[:, 0]) <= 1e-12 and rel(red[:, 2:], ro[:, 2:]) <= 1e-12
+    assert plan.status() == [0, 0, 0, 0, 0]
+    plan.close()
