@@ -259,7 +259,11 @@ ifem_status ifem_element_forces(ifem_plan plan, int32_t dtype, const void* x, co
  * its stencil (its home tile and at most one x-neighbour; a non-finite
  * position is binned at lattice index 0), plus their one-cell y/z halos, into
  * NaN for that component (the plain IFEM_SPREAD_ATOMIC mode spreads it to the
- * 27 stencil cells only). */
+ * 27 stencil cells only).  The plan keeps each call's list lengths to lay out
+ * the next call's lists, so that the node lists are written in one pass over
+ * the nodes while positions move by less than the room left in each list (a
+ * second pass fills the lists that outgrew theirs, and every list on the
+ * plan's first call); the grid does not depend on it. */
 ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F,
                         void* grid, void* stream);
 
@@ -274,7 +278,7 @@ ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const doub
  * array's address on each device is looked up once, on the first call there.
  * Returns IFEM_ERR_UNSUPPORTED, before launching anything, when the plan's
  * workspace does not fit: 4 (3 n_tiles) int32 + (3 n_tiles + 1) int32 + the
- * node lists (3 or 9 int32 per node) + 3 n_tiles tile_x (2 (tile_y +
+ * node lists (6 or 9 int32 per node) + 3 n_tiles tile_x (2 (tile_y +
  * tile_z) + 4) values of the call's precision, each part rounded up to 256
  * bytes (a 128^3 grid with 32 x 16 x 8 tiles takes 21 MB in float64).  Every
  * call on one GPU uses that GPU's one array, whatever the plan: calls that

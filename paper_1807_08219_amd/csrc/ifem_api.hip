@@ -621,13 +621,16 @@ ifem_status build_spread(ifem_plan plan, const int32_t tile[3], hipStream_t st) 
   }
   const int n_tiles = (int)tile_box.size();
   const int64_t list_cap = (int64_t)3 * lists_per_entry * P.n_nodes;
-  if (list_cap >= ((int64_t)1 << 31)) return fail(IFEM_ERR_UNSUPPORTED, "too many nodes for the spread lists");
+  // lists carried between calls: room for the usual entries, half as many again, and a few per list
+  const int64_t bk_cap = list_cap + (int64_t)kBucketSlack * 3 * n_tiles;
+  if (bk_cap >= ((int64_t)1 << 31)) return fail(IFEM_ERR_UNSUPPORTED, "too many nodes for the spread lists");
   const int region_cells = (tile[0] + 5) * (tile[1] + 2) * (tile[2] + 2);
   const int halo_cells = tile[0] * (2 * (tile[1] + tile[2]) + 4);
   DeviceBuffers mem;
   BoxDev* d_boxes = nullptr;
   int32_t *d_tile_box = nullptr, *d_cnt = nullptr, *d_off = nullptr, *d_cur = nullptr, *d_list = nullptr,
-          *d_flag = nullptr;
+          *d_flag = nullptr, *d_bk_list = nullptr, *d_bk_state = nullptr;
+  int2* d_bk_lay = nullptr;
   uint32_t* d_fmax = nullptr;
   double* d_halo = nullptr;  // sized for float64
   hipError_t e = upload(mem, &d_boxes, hb.data(), hb.size(), st);
@@ -639,6 +642,13 @@ ifem_status build_spread(ifem_plan plan, const int32_t tile[3], hipStream_t st) 
   if (e == hipSuccess) e = mem.alloc(&d_flag, (size_t)3 * n_tiles);
   if (e == hipSuccess) e = mem.alloc(&d_fmax, (size_t)3 * n_tiles);
   if (e == hipSuccess) e = mem.alloc(&d_halo, (size_t)3 * n_tiles * halo_cells);
+  // lists carried from one call's counts to the next call's layout: both layouts start without room,
+  // so that the first call fills every list in the second pass
+  if (e == hipSuccess) e = mem.alloc(&d_bk_list, (size_t)bk_cap);
+  if (e == hipSuccess) e = mem.alloc(&d_bk_lay, (size_t)2 * 3 * n_tiles);
+  if (e == hipSuccess) e = mem.alloc(&d_bk_state, 2);
+  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t*>(d_bk_lay), (int64_t)4 * 3 * n_tiles, 0, st);
+  if (e == hipSuccess) e = launch_fill_i32(d_bk_state, 2, 0, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);  // the uploads read host vectors of this frame
   if (e != hipSuccess) {
     mem.release();
@@ -658,6 +668,10 @@ ifem_status build_spread(ifem_plan plan, const int32_t tile[3], hipStream_t st) 
   ta.tile_flag = d_flag;
   ta.tile_fmax = d_fmax;
   ta.halo = d_halo;
+  ta.bk_list = d_bk_list;
+  ta.bk_lay = d_bk_lay;
+  ta.bk_state = d_bk_state;
+  ta.bk_cap = bk_cap;
   ta.region_cells = region_cells;
   ta.halo_cells = halo_cells;
   ta.list_cap = list_cap;
@@ -667,7 +681,8 @@ ifem_status build_spread(ifem_plan plan, const int32_t tile[3], hipStream_t st) 
     ta.tile_shift[a] = __builtin_ctz(tile[a]);
     plan->tune.tile[a] = tile[a];
   }
-  plan->workspace_bytes = (int64_t)(15 * (int64_t)n_tiles + 1 + list_cap) * 4 + (int64_t)3 * n_tiles * halo_cells * 8;
+  plan->workspace_bytes =
+      (int64_t)(27 * (int64_t)n_tiles + 3 + list_cap + bk_cap) * 4 + (int64_t)3 * n_tiles * halo_cells * 8;
   e = prepare_transfer_kernels(P);
   if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "spread kernel attributes: %s", hipGetErrorString(e));
   return IFEM_OK;
@@ -1292,6 +1307,9 @@ ifem_status ifem_spread_noalloc(ifem_plan plan, int32_t dtype, const void* x, co
   a.tile_fmax = reinterpret_cast<uint32_t*>(base + o_fmax);
   a.bin_list = reinterpret_cast<int32_t*>(base + o_list);
   a.halo = base + o_halo;
+  a.bk_list = nullptr;  // no lists carried between calls: every call fills its lists in the second pass
+  a.bk_lay = nullptr;
+  a.bk_state = nullptr;
   return launched(launch_spread_tiled(P, a, dtype, x, anchor, F, grid, (hipStream_t)stream));
 }
 

@@ -63,6 +63,9 @@ struct LargeArgs {
   double* lam;                  // [n_part] its multipliers
 };
 
+// Room a carried spread list gets beyond half as many entries again as it had (see k_scan).
+constexpr int kBucketSlack = 32;
+
 // Everything the transfer kernels read.
 struct TransferArgs {
   const int32_t* node_particle;   // [n_nodes]
@@ -76,8 +79,13 @@ struct TransferArgs {
   int32_t* tile_flag;             // [3 n_tiles] 1 if the tile wrote a halo shell this call
   uint32_t* tile_fmax;            // [3 n_tiles] bound on |F| of each list, float32 bits (atomic max)
   void* halo;                     // [3 n_tiles][halo_cells] y/z halo shell rows (float or double)
+  int32_t* bk_list;               // [bk_cap] node ids in lists laid out from the previous call's counts (NULL: none)
+  int2* bk_lay;                   // [2][3 n_tiles] two such layouts, this call's and the next one's: per list
+                                  // its first slot in bk_list and its room
+  int32_t* bk_state;              // [2] index of this call's layout; 1 if a list outgrew its room this call
   unsigned long long* status;
   int64_t list_cap;
+  int64_t bk_cap;
   int64_t total_cells;
   int32_t n_nodes, n_boxes, n_tiles;
   int32_t tile[3];        // cells per tile and axis (powers of two)

@@ -9,9 +9,14 @@
 //                       (node, component, stencil node).
 //  tiled spread         deterministic and free of global float atomics:
 //    k_bin_count<T>     per (node, component): counts the node in the list
-//                       of the tile holding its nearest lattice node;
-//    k_scan             list offsets from the counts (single workgroup);
-//    k_bin_fill<T>      writes every node into its lists;
+//                       of the tile holding its nearest lattice node and
+//                       writes it into that list as laid out from the
+//                       previous call's counts, when it fits there;
+//    k_scan             list offsets from the counts, and the layout for
+//                       the next call (single workgroup);
+//    k_bin_fill<T>      writes the nodes of the lists that outgrew their
+//                       layout into lists laid out from this call's counts
+//                       (returns at once when none did);
 //    k_spread_home<T>   one workgroup per (component, tile): accumulates all
 //                       contributions of the tile's list in an LDS region
 //                       (tile + one-cell halo) as 64-bit fixed-point
@@ -51,12 +56,18 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
     p[i] = v;
 }
 
-// The list counts and bound codes of the spread, cleared together (graph-safe: no memset node).
-__global__ void k_zero_counters(int32_t* __restrict__ count, uint32_t* __restrict__ code, int n) {
+// The list counts and bound codes of the spread, cleared together (graph-safe: no memset node); the
+// layout the previous call's scan prepared becomes this call's, and its overflow flag is cleared.
+__global__ void k_zero_counters(int32_t* __restrict__ count, uint32_t* __restrict__ code, int n,
+                                int32_t* __restrict__ bk_state) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     count[i] = 0;
     code[i] = 0u;
+  }
+  if (i == 0 && bk_state) {
+    bk_state[0] ^= 1;
+    bk_state[1] = 0;
   }
 }
 
@@ -194,10 +205,26 @@ __global__ void __launch_bounds__(256) k_spread_atomic(const TransferArgs a, con
 // also to the list of the x-neighbour tile that its stencil reaches into.
 // Each tile thus sees every contribution that lands inside its x range (no
 // halo along x) and keeps a one-cell halo along y and z only, whose rows are
-// contiguous in memory.  Count, scan and fill build the lists; the atomics on
-// the list counters are aggregated per wavefront (one per distinct list among
-// 64 consecutive nodes, which lie close together on one surface).
+// contiguous in memory.  The atomics on the list counters are aggregated per
+// wavefront (one per distinct list among 64 consecutive nodes, which lie close
+// together on one surface).
+//
+// Lists change little from one call to the next (positions move by a fraction
+// of a cell per step), so each call lays out the next call's lists from its own
+// counts with some room to grow (bk_want).  The count pass takes a node's slot
+// in a list from the atomic that counts it and writes the node there when the
+// list's room allows; only the lists that outgrow their room (none, in the
+// steady state; all of them on a plan's first call) are filled again by a
+// second pass over the nodes, into lists laid out from this call's counts.
+// The tile sums do not depend on where or in which order a list holds its
+// entries (integer sums), so the result is the same either way.
 constexpr int kListsPerEntry = 3;
+__host__ __device__ __forceinline__ int64_t bk_want(int32_t cnt) { return (int64_t)cnt + (cnt >> 1) + kBucketSlack; }
+
+// This call's layout of the carried lists: per list its first slot in bk_list and its room.
+__device__ __forceinline__ const int2* bk_layout(const TransferArgs& a) {
+  return a.bk_lay + (int64_t)a.bk_state[0] * (3 * a.n_tiles);
+}
 
 // Lists of a node for one component: keys[0] the home tile, keys[1] and
 // keys[2] the left and right x-neighbours when reached (else -1; a tile that
@@ -263,41 +290,89 @@ __device__ __forceinline__ uint32_t bound_code(T f) {
 // Count pass: one thread per node; every (node, component) counts once in
 // each of its lists, one atomic per distinct list per wavefront.  The same
 // atomics raise each list's bound code (bound_code) to the wavefront's largest
-// of that component; the bound sets the list's fixed-point scale.
+// of that component; the bound sets the list's fixed-point scale.  With the
+// carried layout, the count a group's atomic returns places its members in the
+// list; a member past the list's room raises the overflow flag instead.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_count(const TransferArgs a, const T* __restrict__ x,
                                                    const double* __restrict__ anchor, const T* __restrict__ F) {
   constexpr int NK = 3 * kListsPerEntry;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int2* lay = a.bk_list ? bk_layout(a) : nullptr;  // read early: its latency hides under the keys'
   int key[NK];
   all_lists(a, x, anchor, k, key);
+  T fv[3];  // the three loads in flight together (bound_code(0) = 0 past the last node)
+#pragma unroll
+  for (int d = 0; d < 3; ++d) fv[d] = k < a.n_nodes ? F[d * (int64_t)a.n_nodes + k] : T(0);
   uint32_t fm[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    fm[d] = wave_max_u32(k < a.n_nodes ? bound_code(F[d * (int64_t)a.n_nodes + k]) : 0u);
+  for (int d = 0; d < 3; ++d) fm[d] = wave_max_u32(bound_code(fv[d]));
+  if (!a.bk_list) {
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      int leader, rank, size;
+      wave_groups(key[i], leader, rank, size);
+      if (size > 0) {
+        atomicAdd(a.tile_count + key[i], size);
+        atomicMax(a.tile_fmax + key[i], fm[i / kListsPerEntry]);
+      }
+    }
+    return;
   }
+  // the layout loads and all atomics of the wavefront in flight before any result is used
+  int2 lk[NK];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) lk[i] = lay[max(key[i], 0)];
+  int leader[NK], rank[NK], size[NK], base[NK];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) wave_groups(key[i], leader[i], rank[i], size[i]);
+#pragma unroll
+  for (int i = 0; i < NK; ++i)
+    if (size[i] > 0) atomicMax(a.tile_fmax + key[i], fm[i / kListsPerEntry]);
+#pragma unroll
+  for (int i = 0; i < NK; ++i) base[i] = size[i] > 0 ? atomicAdd(a.tile_count + key[i], size[i]) : 0;
+  // every destination before the first store, so that no store waits on another
+  int dst[NK];
+  bool over = false;
 #pragma unroll
   for (int i = 0; i < NK; ++i) {
-    int leader, rank, size;
-    wave_groups(key[i], leader, rank, size);
-    if (size > 0) {
-      atomicAdd(a.tile_count + key[i], size);
-      atomicMax(a.tile_fmax + key[i], fm[i / kListsPerEntry]);
-    }
+    const int slot = __shfl(base[i], leader[i], kWave) + rank[i];
+    const bool fits = slot < lk[i].y;
+    dst[i] = key[i] >= 0 && fits ? lk[i].x + slot : -1;
+    over = over || (key[i] >= 0 && !fits);
   }
+#pragma unroll
+  for (int i = 0; i < NK; ++i)
+    if (dst[i] >= 0) a.bk_list[dst[i]] = k;
+  const unsigned long long ob = __ballot(over);  // one flag store per wavefront
+  if (ob && (threadIdx.x & (kWave - 1)) == __ffsll((long long)ob) - 1) a.bk_state[1] = 1;
 }
 
 // Fill pass: the same keys; each group's leader takes a run of slots from the
 // list's cursor (initialised to the list's offset by the scan) and the group
 // members write the node id into it.  All atomics of a wavefront are issued
-// before any result is used.
+// before any result is used.  With the carried layout only the lists that
+// outgrew their room are filled here, and only when some did.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_fill(const TransferArgs a, const T* __restrict__ x,
                                                   const double* __restrict__ anchor) {
   constexpr int NK = 3 * kListsPerEntry;
+  if (a.bk_list && !a.bk_state[1]) return;  // every list fitted (uniform)
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   int key[NK], leader[NK], rank[NK], size[NK], base[NK];
   all_lists(a, x, anchor, k, key);
+  if (a.bk_list) {  // only the lists that outgrew their room
+    const int2* lay = bk_layout(a);
+    int room[NK], cnt[NK];
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      room[i] = key[i] >= 0 ? lay[key[i]].y : 0;
+      cnt[i] = key[i] >= 0 ? a.tile_count[key[i]] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < NK; ++i)
+      if (cnt[i] <= room[i]) key[i] = -1;
+  }
 #pragma unroll
   for (int i = 0; i < NK; ++i) wave_groups(key[i], leader[i], rank[i], size[i]);
 #pragma unroll
@@ -313,35 +388,66 @@ __global__ void __launch_bounds__(256) k_bin_fill(const TransferArgs a, const T*
 // the counts t, t + nt, t + 2 nt, ... (coalesced loads), the thread totals are
 // scanned across the workgroup, and each thread lays its lists out one after
 // another from its prefix.  Every cursor starts at its list's offset; a total
-// above the list capacity is flagged.
-__global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restrict__ cnt, int32_t* __restrict__ off,
-                                               int32_t* __restrict__ cursor, int64_t cap,
-                                               unsigned long long* status) {
+// above the list capacity is flagged.  With the carried layout the same pass
+// lays out the next call's lists, each with room bk_want(count); lists past
+// the end of bk_list get no room (their nodes take the fill pass).
+__device__ __forceinline__ int2 bk_place(int64_t at, int64_t want, int64_t cap) {
+  const int64_t b = min(at, cap), e = min(at + want, cap);
+  return make_int2((int32_t)b, (int32_t)(e - b));
+}
+
+__global__ void __launch_bounds__(1024) k_scan(const TransferArgs a, int32_t n) {
   __shared__ int32_t wsum[1024 / kWave];
+  __shared__ long long wsum2[1024 / kWave];
+  const int32_t* __restrict__ cnt = a.tile_count;
+  int32_t* __restrict__ off = a.tile_off;
+  int32_t* __restrict__ cursor = a.tile_cursor;
+  int2* __restrict__ next = a.bk_list ? a.bk_lay + (int64_t)(a.bk_state[0] ^ 1) * n : nullptr;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), wave = tid / kWave;
   constexpr int kU = 8;  // loads in flight per thread
   int32_t s = 0;
+  int64_t s2 = 0;
   int i = tid;
   for (; i + (kU - 1) * nt < n; i += kU * nt) {
     int32_t c[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) c[u] = cnt[i + u * nt];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) s += c[u];
+    for (int u = 0; u < kU; ++u) {
+      s += c[u];
+      s2 += bk_want(c[u]);
+    }
   }
-  for (; i < n; i += nt) s += cnt[i];
-  // inclusive scan of the thread totals: within each wavefront, then across the wavefront totals
+  for (; i < n; i += nt) {
+    s += cnt[i];
+    s2 += bk_want(cnt[i]);
+  }
+  // inclusive scans of the thread totals: within each wavefront, then across the wavefront totals
   int32_t incl = s;
+  int64_t incl2 = s2;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const int32_t v = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += v;
+    const int64_t v2 = __shfl_up(incl2, o, kWave);
+    if (lane >= o) {
+      incl += v;
+      incl2 += v2;
+    }
   }
-  if (lane == kWave - 1) wsum[wave] = incl;
+  if (lane == kWave - 1) {
+    wsum[wave] = incl;
+    wsum2[wave] = incl2;
+  }
   __syncthreads();
   int32_t before = 0;
-  for (int w = 0; w < wave; ++w) before += wsum[w];
+  int64_t before2 = 0;
+  for (int w = 0; w < wave; ++w) {
+    before += wsum[w];
+    before2 += wsum2[w];
+  }
   int32_t run = before + incl - s;
+  int64_t run2 = before2 + incl2 - s2;
+  const int64_t bcap = a.bk_cap;
   i = tid;
   for (; i + (kU - 1) * nt < n; i += kU * nt) {
     int32_t c[kU];
@@ -351,18 +457,22 @@ __global__ void __launch_bounds__(1024) k_scan(int32_t n, const int32_t* __restr
     for (int u = 0; u < kU; ++u) {
       off[i + u * nt] = run;
       cursor[i + u * nt] = run;
+      if (next) next[i + u * nt] = bk_place(run2, bk_want(c[u]), bcap);
       run += c[u];
+      run2 += bk_want(c[u]);
     }
   }
   for (; i < n; i += nt) {
     const int32_t c = cnt[i];
     off[i] = run;
     cursor[i] = run;
+    if (next) next[i] = bk_place(run2, bk_want(c), bcap);
     run += c;
+    run2 += bk_want(c);
   }
   if (tid == nt - 1) {
     off[n] = run;
-    if ((int64_t)run > cap) atomicAdd(status + 3, 1ull);
+    if ((int64_t)run > a.list_cap) atomicAdd(a.status + 3, 1ull);
   }
 }
 
@@ -433,7 +543,6 @@ __device__ __forceinline__ void spread_item(const TransferArgs& a, const T* __re
   // the result does not depend on where a share was held).  An odd pitch of 64-bit words spreads the rows and planes of the
   // stencil over the LDS banks.
   const int rx = (ex[0] + 4) | 1, ry = ex[1] + 2, rz = ex[2] + 2, nreg = rx * ry * rz;
-  const int32_t* list = a.bin_list + a.tile_off[L];
   const int cnt = a.tile_count[L];
   T* g = grid + d * a.total_cells + B.cell_off;
   T* halo = reinterpret_cast<T*>(a.halo) + (int64_t)L * a.halo_cells;
@@ -464,6 +573,12 @@ __device__ __forceinline__ void spread_item(const TransferArgs& a, const T* __re
     return;  // no barrier follows
   }
 
+  // the carried layout holds the list when it fitted its room, else the fill pass's layout does
+  const int32_t* list = a.bin_list + a.tile_off[L];
+  if (a.bk_list) {
+    const int2 lk = bk_layout(a)[L];
+    if (cnt <= lk.y) list = a.bk_list + lk.x;
+  }
   // fixed-point scale from the bound code of the list (raised by the count pass) and its length; a
   // non-finite force cannot be held in fixed point and poisons (NaN) the tile's whole region instead,
   // as does an entry whose MLS system has no solution (a non-finite position)
@@ -799,7 +914,7 @@ hipError_t launch_spread_tiled(const PlanDev& P, const TransferArgs& a, int dtyp
   P.timer->begin(K_FILL, st);
   if (nl > 0)
     hipLaunchKernelGGL(k_zero_counters, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, a.tile_count,
-                       a.tile_fmax, nl);
+                       a.tile_fmax, nl, a.bk_list ? a.bk_state : nullptr);
   P.timer->end(st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -813,8 +928,7 @@ hipError_t launch_spread_tiled(const PlanDev& P, const TransferArgs& a, int dtyp
     P.timer->end(st);
   }
   P.timer->begin(K_SCAN, st);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nl, a.tile_count, a.tile_off, a.tile_cursor, a.list_cap,
-                     a.status);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a, nl);
   P.timer->end(st);
   if (a.n_nodes) {
     P.timer->begin(K_BIN_FILL, st);
