@@ -34,19 +34,20 @@
 
 namespace ifem {
 
+// Absolute float64 position of a node of particle p from its stored coordinates xv (float32 offsets
+// from the particle's anchor, or float64 positions).
+template <typename T>
+__device__ __forceinline__ void position_of(const T xv[3], const double* __restrict__ anchor, int p, double out[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c] = sizeof(T) == 4 ? anchor[3 * p + c] + (double)xv[c] : (double)xv[c];
+}
+
 template <typename T>
 __device__ __forceinline__ void node_position(const TransferArgs& a, const T* __restrict__ x,
                                               const double* __restrict__ anchor, int k, int p, double out[3]) {
   const int64_t N = a.n_nodes;
-  if (sizeof(T) == 4) {
-    out[0] = anchor[3 * p] + (double)x[k];
-    out[1] = anchor[3 * p + 1] + (double)x[N + k];
-    out[2] = anchor[3 * p + 2] + (double)x[2 * N + k];
-  } else {
-    out[0] = (double)x[k];
-    out[1] = (double)x[N + k];
-    out[2] = (double)x[2 * N + k];
-  }
+  const T xv[3] = {x[k], x[N + k], x[2 * N + k]};
+  position_of(xv, anchor, p, out);
 }
 
 // ------------------------------------------------------------------ fills (graph-safe, no memset nodes)
@@ -101,10 +102,12 @@ __global__ void __launch_bounds__(256) k_interp(const TransferArgs a, const T* _
                                                 T* __restrict__ v) {
   const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= a.n_nodes) return;
+  const int64_t N = a.n_nodes;
+  const T xv[3] = {x[k], x[N + k], x[2 * N + k]};  // requested before the particle's box is known
   const int p = a.node_particle[k];
   const BoxDev B = box_of(a, p);
   double pos[3];
-  node_position(a, x, anchor, k, p, pos);
+  position_of(xv, anchor, p, pos);
   unsigned int bad = 0;
   // unrolled: the three components' loads and arithmetic interleave
 #pragma unroll
@@ -219,7 +222,10 @@ __global__ void __launch_bounds__(256) k_spread_atomic(const TransferArgs a, con
 // The tile sums do not depend on where or in which order a list holds its
 // entries (integer sums), so the result is the same either way.
 constexpr int kListsPerEntry = 3;
-__host__ __device__ __forceinline__ int64_t bk_want(int32_t cnt) { return (int64_t)cnt + (cnt >> 1) + kBucketSlack; }
+// (32-bit: the rooms of all lists add up to less than 1.5 list_cap + kBucketSlack per list < 2^32)
+__host__ __device__ __forceinline__ uint32_t bk_want(int32_t cnt) {
+  return (uint32_t)cnt + (uint32_t)(cnt >> 1) + kBucketSlack;
+}
 
 // This call's layout of the carried lists: per list its first slot in bk_list and its room.
 __device__ __forceinline__ const int2* bk_layout(const TransferArgs& a) {
@@ -257,10 +263,12 @@ __device__ __forceinline__ void all_lists(const TransferArgs& a, const T* __rest
 #pragma unroll
   for (int i = 0; i < 3 * kListsPerEntry; ++i) keys[i] = -1;
   if (k < a.n_nodes) {
+    const int64_t N = a.n_nodes;
+    const T xv[3] = {x[k], x[N + k], x[2 * N + k]};  // requested before the particle's box is known
     const int p = a.node_particle[k];
     const BoxDev B = box_of(a, p);
     double pos[3];
-    node_position(a, x, anchor, k, p, pos);
+    position_of(xv, anchor, p, pos);
     int32_t b0[3], bh[3];
     nearest_bases(B, pos, b0, bh);
 #pragma unroll
@@ -391,14 +399,14 @@ __global__ void __launch_bounds__(256) k_bin_fill(const TransferArgs a, const T*
 // above the list capacity is flagged.  With the carried layout the same pass
 // lays out the next call's lists, each with room bk_want(count); lists past
 // the end of bk_list get no room (their nodes take the fill pass).
-__device__ __forceinline__ int2 bk_place(int64_t at, int64_t want, int64_t cap) {
-  const int64_t b = min(at, cap), e = min(at + want, cap);
+__device__ __forceinline__ int2 bk_place(uint32_t at, uint32_t want, int64_t cap) {
+  const int64_t b = min((int64_t)at, cap), e = min((int64_t)at + want, cap);
   return make_int2((int32_t)b, (int32_t)(e - b));
 }
 
 __global__ void __launch_bounds__(1024) k_scan(const TransferArgs a, int32_t n) {
   __shared__ int32_t wsum[1024 / kWave];
-  __shared__ long long wsum2[1024 / kWave];
+  __shared__ uint32_t wsum2[1024 / kWave];
   const int32_t* __restrict__ cnt = a.tile_count;
   int32_t* __restrict__ off = a.tile_off;
   int32_t* __restrict__ cursor = a.tile_cursor;
@@ -406,7 +414,7 @@ __global__ void __launch_bounds__(1024) k_scan(const TransferArgs a, int32_t n) 
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), wave = tid / kWave;
   constexpr int kU = 8;  // loads in flight per thread
   int32_t s = 0;
-  int64_t s2 = 0;
+  uint32_t s2 = 0;
   int i = tid;
   for (; i + (kU - 1) * nt < n; i += kU * nt) {
     int32_t c[kU];
@@ -424,11 +432,11 @@ __global__ void __launch_bounds__(1024) k_scan(const TransferArgs a, int32_t n) 
   }
   // inclusive scans of the thread totals: within each wavefront, then across the wavefront totals
   int32_t incl = s;
-  int64_t incl2 = s2;
+  uint32_t incl2 = s2;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const int32_t v = __shfl_up(incl, o, kWave);
-    const int64_t v2 = __shfl_up(incl2, o, kWave);
+    const uint32_t v2 = __shfl_up(incl2, o, kWave);
     if (lane >= o) {
       incl += v;
       incl2 += v2;
@@ -440,13 +448,13 @@ __global__ void __launch_bounds__(1024) k_scan(const TransferArgs a, int32_t n) 
   }
   __syncthreads();
   int32_t before = 0;
-  int64_t before2 = 0;
+  uint32_t before2 = 0;
   for (int w = 0; w < wave; ++w) {
     before += wsum[w];
     before2 += wsum2[w];
   }
   int32_t run = before + incl - s;
-  int64_t run2 = before2 + incl2 - s2;
+  uint32_t run2 = before2 + incl2 - s2;
   const int64_t bcap = a.bk_cap;
   i = tid;
   for (; i + (kU - 1) * nt < n; i += kU * nt) {
