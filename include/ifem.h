@@ -271,20 +271,20 @@ ifem_status ifem_spread(ifem_plan plan, int32_t dtype, const void* x, const doub
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * ifem_spread in the tiled mode (whatever IFEM_OPT_SPREAD_MODE says), with the
  * same kernels and the same result bit for bit, whose workspace (list counts,
- * offsets, cursors, flags, force bounds, node lists and halo rows) lives in a
- * static device array of the library, 64 MiB per GPU, held from the library's
- * first use of a device until the process ends, instead of the plan's.  The
- * call allocates nothing, synchronises nothing and is graph-capturable; the
- * array's address on each device is looked up once, on the first call there.
- * Returns IFEM_ERR_UNSUPPORTED, before launching anything, when the plan's
- * workspace does not fit: 4 (3 n_tiles) int32 + (3 n_tiles + 1) int32 + the
- * node lists (6 or 9 int32 per node) + 3 n_tiles tile_x (2 (tile_y +
- * tile_z) + 4) values of the call's precision, each part rounded up to 256
- * bytes (a 128^3 grid with 32 x 16 x 8 tiles takes 21 MB in float64).  Every
- * call on one GPU uses that GPU's one array, whatever the plan: calls that
- * overlap on a GPU (on different streams or host threads, with any plans)
- * race on it and must be ordered by the caller.  The array keeps the last
- * call's contents; each call clears what it needs cleared.  Arguments and
+ * offsets, cursors, flags, force bounds, placement totals, node lists and
+ * halo rows) lives in a static device array of the library, 64 MiB per GPU,
+ * held from the library's first use of a device until the process ends,
+ * instead of the plan's.  The call allocates nothing, synchronises nothing and
+ * is graph-capturable; the array's address on each device is looked up once,
+ * on the first call there.  Returns IFEM_ERR_UNSUPPORTED, before launching
+ * anything, when the plan's workspace does not fit: 5 (3 n_tiles) int32 + 2
+ * int32 + the node lists (6 or 9 int32 per node) + 3 n_tiles tile_x (2
+ * (tile_y + tile_z) + 4) values of the call's precision, each part rounded up
+ * to 256 bytes (a 128^3 grid with 32 x 16 x 8 tiles takes 21 MB in float64).
+ * Every call on one GPU uses that GPU's one array, whatever the plan: calls
+ * that overlap on a GPU (on different streams or host threads, with any
+ * plans) race on it and must be ordered by the caller.  The array keeps the
+ * last call's contents; each call clears what it needs cleared.  Arguments and
  * errors as ifem_spread. */
 ifem_status ifem_spread_noalloc(ifem_plan plan, int32_t dtype, const void* x, const double* anchor, const void* F,
                                 void* grid, void* stream);

@@ -629,14 +629,15 @@ ifem_status build_spread(ifem_plan plan, const int32_t tile[3], hipStream_t st) 
   DeviceBuffers mem;
   BoxDev* d_boxes = nullptr;
   int32_t *d_tile_box = nullptr, *d_cnt = nullptr, *d_off = nullptr, *d_cur = nullptr, *d_list = nullptr,
-          *d_flag = nullptr, *d_bk_list = nullptr, *d_bk_state = nullptr;
+          *d_flag = nullptr, *d_bk_list = nullptr, *d_bk_state = nullptr, *d_place = nullptr;
   int2* d_bk_lay = nullptr;
   uint32_t* d_fmax = nullptr;
   double* d_halo = nullptr;  // sized for float64
   hipError_t e = upload(mem, &d_boxes, hb.data(), hb.size(), st);
   if (e == hipSuccess) e = upload(mem, &d_tile_box, tile_box.data(), tile_box.size(), st);
   if (e == hipSuccess) e = mem.alloc(&d_cnt, (size_t)3 * n_tiles);
-  if (e == hipSuccess) e = mem.alloc(&d_off, (size_t)3 * n_tiles + 1);
+  if (e == hipSuccess) e = mem.alloc(&d_off, (size_t)3 * n_tiles);
+  if (e == hipSuccess) e = mem.alloc(&d_place, 2);
   if (e == hipSuccess) e = mem.alloc(&d_cur, (size_t)3 * n_tiles);
   if (e == hipSuccess) e = mem.alloc(&d_list, (size_t)std::max<int64_t>(list_cap, 1));
   if (e == hipSuccess) e = mem.alloc(&d_flag, (size_t)3 * n_tiles);
@@ -663,6 +664,7 @@ ifem_status build_spread(ifem_plan plan, const int32_t tile[3], hipStream_t st) 
   ta.tile_box = d_tile_box;
   ta.tile_count = d_cnt;
   ta.tile_off = d_off;
+  ta.place = d_place;
   ta.tile_cursor = d_cur;
   ta.bin_list = d_list;
   ta.tile_flag = d_flag;
@@ -682,7 +684,7 @@ ifem_status build_spread(ifem_plan plan, const int32_t tile[3], hipStream_t st) 
     plan->tune.tile[a] = tile[a];
   }
   plan->workspace_bytes =
-      (int64_t)(27 * (int64_t)n_tiles + 3 + list_cap + bk_cap) * 4 + (int64_t)3 * n_tiles * halo_cells * 8;
+      (int64_t)(27 * (int64_t)n_tiles + 4 + list_cap + bk_cap) * 4 + (int64_t)3 * n_tiles * halo_cells * 8;
   e = prepare_transfer_kernels(P);
   if (e != hipSuccess) return fail(IFEM_ERR_DEVICE, "spread kernel attributes: %s", hipGetErrorString(e));
   return IFEM_OK;
@@ -1289,7 +1291,8 @@ ifem_status ifem_spread_noalloc(ifem_plan plan, int32_t dtype, const void* x, co
     off += (bytes + kStaticAlign - 1) / kStaticAlign * kStaticAlign;
     return at;
   };
-  const size_t o_cnt = take((size_t)nl * 4), o_off = take((size_t)(nl + 1) * 4), o_cur = take((size_t)nl * 4),
+  const size_t o_cnt = take((size_t)nl * 4), o_off = take((size_t)nl * 4), o_cur = take((size_t)nl * 4),
+               o_place = take(2 * 4),
                o_flag = take((size_t)nl * 4), o_fmax = take((size_t)nl * 4),
                o_list = take((size_t)std::max<int64_t>(t.list_cap, 1) * 4),
                o_halo = take((size_t)nl * t.halo_cells * es);
@@ -1302,6 +1305,7 @@ ifem_status ifem_spread_noalloc(ifem_plan plan, int32_t dtype, const void* x, co
   TransferArgs a = t;
   a.tile_count = reinterpret_cast<int32_t*>(base + o_cnt);
   a.tile_off = reinterpret_cast<int32_t*>(base + o_off);
+  a.place = reinterpret_cast<int32_t*>(base + o_place);
   a.tile_cursor = reinterpret_cast<int32_t*>(base + o_cur);
   a.tile_flag = reinterpret_cast<int32_t*>(base + o_flag);
   a.tile_fmax = reinterpret_cast<uint32_t*>(base + o_fmax);

@@ -73,7 +73,8 @@ struct TransferArgs {
   const BoxDev* boxes;            // [n_boxes]
   const int32_t* tile_box;        // [n_tiles]
   int32_t* tile_count;            // [3 n_tiles] list lengths: nodes whose stencil the tile takes, per component
-  int32_t* tile_off;              // [3 n_tiles + 1]
+  int32_t* tile_off;              // [3 n_tiles]
+  int32_t* place;                 // [2] running totals of the list placement: this call's lists, the next one's
   int32_t* tile_cursor;           // [3 n_tiles]
   int32_t* bin_list;              // [list_cap] node ids, grouped by (component, tile)
   int32_t* tile_flag;             // [3 n_tiles] 1 if the tile wrote a halo shell this call

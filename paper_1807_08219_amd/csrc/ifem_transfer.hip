@@ -13,7 +13,7 @@
 //                       writes it into that list as laid out from the
 //                       previous call's counts, when it fits there;
 //    k_scan             list offsets from the counts, and the layout for
-//                       the next call (single workgroup);
+//                       the next call;
 //    k_bin_fill<T>      writes the nodes of the lists that outgrew their
 //                       layout into lists laid out from this call's counts
 //                       (returns at once when none did);
@@ -57,14 +57,19 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
     p[i] = v;
 }
 
-// The list counts and bound codes of the spread, cleared together (graph-safe: no memset node); the
-// layout the previous call's scan prepared becomes this call's, and its overflow flag is cleared.
+// The list counts and bound codes of the spread, cleared together with the placement's running totals
+// (graph-safe: no memset node); the layout the previous call's scan prepared becomes this call's, and
+// its overflow flag is cleared.
 __global__ void k_zero_counters(int32_t* __restrict__ count, uint32_t* __restrict__ code, int n,
-                                int32_t* __restrict__ bk_state) {
+                                int32_t* __restrict__ place, int32_t* __restrict__ bk_state) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     count[i] = 0;
     code[i] = 0u;
+  }
+  if (i == 0) {
+    place[0] = 0;
+    place[1] = 0;
   }
   if (i == 0 && bk_state) {
     bk_state[0] ^= 1;
@@ -392,43 +397,45 @@ __global__ void __launch_bounds__(256) k_bin_fill(const TransferArgs a, const T*
   }
 }
 
-// List placement: any disjoint placement of the lists works, so thread t takes
-// the counts t, t + nt, t + 2 nt, ... (coalesced loads), the thread totals are
-// scanned across the workgroup, and each thread lays its lists out one after
-// another from its prefix.  Every cursor starts at its list's offset; a total
-// above the list capacity is flagged.  With the carried layout the same pass
-// lays out the next call's lists, each with room bk_want(count); lists past
-// the end of bk_list get no room (their nodes take the fill pass).
+// List placement: any disjoint placement of the lists works, so the lists are
+// cut into chunks of kScanThreads * kScanPer, one per workgroup; a workgroup
+// sums its counts (thread t takes the counts t, t + 256, ... of the chunk:
+// coalesced loads), scans the thread totals and reserves its chunk's total
+// with one atomic on a running total, and each thread lays its lists out one
+// after another from there.  No workgroup waits for another.  Every cursor
+// starts at its list's offset; a total above the list capacity is flagged.
+// With the carried layout the same pass lays out the next call's lists, each
+// with room bk_want(count), from a second running total; lists past the end of
+// bk_list get no room (their nodes take the fill pass).
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;  // lists per thread
+
 __device__ __forceinline__ int2 bk_place(uint32_t at, uint32_t want, int64_t cap) {
   const int64_t b = min((int64_t)at, cap), e = min((int64_t)at + want, cap);
   return make_int2((int32_t)b, (int32_t)(e - b));
 }
 
-__global__ void __launch_bounds__(1024) k_scan(const TransferArgs a, int32_t n) {
-  __shared__ int32_t wsum[1024 / kWave];
-  __shared__ uint32_t wsum2[1024 / kWave];
+__global__ void __launch_bounds__(kScanThreads) k_scan(const TransferArgs a, int32_t n) {
+  __shared__ int32_t wsum[kScanThreads / kWave];
+  __shared__ uint32_t wsum2[kScanThreads / kWave];
+  __shared__ int32_t chunk_base;
+  __shared__ uint32_t chunk_base2;
   const int32_t* __restrict__ cnt = a.tile_count;
-  int32_t* __restrict__ off = a.tile_off;
-  int32_t* __restrict__ cursor = a.tile_cursor;
   int2* __restrict__ next = a.bk_list ? a.bk_lay + (int64_t)(a.bk_state[0] ^ 1) * n : nullptr;
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  constexpr int kU = 8;  // loads in flight per thread
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int i0 = blockIdx.x * (kScanThreads * kScanPer) + tid;
+  int32_t c[kScanPer];
   int32_t s = 0;
   uint32_t s2 = 0;
-  int i = tid;
-  for (; i + (kU - 1) * nt < n; i += kU * nt) {
-    int32_t c[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) c[u] = cnt[i + u * nt];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      s += c[u];
-      s2 += bk_want(c[u]);
-    }
+  for (int u = 0; u < kScanPer; ++u) {
+    const int i = i0 + u * kScanThreads;
+    c[u] = i < n ? cnt[i] : 0;
   }
-  for (; i < n; i += nt) {
-    s += cnt[i];
-    s2 += bk_want(cnt[i]);
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    s += c[u];
+    s2 += i0 + u * kScanThreads < n ? bk_want(c[u]) : 0u;
   }
   // inclusive scans of the thread totals: within each wavefront, then across the wavefront totals
   int32_t incl = s;
@@ -447,40 +454,37 @@ __global__ void __launch_bounds__(1024) k_scan(const TransferArgs a, int32_t n) 
     wsum2[wave] = incl2;
   }
   __syncthreads();
-  int32_t before = 0;
-  uint32_t before2 = 0;
-  for (int w = 0; w < wave; ++w) {
-    before += wsum[w];
-    before2 += wsum2[w];
+  int32_t before = 0, total = 0;
+  uint32_t before2 = 0, total2 = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / kWave; ++w) {
+    if (w < wave) {
+      before += wsum[w];
+      before2 += wsum2[w];
+    }
+    total += wsum[w];
+    total2 += wsum2[w];
   }
-  int32_t run = before + incl - s;
-  uint32_t run2 = before2 + incl2 - s2;
+  if (tid == 0) {
+    const int32_t b0 = atomicAdd(a.place, total);
+    chunk_base = b0;
+    chunk_base2 = atomicAdd(reinterpret_cast<uint32_t*>(a.place + 1), total2);
+    if ((int64_t)b0 + total > a.list_cap) atomicAdd(a.status + 3, 1ull);
+  }
+  __syncthreads();
+  int32_t run = chunk_base + before + incl - s;
+  uint32_t run2 = chunk_base2 + before2 + incl2 - s2;
   const int64_t bcap = a.bk_cap;
-  i = tid;
-  for (; i + (kU - 1) * nt < n; i += kU * nt) {
-    int32_t c[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) c[u] = cnt[i + u * nt];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      off[i + u * nt] = run;
-      cursor[i + u * nt] = run;
-      if (next) next[i + u * nt] = bk_place(run2, bk_want(c[u]), bcap);
+  for (int u = 0; u < kScanPer; ++u) {
+    const int i = i0 + u * kScanThreads;
+    if (i < n) {
+      a.tile_off[i] = run;
+      a.tile_cursor[i] = run;
+      if (next) next[i] = bk_place(run2, bk_want(c[u]), bcap);
       run += c[u];
       run2 += bk_want(c[u]);
     }
-  }
-  for (; i < n; i += nt) {
-    const int32_t c = cnt[i];
-    off[i] = run;
-    cursor[i] = run;
-    if (next) next[i] = bk_place(run2, bk_want(c), bcap);
-    run += c;
-    run2 += bk_want(c);
-  }
-  if (tid == nt - 1) {
-    off[n] = run;
-    if ((int64_t)run > a.list_cap) atomicAdd(a.status + 3, 1ull);
   }
 }
 
@@ -922,7 +926,7 @@ hipError_t launch_spread_tiled(const PlanDev& P, const TransferArgs& a, int dtyp
   P.timer->begin(K_FILL, st);
   if (nl > 0)
     hipLaunchKernelGGL(k_zero_counters, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, a.tile_count,
-                       a.tile_fmax, nl, a.bk_list ? a.bk_state : nullptr);
+                       a.tile_fmax, nl, a.place, a.bk_list ? a.bk_state : nullptr);
   P.timer->end(st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -936,7 +940,9 @@ hipError_t launch_spread_tiled(const PlanDev& P, const TransferArgs& a, int dtyp
     P.timer->end(st);
   }
   P.timer->begin(K_SCAN, st);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a, nl);
+  if (nl > 0)
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)((nl + kScanThreads * kScanPer - 1) / (kScanThreads * kScanPer))),
+                       dim3(kScanThreads), 0, st, a, nl);
   P.timer->end(st);
   if (a.n_nodes) {
     P.timer->begin(K_BIN_FILL, st);
