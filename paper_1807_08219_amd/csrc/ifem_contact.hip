@@ -209,7 +209,15 @@ __global__ void __launch_bounds__(256) k_ac_owner(const ContactArgs a) {
   if (c >= a.n_cells) return;
   const int n = a.count[c], o = a.off[c];
   int owner = -1;
-  for (int i = 0; i < n; ++i) {
+  int i = 0;
+  for (; i + 4 <= n; i += 4) {  // four records' loads in flight at a time
+    int pp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pp[u] = a.rec[o + i + u].p;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) owner = (owner == -1 || owner == pp[u]) ? pp[u] : -2;
+  }
+  for (; i < n; ++i) {
     const int p = a.rec[o + i].p;
     owner = (owner == -1 || owner == p) ? p : -2;
   }
