@@ -995,7 +995,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(upload(mem, &d_cboxes, cb.data(), cb.size(), st));
   HIP_TRY(upload(mem, &d_bface, bfaces.data(), bfaces.size(), st));
   HIP_TRY(mem.alloc(&d_ccount, (size_t)n_ccells));
-  HIP_TRY(mem.alloc(&d_coff, (size_t)n_ccells + 1));
+  HIP_TRY(mem.alloc(&d_coff, (size_t)n_ccells));
   HIP_TRY(mem.alloc(&d_ccur, (size_t)n_ccells));
   HIP_TRY(mem.alloc(&d_cown, (size_t)n_ccells));
   int32_t *d_nlo, *d_nhi, *d_nlo2, *d_nhi2;
@@ -1007,8 +1007,6 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_ckeys, (size_t)m.n_nodes));
   int32_t* d_ckeyf;
   HIP_TRY(mem.alloc(&d_ckeyf, (size_t)m.n_nodes));
-  int32_t* d_cscan;
-  HIP_TRY(mem.alloc(&d_cscan, (size_t)contact_scan_blocks((int32_t)n_ccells) + 1));
   // (face, cell) work of the contact search, in 256 equal segments: two items per face on average
   // fit; a face whose items do not fit its segment is searched whole from the slow list
   const int32_t work_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(2 * ((int64_t)m.n_tris + n_bfaces), 1 << 16),
@@ -1017,7 +1015,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   int32_t* d_cwcount;
   int32_t* d_cslow;
   HIP_TRY(mem.alloc(&d_cwork, (size_t)work_cap));
-  HIP_TRY(mem.alloc(&d_cwcount, 256 + 2));
+  HIP_TRY(mem.alloc(&d_cwcount, 256 + 3));
   int32_t* d_chits;
   HIP_TRY(mem.alloc(&d_chits, (size_t)work_cap));
   HIP_TRY(mem.alloc(&d_cslow, (size_t)m.n_tris + n_bfaces));
@@ -1090,11 +1088,11 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ca.rec = d_crec;
   ca.keys = d_ckeys;
   ca.keyf = d_ckeyf;
-  ca.scan_tmp = d_cscan;
   ca.work = d_cwork;
   ca.work_count = d_cwcount;
   ca.slow_count = d_cwcount + 256;
   ca.hit_count = d_cwcount + 257;
+  ca.place = d_cwcount + 258;
   ca.hits = d_chits;
   ca.slow = d_cslow;
   ca.status = d_status;

@@ -9,7 +9,8 @@
 // skipped whole.
 //
 //  k_ac_count<T>  per node: its cell; one atomic per distinct cell and wavefront;
-//  k_cscan_*      cell offsets (a three-kernel scan over all cells);
+//  k_cscan        cell offsets (any disjoint placement: one pass, a running
+//                 total per workgroup chunk);
 //  k_ac_fill<T>   per node: a record {position, node, particle} in its cell's list;
 //  k_ac_owner     per cell: the particle owning all its nodes, -2 if mixed, -1 empty;
 //  k_ac_near_*    per cell: the least and greatest owner over the 3^3 cells around
@@ -614,14 +615,31 @@ __global__ void __launch_bounds__(256) k_ac_push(const ContactArgs a, const T* _
 }
 
 // ------------------------------------------------------------------ cell offsets
-// Exclusive prefix sum of the cell counts in index order, in three passes:
-// block totals (kScanItems cells per workgroup), one workgroup scanning the
-// totals, then each block's cells.  off[n] receives the total.
+// Any disjoint placement of the cells' record ranges works, so the cells are cut
+// into chunks of kScanItems, one per workgroup: a workgroup sums its counts
+// (thread t takes the counts t, t + kScanBlock, ... of the chunk: coalesced
+// loads; kScanPer consecutive cells per thread made the loads strided and the
+// pass twice as slow), scans the thread totals, reserves its chunk's total with
+// one atomic on a running total, and each thread lays its cells out one after
+// another from there.  No workgroup waits for another.
 constexpr int kScanBlock = 256, kScanPer = 16, kScanItems = kScanBlock * kScanPer;
 
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* wsum, int32_t& total) {
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  int32_t incl = v;
+__global__ void __launch_bounds__(kScanBlock) k_cscan(int32_t n, const int32_t* __restrict__ cnt,
+                                                      int32_t* __restrict__ running, int32_t* __restrict__ off,
+                                                      int32_t* __restrict__ cursor) {
+  __shared__ int32_t wsum[kScanBlock / kWave];
+  __shared__ int32_t chunk_base;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int64_t i0 = (int64_t)blockIdx.x * kScanItems + tid;
+  int32_t c[kScanPer], s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const int64_t i = i0 + (int64_t)j * kScanBlock;
+    c[j] = i < n ? cnt[i] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) s += c[j];
+  int32_t incl = s;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const int32_t u = __shfl_up(incl, o, kWave);
@@ -629,67 +647,24 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* wsum
   }
   if (lane == kWave - 1) wsum[wave] = incl;
   __syncthreads();
-  int32_t before = 0;
-  total = 0;
-  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+  int32_t before = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kScanBlock / kWave; ++w) {
     if (w < wave) before += wsum[w];
     total += wsum[w];
   }
+  if (tid == 0) chunk_base = atomicAdd(running, total);
   __syncthreads();
-  return before + incl - v;
-}
-
-__global__ void __launch_bounds__(kScanBlock) k_cscan_totals(int32_t n, const int32_t* __restrict__ cnt,
-                                                             int32_t* __restrict__ totals) {
-  __shared__ int32_t wsum[kScanBlock / kWave];
-  const int64_t b0 = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * kScanPer;
-  int32_t s = 0;
-  for (int j = 0; j < kScanPer; ++j)
-    if (b0 + j < n) s += cnt[b0 + j];
-  int32_t total;
-  block_exclusive_scan(s, wsum, total);
-  if (threadIdx.x == 0) totals[blockIdx.x] = total;
-}
-
-__global__ void __launch_bounds__(1024) k_cscan_top(int32_t nb, int32_t* __restrict__ totals) {
-  __shared__ int32_t wsum[1024 / kWave];
-  const int per = (nb + 1023) / 1024;
-  const int b0 = threadIdx.x * per;
-  int32_t s = 0;
-  for (int j = 0; j < per; ++j)
-    if (b0 + j < nb) s += totals[b0 + j];
-  int32_t total;
-  int32_t run = block_exclusive_scan(s, wsum, total);
-  for (int j = 0; j < per; ++j)
-    if (b0 + j < nb) {
-      const int32_t t = totals[b0 + j];
-      totals[b0 + j] = run;
-      run += t;
-    }
-  if (threadIdx.x == 0) totals[nb] = total;
-}
-
-__global__ void __launch_bounds__(kScanBlock) k_cscan_cells(int32_t n, const int32_t* __restrict__ cnt,
-                                                            const int32_t* __restrict__ totals,
-                                                            int32_t* __restrict__ off, int32_t* __restrict__ cursor) {
-  __shared__ int32_t wsum[kScanBlock / kWave];
-  const int64_t b0 = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * kScanPer;
-  int32_t c[kScanPer], s = 0;
+  int32_t run = chunk_base + before + incl - s;
 #pragma unroll
   for (int j = 0; j < kScanPer; ++j) {
-    c[j] = b0 + j < n ? cnt[b0 + j] : 0;
-    s += c[j];
-  }
-  int32_t total;
-  int32_t run = totals[blockIdx.x] + block_exclusive_scan(s, wsum, total);
-#pragma unroll
-  for (int j = 0; j < kScanPer; ++j)
-    if (b0 + j < n) {
-      off[b0 + j] = run;
-      cursor[b0 + j] = run;
+    const int64_t i = i0 + (int64_t)j * kScanBlock;
+    if (i < n) {
+      off[i] = run;
+      cursor[i] = run;
       run += c[j];
     }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) off[n] = totals[gridDim.x];
+  }
 }
 
 int32_t contact_scan_blocks(int32_t n_cells) { return (n_cells + kScanItems - 1) / kScanItems; }
@@ -705,7 +680,8 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
   hipError_t e;
   P.timer->begin(K_FILL, st);
   e = launch_fill_i32(a.count, a.n_cells, 0, st);
-  if (e == hipSuccess) e = launch_fill_i32(a.work_count, kWorkSegs + 2, 0, st);  // segment, slow-face, hit counters
+  // segment, slow-face and hit counters, and the running total of the cell placement
+  if (e == hipSuccess) e = launch_fill_i32(a.work_count, kWorkSegs + 3, 0, st);
   if (e == hipSuccess) e = launch_fill_u64(a.keys, a.n_nodes, kNoFace, st);
   if (e == hipSuccess) e = launch_fill_i32(a.keyf, a.n_nodes, kNoFaceId, st);
   P.timer->end(st);
@@ -715,11 +691,8 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
     hipLaunchKernelGGL(k_ac_count<float>, gn, dim3(B), 0, st, a, (const float*)x, anchor);
   else
     hipLaunchKernelGGL(k_ac_count<double>, gn, dim3(B), 0, st, a, (const double*)x, anchor);
-  const int nb = contact_scan_blocks(a.n_cells);
-  hipLaunchKernelGGL(k_cscan_totals, dim3(nb), dim3(kScanBlock), 0, st, a.n_cells, a.count, a.scan_tmp);
-  hipLaunchKernelGGL(k_cscan_top, dim3(1), dim3(1024), 0, st, nb, a.scan_tmp);
-  hipLaunchKernelGGL(k_cscan_cells, dim3(nb), dim3(kScanBlock), 0, st, a.n_cells, a.count, a.scan_tmp, a.off,
-                     a.cursor);
+  hipLaunchKernelGGL(k_cscan, dim3((unsigned)contact_scan_blocks(a.n_cells)), dim3(kScanBlock), 0, st, a.n_cells,
+                     a.count, a.place, a.off, a.cursor);
   if (dtype == 0)
     hipLaunchKernelGGL(k_ac_fill<float>, gn, dim3(B), 0, st, a, (const float*)x, anchor);
   else

@@ -135,7 +135,7 @@ struct ContactArgs {
   const int32_t* tri;            // [3][n_tris] membrane triangles, global node ids (input order)
   const int32_t* bface;          // [3][n_bfaces] boundary faces of the solids, outward
   int32_t* count;                // [n_cells] nodes per cell
-  int32_t* off;                  // [n_cells + 1]
+  int32_t* off;                  // [n_cells] first record of each cell
   int32_t* cursor;               // [n_cells]
   int32_t* owner;                // [n_cells] particle of all the cell's nodes, -2 mixed, -1 empty
   int32_t *near_lo, *near_hi;    // [n_cells] least / greatest owner around each cell (filter passes)
@@ -143,11 +143,11 @@ struct ContactArgs {
   ContactNode* rec;              // [n_nodes] the nodes grouped by cell
   unsigned long long* keys;      // [n_nodes] float64 bits of the least distance below d_min (atomic min)
   int32_t* keyf;                 // [n_nodes] least face id at exactly that distance (second pass)
-  int32_t* scan_tmp;             // [cell blocks + 1] block totals of the offset scan
   uint2* work;                   // [work_cap] (face, cell) pairs to search
-  int32_t* work_count;           // [256 + 2]: items per work-list segment, slow faces, hits
+  int32_t* work_count;           // [256 + 3]: items per work-list segment, slow faces, hits, cell placement
   int32_t* slow_count;           // work_count + 256
   int32_t* hit_count;            // work_count + 257
+  int32_t* place;                // work_count + 258: running total of the cell placement
   int32_t* hits;                 // [work_cap] work-list slots of items that found a pair below d_min
   int32_t* slow;                 // [n_tris + n_bfaces] faces searched whole
   unsigned long long* status;    // the plan's status counters
