@@ -9,6 +9,7 @@
 // skipped whole.
 //
 //  k_ac_count<T>  per node: its cell; one atomic per distinct cell and wavefront;
+//                 the node's least distance and face cleared;
 //  k_cscan        cell offsets (any disjoint placement: one pass, a running
 //                 total per workgroup chunk);
 //  k_ac_fill<T>   per node: a record {position, node, particle} in its cell's list;
@@ -169,6 +170,8 @@ __global__ void __launch_bounds__(256) k_ac_count(const ContactArgs a, const T* 
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   int key = -1;
   if (k < a.n_nodes) {
+    a.keys[k] = kNoFace;  // the node's least distance and face so far: none
+    a.keyf[k] = kNoFaceId;
     const int p = a.node_particle[k];
     double pos[3];
     abs_position(a, x, anchor, k, p, pos);
@@ -682,8 +685,6 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
   e = launch_fill_i32(a.count, a.n_cells, 0, st);
   // segment, slow-face and hit counters, and the running total of the cell placement
   if (e == hipSuccess) e = launch_fill_i32(a.work_count, kWorkSegs + 3, 0, st);
-  if (e == hipSuccess) e = launch_fill_u64(a.keys, a.n_nodes, kNoFace, st);
-  if (e == hipSuccess) e = launch_fill_i32(a.keyf, a.n_nodes, kNoFaceId, st);
   P.timer->end(st);
   if (e != hipSuccess) return e;
   P.timer->begin(K_CONTACT, st);
