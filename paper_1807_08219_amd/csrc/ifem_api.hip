@@ -998,11 +998,9 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(mem.alloc(&d_coff, (size_t)n_ccells));
   HIP_TRY(mem.alloc(&d_ccur, (size_t)n_ccells));
   HIP_TRY(mem.alloc(&d_cown, (size_t)n_ccells));
-  int32_t *d_nlo, *d_nhi, *d_nlo2, *d_nhi2;
+  int32_t *d_nlo, *d_nhi;
   HIP_TRY(mem.alloc(&d_nlo, (size_t)n_ccells));
   HIP_TRY(mem.alloc(&d_nhi, (size_t)n_ccells));
-  HIP_TRY(mem.alloc(&d_nlo2, (size_t)n_ccells));
-  HIP_TRY(mem.alloc(&d_nhi2, (size_t)n_ccells));
   HIP_TRY(mem.alloc(&d_crec, (size_t)m.n_nodes));
   HIP_TRY(mem.alloc(&d_ckeys, (size_t)m.n_nodes));
   int32_t* d_ckeyf;
@@ -1082,8 +1080,6 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   ca.owner = d_cown;
   ca.near_lo = d_nlo;
   ca.near_hi = d_nhi;
-  ca.near_lo2 = d_nlo2;
-  ca.near_hi2 = d_nhi2;
   ca.n_boxes = n_boxes;
   ca.rec = d_crec;
   ca.keys = d_ckeys;

@@ -14,9 +14,9 @@
 //                 total per workgroup chunk);
 //  k_ac_fill<T>   per node: a record {position, node, particle} in its cell's list;
 //  k_ac_owner     per cell: the particle owning all its nodes, -2 if mixed, -1 empty;
-//  k_ac_near_*    per cell: the least and greatest owner over the 3^3 cells around
-//                 it (separable, one pass per axis), so that a face whose whole
-//                 neighbourhood holds only its own particle is dropped at once;
+//  k_ac_near      per cell: the least and greatest owner over the 3^3 cells around
+//                 it, so that a face whose whole neighbourhood holds only its own
+//                 particle is dropped at once;
 //  k_ac_faces<T>  per face: the cells it reaches that hold nodes of other
 //                 particles, appended as (face, cell) work items to one of
 //                 kWorkSegs segments (one counter per segment); a face reaching
@@ -228,28 +228,24 @@ __global__ void __launch_bounds__(256) k_ac_owner(const ContactArgs a) {
   a.owner[c] = owner;
 }
 
-// Neighbourhood test, separable: every cell gets the least and the greatest
-// owner over the cells within kNear cells along each axis in turn (periodic),
-// empty cells neutral and mixed cells forcing lo < hi.  After the three passes
-// lo < hi says that the (2 kNear + 1)^3 cells around hold nodes of more than
-// one particle; a face whose grown box stays inside that neighbourhood of its
-// first corner's cell, and finds lo == hi there, has no other particle's node
-// to test and is skipped.
+// Neighbourhood test: every cell gets the least and the greatest owner over the
+// (2 kNear + 1)^3 cells around it (periodic), empty cells neutral and mixed
+// cells forcing lo < hi, so that lo < hi says that those cells hold nodes of
+// more than one particle; a face whose grown box stays inside that
+// neighbourhood of its first corner's cell, and finds lo == hi there, has no
+// other particle's node to test and is skipped.
 constexpr int kNear = 1;  // a face with d_min <= h reaches at most one contact cell past its first corner
 constexpr int kOwnerEmptyLo = 0x7fffffff, kOwnerEmptyHi = -0x7fffffff;
 
-__global__ void __launch_bounds__(256) k_ac_near_init(const ContactArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.n_cells) return;
-  const int o = a.owner[c];
-  a.near_lo[c] = o == -1 ? kOwnerEmptyLo : (o == -2 ? -1 : o);
-  a.near_hi[c] = o == -1 ? kOwnerEmptyHi : (o == -2 ? kOwnerEmptyLo : o);
-}
+// The whole neighbourhood at once: every cell reads the owners of the 3^3 cells around it (the
+// window of kNear = 1, periodic; on an axis shorter than the window a cell may come twice:
+// harmless) and keeps the least and the greatest.  One pass over the owners instead of an
+// initialisation and one pass per axis.
+static_assert(kNear == 1, "the neighbourhood pass reads a 3^3 window");
+__device__ __forceinline__ int near_lo_of(int o) { return o == -1 ? kOwnerEmptyLo : (o == -2 ? -1 : o); }
+__device__ __forceinline__ int near_hi_of(int o) { return o == -1 ? kOwnerEmptyHi : (o == -2 ? kOwnerEmptyLo : o); }
 
-// One axis of the filter: (lo, hi) -> (lo2, hi2), cells of every box.
-__global__ void __launch_bounds__(256) k_ac_near_axis(const ContactArgs a, int axis, const int32_t* __restrict__ lo,
-                                                      const int32_t* __restrict__ hi, int32_t* __restrict__ lo2,
-                                                      int32_t* __restrict__ hi2) {
+__global__ void __launch_bounds__(256) k_ac_near(const ContactArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n_cells) return;
   // the box holding cell c: boxes are few and ordered by base
@@ -257,18 +253,22 @@ __global__ void __launch_bounds__(256) k_ac_near_axis(const ContactArgs a, int a
   while (b + 1 < a.n_boxes && a.boxes[b + 1].base <= c) ++b;
   const ContactBoxDev& C = a.boxes[b];
   const int r = c - C.base;
-  const int ix = r % C.nc[0], iy = (r / C.nc[0]) % C.nc[1], iz = r / (C.nc[0] * C.nc[1]);
-  const int stride = axis == 0 ? 1 : (axis == 1 ? C.nc[0] : C.nc[0] * C.nc[1]);
-  const int i0 = axis == 0 ? ix : (axis == 1 ? iy : iz), n = C.nc[axis];
+  const int n0 = C.nc[0], n1 = C.nc[1], n2 = C.nc[2];
+  const int ix = r % n0, iy = (r / n0) % n1, iz = r / (n0 * n1);
+  const int xs[3] = {ix == 0 ? n0 - 1 : ix - 1, ix, ix == n0 - 1 ? 0 : ix + 1};
+  const int ys[3] = {(iy == 0 ? n1 - 1 : iy - 1) * n0, iy * n0, (iy == n1 - 1 ? 0 : iy + 1) * n0};
+  const int zs[3] = {(iz == 0 ? n2 - 1 : iz - 1) * n0 * n1, iz * n0 * n1, (iz == n2 - 1 ? 0 : iz + 1) * n0 * n1};
+  int o[27];  // all 27 owners requested before any is used
+#pragma unroll
+  for (int j = 0; j < 27; ++j) o[j] = a.owner[C.base + zs[j / 9] + ys[(j / 3) % 3] + xs[j % 3]];
   int l = kOwnerEmptyLo, h = kOwnerEmptyHi;
-  for (int d = -kNear; d <= kNear; ++d) {  // on an axis shorter than the window a cell may come twice: harmless
-    const int j = ((i0 + d) % n + n) % n;
-    const int cc = c + (j - i0) * stride;
-    l = min(l, lo[cc]);
-    h = max(h, hi[cc]);
+#pragma unroll
+  for (int j = 0; j < 27; ++j) {
+    l = min(l, near_lo_of(o[j]));
+    h = max(h, near_hi_of(o[j]));
   }
-  lo2[c] = l;
-  hi2[c] = h;
+  a.near_lo[c] = l;
+  a.near_hi[c] = h;
 }
 
 // The corners of contact face f (global node ids) and its particle.
@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(256) k_ac_faces(const ContactArgs a, const T* 
     for (int i = 0; i < 3; ++i) inside = inside && lo[i] >= c0[i] - kNear && lo[i] + cnt[i] - 1 <= c0[i] + kNear;
     if (inside) {
       const int cell0 = contact_cell(C, c0[0], c0[1], c0[2]);
-      if (a.near_lo2[cell0] >= a.near_hi2[cell0]) ok = false;
+      if (a.near_lo[cell0] >= a.near_hi[cell0]) ok = false;
     }
   }
   if (!ok) ncell = 0;
@@ -699,12 +699,7 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
   else
     hipLaunchKernelGGL(k_ac_fill<double>, gn, dim3(B), 0, st, a, (const double*)x, anchor);
   hipLaunchKernelGGL(k_ac_owner, gc, dim3(B), 0, st, a);
-  hipLaunchKernelGGL(k_ac_near_init, gc, dim3(B), 0, st, a);
-  for (int axis = 0; axis < 3; ++axis) {  // ping-pong, three passes: the result lands in near_lo2, near_hi2
-    const bool even = axis % 2 == 0;
-    hipLaunchKernelGGL(k_ac_near_axis, gc, dim3(B), 0, st, a, axis, even ? a.near_lo : a.near_lo2,
-                       even ? a.near_hi : a.near_hi2, even ? a.near_lo2 : a.near_lo, even ? a.near_hi2 : a.near_hi);
-  }
+  hipLaunchKernelGGL(k_ac_near, gc, dim3(B), 0, st, a);
   if (nf > 0) {
     const dim3 gf((unsigned)((nf + B - 1) / B));
     if (dtype == 0)

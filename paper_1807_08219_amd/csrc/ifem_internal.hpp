@@ -138,8 +138,7 @@ struct ContactArgs {
   int32_t* off;                  // [n_cells] first record of each cell
   int32_t* cursor;               // [n_cells]
   int32_t* owner;                // [n_cells] particle of all the cell's nodes, -2 mixed, -1 empty
-  int32_t *near_lo, *near_hi;    // [n_cells] least / greatest owner around each cell (filter passes)
-  int32_t *near_lo2, *near_hi2;  // [n_cells] the same, second buffers (the final result)
+  int32_t *near_lo, *near_hi;  // [n_cells] least / greatest owner over the 3^3 cells around each cell
   ContactNode* rec;              // [n_nodes] the nodes grouped by cell
   unsigned long long* keys;      // [n_nodes] float64 bits of the least distance below d_min (atomic min)
   int32_t* keyf;                 // [n_nodes] least face id at exactly that distance (second pass)
