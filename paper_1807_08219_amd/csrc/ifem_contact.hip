@@ -11,9 +11,10 @@
 //  k_ac_count<T>  per node: its cell; one atomic per distinct cell and wavefront;
 //                 the node's least distance and face cleared;
 //  k_cscan        cell offsets (any disjoint placement: one pass, a running
-//                 total per workgroup chunk);
-//  k_ac_fill<T>   per node: a record {position, node, particle} in its cell's list;
-//  k_ac_owner     per cell: the particle owning all its nodes, -2 if mixed, -1 empty;
+//                 total per workgroup chunk), owners cleared;
+//  k_ac_fill<T>   per node: a record {position, node, particle} in its cell's list,
+//                 and the cell's owner: the particle of all its nodes, -2 if
+//                 mixed, -1 empty (a compare-and-swap per wavefront group);
 //  k_ac_near      per cell: the least and greatest owner over the 3^3 cells around
 //                 it, so that a face whose whole neighbourhood holds only its own
 //                 particle is dropped at once;
@@ -196,6 +197,15 @@ __global__ void __launch_bounds__(256) k_ac_fill(const ContactArgs a, const T* _
   int leader, rank, size;
   wave_groups(key, leader, rank, size);
   const int base = size > 0 ? atomicAdd(a.cursor + key, size) : 0;
+  // the cell's owner (cleared to -1 by the placement pass): the group leader claims the cell for its
+  // particle; a cell claimed for another particle, or a member of another particle than its leader's,
+  // marks the cell mixed (-2), whatever the order of the atomics
+  const int pl = __shfl(p, leader, kWave);
+  if (size > 0) {
+    const int old = atomicCAS(a.owner + key, -1, pl);
+    if (old != -1 && old != pl) atomicExch(a.owner + key, -2);
+  }
+  if (key >= 0 && p != pl) atomicExch(a.owner + key, -2);
   const int slot = __shfl(base, leader, kWave) + rank;
   if (key >= 0 && slot < a.n_nodes) {
     ContactNode r;
@@ -206,26 +216,6 @@ __global__ void __launch_bounds__(256) k_ac_fill(const ContactArgs a, const T* _
     r.p = p;
     a.rec[slot] = r;
   }
-}
-
-__global__ void __launch_bounds__(256) k_ac_owner(const ContactArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.n_cells) return;
-  const int n = a.count[c], o = a.off[c];
-  int owner = -1;
-  int i = 0;
-  for (; i + 4 <= n; i += 4) {  // four records' loads in flight at a time
-    int pp[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) pp[u] = a.rec[o + i + u].p;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) owner = (owner == -1 || owner == pp[u]) ? pp[u] : -2;
-  }
-  for (; i < n; ++i) {
-    const int p = a.rec[o + i].p;
-    owner = (owner == -1 || owner == p) ? p : -2;
-  }
-  a.owner[c] = owner;
 }
 
 // Neighbourhood test: every cell gets the least and the greatest owner over the
@@ -629,7 +619,7 @@ constexpr int kScanBlock = 256, kScanPer = 16, kScanItems = kScanBlock * kScanPe
 
 __global__ void __launch_bounds__(kScanBlock) k_cscan(int32_t n, const int32_t* __restrict__ cnt,
                                                       int32_t* __restrict__ running, int32_t* __restrict__ off,
-                                                      int32_t* __restrict__ cursor) {
+                                                      int32_t* __restrict__ cursor, int32_t* __restrict__ owner) {
   __shared__ int32_t wsum[kScanBlock / kWave];
   __shared__ int32_t chunk_base;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -665,6 +655,7 @@ __global__ void __launch_bounds__(kScanBlock) k_cscan(int32_t n, const int32_t* 
     if (i < n) {
       off[i] = run;
       cursor[i] = run;
+      owner[i] = -1;  // no node yet (the fill pass claims the cell)
       run += c[j];
     }
   }
@@ -693,12 +684,11 @@ hipError_t launch_antistick(const PlanDev& P, int dtype, const void* x, const do
   else
     hipLaunchKernelGGL(k_ac_count<double>, gn, dim3(B), 0, st, a, (const double*)x, anchor);
   hipLaunchKernelGGL(k_cscan, dim3((unsigned)contact_scan_blocks(a.n_cells)), dim3(kScanBlock), 0, st, a.n_cells,
-                     a.count, a.place, a.off, a.cursor);
+                     a.count, a.place, a.off, a.cursor, a.owner);
   if (dtype == 0)
     hipLaunchKernelGGL(k_ac_fill<float>, gn, dim3(B), 0, st, a, (const float*)x, anchor);
   else
     hipLaunchKernelGGL(k_ac_fill<double>, gn, dim3(B), 0, st, a, (const double*)x, anchor);
-  hipLaunchKernelGGL(k_ac_owner, gc, dim3(B), 0, st, a);
   hipLaunchKernelGGL(k_ac_near, gc, dim3(B), 0, st, a);
   if (nf > 0) {
     const dim3 gf((unsigned)((nf + B - 1) / B));
