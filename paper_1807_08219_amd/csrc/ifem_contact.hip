@@ -133,6 +133,21 @@ __device__ __forceinline__ void abs_position(const ContactArgs& a, const T* __re
   for (int i = 0; i < 3; ++i) out[i] = (sizeof(T) == 4 ? anchor[3 * p + i] : 0.0) + (double)x[i * N + k];
 }
 
+// The stored coordinates of node k, requested before its particle (and so its anchor) is known.
+template <typename T>
+__device__ __forceinline__ void load_coords(const ContactArgs& a, const T* __restrict__ x, int k, T out[3]) {
+  const int64_t N = a.n_nodes;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[i] = x[i * N + k];
+}
+
+// Absolute float64 position from stored coordinates and the particle's anchor (float32 offsets).
+template <typename T>
+__device__ __forceinline__ void abs_from(const double* __restrict__ anchor, int p, const T xv[3], double out[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[i] = (sizeof(T) == 4 ? anchor[3 * p + i] : 0.0) + (double)xv[i];
+}
+
 // Corners of a face relative to point xk, in the periodic image of the face
 // nearest to xk: the image of the first corner, applied to all three (a face
 // is one piece; wrapping each corner on its own could tear a face that sits
@@ -173,9 +188,11 @@ __global__ void __launch_bounds__(256) k_ac_count(const ContactArgs a, const T* 
   if (k < a.n_nodes) {
     a.keys[k] = kNoFace;  // the node's least distance and face so far: none
     a.keyf[k] = kNoFaceId;
+    T xv[3];
+    load_coords(a, x, k, xv);
     const int p = a.node_particle[k];
     double pos[3];
-    abs_position(a, x, anchor, k, p, pos);
+    abs_from(anchor, p, xv, pos);
     key = cell_of(cbox_of(a, p), pos);
   }
   int leader, rank, size;
@@ -190,8 +207,10 @@ __global__ void __launch_bounds__(256) k_ac_fill(const ContactArgs a, const T* _
   int key = -1, p = 0;
   double pos[3] = {0.0, 0.0, 0.0};
   if (k < a.n_nodes) {
+    T xv[3];
+    load_coords(a, x, k, xv);
     p = a.node_particle[k];
-    abs_position(a, x, anchor, k, p, pos);
+    abs_from(anchor, p, xv, pos);
     key = cell_of(cbox_of(a, p), pos);
   }
   int leader, rank, size;
@@ -355,10 +374,13 @@ __device__ __forceinline__ bool face_setup(const ContactArgs& a, const T* __rest
                                            double bhi[3]) {
   int v[3];
   face_nodes(a, f, v);
+  T xv[3][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) load_coords(a, x, v[m], xv[m]);
   q = a.node_particle[v[0]];
   C = cbox_of(a, q);
 #pragma unroll
-  for (int m = 0; m < 3; ++m) abs_position(a, x, anchor, v[m], q, pv[m]);
+  for (int m = 0; m < 3; ++m) abs_from(anchor, q, xv[m], pv[m]);
   bool ok = true;
   const double g = d_min * (1.0 + 1e-6);
 #pragma unroll
