@@ -227,7 +227,9 @@ __global__ void __launch_bounds__(256) k_spread_atomic(const TransferArgs a, con
 // The tile sums do not depend on where or in which order a list holds its
 // entries (integer sums), so the result is the same either way.
 constexpr int kListsPerEntry = 3;
-// (32-bit: the rooms of all lists add up to less than 1.5 list_cap + kBucketSlack per list < 2^32)
+// Room of a list of cnt entries in the next call's layout.  32-bit: the rooms of all lists add up to
+// at most 1.5 list_cap + kBucketSlack per list, less than 1.5 times the carried array (< 2^31), so
+// below 2^32.
 __host__ __device__ __forceinline__ uint32_t bk_want(int32_t cnt) {
   return (uint32_t)cnt + (uint32_t)(cnt >> 1) + kBucketSlack;
 }
