@@ -32,7 +32,8 @@ def log(msg):
 # Per-unit algorithmic figures (float32 path; float64 doubles the node and grid terms):
 #   node 12 B per 3-vector access, cell 12 B per 3-component access,
 #   triangle 44 B (12 B indices + 24 B float64 metric + 8 B area),
-#   tetrahedron 72 B (16 B indices + 48 B metric + 8 B volume), bending one-rings
+#   tetrahedron 96 B (16 B indices + 72 B inverse reference edge matrix + 8 B volume; the scope
+#   table's 72 B counts a 48 B metric, which squares the condition number of flat tetrahedra), bending one-rings
 #   +12 B per triangle (3 neighbour ids per triangle of a closed surface) and +4 B per node;
 #   MLS weights + one transfer: 753 flops per (node, component)
 #   [27 stencil nodes x 14 (distance, spline, moments) + 9 x 20 (moment sums)
@@ -53,7 +54,7 @@ def algorithmic(sc, fp64: bool):
     nodes_bend = int(np.diff(sc.node_start)[bend].sum())
     transfer_flops = 3 * sc.n_nodes * MLS_FLOPS
     return {
-        "k_forces": (sc.n_nodes * 2 * vec + sc.n_tris * 44 + sc.n_tets * 72 + tris_bend * 12 + nodes_bend * 4, None),
+        "k_forces": (sc.n_nodes * 2 * vec + sc.n_tris * 44 + sc.n_tets * 96 + tris_bend * 12 + nodes_bend * 4, None),
         "k_spread_home": (sc.n_nodes * 2 * vec + cells * vec, transfer_flops),
         "k_spread_atomic": (sc.n_nodes * 2 * vec + cells * vec, transfer_flops),
         "k_interp": (sc.n_nodes * 2 * vec + cells * vec, transfer_flops),

@@ -985,7 +985,7 @@ ifem_status ifem_plan_create(const ifem_mesh_desc* mesh, const ifem_box* boxes, 
   HIP_TRY(upload(mem, &d_np, node_particle.data(), node_particle.size(), st));
   HIP_TRY(upload(mem, &d_X, m.X_ref, (size_t)3 * m.n_nodes, st));
   HIP_TRY(mem.alloc(&d_tri_ref, (size_t)4 * m.n_tris));
-  HIP_TRY(mem.alloc(&d_tet_ref, (size_t)7 * m.n_tets));
+  HIP_TRY(mem.alloc(&d_tet_ref, (size_t)10 * m.n_tets));
   HIP_TRY(mem.alloc(&d_status, 5));
   HIP_TRY(mem.alloc(&d_vref, (size_t)np));
   ContactBoxDev* d_cboxes;

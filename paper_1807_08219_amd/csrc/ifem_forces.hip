@@ -1,9 +1,9 @@
 // Element forces of the IFEM coupling step on gfx950.
 //
-//  k_ref_tri / k_ref_tet  reference metric of every element (float64 setup):
-//                         G = D0^T D0 of the reference edge matrix D0, the
-//                         reference area A0 = sqrt(det G)/2 (triangles) or
-//                         volume V0 = det D0 / 6 (tetrahedra).
+//  k_ref_tri / k_ref_tet  reference data of every element (float64 setup):
+//                         triangles the metric G = D0^T D0 of the reference
+//                         edge matrix D0 and the area A0 = sqrt(det G)/2,
+//                         tetrahedra D0^-1 and the volume V0 = det D0 / 6.
 //  k_forces<T>            one workgroup per particle: elastic element forces,
 //                         Helfrich bending, float64 volume/area/centroid, and a
 //                         single coalesced write of the nodal forces.
@@ -12,27 +12,42 @@
 //                         curvature and Laplacian passes per node, a fixed-order
 //                         gather per node (see the section below).
 //
-// Element forces use the covariant form of the paper's constitutive laws.
-// With current edges D = [d1 d2 (d3)], g = D^T D, Delta = g - G and
-// M = G^-1 Delta, the second Piola-Kirchhoff stress in edge coordinates is
-//   membrane (Sec. II.A tension relation):  S = 2 (W1 I + W2 adj(I + M)) G^-1
+// Membrane forces use the covariant form of the paper's constitutive laws.
+// With current edges D = [d1 d2], g = D^T D, Delta = g - G and M = G^-1 Delta,
+// the second Piola-Kirchhoff stress in edge coordinates is (Sec. II.A tension
+// relation)  S = 2 (W1 I + W2 adj(I + M)) G^-1,
 //     Skalak:       S G = mu M + (mu_D / 2) I2b ((1 + tr M) I - M)
 //     neo-Hookean:  S G = mu ((tr M + 2 det M + I2b^2) I + M) / (1 + I2b)^2
-//     with I1 - 2 = tr M and I2b = I2 - 1 = tr M + det M;
-//   solid (Sec. II.B stress of the tetrahedral element):
-//     S = lam/2 (J^2 - 1) g^-1 + mu g^-1 Delta G^-1,  J^2 - 1 = e1(M) + e2(M) + e3(M);
-// and the nodal forces are [f1 f2 (f3)] = -A0 (V0) D S, f0 = -(f1 + f2 (+ f3))
-// (eq. FEM / FEM_Membrane with linear shape functions).  These equal the
-// paper's frame-based expressions exactly; the per-element tangent frame
-// drops out because the laws depend on the invariants only.  In float32 the
-// metric difference Delta is formed error-free (float-float), so the small
-// strain invariants carry no cancellation error.
+//     with I1 - 2 = tr M and I2b = I2 - 1 = tr M + det M,
+// and the nodal forces are [f1 f2] = -A0 D S, f0 = -(f1 + f2) (eq.
+// FEM_Membrane with linear shape functions).  These equal the paper's
+// frame-based expressions exactly; the per-element tangent frame drops out
+// because the laws depend on the invariants only.  In float32 the metric
+// difference Delta is formed error-free (float-float), so the small strain
+// invariants carry no cancellation error.  Tetrahedra (Sec. II.B, eq. FEM)
+// use the deformation gradient F = D D0^-1 directly (tet_element below).
 #include "ifem_device.hpp"
 #include "ifem_internal.hpp"
 
 namespace ifem {
 
 // ------------------------------------------------------------------ setup: reference metrics
+// Inverse of a 3 x 3 matrix by cofactors; returns the determinant.
+__device__ __forceinline__ double inverse3(const double m[3][3], double r[3][3]) {
+  const double d = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                   m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+  r[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) / d;
+  r[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) / d;
+  r[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) / d;
+  r[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) / d;
+  r[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) / d;
+  r[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) / d;
+  r[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) / d;
+  r[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) / d;
+  r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) / d;
+  return d;
+}
+
 __global__ void k_ref_tri(int n_tris, int n_nodes, const int32_t* __restrict__ src, const int32_t* __restrict__ tri,
                           const double* __restrict__ X, double* __restrict__ ref, unsigned long long* status) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -62,21 +77,17 @@ __global__ void k_ref_tet(int n_tets, int n_nodes, const int32_t* __restrict__ s
   const int e = src[s];
   int id[4];
   for (int v = 0; v < 4; ++v) id[v] = tet[v * n_tets + e];
-  double d[3][3];  // d[a] = X_{a+1} - X_0
+  // reference edge matrix D0 (column a = X_{a+1} - X_0) and its inverse, whose row a is the
+  // gradient of node a+1's shape function; the inverse's condition number is that of D0, where a
+  // metric (D0^T D0) would square it
+  double D0[3][3];
   for (int a = 0; a < 3; ++a)
-    for (int c = 0; c < 3; ++c) d[a][c] = X[c * n_nodes + id[a + 1]] - X[c * n_nodes + id[0]];
-  double G[6];
-  G[0] = d[0][0] * d[0][0] + d[0][1] * d[0][1] + d[0][2] * d[0][2];
-  G[1] = d[0][0] * d[1][0] + d[0][1] * d[1][1] + d[0][2] * d[1][2];
-  G[2] = d[0][0] * d[2][0] + d[0][1] * d[2][1] + d[0][2] * d[2][2];
-  G[3] = d[1][0] * d[1][0] + d[1][1] * d[1][1] + d[1][2] * d[1][2];
-  G[4] = d[1][0] * d[2][0] + d[1][1] * d[2][1] + d[1][2] * d[2][2];
-  G[5] = d[2][0] * d[2][0] + d[2][1] * d[2][1] + d[2][2] * d[2][2];
-  const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
-                     d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
-                     d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
-  for (int k = 0; k < 6; ++k) ref[k * n_tets + s] = G[k];
-  ref[6 * n_tets + s] = det / 6.0;
+    for (int c = 0; c < 3; ++c) D0[c][a] = X[c * n_nodes + id[a + 1]] - X[c * n_nodes + id[0]];
+  double Di[3][3];
+  const double det = inverse3(D0, Di);
+  for (int a = 0; a < 3; ++a)
+    for (int j = 0; j < 3; ++j) ref[(3 * a + j) * n_tets + s] = Di[a][j];
+  ref[9 * n_tets + s] = det / 6.0;
   if (!(det > 0.0)) atomicAdd(status + 3, 1ull);
 }
 
@@ -105,27 +116,6 @@ __device__ __forceinline__ void metric_delta(const double xs[][3], int ne, doubl
   for (int a = 0; a < ne; ++a)
     for (int b = a; b < ne; ++b, ++k)
       Delta[k] = (dh[a][0] * dh[b][0] + dh[a][1] * dh[b][1] + dh[a][2] * dh[b][2]) - Gref[k];
-}
-
-// Delta = g - G returned in float64: the float-float Gram sum (s, e) minus the
-// float64 reference, with no rounding of Delta to float (s - G is exact by
-// Sterbenz for strains below 100 %).  The float64 path forms it directly.
-__device__ __forceinline__ void metric_delta_f64(const float xs[][3], int ne, float (*dh)[3], float (*dl)[3],
-                                                 const double* Gref, double* Delta) {
-  for (int a = 0; a < ne; ++a)
-    for (int c = 0; c < 3; ++c) two_diff(xs[a + 1][c], xs[0][c], dh[a][c], dl[a][c]);
-  int k = 0;
-  for (int a = 0; a < ne; ++a)
-    for (int b = a; b < ne; ++b, ++k) {
-      float s, e;
-      dot3_ff(dh[a], dl[a], dh[b], dl[b], s, e);
-      Delta[k] = ((double)s - Gref[k]) + (double)e;
-    }
-}
-
-__device__ __forceinline__ void metric_delta_f64(const double xs[][3], int ne, double (*dh)[3], double (*dl)[3],
-                                                 const double* Gref, double* Delta) {
-  metric_delta(xs, ne, dh, dl, Gref, Delta);
 }
 
 // ------------------------------------------------------------------ membrane element
@@ -179,91 +169,55 @@ __device__ __forceinline__ bool tri_element(const T xs[3][3], const double G[3],
 }
 
 // ------------------------------------------------------------------ tetrahedral element
+// Slightly compressible neo-Hookean tetrahedron (Sec. II.B) in the deformation-gradient form:
+// F = sum_a e_a (x) g_a with the current edges e_a = x_{a+1} - x_0 and the rows g_a of the inverse
+// reference edge matrix, J = det F, C^-1 = F^-1 F^-T, S = lam/2 (J^2 - 1) C^-1 + mu (I - C^-1),
+// P = F S and f_k = -V0 P g_k (g_0 = -(g_1 + g_2 + g_3)).  All of it in float64 from exact edges
+// (float32 offsets split into (hi, lo) pairs): near-incompressible solids turn any rounding of the
+// volumetric strain into a stress error lambda / mu times larger, and flat reference tetrahedra are
+// ill-conditioned, so the element works with the edge matrices themselves, never with their metrics
+// (which square the condition number).  Returns false (and zero forces) for an inverted element.
 template <typename T>
-__device__ __forceinline__ void sym3_inverse(const T g[6], T gi[6]) {
-  // g = {g11, g12, g13, g22, g23, g33}
-  const T c11 = g[3] * g[5] - g[4] * g[4];
-  const T c12 = g[2] * g[4] - g[1] * g[5];
-  const T c13 = g[1] * g[4] - g[2] * g[3];
-  const T c22 = g[0] * g[5] - g[2] * g[2];
-  const T c23 = g[1] * g[2] - g[0] * g[4];
-  const T c33 = g[0] * g[3] - g[1] * g[1];
-  const T det = g[0] * c11 + g[1] * c12 + g[2] * c13;
-  const T r = T(1) / det;
-  gi[0] = c11 * r;
-  gi[1] = c12 * r;
-  gi[2] = c13 * r;
-  gi[3] = c22 * r;
-  gi[4] = c23 * r;
-  gi[5] = c33 * r;
-}
-
-template <typename T>
-__device__ __forceinline__ T symget(const T s[6], int a, int b) {
-  const int lo = a < b ? a : b, hi = a < b ? b : a;
-  return s[lo == 0 ? hi : (lo == 1 ? 2 + hi : 5)];
-}
-
-// Returns false (and zero forces) for an inverted element (det D <= 0).
-// Only the Gram matrix comes from the working precision (float-float in the
-// float32 path, exact to about u^2 |g|); Delta, the stress and the forces are
-// formed in float64 from the exact edges.  Near-incompressible solids turn
-// any rounding of Delta into a large volumetric stress error (lambda / mu
-// times it), flat tetrahedra have ill-conditioned metrics, and the few
-// tetrahedra of a suspension make the float64 cost small.
-template <typename T>
-__device__ __forceinline__ bool tet_element(const T xs[4][3], const double G[6], double V0, T mu_t, T lam_t,
+__device__ __forceinline__ bool tet_element(const T xs[4][3], const double Di[9], double V0, T mu_t, T lam_t,
                                             T f[4][3]) {
-  T dh[3][3], dl[3][3];
-  double D[6];
-  metric_delta_f64(xs, 3, dh, dl, G, D);
-  double e[3][3];
+  double e[3][3];  // e[a] = x_{a+1} - x_0, exactly in the float32 path
   for (int a = 0; a < 3; ++a)
-    for (int c = 0; c < 3; ++c) e[a][c] = (double)dh[a][c] + (sizeof(T) == 4 ? (double)dl[a][c] : 0.0);
-  const double mu = (double)mu_t, lam = (double)lam_t;
-  double Gi[6];
-  sym3_inverse<double>(G, Gi);
-  // M = G^-1 Delta (full 3x3)
-  double M[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      M[a][b] = symget(Gi, a, 0) * symget(D, 0, b) + symget(Gi, a, 1) * symget(D, 1, b) + symget(Gi, a, 2) * symget(D, 2, b);
-  const double e1 = M[0][0] + M[1][1] + M[2][2];
-  const double e2 = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) + (M[0][0] * M[2][2] - M[0][2] * M[2][0]) +
-                    (M[1][1] * M[2][2] - M[1][2] * M[2][1]);
-  const double e3 = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
-                    M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
-                    M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
-  const double J2m1 = e1 + e2 + e3;
-  // orientation of the current element
-  const double detD = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
-                      e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
-                      e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
-  const bool ok = detD > 0.0;
-  // current metric g = G + Delta and its inverse
-  double gd[6], gi[6];
-  for (int k = 0; k < 6; ++k) gd[k] = G[k] + D[k];
-  sym3_inverse<double>(gd, gi);
-  // S = lam/2 (J^2 - 1) g^-1 + mu g^-1 Delta G^-1
-  double DG[3][3];  // Delta G^-1
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      DG[a][b] = symget(D, a, 0) * symget(Gi, 0, b) + symget(D, a, 1) * symget(Gi, 1, b) + symget(D, a, 2) * symget(Gi, 2, b);
-  double S[3][3];
-  const double kv = 0.5 * lam * J2m1;
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      S[a][b] = kv * symget(gi, a, b) +
-                mu * (symget(gi, a, 0) * DG[0][b] + symget(gi, a, 1) * DG[1][b] + symget(gi, a, 2) * DG[2][b]);
-  for (int c = 0; c < 3; ++c) {
-    double s0 = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      const double fa = ok ? -V0 * (e[0][c] * S[0][a] + e[1][c] * S[1][a] + e[2][c] * S[2][a]) : 0.0;
-      f[a + 1][c] = (T)fa;
-      s0 += fa;
+    for (int c = 0; c < 3; ++c) {
+      if (sizeof(T) == 4) {
+        float hi, lo;
+        two_diff((float)xs[a + 1][c], (float)xs[0][c], hi, lo);
+        e[a][c] = (double)hi + (double)lo;
+      } else {
+        e[a][c] = (double)xs[a + 1][c] - (double)xs[0][c];
+      }
     }
-    f[0][c] = (T)(-s0);
+  const double mu = (double)mu_t, lam = (double)lam_t;
+  double F[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) F[i][j] = e[0][i] * Di[j] + e[1][i] * Di[3 + j] + e[2][i] * Di[6 + j];
+  double Fi[3][3];
+  const double J = inverse3(F, Fi);
+  const bool ok = J > 0.0;
+  double Ci[3][3];  // F^-1 F^-T
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) Ci[k][j] = Fi[k][0] * Fi[j][0] + Fi[k][1] * Fi[j][1] + Fi[k][2] * Fi[j][2];
+  const double kv = 0.5 * lam * (J * J - 1.0);
+  double S[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) S[k][j] = kv * Ci[k][j] + mu * ((k == j ? 1.0 : 0.0) - Ci[k][j]);
+  double P[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[i][j] = F[i][0] * S[0][j] + F[i][1] * S[1][j] + F[i][2] * S[2][j];
+  double g[4][3];
+  for (int j = 0; j < 3; ++j) {
+    g[1][j] = Di[j];
+    g[2][j] = Di[3 + j];
+    g[3][j] = Di[6 + j];
+    g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
   }
+  for (int k = 0; k < 4; ++k)
+    for (int i = 0; i < 3; ++i)
+      f[k][i] = ok ? (T)(-V0 * (P[i][0] * g[k][0] + P[i][1] * g[k][1] + P[i][2] * g[k][2])) : T(0);
   return ok;
 }
 
@@ -508,12 +462,12 @@ __global__ void __launch_bounds__(512) k_forces(const ForceArgs a, const T* __re
         xs[v][1] = xy[ids[v]];
         xs[v][2] = xz[ids[v]];
       }
-      double G[6];
+      double Di[9];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) G[k] = a.tet_ref[k * a.n_tets + s];
-      const double V0 = a.tet_ref[6 * a.n_tets + s];
+      for (int k = 0; k < 9; ++k) Di[k] = a.tet_ref[k * a.n_tets + s];
+      const double V0 = a.tet_ref[9 * a.n_tets + s];
       T f[4][3];
-      if (!tet_element<T>(xs, G, V0, mu, mu2, f)) ++my_bad;
+      if (!tet_element<T>(xs, Di, V0, mu, mu2, f)) ++my_bad;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         acc[ids[v]] += f[v][0];
@@ -703,10 +657,10 @@ __global__ void __launch_bounds__(256) k_large_elems(const ForceArgs a, const La
       const int et = e - L.n_tri;
       T xs[4][3];
       for (int v = 0; v < 4; ++v) large_pos(x, N, n0 + a.tet_local[v * a.n_tets + s], xs[v]);
-      double G[6];
-      for (int k = 0; k < 6; ++k) G[k] = a.tet_ref[k * a.n_tets + s];
+      double Di[9];
+      for (int k = 0; k < 9; ++k) Di[k] = a.tet_ref[k * a.n_tets + s];
       T f[4][3];
-      bad = !tet_element<T>(xs, G, a.tet_ref[6 * a.n_tets + s], mu, mu2, f);
+      bad = !tet_element<T>(xs, Di, a.tet_ref[9 * a.n_tets + s], mu, mu2, f);
       for (int v = 0; v < 4; ++v) store_corner(reinterpret_cast<T*>(L.ef_tet) + ((int64_t)v * L.n_tet + et) * 4, f[v]);
       double q[4][3];
       for (int v = 0; v < 4; ++v)

@@ -25,7 +25,8 @@ struct ForceArgs {
   const int32_t* pcol_tet;
   const int32_t* colb_tet;
   const int32_t* tet_local;  // [4][n_tets]
-  const double* tet_ref;     // [7][n_tets] G11 G12 G13 G22 G23 G33 V0
+  const double* tet_ref;     // [10][n_tets] inverse reference edge matrix (row-major: the shape gradients
+                             // of nodes 1..3), V0
   const int32_t* ring_start; // [n_nodes + 1]: one-rings of bending and (when all close) membrane nodes, or null
   const int32_t* ring;       // one-ring neighbours, particle-local ids
   const int32_t* lds_part;   // [grid of k_forces] the particles it takes, or null for all of them
