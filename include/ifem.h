@@ -50,8 +50,9 @@
  *   IFEM_F32  positions are float32 offsets from a per-particle float64 anchor
  *             (`anchor` [n_particles][3], device, required): the node position
  *             is anchor[p] + (double)offset.  Forces, grids, velocities float32.
- *             Strain invariants are formed without cancellation (the metric
- *             difference g - G is computed error-free in float-float).
+ *             Strain invariants are formed without cancellation (membranes:
+ *             the metric difference g - G error-free in float-float;
+ *             tetrahedra: exact edges, the deformation gradient in float64).
  *   Per-particle reductions are float64 in both precisions.
  *
  * Lattices: box b has n = (nx, ny, nz) cells of spacing h, periodic on every
@@ -213,7 +214,8 @@ ifem_status ifem_plan_autotune(ifem_plan plan, int32_t dtype, const void* x, con
 
 /* Build a plan for one set of meshes and boxes (Sec. II.B reference
  * configuration): copies connectivity and materials to the device, computes
- * the float64 reference metrics of every element on the device, colours the
+ * the float64 reference data of every element on the device (triangles their
+ * metric and area, tetrahedra the inverse edge matrix and volume), colours the
  * elements of each particle for conflict-free accumulation, builds the
  * one-ring of every bending node and sizes the spreading workspace.  A
  * particle whose float64 nodal accumulators fit one workgroup's LDS (up to
