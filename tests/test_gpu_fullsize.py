@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import fixed_point
-import extended_tet
+import extended_elements
 import oracle
 from paper_1807_08219_amd import ifem
 from paper_1807_08219_amd.inputs import fields, scenes
@@ -330,7 +330,7 @@ def test_fullsize_fp64_forces_and_interp_sampled(full):
     # near-incompressible platelets (lambda / mu = 50, flat reference tetrahedra) under small, nearly
     # isochoric strain change by 3e-10 to 1e-9 relative under such a move, and the oracle itself is
     # 1e-12 off their 80-bit forces, so two float64 evaluations of them cannot agree to 1e-12.  Solids
-    # are also measured against those 80-bit forces (tests/extended_tet.py): the library must be as
+    # are also measured against those 80-bit forces (tests/extended_elements.py): the library must be as
     # close to them as the oracle
     cfg, sc, plan = full
     rng = np.random.default_rng(500 + cfg)
@@ -352,13 +352,22 @@ def test_fullsize_fp64_forces_and_interp_sampled(full):
         bar = max(1e-12 * nF, 0.5 * _one_ulp_change(one, Fo))
         say(f"    particle {p} (law {int(sc.law[p])}): rel err {err / nF:.3e}, bar {bar / nF:.3e}")
         assert err <= bar
+        # both float64 evaluations against the 80-bit forces of the same particle (membranes: their
+        # elastic part, from a plan of the particle alone without bending): the library must be as
+        # close to the exact forces as the oracle (measured: closer)
         if int(sc.law[p]) == scenes.LAW_TET_NEOHOOKE:
-            # both float64 evaluations against the 80-bit forces of the same particle
-            Fx = extended_tet.particle_forces(one, 0)
-            e_lib, e_orc = extended_tet.rel_ld(Fh[:, nodes], Fx), extended_tet.rel_ld(Fo, Fx)
-            say(f"    particle {p}: off the 80-bit forces by {e_lib:.3e} (library), {e_orc:.3e} (oracle)")
-            # the library is as close to the exact forces as the oracle (measured: closer)
-            assert e_lib <= max(1e-12, 1.5 * e_orc)
+            Fx = extended_elements.particle_forces(one, 0)
+            F_lib, F_orc = Fh[:, nodes], Fo
+        else:
+            el = scenes.Scene(**{**one.__dict__, "kb": np.zeros_like(one.kb)})
+            Fe = torch.empty((3, el.n_nodes), dtype=torch.float64, device="cuda")
+            ifem.Plan(el).element_forces(ifem.IFEM_F64, cu(el.x64, torch.float64), None, Fe, None)
+            torch.cuda.synchronize()
+            Fx = extended_elements.particle_membrane_forces(el, 0)
+            F_lib, F_orc = Fe.cpu().numpy(), oracle.forces(el)[0]
+        e_lib, e_orc = extended_elements.rel_ld(F_lib, Fx), extended_elements.rel_ld(F_orc, Fx)
+        say(f"    particle {p}: off the 80-bit forces by {e_lib:.3e} (library), {e_orc:.3e} (oracle)")
+        assert e_lib <= max(1e-12, 1.5 * e_orc)
     sub = scenes.subset(sc, parts)
     ro = oracle.reduce(sub)
     assert rel(red.cpu().numpy()[parts], ro) <= 1e-12

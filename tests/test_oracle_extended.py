@@ -1,7 +1,8 @@
-"""The extended-precision tetrahedron forces (tests/extended_tet.py) against the oracle.
+"""The extended-precision element forces (tests/extended_elements.py) against the oracle.
 
-Both evaluate the element force of slightly compressible neo-Hookean tetrahedra (Sec. II.B), one in
-80-bit and one in 64-bit arithmetic.  On every solid tried the oracle stays within a tenth of the
+Both evaluate the element forces of slightly compressible neo-Hookean tetrahedra (Sec. II.B) and of
+neo-Hookean and Skalak membranes (Sec. II.A, elastic part), one in 80-bit and one in 64-bit
+arithmetic.  On every solid tried the oracle stays within a tenth of the
 forces' own conditioning (the change a one-ulp move of the positions produces) of the 80-bit result,
 and to 2e-14 on a well-conditioned one; on a near-incompressible platelet under a small isochoric shear
 (lambda / mu = 50, flattened reference tetrahedra) it is more than 1e-12 off, which bounds what any
@@ -10,7 +11,7 @@ float64 evaluation of those forces can reach.
 import numpy as np
 import pytest
 
-import extended_tet
+import extended_elements
 import oracle
 from paper_1807_08219_amd.inputs import scenes
 
@@ -46,7 +47,7 @@ def test_oracle_is_within_a_tenth_of_its_conditioning_of_the_80_bit_forces(ratio
     # formula (a dropped or scaled term) would be off by the order of the strain
     sc = _platelet(gamma=gamma, ratio=ratio)
     Fo, _ = oracle.forces(sc)
-    e = extended_tet.rel_ld(Fo, extended_tet.particle_forces(sc, 0))
+    e = extended_elements.rel_ld(Fo, extended_elements.particle_forces(sc, 0))
     one = _one_ulp_change(sc, Fo)
     assert e <= 0.1 * one, (e, one)
     if (ratio, gamma) == (1.0, 0.6):
@@ -58,5 +59,16 @@ def test_near_incompressible_platelet_cannot_meet_1e_12_in_float64():
     # 1e-12 relative, so no float64 evaluation can be held to 1e-12 there
     sc = _platelet(gamma=0.01, ratio=50.0)
     Fo, _ = oracle.forces(sc)
-    e = extended_tet.rel_ld(Fo, extended_tet.particle_forces(sc, 0))
+    e = extended_elements.rel_ld(Fo, extended_elements.particle_forces(sc, 0))
     assert e > 1e-12, e
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_oracle_membranes_are_within_a_tenth_of_their_conditioning_of_the_80_bit_forces(cfg):
+    # the noisy neo-Hookean capsule and the sheared Skalak red cell, elastic forces only
+    sc = scenes.make_config(cfg)
+    sc = scenes.Scene(**{**sc.__dict__, "kb": np.zeros_like(sc.kb)})
+    Fo, _ = oracle.forces(sc)
+    e = extended_elements.rel_ld(Fo, extended_elements.particle_membrane_forces(sc, 0))
+    one = _one_ulp_change(sc, Fo)
+    assert e <= 0.1 * one, (e, one)
