@@ -83,3 +83,23 @@ def test_carried_lists_give_the_first_call_grid(case, dtype, tile):
         say(f"  call {i} shift {shift}: rel {e:.2e}")
         assert e <= (F64_TOL if dtype == ifem.IFEM_F64 else F32_TRANSFER_TOL)
     assert plan.status()[3] == 0
+
+
+# the 64-box workload (sparse tiles, lists of every length, boxes of different sizes) in the default
+# launch shape: every call equals a fresh plan's first call bit for bit; that call is checked against
+# the oracle at full size elsewhere
+@pytest.mark.parametrize("dtype", [ifem.IFEM_F64, ifem.IFEM_F32])
+def test_carried_lists_batched_boxes(dtype):
+    sc = scenes.make_config(4)
+    say(f"[carried] {sc.name} dtype {dtype}: {sc.n_nodes} nodes, {sc.total_cells} cells")
+    F = np.random.default_rng(6).normal(size=(3, sc.n_nodes))
+    if dtype == ifem.IFEM_F32:
+        F = F.astype(np.float32).astype(np.float64)
+    plan = ifem.Plan(sc)
+    for i, shift in enumerate(MOVES[:5]):
+        got = _spread(plan, sc, dtype, shift, F)
+        fresh = _spread(ifem.Plan(sc), sc, dtype, shift, F)
+        say(f"  call {i} shift {shift}: {int(np.count_nonzero(got))} non-zero values")
+        assert np.all(np.isfinite(got))
+        assert np.array_equal(got, fresh), f"call {i} (shift {shift}) differs from a fresh plan's"
+    assert plan.status()[3] == 0
