@@ -345,3 +345,31 @@ def test_fp64_spread_of_one_long_tile_list():
     assert rel(got, Go) <= 1e-12
     assert np.all(err <= 1e-12 * mag + nJ * U)
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", [ifem.IFEM_F64, ifem.IFEM_F32])
+def test_zero_forces_give_a_zero_grid(dtype):
+    # every list's force bound is 0 (no fixed-point scale): the entries still run through the weights
+    # (a non-finite position would be found), and every cell, halo rows included, is exactly +0
+    sc = scenes.small_mixed()
+    say(f"[gpu] zero forces dtype {dtype}: {sc.n_nodes} nodes")
+    dt = torch.float64 if dtype == ifem.IFEM_F64 else torch.float32
+    if dtype == ifem.IFEM_F64:
+        x, a = cu(sc.x64, torch.float64), None
+    else:
+        x, a = cu(sc.x32, torch.float32), cu(sc.anchor, torch.float64)
+    F = torch.zeros((3, sc.n_nodes), dtype=dt, device="cuda")
+    G = torch.empty((3, sc.total_cells), dtype=dt, device="cuda")
+    plan = ifem.Plan(sc)
+    for mode in (ifem.IFEM_SPREAD_TILED, ifem.IFEM_SPREAD_ATOMIC, ifem.IFEM_SPREAD_TILED):
+        plan.set(ifem.IFEM_OPT_SPREAD_MODE, mode)
+        G.fill_(float("nan"))
+        plan.spread(dtype, x, a, F, G)
+        torch.cuda.synchronize()
+        g = G.cpu().numpy()
+        assert np.all(g == 0.0) and not np.any(np.signbit(g)), f"mode {mode}"
+    plan.spread_noalloc(dtype, x, a, F, G)
+    torch.cuda.synchronize()
+    assert float(G.abs().max()) == 0.0
+    assert plan.status() == [0, 0, 0, 0, 0]
+    plan.close()
