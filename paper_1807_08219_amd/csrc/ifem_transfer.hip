@@ -761,9 +761,12 @@ __device__ __forceinline__ void spread_item(const TransferArgs& a, const T* __re
   if (tid == 0) a.tile_flag[L] = halo_on ? 1 : 0;
 }
 
-// One workgroup per item (tile, component), the items of neighbouring tiles on one XCD.
+// One workgroup per item (tile, component), the items of neighbouring tiles on one XCD.  Float64: at
+// least four wavefronts per SIMD (at most 128 registers), so that two workgroups share a compute unit
+// as their LDS regions allow (float32 needs no hint: 80 registers).
 template <typename T>
-__global__ void __launch_bounds__(kTileThreads) k_spread_home(const TransferArgs a, const T* __restrict__ x,
+__global__ void __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1)))
+k_spread_home(const TransferArgs a, const T* __restrict__ x,
                                                               const double* __restrict__ anchor,
                                                               const T* __restrict__ F, T* __restrict__ grid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
